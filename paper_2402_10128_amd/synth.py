@@ -1,0 +1,222 @@
+"""Seeded synthetic GES scenes and cameras.
+
+This module only draws random inputs and builds pinhole cameras; it holds none
+of the rendering arithmetic.  Both the HIP path and the CPU oracle consume what
+it produces, so every array is float32 and C-contiguous.
+
+Scene recipes (all parameters in the form the paper states the problem in,
+Sec. 4.1: position, log-scale, quaternion, opacity logit, SH colour, shape beta):
+
+* ``uniform``  -- means U[-1,1]^3, log-scales N(-3,0.5), SH degree 0 with the DC
+  colour U[0,1], beta U[1,4], opacity sigmoid(N(0,1)).
+* ``clusters`` -- means from 64 isotropic clusters (sigma 0.3) with centres
+  U[-5,5]^3, log-scales N(-4,0.7), opacity sigmoid(N(0,1.5)), SH degree 3 with
+  DC colour U[0,1] and higher orders N(0,0.05), beta log-uniform [0.5,8].
+* ``overlap``  -- 16 dense clusters (sigma 0.25) on a 4x4 grid in front of the
+  camera, one log-scale axis N(-1.5,0.5) and two N(-5,0.5) (long axis in a
+  random direction via the random quaternion), opacity sigmoid(N(1,1)),
+  beta U[0.5,2], SH degree 3.
+
+The DC colour c is stored as the SH coefficient (c - 0.5) / Y00 so that the
+rendered colour of a degree-0 splat is exactly c before clamping.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+Y00 = 0.28209479177387814  # 1 / (2 sqrt(pi)), the l=0 real SH value
+
+
+@dataclass
+class Camera:
+    width: int
+    height: int
+    R: np.ndarray          # (3,3) float32, world -> camera rotation (rows = camera axes)
+    t: np.ndarray          # (3,) float32, world -> camera translation
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    near: float = 0.2
+
+    def as_dict(self):
+        return dict(width=self.width, height=self.height, R=self.R, t=self.t,
+                    fx=self.fx, fy=self.fy, cx=self.cx, cy=self.cy, near=self.near)
+
+
+@dataclass
+class Scene:
+    means: np.ndarray
+    log_scales: np.ndarray
+    quats: np.ndarray
+    opacity_logits: np.ndarray
+    sh: np.ndarray
+    beta: np.ndarray
+    sh_degree: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    def arrays(self):
+        return dict(means=self.means, log_scales=self.log_scales, quats=self.quats,
+                    opacity_logits=self.opacity_logits, sh=self.sh, beta=self.beta)
+
+
+def look_at(position, target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0)):
+    """World->camera (R, t) for a camera at ``position`` looking at ``target``.
+
+    Camera axes: x right, y down (image rows grow downwards), z forward.
+    """
+    p = np.asarray(position, dtype=np.float64)
+    f = np.asarray(target, dtype=np.float64) - p
+    f /= np.linalg.norm(f)
+    x = np.cross(f, np.asarray(up, dtype=np.float64))
+    x /= np.linalg.norm(x)
+    y = np.cross(f, x)
+    R = np.stack([x, y, f], axis=0)
+    t = -R @ p
+    return R.astype(np.float32), t.astype(np.float32)
+
+
+def pinhole(width: int, height: int, position, target=(0.0, 0.0, 0.0), fov_x_deg: float = 60.0,
+            near: float = 0.2) -> Camera:
+    R, t = look_at(position, target)
+    fx = width / (2.0 * math.tan(math.radians(fov_x_deg) / 2.0))
+    return Camera(width=int(width), height=int(height), R=R, t=t, fx=float(np.float32(fx)),
+                  fy=float(np.float32(fx)), cx=(width - 1) / 2.0, cy=(height - 1) / 2.0, near=near)
+
+
+def orbit_camera(rng: np.random.Generator, width: int, height: int, radius: float = 8.0) -> Camera:
+    az = rng.uniform(0.0, 2.0 * math.pi)
+    el = math.radians(rng.uniform(-20.0, 20.0))
+    pos = radius * np.array([math.cos(el) * math.sin(az), math.sin(el), math.cos(el) * math.cos(az)])
+    return pinhole(width, height, pos)
+
+
+def _quats(rng, n):
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return q.astype(np.float32)
+
+
+def _sh(rng, n, degree, dc_rgb, high_std):
+    k = (degree + 1) ** 2
+    sh = np.zeros((n, k, 3), dtype=np.float32)
+    sh[:, 0, :] = (dc_rgb - 0.5) / Y00
+    if k > 1:
+        sh[:, 1:, :] = rng.normal(0.0, high_std, size=(n, k - 1, 3))
+    return sh
+
+
+def scene_uniform(n: int, seed: int) -> Scene:
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(-1.0, 1.0, size=(n, 3)).astype(np.float32)
+    log_scales = rng.normal(-3.0, 0.5, size=(n, 3)).astype(np.float32)
+    quats = _quats(rng, n)
+    logits = rng.normal(0.0, 1.0, size=n).astype(np.float32)
+    sh = _sh(rng, n, 0, rng.uniform(0.0, 1.0, size=(n, 3)), 0.0)
+    beta = rng.uniform(1.0, 4.0, size=n).astype(np.float32)
+    return Scene(means, log_scales, quats, logits, sh, beta, 0, dict(kind="uniform", seed=seed))
+
+
+def scene_clusters(n: int, seed: int, degree: int = 3, n_clusters: int = 64) -> Scene:
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-5.0, 5.0, size=(n_clusters, 3))
+    which = rng.integers(0, n_clusters, size=n)
+    means = (centres[which] + rng.normal(0.0, 0.3, size=(n, 3))).astype(np.float32)
+    log_scales = rng.normal(-4.0, 0.7, size=(n, 3)).astype(np.float32)
+    quats = _quats(rng, n)
+    logits = rng.normal(0.0, 1.5, size=n).astype(np.float32)
+    sh = _sh(rng, n, degree, rng.uniform(0.0, 1.0, size=(n, 3)), 0.05)
+    beta = np.exp(rng.uniform(math.log(0.5), math.log(8.0), size=n)).astype(np.float32)
+    return Scene(means, log_scales, quats, logits, sh, beta, degree, dict(kind="clusters", seed=seed))
+
+
+def scene_overlap(n: int, seed: int, cam: Camera, depth_range=(6.0, 10.0)) -> Scene:
+    """Heavy-overlap scene: 16 dense clusters laid out in front of ``cam``."""
+    rng = np.random.default_rng(seed)
+    # cluster centres on a 4x4 grid spanning 60% of the frame, depth 6..10 along the view axis
+    gx, gy = np.meshgrid(np.linspace(-0.3, 0.3, 4), np.linspace(-0.3, 0.3, 4))
+    depth = rng.uniform(*depth_range, size=16)
+    ndc = np.stack([gx.ravel(), gy.ravel()], axis=1)
+    half_w = cam.width / (2.0 * cam.fx)
+    half_h = cam.height / (2.0 * cam.fy)
+    cam_pts = np.stack([ndc[:, 0] * 2 * half_w * depth, ndc[:, 1] * 2 * half_h * depth, depth], axis=1)
+    R = cam.R.astype(np.float64)
+    t = cam.t.astype(np.float64)
+    centres = (cam_pts - t) @ R  # camera -> world: R^T (p - t)
+    which = rng.integers(0, 16, size=n)
+    means = (centres[which] + rng.normal(0.0, 0.25, size=(n, 3))).astype(np.float32)
+    ls = rng.normal(-5.0, 0.5, size=(n, 3))
+    ls[:, 0] = rng.normal(-1.5, 0.5, size=n)
+    log_scales = ls.astype(np.float32)
+    quats = _quats(rng, n)
+    logits = rng.normal(1.0, 1.0, size=n).astype(np.float32)
+    sh = _sh(rng, n, 3, rng.uniform(0.0, 1.0, size=(n, 3)), 0.05)
+    beta = rng.uniform(0.5, 2.0, size=n).astype(np.float32)
+    return Scene(means, log_scales, quats, logits, sh, beta, 3, dict(kind="overlap", seed=seed))
+
+
+def random_target(rng: np.random.Generator, width: int, height: int) -> np.ndarray:
+    return rng.uniform(0.0, 1.0, size=(height, width, 3)).astype(np.float32)
+
+
+# ---- the five workloads -------------------------------------------------------------------
+
+CONFIG_NAMES = {
+    0: "fwd+bwd 1k splats 64x64 (uniform cube, SH0)",
+    1: "fwd+bwd 1M splats 1600x1040 (64 clusters, SH3)",
+    2: "train step 3M splats 1920x1080 (64 clusters, SH3, L1 + freq-masked L1)",
+    3: "fwd+bwd 5M splats 1920x1080 (16 dense anisotropic clusters)",
+    4: "serving: 8 resident scenes 0.2M..4M splats, mixed resolutions",
+}
+
+
+def make_config(k: int, n_override: int | None = None, seed: int | None = None):
+    """Inputs for workload ``k``: dict(scene=..., camera=..., target=..., extra...).
+
+    ``n_override`` shrinks the splat count (same recipe) for parity tests.
+    """
+    seed = 1000 + k if seed is None else seed
+    if k == 0:
+        n = 1000 if n_override is None else n_override
+        sc = scene_uniform(n, seed)
+        cam = pinhole(64, 64, (0.0, 0.0, -4.0))
+        tgt = random_target(np.random.default_rng(seed + 7), 64, 64)
+        return dict(scene=sc, camera=cam, target=tgt, loss="l1")
+    if k in (1, 2):
+        n = (1_000_000 if k == 1 else 3_000_000) if n_override is None else n_override
+        sc = scene_clusters(n, seed)
+        w, h = (1600, 1040) if k == 1 else (1920, 1080)
+        cam = orbit_camera(np.random.default_rng(seed + 1), w, h)
+        tgt = random_target(np.random.default_rng(seed + 7), w, h)
+        return dict(scene=sc, camera=cam, target=tgt, loss="l1" if k == 1 else "l1+freq", omega=0.75)
+    if k == 3:
+        n = 5_000_000 if n_override is None else n_override
+        cam = pinhole(1920, 1080, (0.0, 0.0, -8.0))
+        sc = scene_overlap(n, seed, cam)
+        tgt = random_target(np.random.default_rng(seed + 7), 1920, 1080)
+        return dict(scene=sc, camera=cam, target=tgt, loss="l1")
+    if k == 4:
+        sizes = [200_000, 500_000, 1_000_000, 1_000_000, 2_000_000, 2_000_000, 3_000_000, 4_000_000]
+        if n_override is not None:
+            sizes = [max(1, int(s * n_override / 4_000_000)) for s in sizes]
+        scenes = [scene_clusters(s, seed + 10 * i) for i, s in enumerate(sizes)]
+        return dict(scenes=scenes, resolutions=[(256, 256), (512, 512), (1280, 720), (1920, 1080)])
+    raise ValueError(f"unknown workload {k}")
+
+
+def serving_requests(n_req: int, n_scenes: int, resolutions, seed: int = 2000):
+    """Request list: (scene index, camera) with a uniformly drawn resolution and orbit camera."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_req):
+        s = int(rng.integers(0, n_scenes))
+        w, h = resolutions[int(rng.integers(0, len(resolutions)))]
+        out.append((s, orbit_camera(np.random.default_rng(seed + 1 + i), w, h)))
+    return out

@@ -1,0 +1,519 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+invariants, Monte-Carlo, quadrature, finite differences or brute force.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gef1d
+from oracle import loss as OL
+from oracle import oracle as O
+from oracle import preprocess_f64 as PF
+from paper_2402_10128_amd import synth
+
+
+def ulp_error(approx32, exact64):
+    a = approx32.astype(np.float64)
+    ulp = np.spacing(np.abs(exact64).astype(np.float32)).astype(np.float64)
+    return np.abs(a - exact64) / ulp
+
+
+# ---------------------------------------------------------------- canonical exp / log
+def test_canonical_exp_within_2ulp(oracle_mod):
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.uniform(-87.0, 88.5, 200_000), rng.uniform(-1, 1, 100_000),
+                        np.linspace(-20, 20, 100_001)]).astype(np.float32)
+    y = O.exp_c(x)
+    err = ulp_error(y, np.exp(x.astype(np.float64)))
+    assert err.max() <= 2.0, err.max()
+    assert O.exp_c(np.array([0.0], np.float32))[0] == 1.0
+    assert O.exp_c(np.array([100.0], np.float32))[0] == np.inf
+    assert O.exp_c(np.array([-100.0], np.float32))[0] == 0.0
+
+
+def test_canonical_log_within_2ulp(oracle_mod):
+    rng = np.random.default_rng(1)
+    x = np.concatenate([np.exp(rng.uniform(-80, 80, 200_000)), rng.uniform(0.5, 2.0, 200_000),
+                        np.array([1.0, 2.0, 0.5, 1e-40, 3e38])]).astype(np.float32)
+    x = x[x > 0]
+    y = O.log_c(x)
+    ex = np.log(x.astype(np.float64))
+    nz = np.abs(ex) > 1e-30
+    err = ulp_error(y[nz], ex[nz])
+    assert err.max() <= 2.0, err.max()
+    assert O.log_c(np.array([1.0], np.float32))[0] == 0.0
+    assert O.log_c(np.array([0.0], np.float32))[0] == -np.inf
+
+
+# ---------------------------------------------------------------- phi_rho and shape reductions
+def test_phi_bar_closed_form_values():
+    # Eq. approx at rho = 0.1: phi(2) = 1, and the tabulated values of the sigmoid form
+    assert gef1d.phi_bar(2.0) == 1.0
+    np.testing.assert_allclose(gef1d.phi_bar([0.5, 1.0, 4.0, 8.0]), [0.925140, 0.950042, 1.099668, 1.291313], atol=1e-6)
+    assert np.all(gef1d.phi_bar(np.linspace(0.1, 10, 50), rho=0.0) == 1.0)
+    # exact ratio of Eq. probablity at beta = 2 is 1/2 (it is not 1 as the approximation is)
+    assert abs(gef1d.phi_exact(2.0) - 0.5) < 1e-12
+
+
+def _one_splat_scene(z0, s, beta, logit=0.0, color=(0.8, 0.3, 0.1)):
+    arr = dict(means=np.array([[0.0, 0.0, z0]], np.float32),
+               log_scales=np.full((1, 3), math.log(s), np.float32),
+               quats=np.array([[1.0, 0.0, 0.0, 0.0]], np.float32),
+               opacity_logits=np.array([logit], np.float32),
+               sh=((np.array(color, np.float32) - 0.5) / synth.Y00).reshape(1, 1, 3).astype(np.float32),
+               beta=np.array([beta], np.float32))
+    return arr
+
+
+def _axis_camera(W=33, H=33, f=40.0):
+    R = np.eye(3, dtype=np.float32)
+    return synth.Camera(W, H, R, np.zeros(3, np.float32), f, f, (W - 1) / 2.0, (H - 1) / 2.0, 0.2)
+
+
+@pytest.mark.parametrize("beta", [0.5, 1.0, 2.0, 4.0, 8.0])
+def test_single_splat_closed_form(oracle_mod, beta):
+    """Isotropic splat on the optical axis: Sigma' = (f phi s / z0)^2 I + 0.3 I, and the image is
+    bg + alpha(P) (c - bg) with alpha = o exp(-r^2 / (2 sigma'^2)) wherever alpha >= 1/255."""
+    z0, s, f, logit = 3.0, 0.04, 40.0, 0.7
+    cam = _axis_camera(f=f)
+    arr = _one_splat_scene(z0, s, beta, logit)
+    bg = (0.2, 0.1, 0.05)
+    orc = O.Oracle(arr, 0, cam, bg=bg)
+    rec = orc.preprocess(O.MODE_F64)
+    # the inputs are binary32: use the values the oracle actually receives
+    s = math.exp(float(np.float32(math.log(s))))
+    logit = float(np.float32(logit))
+    phi = gef1d.phi_bar(float(np.float32(beta)), rho=float(np.float32(0.1)))
+    var = (f * phi * s / z0) ** 2 + 0.3
+    np.testing.assert_allclose(rec.conic[0], [1 / var, 0.0, 1 / var], rtol=1e-12, atol=1e-15)
+    o = 1 / (1 + math.exp(-logit))
+    assert abs(rec.qmax[0] - 2 * math.log(255 * o)) < 1e-12
+    img = orc.render_untiled(rec, O.MODE_F64)["img"]
+    ys, xs = np.mgrid[0:33, 0:33]
+    r2 = (xs - 16.0) ** 2 + (ys - 16.0) ** 2
+    alpha = np.minimum(0.99, o * np.exp(-0.5 * r2 / var))
+    alpha[r2 / var > 2 * math.log(255 * o)] = 0.0
+    c = 0.5 * math.sqrt(1.0 / math.pi) * arr["sh"][0, 0].astype(np.float64) + 0.5
+    expect = np.array(bg)[None, None, :] + alpha[:, :, None] * (c - np.array(bg))[None, None, :]
+    np.testing.assert_allclose(img, expect, atol=1e-12)
+
+
+def test_gef_single_splat_closed_form(oracle_mod):
+    """GEF falloff (Eq. ges): alpha = o exp(-(r^2/sigma'^2)^(beta/2) / 2) with no phi scaling."""
+    z0, s, f, beta = 3.0, 0.04, 40.0, 5.0
+    cam = _axis_camera(f=f)
+    arr = _one_splat_scene(z0, s, beta, 1.0)
+    orc = O.Oracle(arr, 0, cam, falloff=O.FALLOFF_GEF)
+    rec = orc.preprocess(O.MODE_F64)
+    s = math.exp(float(np.float32(math.log(s))))
+    var = (f * s / z0) ** 2 + 0.3
+    o = 1 / (1 + math.exp(-1.0))
+    qm = (2 * math.log(255 * o)) ** (2 / beta)
+    assert abs(rec.qmax[0] - qm) < 1e-12 * qm
+    img = orc.render_untiled(rec, O.MODE_F64)["img"]
+    ys, xs = np.mgrid[0:33, 0:33]
+    q = ((xs - 16.0) ** 2 + (ys - 16.0) ** 2) / var
+    alpha = np.minimum(0.99, o * np.exp(-0.5 * q ** (beta / 2)))
+    alpha[q > qm] = 0.0
+    c0 = 0.5 * math.sqrt(1.0 / math.pi) * float(arr["sh"][0, 0, 0]) + 0.5
+    np.testing.assert_allclose(img[:, :, 0], alpha * c0, atol=1e-12)
+    # 1-D slice through the centre is the GEF of Eq. gef with A = o, alpha = sqrt(var) 2^(1/beta)
+    xs1 = np.arange(33) - 16.0
+    expect = gef1d.gef(xs1, 0.0, math.sqrt(var) * 2 ** (1 / beta), beta, o)
+    expect[(xs1 ** 2 / var) > qm] = 0.0
+    np.testing.assert_allclose(img[16, :, 0], np.minimum(expect, 0.99) * c0, atol=1e-12)
+
+
+def test_beta2_phi_equals_gef_and_rho0_ignores_beta(oracle_mod):
+    cfg = synth.make_config(0, n_override=300)
+    sc, cam = cfg["scene"], cfg["camera"]
+    a2 = dict(sc.arrays())
+    a2["beta"] = np.full_like(a2["beta"], 2.0)
+    # PHI at beta = 2 (phi = 1 exactly in binary32) == PHI with rho = 0, bit for bit
+    r1 = O.Oracle(a2, 0, cam, rho=0.1).preprocess()
+    r0 = O.Oracle(a2, 0, cam, rho=0.0).preprocess()
+    for f in ("u", "v", "conic", "qmax", "rgb", "radius", "rect", "tiles_touched"):
+        assert np.array_equal(getattr(r1, f), getattr(r0, f)), f
+    # PHI(beta=2) and GEF(beta=2) render the same image (binary64)
+    oP = O.Oracle(a2, 0, cam, falloff=O.FALLOFF_PHI)
+    oG = O.Oracle(a2, 0, cam, falloff=O.FALLOFF_GEF)
+    iP = oP.render_untiled(oP.preprocess(O.MODE_F64), O.MODE_F64)["img"]
+    iG = oG.render_untiled(oG.preprocess(O.MODE_F64), O.MODE_F64)["img"]
+    assert np.abs(iP - iG).max() < 1e-9
+    # rho = 0: the image does not depend on beta
+    a3 = dict(sc.arrays())
+    a3["beta"] = np.random.default_rng(5).uniform(0.3, 9.0, size=a3["beta"].shape).astype(np.float32)
+    o0 = O.Oracle(a2, 0, cam, rho=0.0)
+    o3 = O.Oracle(a3, 0, cam, rho=0.0)
+    assert np.array_equal(o0.render_untiled(o0.preprocess())["img"], o3.render_untiled(o3.preprocess())["img"])
+
+
+# ---------------------------------------------------------------- compositing invariants
+def test_partition_of_unity_and_transmittance(oracle_mod):
+    cfg = synth.make_config(0, n_override=400)
+    sc, cam = cfg["scene"], cfg["camera"]
+    arr = dict(sc.arrays())
+    arr["sh"] = np.zeros_like(arr["sh"])   # every colour exactly 0.5
+    orc = O.Oracle(arr, 0, cam, bg=(0.5, 0.5, 0.5))
+    rec = orc.preprocess(O.MODE_F64)
+    assert np.all(rec.rgb[rec.tiles_touched > 0] == 0.5)
+    out = orc.render_untiled(rec, O.MODE_F64)
+    np.testing.assert_allclose(out["img"], 0.5, atol=1e-12)
+    # final T = prod (1 - alpha_i): with black background, 0.5 - C == 0.5 T when every colour is 0.5
+    orc2 = O.Oracle(arr, 0, cam, bg=(0.0, 0.0, 0.0))
+    out2 = orc2.render_untiled(rec, O.MODE_F64)
+    np.testing.assert_allclose(1.0 - 2.0 * out2["img"][:, :, 0], out2["final_T"], atol=1e-12)
+
+
+def test_two_splat_blend_order(oracle_mod):
+    cam = _axis_camera()
+    arr = dict(means=np.array([[0, 0, 3.0], [0, 0, 4.0]], np.float32),
+               log_scales=np.full((2, 3), math.log(0.05), np.float32),
+               quats=np.tile(np.array([1, 0, 0, 0], np.float32), (2, 1)),
+               opacity_logits=np.array([0.3, 1.2], np.float32),
+               sh=((np.array([[1.0, 0, 0], [0, 0, 1.0]], np.float32) - 0.5) / synth.Y00).reshape(2, 1, 3),
+               beta=np.array([2.0, 2.0], np.float32))
+    orc = O.Oracle(arr, 0, cam)
+    rec = orc.preprocess(O.MODE_F64)
+    img = orc.render_untiled(rec, O.MODE_F64)["img"]
+    a1 = 1 / (1 + math.exp(-float(np.float32(0.3))))
+    a2 = 1 / (1 + math.exp(-float(np.float32(1.2))))
+    col = 0.5 * math.sqrt(1.0 / math.pi) * arr["sh"][:, 0, :].astype(np.float64) + 0.5
+    # centre pixel: splat 0 in front, splat 1 behind
+    np.testing.assert_allclose(img[16, 16], a1 * col[0] + (1 - a1) * a2 * col[1], atol=1e-12)
+    arr2 = dict(arr)
+    arr2["means"] = np.array([[0, 0, 4.0], [0, 0, 3.0]], np.float32)
+    orc2 = O.Oracle(arr2, 0, cam)
+    img2 = orc2.render_untiled(orc2.preprocess(O.MODE_F64), O.MODE_F64)["img"]
+    # the nearer splat changed; compare against the formula with the order swapped (scales differ with depth)
+    r2 = orc2.preprocess(O.MODE_F64)
+    assert r2.depth[1] < r2.depth[0]
+    np.testing.assert_allclose(img2[16, 16], a2 * col[1] + (1 - a2) * a1 * col[0], atol=1e-12)
+
+
+def test_early_termination_threshold(oracle_mod):
+    """Many opaque splats on the axis: compositing stops before T(1-alpha) drops below 1e-4."""
+    n = 40
+    cam = _axis_camera()
+    arr = dict(means=np.stack([np.zeros(n), np.zeros(n), 2.0 + 0.1 * np.arange(n)], 1).astype(np.float32),
+               log_scales=np.full((n, 3), math.log(0.2), np.float32),
+               quats=np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)),
+               opacity_logits=np.full(n, 1.0, np.float32),
+               sh=np.zeros((n, 1, 3), np.float32), beta=np.full(n, 2.0, np.float32))
+    orc = O.Oracle(arr, 0, cam)
+    rec = orc.preprocess(O.MODE_F64)
+    out = orc.render_untiled(rec, O.MODE_F64)
+    o = 1 / (1 + math.exp(-1.0))
+    # at the centre alpha = o for every splat: T_k = (1-o)^k; stop at the first k with (1-o)^(k+1) < 1e-4
+    k = next(k for k in range(n) if (1 - o) ** (k + 1) < 1e-4)
+    assert out["n_contrib"][16, 16] == k
+    assert abs(out["final_T"][16, 16] - (1 - o) ** k) < 1e-12
+
+
+# ---------------------------------------------------------------- EWA projection
+def test_ewa_against_monte_carlo(oracle_mod):
+    """Sigma' of the oracle vs the covariance of exactly projected samples of a small 3-D Gaussian."""
+    rng = np.random.default_rng(3)
+    cam = synth.pinhole(400, 300, (0.3, -0.2, -6.0), target=(0.2, 0.1, 0.0))
+    for trial in range(4):
+        mu = rng.uniform(-0.5, 0.5, 3).astype(np.float32)
+        ls = rng.normal(-3.2, 0.3, 3).astype(np.float32)
+        q = rng.normal(size=4).astype(np.float32)
+        arr = dict(means=mu[None], log_scales=ls[None], quats=q[None], opacity_logits=np.array([2.0], np.float32),
+                   sh=np.zeros((1, 1, 3), np.float32), beta=np.array([2.0], np.float32))
+        orc = O.Oracle(arr, 0, cam, rho=0.0)
+        rec = orc.preprocess(O.MODE_F64)
+        a, b, c = rec.conic[0]
+        det = a * c - b * b
+        cov = np.array([[c, -b], [-b, a]]) / det - 0.3 * np.eye(2)
+        # Monte-Carlo: sample, transform, project exactly
+        qn = q.astype(np.float64) / np.linalg.norm(q)
+        w, x, y, z = qn
+        Rq = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                       [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                       [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+        S = np.diag(np.exp(ls.astype(np.float64)))
+        L = Rq @ S
+        pts = mu.astype(np.float64) + rng.standard_normal((400_000, 3)) @ L.T
+        pc = pts @ cam.R.astype(np.float64).T + cam.t.astype(np.float64)
+        uv = np.stack([cam.fx * pc[:, 0] / pc[:, 2], cam.fy * pc[:, 1] / pc[:, 2]], 1)
+        mc = np.cov(uv.T)
+        sig = math.exp(ls.max()) / 6.0
+        tol = 0.02 + 3 * sig   # sampling error + O(sigma/z) linearisation error
+        assert np.abs(mc - cov).max() / np.abs(cov).max() < tol, (mc, cov)
+
+
+# ---------------------------------------------------------------- spherical harmonics
+def test_sh_orthonormal_by_quadrature(oracle_mod):
+    """Basis values read back through the preprocess (rgb = 5.5 + Y_k) are orthonormal on the sphere.
+
+    Gauss-Legendre in cos(theta) x uniform phi integrates products of degree <= 6 exactly."""
+    nt, nphi = 8, 16
+    ct, wt = np.polynomial.legendre.leggauss(nt)
+    phis = (np.arange(nphi) + 0.5) * 2 * math.pi / nphi
+    K = 16
+    Ys, ws = [], []
+    for i, c in enumerate(ct):
+        st = math.sqrt(1 - c * c)
+        for ph in phis:
+            d = np.array([st * math.cos(ph), st * math.sin(ph), c])
+            # camera at the origin looking along d; one splat per basis function at 2 d
+            cam = synth.pinhole(64, 64, (0.0, 0.0, 0.0), target=tuple(d), fov_x_deg=60.0)
+            if abs(d[1]) > 0.999:
+                continue
+            sh = np.zeros((K, K, 3), np.float32)
+            sh[:, 0, 0] = 5.0 / synth.Y00
+            for k in range(1, K):
+                sh[k, k, 0] = 1.0
+            arr = dict(means=np.tile((2 * d).astype(np.float32), (K, 1)),
+                       log_scales=np.full((K, 3), -3.0, np.float32),
+                       quats=np.tile(np.array([1, 0, 0, 0], np.float32), (K, 1)),
+                       opacity_logits=np.full(K, 2.0, np.float32), sh=sh, beta=np.full(K, 2.0, np.float32))
+            rec = O.Oracle(arr, 3, cam).preprocess(O.MODE_F32)
+            assert np.all(rec.tiles_touched > 0)
+            dirn = (2 * d).astype(np.float32).astype(np.float64)
+            y = rec.rgb[:, 0] - 5.5
+            y[0] = synth.Y00
+            Ys.append(y)
+            ws.append(wt[i] * 2 * math.pi / nphi)
+    Y = np.array(Ys)
+    w = np.array(ws)
+    G = (Y * w[:, None]).T @ Y
+    # rows skipped near the poles remove a tiny weight; tolerance reflects binary32 basis values
+    np.testing.assert_allclose(G, np.eye(K), atol=2e-5)
+
+
+# ---------------------------------------------------------------- keys, sort, ranges
+@pytest.mark.parametrize("tile_cull", [O.TILES_SQUARE, O.TILES_ELLIPSE])
+def test_keys_sort_ranges_brute_force(oracle_mod, tile_cull):
+    cfg = synth.make_config(0)
+    sc, cam = cfg["scene"], cfg["camera"]
+    orc = O.Oracle(sc.arrays(), 0, cam, tile_cull=tile_cull)
+    rec = orc.preprocess()
+    keys, vals, ranges = orc.build_keys(rec)
+    assert len(keys) == rec.tiles_touched.sum()
+    # brute force: every tile's list by scanning all splats, sorted by (depth, index)
+    for t in range(orc.TX * orc.TY):
+        tx, ty = t % orc.TX, t // orc.TX
+        members = [i for i in range(rec.n) if rec.tiles_touched[i] > 0
+                   and rec.rect[i, 0] <= tx <= rec.rect[i, 2] and rec.rect[i, 1] <= ty <= rec.rect[i, 3]
+                   and O.lib().oc_splat_in_tile(0, O.C.byref(rec.c()), O.C.c_int64(i), O.C.byref(orc.cs),
+                                                O.C.byref(orc.ps), tx, ty)]
+        members.sort(key=lambda i: (np.float32(rec.depth[i]), i))
+        s0, s1 = ranges[t]
+        assert list(vals[s0:s1]) == members
+        if not members:
+            assert (s0, s1) == (0, 0)
+    # keys strictly ordered lexicographically with the index tie-break
+    trip = list(zip(keys >> np.uint64(32), keys & np.uint64(0xffffffff), vals))
+    assert all(trip[i] < trip[i + 1] for i in range(len(trip) - 1))
+
+
+def test_ellipse_tiles_are_lossless(oracle_mod):
+    """Every pixel whose q passes the alpha floor lies in a tile kept by the ellipse test, and the
+    tiled image equals the untiled one bit for bit (both tile rules)."""
+    cfg = synth.make_config(3, n_override=300)
+    sc = cfg["scene"]
+    cam = synth.pinhole(128, 96, (0.0, 0.0, -8.0))
+    orc = O.Oracle(sc.arrays(), 3, cam, tile_cull=O.TILES_ELLIPSE)
+    rec = orc.preprocess()
+    vis = np.nonzero(rec.tiles_touched)[0]
+    assert len(vis) > 20
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    for i in vis[:60]:
+        u, v = np.float32(rec.u[i]), np.float32(rec.v[i])
+        a, b, c = (np.float32(x) for x in rec.conic[i])
+        dx = (u - xs.astype(np.float32)).astype(np.float32)
+        dy = (v - ys.astype(np.float32)).astype(np.float32)
+        q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+        hit = q <= np.float32(rec.qmax[i]) * (1 - 1e-5)
+        for yy, xx in zip(*np.nonzero(hit)):
+            assert O.lib().oc_splat_in_tile(0, O.C.byref(rec.c()), O.C.c_int64(int(i)), O.C.byref(orc.cs),
+                                            O.C.byref(orc.ps), int(xx) // 16, int(yy) // 16)
+    _, vals, ranges = orc.build_keys(rec)
+    tiled = orc.render(rec, vals, ranges)["img"]
+    assert np.array_equal(tiled, orc.render_untiled(rec)["img"])
+    orcS = O.Oracle(sc.arrays(), 3, cam, tile_cull=O.TILES_SQUARE)
+    recS = orcS.preprocess()
+    assert recS.tiles_touched.sum() >= rec.tiles_touched.sum()
+    _, vS, rS = orcS.build_keys(recS)
+    assert np.array_equal(orcS.render(recS, vS, rS)["img"], tiled)
+
+
+def test_tiled_equals_untiled_workload0(oracle_mod):
+    cfg = synth.make_config(0)
+    sc, cam = cfg["scene"], cfg["camera"]
+    for falloff in (O.FALLOFF_PHI, O.FALLOFF_GEF):
+        orc = O.Oracle(sc.arrays(), 0, cam, falloff=falloff)
+        rec = orc.preprocess()
+        _, vals, ranges = orc.build_keys(rec)
+        a = orc.render(rec, vals, ranges)
+        b = orc.render_untiled(rec)
+        assert np.array_equal(a["img"], b["img"])
+        # n_contrib is a position in the pixel's list, so it differs between the two; T does not
+        assert np.array_equal(a["final_T"], b["final_T"])
+        assert a["stats"]["pairs_blended"] == b["stats"]["pairs_blended"]
+
+
+def test_f32_record_close_to_f64(oracle_mod):
+    cfg = synth.make_config(1, n_override=20_000)
+    sc, cam = cfg["scene"], cfg["camera"]
+    orc = O.Oracle(sc.arrays(), 3, cam)
+    r32, r64 = orc.preprocess(O.MODE_F32), orc.preprocess(O.MODE_F64)
+    both = (r32.tiles_touched > 0) & (r64.tiles_touched > 0)
+    assert both.sum() > 0.9 * max((r64.tiles_touched > 0).sum(), 1)
+    np.testing.assert_allclose(r32.u[both], r64.u[both], rtol=1e-5, atol=1e-3)
+    np.testing.assert_allclose(r32.rgb[both], r64.rgb[both], atol=1e-5)
+    np.testing.assert_allclose(r32.opacity[both], r64.opacity[both], rtol=1e-6)
+    # the torch binary64 restatement agrees with the C++ binary64 mode
+    P = PF.to_params(sc.arrays())
+    out = PF.preprocess(P, 3, cam, 0, 0.1, r64.clamp_bits)
+    vis = r64.tiles_touched > 0
+    np.testing.assert_allclose(out["u"].numpy()[vis], r64.u[vis], rtol=1e-12)
+    np.testing.assert_allclose(out["a"].numpy()[vis], r64.conic[vis, 0], rtol=1e-9)
+    np.testing.assert_allclose(out["rgb"].numpy()[vis], r64.rgb[vis], atol=1e-12)
+
+
+# ---------------------------------------------------------------- gradients
+def _fd_setup(falloff, n=1000):
+    cfg = synth.make_config(0, n_override=n)
+    sc, cam = cfg["scene"], cfg["camera"]
+    arrays = {k: v.astype(np.float64) for k, v in sc.arrays().items()}
+    return sc, cam, arrays
+
+
+def _render_f64(arrays, sc, cam, falloff, base_rec, g):
+    P = PF.to_params(arrays)
+    out = PF.preprocess(P, 0, cam, falloff, 0.1, base_rec.clamp_bits)
+    rec = PF.record_from(out, base_rec)
+    orc = O.Oracle(sc.arrays(), 0, cam, falloff=falloff)
+    res = orc.render_untiled(rec, O.MODE_F64)
+    return float((res["img"] * g).sum()), res["stats"]["decision_hash"]
+
+
+@pytest.mark.parametrize("falloff", [O.FALLOFF_PHI, O.FALLOFF_GEF])
+def test_oracle_gradient_matches_central_fd(oracle_mod, falloff):
+    """Analytic binary64 gradient (reverse pass + autograd chain) vs central finite differences."""
+    sc, cam, arrays = _fd_setup(falloff, n=300)
+    orc = O.Oracle(sc.arrays(), 0, cam, falloff=falloff)
+    base = orc.preprocess(O.MODE_F64)
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal((cam.height, cam.width, 3))
+    P = PF.to_params(arrays)
+    out = PF.preprocess(P, 0, cam, falloff, 0.1, base.clamp_bits)
+    rec = PF.record_from(out, base)
+    g2d, _ = orc.backward2d(rec, g, mode=O.MODE_F64)
+    grads = PF.chain_to_params(arrays, 0, cam, g2d, base.tiles_touched > 0, base.clamp_bits, falloff, 0.1)
+    _, h0 = _render_f64(arrays, sc, cam, falloff, base, g)
+    vis = np.nonzero(base.tiles_touched > 0)[0]
+    names = ["means", "log_scales", "quats", "opacity_logits", "sh", "beta"]
+    checked = excluded = 0
+    errs = []
+    for trial in range(60):
+        name = names[trial % len(names)]
+        i = int(rng.choice(vis))
+        shape = arrays[name].shape[1:]
+        idx = (i,) + tuple(int(rng.integers(0, s)) for s in shape)
+        x0 = arrays[name][idx]
+        h = 1e-6 * max(1.0, abs(x0))
+        vals = []
+        ok = True
+        for sgn in (1, -1):
+            a2 = {k: v.copy() for k, v in arrays.items()}
+            a2[name][idx] = x0 + sgn * h
+            L, hh = _render_f64(a2, sc, cam, falloff, base, g)
+            ok &= hh == h0
+            vals.append(L)
+        if not ok:
+            excluded += 1
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = grads[name][idx]
+        errs.append((fd, an))
+        checked += 1
+    fd = np.array([e[0] for e in errs])
+    an = np.array([e[1] for e in errs])
+    floor = 1e-2 * np.sqrt(np.mean(an ** 2))
+    rel = np.abs(fd - an) / np.maximum(np.abs(an), floor)
+    assert checked >= 40, (checked, excluded)
+    assert rel.max() < 1e-5, (rel.max(), errs[int(rel.argmax())])
+
+
+# ---------------------------------------------------------------- 1-D GEF (Sec. 3, App. A)
+def test_gef_reduces_to_gaussian_and_laplace():
+    x = np.linspace(-4, 4, 1001)
+    for alpha in (0.5, 1.0, 2.0):
+        # beta = 2: a Gaussian of standard deviation alpha / sqrt(2)
+        sd = alpha / math.sqrt(2)
+        np.testing.assert_allclose(gef1d.gef(x, 0.3, alpha, 2.0, 1.7), 1.7 * np.exp(-0.5 * ((x - 0.3) / sd) ** 2),
+                                   rtol=1e-13)
+        # beta = 1: a Laplace shape
+        np.testing.assert_allclose(gef1d.gef(x, 0.0, alpha, 1.0), np.exp(-np.abs(x) / alpha), rtol=1e-13)
+
+
+def test_gef_mixture_equals_gmm_at_beta2():
+    rng = np.random.default_rng(2)
+    x = np.linspace(-5, 5, 1000)
+    w, mu, sg = rng.normal(size=7), rng.uniform(-3, 3, 7), rng.uniform(0.1, 2, 7)
+    np.testing.assert_allclose(gef1d.gef_mixture(x, w, mu, sg, np.full(7, 2.0)), gef1d.gmm(x, w, mu, sg), rtol=1e-13, atol=1e-15)
+
+
+def test_theorem1_existence_by_quadrature():
+    """For every scale alpha some beta gives a strictly smaller L1 error on the square wave."""
+    for alpha in (0.25, 0.5, 1.0, 2.0, 4.0):
+        eg, _ = gef1d.theorem1_errors(alpha, 2.0)
+        best = min(gef1d.theorem1_errors(alpha, b)[1] for b in (0.5, 1.0, 1.5, 3.0, 4.0, 8.0, 16.0))
+        assert best < eg, (alpha, eg, best)
+    # closed-form sanity: with beta = 2 the GEF and G(t) = A exp(-t^2/alpha^2) coincide
+    eg, ef = gef1d.theorem1_errors(1.0, 2.0)
+    assert abs(eg - ef) < 1e-12
+    # E_G for alpha -> large tends to the tail-free middle error 2 int_0^{L/2} (1 - e^{-t^2/a^2}) ~ L^3/(12 a^2)
+    eg, _ = gef1d.theorem1_errors(50.0, 2.0, L=2.0)
+    assert eg > 0.0
+
+
+def test_square_signal_and_eta_bounds():
+    x = np.array([-1.5, -0.99, 0.0, 0.99, 1.0, 1.5])
+    assert list(gef1d.signal("square", x, 2.0)) == [0, 1, 1, 1, 0, 0]
+    assert abs(gef1d.ETA_SQUARE_LARGER - 0.27324) < 1e-5
+    assert abs(gef1d.ETA_CIRCLE_LARGER - 0.36338) < 1e-5
+
+
+# ---------------------------------------------------------------- frequency mask and loss
+def test_freq_mask_constant_and_edge():
+    flat = np.full((40, 60, 3), 0.37)
+    assert OL.freq_mask(flat, 0.75).sum() == 0
+    img = np.zeros((200, 200, 3))
+    img[:, 100:] = 1.0
+    resp = OL.dog_response(img, 0.75)
+    col = resp.mean(axis=0)
+    # The DoG of a step is odd about the edge (x = 19.5 after the 5x down-sampling): zero there, with
+    # its extremes where the two Gaussian kernels cross, d* = sqrt(2 ln(s1/s2) / (1/s2^2 - 1/s1^2)).
+    s2 = 0.1 + 10 * 0.75
+    s1 = 2 * s2
+    d = math.sqrt(2 * math.log(s1 / s2) / (1 / s2 ** 2 - 1 / s1 ** 2))
+    left, right = int(np.argmax(col[:20])), 20 + int(np.argmax(col[20:]))
+    assert abs(left - (19.5 - d)) <= 1.0 and abs(right - (19.5 + d)) <= 1.0, (left, right, d)
+    assert col[19] < 0.15 * col.max() and col[20] < 0.15 * col.max()
+    m75 = OL.freq_mask(img, 0.75)
+    m25 = OL.freq_mask(img, 0.25)
+    assert np.array_equal(m25, 1 - m75)
+
+
+def test_loss_gradient_matches_fd():
+    rng = np.random.default_rng(4)
+    I = rng.uniform(size=(8, 9, 3))
+    T = rng.uniform(size=(8, 9, 3))
+    M = (rng.uniform(size=(8, 9)) > 0.5).astype(np.uint8)
+    L, g = OL.loss_and_grad(I, T, M, 0.5, 0.5)
+    h = 1e-7
+    for _ in range(20):
+        idx = tuple(int(rng.integers(0, s)) for s in I.shape)
+        Ip, Im = I.copy(), I.copy()
+        Ip[idx] += h
+        Im[idx] -= h
+        fd = (OL.loss_and_grad(Ip, T, M, 0.5, 0.5)[0] - OL.loss_and_grad(Im, T, M, 0.5, 0.5)[0]) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-6
