@@ -1,0 +1,230 @@
+/*
+ * ges.h -- C ABI of the MI355X (gfx950) GES tile rasterizer.
+ *
+ * GES: Generalized Exponential Splatting (arXiv 2402.10128).  The library renders
+ * and differentiates splats whose falloff is a generalized exponential with a
+ * per-splat shape beta.  The arguments follow the paper's statement of the problem
+ * (Sec. 4.1): per-splat position, scale vector and quaternion (the covariance
+ * Sigma = R S S^T R^T, S modified by the shape function phi(beta), Sec. 4.2),
+ * opacity, spherical-harmonic colour and beta, seen by a calibrated pinhole camera.
+ *
+ * Conventions shared by every entry point
+ *   - All tensor arguments are DEVICE pointers to contiguous row-major FP32 (or the
+ *     stated integer type) buffers owned by the caller.  The library never frees
+ *     them and never allocates on the render path; the workspace buffers it needs
+ *     are caller-allocated with the sizes returned by the *_query calls.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and is
+ *     asynchronous unless a call says otherwise.  Calls on one frame's buffers must
+ *     be issued on one stream in the order preprocess -> forward -> backward.
+ *   - Every call returns a ges_status.  On failure nothing has been enqueued unless
+ *     the status is GES_ERR_DEVICE; ges_last_error() then describes the problem
+ *     (thread-local string, valid until the next call on the same thread).
+ *   - Splats with non-finite inputs, a zero quaternion, opacity <= 1/255, a mean
+ *     at or behind the near plane, a degenerate projected covariance, no tile on
+ *     screen, or (GEF falloff) beta <= 0 are culled, not reported as errors.
+ *   - Limits: 0 <= n < 2^31, sh_degree in [0,3], 1 <= width,height <= 16384, at
+ *     most 2^32 - 1 (tile, splat) keys per frame.
+ */
+#ifndef GES_H
+#define GES_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GES_ABI_VERSION 1u
+#define GES_TILE 16
+
+typedef enum {
+  GES_OK = 0,
+  GES_ERR_INVALID_ARGUMENT = 1,  /* null/inconsistent pointers, bad sizes, non-finite camera, R not a rotation */
+  GES_ERR_CAPACITY = 2,          /* a workspace is smaller than the matching *_query result */
+  GES_ERR_OUT_OF_MEMORY = 3,     /* serving pool exhausted for a request that can never fit */
+  GES_ERR_DEVICE = 4,            /* a HIP call failed; ges_last_error() holds hipGetErrorString */
+  GES_ERR_BUSY = 5,              /* serving queue full */
+  GES_ERR_NOT_FOUND = 6,         /* unknown scene or request id */
+  GES_ERR_INTERNAL = 7
+} ges_status;
+
+/* Pixel falloff of a splat.
+ * PHI: the paper's approximate rasterization (Sec. 4.2, Eq. approx): the scales are
+ *      multiplied by phi_rho(beta) = 2 / (1 + exp(-(rho beta - 2 rho))) and the 2-D
+ *      falloff is the Gaussian exp(-q/2).
+ * GEF: the exact GES kernel of Eq. ges projected to the image: exp(-q^(beta/2) / 2)
+ *      on the unmodified covariance.
+ * q is the quadratic form of the (0.3-dilated) projected covariance. */
+typedef enum { GES_FALLOFF_PHI = 0, GES_FALLOFF_GEF = 1 } ges_falloff;
+
+/* Which tiles list a splat: every tile of its bounding square (SQUARE) or only the
+ * tiles whose pixel-centre box meets its alpha-floor ellipse (ELLIPSE).  Both give
+ * identical images; ELLIPSE produces fewer keys. */
+typedef enum { GES_TILES_SQUARE = 0, GES_TILES_ELLIPSE = 1 } ges_tile_cull;
+
+typedef struct {
+  int64_t n;                     /* number of splats */
+  int32_t sh_degree;             /* 0..3; (sh_degree+1)^2 coefficients per colour channel */
+  const float* means;            /* [n,3] world position */
+  const float* log_scales;       /* [n,3] log of the per-axis scale */
+  const float* quats;            /* [n,4] rotation (w,x,y,z), normalised internally */
+  const float* opacity_logits;   /* [n] opacity = sigmoid(logit) */
+  const float* sh;               /* [n,(D+1)^2,3] real SH coefficients, m-ordered, Condon-Shortley phase */
+  const float* beta;             /* [n] shape parameter beta (2 = Gaussian), the true value */
+} ges_splats;
+
+typedef struct {                 /* host struct, passed by pointer, read during the call */
+  int32_t width, height;
+  float R[9];                    /* world->camera rotation, row-major; camera x right, y down, z forward */
+  float t[3];                    /* world->camera translation: p_cam = R p_world + t */
+  float fx, fy, cx, cy;          /* pixel units; pixel (i,j) has its centre at (i,j) */
+  float near_z;                  /* splats with camera z <= near_z are culled (0.2 typical) */
+} ges_camera;
+
+typedef struct {
+  int32_t falloff;               /* ges_falloff */
+  int32_t tile_cull;             /* ges_tile_cull */
+  float rho;                     /* shape strength of phi_rho (the paper uses 0.1) */
+  float bg[3];                   /* background colour composited behind the splats */
+} ges_raster_params;
+
+typedef struct {                 /* device pointers, same shapes as ges_splats; overwritten (not accumulated) */
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh;
+  float* beta;
+} ges_splat_grads;
+
+uint32_t ges_abi_version(void);
+const char* ges_last_error(void);
+
+/* Sizes of the per-frame workspaces for n splats at width x height.
+ * splat_ws holds the per-splat projected records, the tile-binning tables, the
+ * tile ranges and the per-splat 2-D gradient accumulators; pixel_ws holds the
+ * per-pixel final transmittance and contributor count that the backward pass
+ * re-uses (so no per-pixel lists are stored).  Either output pointer may be NULL. */
+ges_status ges_workspace_query(int64_t n, int32_t width, int32_t height, size_t* splat_ws_bytes,
+                               size_t* pixel_ws_bytes);
+
+/* Size of the key workspace for num_keys (tile, splat) pairs of a frame with n splats. */
+ges_status ges_key_workspace_query(uint64_t num_keys, int64_t n, int32_t width, int32_t height,
+                                   size_t* key_ws_bytes);
+
+/* Preprocess (Sec. 4.1-4.2): per splat, view transform, 3-D covariance from scale and
+ * rotation with the shape modification, EWA projection J W Sigma W^T J^T, conic,
+ * mean2D, alpha-floor threshold, beta-dependent screen radius, tile rectangle and
+ * SH colour; then counts the (tile, splat) pairs per tile and fixes every tile's
+ * [start,end) range in the sorted key order.
+ * num_keys_host: if not NULL, the call waits for the stream and stores the number
+ * of keys of this frame there (the only host synchronisation of a frame).
+ * Errors: INVALID_ARGUMENT (see conventions), CAPACITY if splat_ws_bytes is too small. */
+ges_status ges_preprocess(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                          void* splat_ws, size_t splat_ws_bytes, uint64_t* num_keys_host, void* stream);
+
+/* Forward render (Sec. 4.2, Eq. transimttance discretised): scatters the pairs into
+ * their tiles, sorts every tile's list by (depth, splat index) in LDS, and
+ * composites front to back per pixel with alpha = min(0.99, opacity * falloff),
+ * skipping pairs below the 1/255 alpha floor and stopping a pixel before the splat
+ * that would take its transmittance below 1e-4.
+ * out_rgb: [height,width,3] FP32, overwritten.  num_keys must be the value returned
+ * by ges_preprocess for the same splat_ws; key_ws_bytes >= ges_key_workspace_query().
+ * The splat, pixel and key workspaces must stay untouched until the matching
+ * ges_render_backward (if any) has been enqueued. */
+ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                              void* splat_ws, void* key_ws, size_t key_ws_bytes, uint64_t num_keys,
+                              void* pixel_ws, float* out_rgb, void* stream);
+
+/* Backward pass: given dL/d(out_rgb) [height,width,3], walks every pixel's
+ * contributors back to front recovering the transmittance by division, accumulates
+ * the gradient of each splat's 2-D quantities (mean2D, conic, opacity, colour and,
+ * with the GEF falloff, beta), then maps them to the parameters through the
+ * preprocess chain rule.  Every gradient buffer of `grads` is overwritten; NULL
+ * members are skipped.  Must follow the ges_render_forward of the same frame. */
+ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                               void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
+                               const ges_splat_grads* grads, void* stream);
+
+/* ---- inspection (tests) ------------------------------------------------------------
+ * Device views into a frame's workspaces, valid after the call that fills them. */
+typedef struct {
+  const float* records;          /* [n,16] per-splat record, see below (after ges_preprocess) */
+  const uint32_t* tile_ranges;   /* [tiles,2] [start,end) into the sorted lists (after ges_preprocess) */
+  const uint32_t* sorted_ids;    /* [num_keys] splat index per sorted entry (after ges_render_forward) */
+  const uint32_t* bucket_pairs;  /* [num_keys,2] (depth bits, splat index) in tile order, unsorted within a tile */
+  const float* final_T;          /* [height,width] (after ges_render_forward) */
+  const uint32_t* n_contrib;     /* [height,width] list position + 1 of the last composited splat */
+  const float* grad2d;           /* [n,12] dL/d(u,v,a,b,c,opacity,r,g,b,beta) (after ges_render_backward) */
+  int32_t tiles_x, tiles_y;
+} ges_frame_view;
+/* Record layout, 16 x 32-bit words per splat:
+ *   0 u, 1 v, 2 conic a, 3 conic b, 4 conic c, 5 q_max, 6 opacity, 7 beta,
+ *   8 r, 9 g, 10 b, 11 depth, 12 radius | flags << 24 (int32), 13 tx0 | ty0 << 16,
+ *   14 tx1 | ty1 << 16 (inclusive), 15 tiles_touched (uint32; 0 = culled).
+ *   flags: bit0..2 colour channel clamped at 0, bit3/4 x/y guard clamp. */
+ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* splat_ws, void* key_ws,
+                              uint64_t num_keys, void* pixel_ws, ges_frame_view* out);
+
+/* ---- frequency-modulated loss (Sec. 4.3) ------------------------------------------
+ * Mask M_omega = 1(|DoG_omega(grey(target))| / max > 0.5) computed on the target
+ * down-sampled by 5 (scale 0.2), sigma2 = 0.1 + 10 omega, sigma1 = 2 sigma2, up-sampled
+ * by nearest lookup; for omega <= 0.5 the mask is 1 - M_(omega + 0.5).
+ * scratch: device buffer of ges_mask_scratch_bytes(width,height) bytes. mask: [h,w] uint8. */
+size_t ges_mask_scratch_bytes(int32_t width, int32_t height);
+ges_status ges_freq_mask(const float* target, int32_t width, int32_t height, float omega, void* scratch,
+                         uint8_t* mask, void* stream);
+
+/* L = lam_l1 mean|I - T| + lam_w mean(|I - T| M) over height*width*3 values, and
+ * dL/dI = (lam_l1 + lam_w M) sign(I - T) / (3 h w).  mask may be NULL (then lam_w is
+ * ignored).  scratch: device buffer of ges_loss_scratch_bytes() bytes (per-block partial sums, added in
+ * a fixed order so the loss is deterministic).  loss_out: one FP32 device scalar (overwritten).
+ * dL_dimg: [h,w,3]. */
+size_t ges_loss_scratch_bytes(void);
+ges_status ges_loss(const float* img, const float* target, const uint8_t* mask, int32_t width, int32_t height,
+                    float lam_l1, float lam_w, void* scratch, float* loss_out, float* dL_dimg, void* stream);
+
+/* ---- serving: continuous batching of render requests ----------------------------- */
+typedef struct ges_server ges_server;
+
+typedef struct {
+  int32_t max_slots;             /* requests rendered together in one batched launch (1..32) */
+  int32_t queue_capacity;        /* pending requests accepted before submit returns BUSY */
+  int32_t falloff, tile_cull;    /* raster mode for every request */
+  float rho;
+  float bg[3];
+  int32_t sequential;            /* 1: one request per launch (the baseline policy) */
+} ges_serve_config;
+
+typedef enum { GES_REQ_QUEUED = 0, GES_REQ_RUNNING = 1, GES_REQ_DONE = 2, GES_REQ_FAILED = 3,
+               GES_REQ_REJECTED = 4, GES_REQ_CANCELLED = 5 } ges_request_state;
+
+typedef struct {
+  int32_t state;                 /* ges_request_state */
+  int32_t status;                /* ges_status of the request (DONE -> GES_OK) */
+  uint64_t t_submit_ns;          /* steady clock, submit */
+  uint64_t t_start_ns;           /* admitted into a batch */
+  uint64_t t_done_ns;            /* completion observed on the device */
+  uint64_t num_keys;
+  int32_t batch_size;            /* slots in the batch that rendered it */
+} ges_request_info;
+
+/* pool: caller-owned device buffer the server sub-allocates all per-request
+ * workspaces from (the admission budget). */
+ges_status ges_serve_create(const ges_serve_config* cfg, void* pool, size_t pool_bytes, ges_server** out);
+/* The scene's device buffers must stay alive and unchanged until ges_serve_destroy. */
+ges_status ges_serve_add_scene(ges_server* s, const ges_splats* scene, int32_t* scene_id);
+/* Queue a render of scene_id from cam into out_rgb_device [h,w,3] FP32.  Returns BUSY when
+ * the queue is full, NOT_FOUND for an unknown scene, INVALID_ARGUMENT for a bad camera. */
+ges_status ges_serve_submit(ges_server* s, int32_t scene_id, const ges_camera* cam, float* out_rgb_device,
+                            uint64_t* request_id);
+ges_status ges_serve_poll(ges_server* s, uint64_t request_id, ges_request_info* info);
+/* Block until every request submitted so far has finished (done, failed or rejected). */
+ges_status ges_serve_drain(ges_server* s);
+/* Stops the server; requests still queued are cancelled, running ones are completed. */
+ges_status ges_serve_destroy(ges_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -8,6 +8,7 @@
 #include "ges_oracle.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -643,13 +644,26 @@ void render_list(int mode, const oc_camera* cam, const oc_params* p, const Splat
 //        dG/dbeta = -(1/4) q^(beta/2) ln(q) G (0 at q = 0).
 //   q = a dx^2 + 2 b dx dy + c dy^2, dx = u - px:  dq/du = 2(a dx + b dy), dq/dv = 2(b dx + c dy),
 //   dq/da = dx^2, dq/db = 2 dx dy, dq/dc = dy^2.
+// Two decisions of a pixel are taken on floating-point values that a binary32 implementation can
+// legitimately take the other way: the termination test t < 1e-4 and the clamp o G > 0.99.  The
+// pixel is ambiguous when either lies within kFlagRel (termination, relative) or kClampAbs (clamp)
+// of its threshold; for such a pixel the contributions of the other branch of the nearest decision
+// are also computed and |other - primary| is accumulated per splat into `delta` (the amount by which
+// a correct implementation may differ from the primary result).
 struct Contrib { int64_t j; double alpha, T, G, q, dx, dy; bool clamped; };
+constexpr double kClampAbs = 1e-5;
 
-void pixel_backward(int mode, const oc_params* p, const Splat2D* L, const uint32_t* ids, int64_t len, int px,
-                    int py, const double g[3], double* g2d, int64_t* examined) {
-  std::vector<Contrib> cs;
+struct PixelGrad { int64_t j; double v[10]; };
+
+// Forward walk with optional forced flips; returns the composited pairs and the final transmittance.
+double pixel_contribs(int mode, const oc_params* p, const Splat2D* L, int64_t len, int px, int py,
+                      int64_t flip_term_at, int64_t flip_clamp_at, std::vector<Contrib>& cs, int64_t* ex_out,
+                      double* term_margin, int64_t* term_pos, double* clamp_margin, int64_t* clamp_pos) {
+  cs.clear();
   double T = 1.0;
   int64_t ex = 0;
+  double tm = 1e300, cm = 1e300;
+  int64_t tp = -1, cp = -1;
   for (int64_t j = 0; j < len; ++j) {
     const Splat2D& s = L[j];
     double q, dx, dy;
@@ -658,26 +672,37 @@ void pixel_backward(int mode, const oc_params* p, const Splat2D* L, const uint32
     double G = falloff(p->falloff, q, s.beta);
     double oG = s.o * G;
     bool clamped = oG > kAlphaMax;
+    const double cmar = std::fabs(oG - kAlphaMax);
+    if (cmar < cm) { cm = cmar; cp = j; }
+    if (j == flip_clamp_at) clamped = !clamped;
     double alpha = clamped ? kAlphaMax : oG;
     double t = T * (1.0 - alpha);
-    if (t < kTMin) break;
+    const double tmar = std::fabs(t - kTMin) / kTMin;
+    if (tmar < tm) { tm = tmar; tp = j; }
+    bool stop = t < kTMin;
+    if (j == flip_term_at) stop = !stop;
+    if (stop) break;
     cs.push_back(Contrib{j, alpha, T, G, q, dx, dy, clamped});
     T = t;
   }
-  *examined += ex;
-  const double Tfin = T;
+  if (ex_out) *ex_out += ex;
+  if (term_margin) { *term_margin = tm; *term_pos = tp; *clamp_margin = cm; *clamp_pos = cp; }
+  return T;
+}
+
+void pixel_grads(const oc_params* p, const Splat2D* L, const std::vector<Contrib>& cs, double Tfin, const double g[3],
+                 std::vector<PixelGrad>& out) {
+  out.clear();
   const double bgg = p->bg[0] * g[0] + p->bg[1] * g[1] + p->bg[2] * g[2];
   double Sb[3] = {0.0, 0.0, 0.0};
   for (int64_t k = (int64_t)cs.size() - 1; k >= 0; --k) {
-    const Contrib& c = cs[k];
+    const Contrib& c = cs[(size_t)k];
     const Splat2D& s = L[c.j];
     const double col[3] = {s.r, s.g, s.bl};
     double dalpha = 0.0;
     for (int ch = 0; ch < 3; ++ch) dalpha += g[ch] * c.T * (col[ch] - Sb[ch]);
     dalpha -= Tfin * bgg / (1.0 - c.alpha);
     for (int ch = 0; ch < 3; ++ch) Sb[ch] = c.alpha * col[ch] + (1.0 - c.alpha) * Sb[ch];
-    double* gs = g2d + 10 * (int64_t)ids[c.j];
-    double grgb[3] = {c.alpha * c.T * g[0], c.alpha * c.T * g[1], c.alpha * c.T * g[2]};
     double dG = 0.0, dop = 0.0;
     if (!c.clamped) { dG = s.o * dalpha; dop = c.G * dalpha; }
     double q = c.q < 0.0 ? 0.0 : c.q;
@@ -690,13 +715,63 @@ void pixel_backward(int mode, const oc_params* p, const Splat2D* L, const uint32
       dbeta = q > 0.0 ? -0.25 * std::pow(q, 0.5 * s.beta) * std::log(q) * c.G * dG : 0.0;
     }
     const double dx = c.dx, dy = c.dy;
-    double gu = dq * 2.0 * (s.a * dx + s.b * dy);
-    double gv = dq * 2.0 * (s.b * dx + s.c * dy);
-    double ga = dq * dx * dx, gb = dq * 2.0 * dx * dy, gc = dq * dy * dy;
-    const double vals[10] = {gu, gv, ga, gb, gc, dop, grgb[0], grgb[1], grgb[2], dbeta};
-    for (int k2 = 0; k2 < 10; ++k2) {
+    PixelGrad pg;
+    pg.j = c.j;
+    pg.v[0] = dq * 2.0 * (s.a * dx + s.b * dy);
+    pg.v[1] = dq * 2.0 * (s.b * dx + s.c * dy);
+    pg.v[2] = dq * dx * dx;
+    pg.v[3] = dq * 2.0 * dx * dy;
+    pg.v[4] = dq * dy * dy;
+    pg.v[5] = dop;
+    pg.v[6] = c.alpha * c.T * g[0];
+    pg.v[7] = c.alpha * c.T * g[1];
+    pg.v[8] = c.alpha * c.T * g[2];
+    pg.v[9] = dbeta;
+    out.push_back(pg);
+  }
+}
+
+void pixel_backward(int mode, const oc_params* p, const Splat2D* L, const uint32_t* ids, int64_t len, int px,
+                    int py, const double g[3], double* g2d, double* delta, int64_t* examined) {
+  std::vector<Contrib> cs;
+  std::vector<PixelGrad> prim, alt;
+  double tm, cm;
+  int64_t tp, cp;
+  const double Tfin = pixel_contribs(mode, p, L, len, px, py, -1, -1, cs, examined, &tm, &tp, &cm, &cp);
+  pixel_grads(p, L, cs, Tfin, g, prim);
+  for (const PixelGrad& pg : prim) {
+    double* gs = g2d + 10 * (int64_t)ids[pg.j];
+    for (int k = 0; k < 10; ++k) {
 #pragma omp atomic
-      gs[k2] += vals[k2];
+      gs[k] += pg.v[k];
+    }
+  }
+  if (!delta) return;
+  const bool term_amb = tm < kFlagRel, clamp_amb = cm < kClampAbs;
+  if (!term_amb && !clamp_amb) return;
+  // the other branch of the nearer decision
+  const bool use_term = term_amb && (!clamp_amb || tm * kTMin <= cm);
+  const double Tf2 = pixel_contribs(mode, p, L, len, px, py, use_term ? tp : -1, use_term ? -1 : cp, cs, nullptr,
+                                    nullptr, nullptr, nullptr, nullptr);
+  pixel_grads(p, L, cs, Tf2, g, alt);
+  // |alt - prim| per splat: accumulate both lists keyed by list position
+  std::vector<std::pair<int64_t, std::array<double, 10>>> acc;
+  auto add = [&](const std::vector<PixelGrad>& v, double sgn) {
+    for (const PixelGrad& pg : v) {
+      size_t k = 0;
+      while (k < acc.size() && acc[k].first != pg.j) ++k;
+      if (k == acc.size()) { acc.push_back({pg.j, {}}); acc.back().second.fill(0.0); }
+      for (int c = 0; c < 10; ++c) acc[k].second[(size_t)c] += sgn * pg.v[c];
+    }
+  };
+  add(alt, 1.0);
+  add(prim, -1.0);
+  for (const auto& e : acc) {
+    double* ds = delta + 10 * (int64_t)ids[e.first];
+    for (int c = 0; c < 10; ++c) {
+      const double d = std::fabs(e.second[(size_t)c]);
+#pragma omp atomic
+      ds[c] += d;
     }
   }
 }
@@ -885,7 +960,7 @@ int oc_render_untiled(int mode, const oc_record* r, int64_t n, const oc_camera* 
 }
 
 int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera* cam, const oc_params* p,
-                        const double* dL_dimg, double* g2d, oc_stats* stats) {
+                        const double* dL_dimg, double* g2d, double* delta, oc_stats* stats) {
   std::vector<uint32_t> ids;
   for (int64_t i = 0; i < n; ++i)
     if (r->tiles_touched[i] > 0) ids.push_back((uint32_t)i);
@@ -900,7 +975,7 @@ int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera
   for (int py = 0; py < cam->height; ++py)
     for (int px = 0; px < cam->width; ++px) {
       const int64_t pix = (int64_t)py * cam->width + px;
-      pixel_backward(mode, p, L.data(), ids.data(), (int64_t)L.size(), px, py, dL_dimg + 3 * pix, g2d, &tot);
+      pixel_backward(mode, p, L.data(), ids.data(), (int64_t)L.size(), px, py, dL_dimg + 3 * pix, g2d, delta, &tot);
     }
   if (stats) { std::memset(stats, 0, sizeof(*stats)); stats->pairs_examined = tot; }
   return 0;
@@ -908,7 +983,7 @@ int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera
 
 int oc_backward(int mode, const oc_record* r, int64_t n, const oc_camera* cam, const oc_params* p,
                 const uint32_t* values, const int64_t* ranges, const int32_t* tiles, int64_t n_tiles,
-                const double* dL_dimg, double* g2d, oc_stats* stats) {
+                const double* dL_dimg, double* g2d, double* delta, oc_stats* stats) {
   (void)n;
   const int TX = tiles_x(cam), TY = tiles_y(cam);
   const int64_t nt = tiles ? n_tiles : (int64_t)TX * TY;
@@ -928,7 +1003,7 @@ int oc_backward(int mode, const oc_record* r, int64_t n, const oc_camera* cam, c
       for (int py = y0; py <= y1; ++py)
         for (int px = x0; px <= x1; ++px) {
           const int64_t pix = (int64_t)py * cam->width + px;
-          pixel_backward(mode, p, L.data(), values + s0, s1 - s0, px, py, dL_dimg + 3 * pix, g2d, &ex);
+          pixel_backward(mode, p, L.data(), values + s0, s1 - s0, px, py, dL_dimg + 3 * pix, g2d, delta, &ex);
         }
     }
 #pragma omp critical

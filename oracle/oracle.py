@@ -215,22 +215,28 @@ class Oracle:
         assert rv == 0, rv
         return dict(img=img, final_T=fT, n_contrib=nc, flags=fl, alt=alt, stats=_stats_dict(st))
 
-    def backward2d(self, rec: Record, dL_dimg, values=None, ranges=None, tiles=None, mode=MODE_F32):
-        """Per-splat gradient of <dL_dimg, image> w.r.t. (u,v,a,b,c,opacity,r,g,b,beta)."""
+    def backward2d(self, rec: Record, dL_dimg, values=None, ranges=None, tiles=None, mode=MODE_F32,
+                   with_delta=False):
+        """Per-splat gradient of <dL_dimg, image> w.r.t. (u,v,a,b,c,opacity,r,g,b,beta).
+
+        with_delta: also return the per-splat allowance from floating-point-ambiguous decisions."""
         g2d = np.zeros((rec.n, 10))
+        delta = np.zeros((rec.n, 10)) if with_delta else None
         d = np.ascontiguousarray(dL_dimg, np.float64)
         st = _Stats()
         rc = rec.c()
         if values is None:
             rv = lib().oc_backward_untiled(mode, C.byref(rc), C.c_int64(rec.n), C.byref(self.cs), C.byref(self.ps),
-                                           _p(d), _p(g2d), C.byref(st))
+                                           _p(d), _p(g2d), _p(delta), C.byref(st))
         else:
             tl = None if tiles is None else np.ascontiguousarray(tiles, np.int32)
             rv = lib().oc_backward(mode, C.byref(rc), C.c_int64(rec.n), C.byref(self.cs), C.byref(self.ps),
                                    _p(np.ascontiguousarray(values, np.uint32)),
                                    _p(np.ascontiguousarray(ranges, np.int64)), _p(tl),
-                                   C.c_int64(0 if tl is None else len(tl)), _p(d), _p(g2d), C.byref(st))
+                                   C.c_int64(0 if tl is None else len(tl)), _p(d), _p(g2d), _p(delta), C.byref(st))
         assert rv == 0, rv
+        if with_delta:
+            return g2d, delta, _stats_dict(st)
         return g2d, _stats_dict(st)
 
 

@@ -1,0 +1,234 @@
+// abi.cpp -- the C ABI of the GES rasterizer (include/ges.h): validation, workspace planning and
+// the launch sequences of one frame.  No allocation happens here: every buffer is the caller's.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "frame.h"
+#include "ges_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+thread_local ges::DeviceBatch g_host_batch;   // staging copy of the view table (pageable; copied per call)
+
+ges_status fail(ges_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+ges_status device_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return GES_ERR_DEVICE;
+}
+
+#define GES_CHECK_HIP(expr, where)                 \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return device_fail(e_, where); \
+  } while (0)
+
+// Build the single-view batch of a frame and copy it into the splat workspace.
+hipError_t upload_single_view(const ges_splats* s, const ges_camera* c, const ges_raster_params* p,
+                              const ges::FramePlan& fp, void* splat_ws, void* pixel_ws, float* out_rgb,
+                              const float* dL_drgb, hipStream_t stream) {
+  ges::DeviceBatch& hb = g_host_batch;
+  hb.nviews = 1;
+  hb.pre_prefix[0] = 0;
+  hb.pre_prefix[1] = (s->n + 255) / 256;
+  hb.bin_prefix[0] = 0;
+  hb.bin_prefix[1] = fp.bin_blocks;
+  hb.tile_prefix[0] = 0;
+  hb.tile_prefix[1] = fp.tiles;
+  ges::ViewDesc& V = hb.views[0];
+  ges::fill_view(V, s, c, p);
+  ges::attach_splat_ws(V, fp, splat_ws);
+  if (pixel_ws) {
+    char* pw = reinterpret_cast<char*>(pixel_ws);
+    V.final_T = reinterpret_cast<float*>(pw + fp.off_final_T);
+    V.n_contrib = reinterpret_cast<uint32_t*>(pw + fp.off_n_contrib);
+  }
+  V.out_rgb = out_rgb;
+  V.dL_drgb = dL_drgb;
+  void* dst = reinterpret_cast<char*>(splat_ws) + fp.off_db;
+  return hipMemcpyAsync(dst, &hb, ges::device_batch_bytes(1), hipMemcpyHostToDevice, stream);
+}
+
+ges::Batch single_batch(const ges_splats* s, const ges_raster_params* p, const ges::FramePlan& fp, void* splat_ws) {
+  ges::Batch b{};
+  b.nviews = 1;
+  b.falloff = p->falloff;
+  b.total_tiles = fp.tiles;
+  b.pre_blocks = (s->n + 255) / 256;
+  b.bin_blocks = fp.bin_blocks;
+  b.keys_total = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(splat_ws) + fp.off_hdr + 128);
+  return b;
+}
+
+const ges::DeviceBatch* dev_batch(void* splat_ws, const ges::FramePlan& fp) {
+  return reinterpret_cast<const ges::DeviceBatch*>(reinterpret_cast<char*>(splat_ws) + fp.off_db);
+}
+
+std::string check_all(const ges_splats* s, const ges_camera* c, const ges_raster_params* p) {
+  std::string e = ges::check_splats(s);
+  if (e.empty()) e = ges::check_camera(c);
+  if (e.empty()) e = ges::check_params(p);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t ges_abi_version(void) { return GES_ABI_VERSION; }
+
+const char* ges_last_error(void) { return g_last_error.c_str(); }
+
+ges_status ges_workspace_query(int64_t n, int32_t width, int32_t height, size_t* splat_ws_bytes,
+                               size_t* pixel_ws_bytes) {
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(GES_ERR_INVALID_ARGUMENT, "n outside [0, 2^31)");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(GES_ERR_INVALID_ARGUMENT, "width/height outside [1,16384]");
+  const ges::FramePlan fp = ges::plan_frame(n, width, height);
+  if (splat_ws_bytes) *splat_ws_bytes = fp.splat_bytes;
+  if (pixel_ws_bytes) *pixel_ws_bytes = fp.pixel_bytes;
+  return GES_OK;
+}
+
+ges_status ges_key_workspace_query(uint64_t num_keys, int64_t n, int32_t width, int32_t height, size_t* key_ws_bytes) {
+  (void)n; (void)width; (void)height;
+  if (!key_ws_bytes) return fail(GES_ERR_INVALID_ARGUMENT, "key_ws_bytes is NULL");
+  if (num_keys >= 0xffffffffull) return fail(GES_ERR_CAPACITY, "more than 2^32-2 keys");
+  *key_ws_bytes = ges::plan_keys(num_keys).bytes;
+  return GES_OK;
+}
+
+ges_status ges_preprocess(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                          void* splat_ws, size_t splat_ws_bytes, uint64_t* num_keys_host, void* stream_) {
+  const std::string e = check_all(splats, cam, params);
+  if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
+  if (!splat_ws) return fail(GES_ERR_INVALID_ARGUMENT, "splat_ws is NULL");
+  const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
+  if (splat_ws_bytes < fp.splat_bytes) return fail(GES_ERR_CAPACITY, "splat workspace too small");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, nullptr, nullptr, nullptr, stream), "upload");
+  const ges::Batch b = single_batch(splats, params, fp, splat_ws);
+  const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
+  GES_CHECK_HIP(ges::launch_preprocess(db, b, stream), "preprocess");
+  GES_CHECK_HIP(ges::launch_bin_count(db, b, stream), "bin_count");
+  GES_CHECK_HIP(ges::launch_bin_scan(db, b, nullptr, stream), "bin_scan");
+  if (num_keys_host) {
+    uint32_t k = 0;
+    GES_CHECK_HIP(hipMemcpyAsync(&k, b.keys_total, 4, hipMemcpyDeviceToHost, stream), "read num_keys");
+    GES_CHECK_HIP(hipStreamSynchronize(stream), "sync");
+    if (k == 0xffffffffu) return fail(GES_ERR_CAPACITY, "more than 2^32-2 (tile, splat) keys in one frame");
+    *num_keys_host = k;
+  }
+  return GES_OK;
+}
+
+ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                              void* splat_ws, void* key_ws, size_t key_ws_bytes, uint64_t num_keys, void* pixel_ws,
+                              float* out_rgb, void* stream_) {
+  const std::string e = check_all(splats, cam, params);
+  if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
+  if (!splat_ws || !pixel_ws || !out_rgb) return fail(GES_ERR_INVALID_ARGUMENT, "NULL workspace or output");
+  if (num_keys >= 0xffffffffull) return fail(GES_ERR_CAPACITY, "more than 2^32-2 keys");
+  const ges::KeyPlan kp = ges::plan_keys(num_keys);
+  if (num_keys > 0 && (!key_ws || key_ws_bytes < kp.bytes)) return fail(GES_ERR_CAPACITY, "key workspace too small");
+  const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, out_rgb, nullptr, stream), "upload");
+  ges::Batch b = single_batch(splats, params, fp, splat_ws);
+  char* kw = reinterpret_cast<char*>(key_ws);
+  b.key_capacity = num_keys;
+  if (num_keys > 0) {
+    b.pairs = reinterpret_cast<uint2*>(kw + kp.off_pairs);
+    b.pairs_tmp = reinterpret_cast<uint2*>(kw + kp.off_tmp);
+    b.sorted_ids = reinterpret_cast<uint32_t*>(kw + kp.off_sorted);
+  }
+  const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
+  GES_CHECK_HIP(ges::launch_bin_scatter(db, b, stream), "bin_scatter");
+  GES_CHECK_HIP(ges::launch_tile_sort(db, b, stream), "tile_sort");
+  GES_CHECK_HIP(ges::launch_raster_forward(db, b, stream), "raster_forward");
+  return GES_OK;
+}
+
+ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                               void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
+                               const ges_splat_grads* grads, void* stream_) {
+  const std::string e = check_all(splats, cam, params);
+  if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
+  if (!splat_ws || !pixel_ws || !dL_drgb || !grads) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, nullptr, dL_drgb, stream), "upload");
+  ges::Batch b = single_batch(splats, params, fp, splat_ws);
+  // the sorted ids of the forward pass; ranges bound every access, so the capacity is not needed here
+  if (key_ws) b.sorted_ids = reinterpret_cast<uint32_t*>(key_ws);   // KeyPlan::off_sorted == 0
+  const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
+  GES_CHECK_HIP(ges::launch_zero(reinterpret_cast<char*>(splat_ws) + fp.off_grad,
+                                 (size_t)splats->n * ges::kGradStride * 4, stream), "zero grad2d");
+  GES_CHECK_HIP(ges::launch_raster_backward(db, b, stream), "raster_backward");
+  GES_CHECK_HIP(ges::launch_preprocess_backward(db, b, grads, stream), "preprocess_backward");
+  return GES_OK;
+}
+
+ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* splat_ws, void* key_ws, uint64_t num_keys,
+                              void* pixel_ws, ges_frame_view* out) {
+  if (!out || !splat_ws) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (n < 0 || width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(GES_ERR_INVALID_ARGUMENT, "bad sizes");
+  const ges::FramePlan fp = ges::plan_frame(n, width, height);
+  char* sw = reinterpret_cast<char*>(splat_ws);
+  std::memset(out, 0, sizeof(*out));
+  out->records = reinterpret_cast<const float*>(sw + fp.off_rec);
+  out->tile_ranges = reinterpret_cast<const uint32_t*>(sw + fp.off_ranges);
+  out->grad2d = reinterpret_cast<const float*>(sw + fp.off_grad);
+  if (key_ws) {
+    const ges::KeyPlan kp = ges::plan_keys(num_keys);
+    char* kw = reinterpret_cast<char*>(key_ws);
+    out->sorted_ids = reinterpret_cast<const uint32_t*>(kw + kp.off_sorted);
+    out->bucket_pairs = reinterpret_cast<const uint32_t*>(kw + kp.off_pairs);
+  }
+  if (pixel_ws) {
+    char* pw = reinterpret_cast<char*>(pixel_ws);
+    out->final_T = reinterpret_cast<const float*>(pw + fp.off_final_T);
+    out->n_contrib = reinterpret_cast<const uint32_t*>(pw + fp.off_n_contrib);
+  }
+  out->tiles_x = fp.tiles_x;
+  out->tiles_y = fp.tiles_y;
+  return GES_OK;
+}
+
+size_t ges_mask_scratch_bytes(int32_t width, int32_t height) {
+  if (width < 1 || height < 1) return 0;
+  return ges::freq_mask_scratch_bytes(width, height);
+}
+
+ges_status ges_freq_mask(const float* target, int32_t width, int32_t height, float omega, void* scratch,
+                         uint8_t* mask, void* stream) {
+  if (!target || !scratch || !mask) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return fail(GES_ERR_INVALID_ARGUMENT, "bad sizes");
+  if (!(omega >= 0.f && omega <= 1.f)) return fail(GES_ERR_INVALID_ARGUMENT, "omega outside [0,1]");
+  GES_CHECK_HIP(ges::launch_freq_mask(target, width, height, omega, scratch, mask, reinterpret_cast<hipStream_t>(stream)),
+                "freq_mask");
+  return GES_OK;
+}
+
+size_t ges_loss_scratch_bytes(void) { return ges::loss_scratch_bytes(); }
+
+ges_status ges_loss(const float* img, const float* target, const uint8_t* mask, int32_t width, int32_t height,
+                    float lam_l1, float lam_w, void* scratch, float* loss_out, float* dL_dimg, void* stream) {
+  if (!img || !target || !scratch || !loss_out || !dL_dimg) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return fail(GES_ERR_INVALID_ARGUMENT, "bad sizes");
+  if (!std::isfinite(lam_l1) || !std::isfinite(lam_w)) return fail(GES_ERR_INVALID_ARGUMENT, "non-finite weight");
+  GES_CHECK_HIP(ges::launch_loss(img, target, mask, width, height, lam_l1, mask ? lam_w : 0.f, scratch, loss_out,
+                                 dL_dimg, reinterpret_cast<hipStream_t>(stream)),
+                "loss");
+  return GES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// frame.h -- host-side planning of one render frame (workspace layout, view descriptor, launches).
+// Shared by the C-ABI entry points and the serving loop.
+#pragma once
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "ges_internal.h"
+
+namespace ges {
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct FramePlan {
+  int tiles_x = 0, tiles_y = 0;
+  int64_t tiles = 0;
+  int bin_blocks = 1, bin_chunk = 0;
+  // splat workspace
+  size_t off_db = 0, off_hdr = 0, off_rec = 0, off_grad = 0, off_counts = 0, off_total = 0, off_ranges = 0;
+  size_t splat_bytes = 0;
+  // pixel workspace
+  size_t off_final_T = 0, off_n_contrib = 0, pixel_bytes = 0;
+};
+
+inline FramePlan plan_frame(int64_t n, int w, int h) {
+  FramePlan p;
+  p.tiles_x = (w + kTile - 1) / kTile;
+  p.tiles_y = (h + kTile - 1) / kTile;
+  p.tiles = (int64_t)p.tiles_x * p.tiles_y;
+  int64_t g = (n + 8191) / 8192;
+  if (g < 1) g = 1;
+  if (g > kMaxBinBlocks) g = kMaxBinBlocks;
+  p.bin_blocks = (int)g;
+  p.bin_chunk = (int)((n + g - 1) / g);
+  size_t o = 0;
+  p.off_db = o;      o += align256(sizeof(DeviceBatch));
+  p.off_hdr = o;     o += 256;
+  p.off_rec = o;     o += align256((size_t)n * kRecWords * 4);
+  p.off_grad = o;    o += align256((size_t)n * kGradStride * 4);
+  p.off_counts = o;  o += align256((size_t)p.bin_blocks * (size_t)p.tiles * 4);
+  p.off_total = o;   o += align256((size_t)p.tiles * 4);
+  p.off_ranges = o;  o += align256((size_t)p.tiles * 8);
+  p.splat_bytes = o;
+  size_t q = 0;
+  const size_t px = (size_t)w * h;
+  p.off_final_T = q;   q += align256(px * 4);
+  p.off_n_contrib = q; q += align256(px * 4);
+  p.pixel_bytes = q;
+  return p;
+}
+
+// The sorted ids come first so that the backward pass can find them without the key count.
+struct KeyPlan {
+  size_t off_sorted = 0, off_pairs = 0, off_tmp = 0, bytes = 0;
+};
+
+inline KeyPlan plan_keys(uint64_t k) {
+  KeyPlan p;
+  size_t o = 0;
+  p.off_sorted = o; o += align256((size_t)k * 4);
+  p.off_pairs = o;  o += align256((size_t)k * 8);
+  p.off_tmp = o;    o += align256((size_t)k * 8);
+  p.bytes = o;
+  return p;
+}
+
+// Validation of the public structs; returns an empty string when valid.
+inline std::string check_camera(const ges_camera* c) {
+  if (!c) return "camera is NULL";
+  if (c->width < 1 || c->height < 1 || c->width > 16384 || c->height > 16384) return "width/height outside [1,16384]";
+  const float vals[] = {c->fx, c->fy, c->cx, c->cy, c->near_z};
+  for (float v : vals)
+    if (!std::isfinite(v)) return "non-finite camera intrinsics";
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(c->R[k])) return "non-finite rotation";
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(c->t[k])) return "non-finite translation";
+  if (!(c->fx > 0.f) || !(c->fy > 0.f)) return "focal lengths must be positive";
+  if (!(c->near_z > 0.f)) return "near_z must be positive";
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double d = 0.0;
+      for (int k = 0; k < 3; ++k) d += (double)c->R[3 * i + k] * (double)c->R[3 * j + k];
+      if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-4) return "R is not orthonormal to 1e-4";
+    }
+  double det = (double)c->R[0] * ((double)c->R[4] * c->R[8] - (double)c->R[5] * c->R[7]) -
+               (double)c->R[1] * ((double)c->R[3] * c->R[8] - (double)c->R[5] * c->R[6]) +
+               (double)c->R[2] * ((double)c->R[3] * c->R[7] - (double)c->R[4] * c->R[6]);
+  if (det < 0.0) return "R is a reflection";
+  return "";
+}
+
+inline std::string check_splats(const ges_splats* s) {
+  if (!s) return "splats is NULL";
+  if (s->n < 0 || s->n >= (int64_t(1) << 31)) return "n outside [0, 2^31)";
+  if (s->sh_degree < 0 || s->sh_degree > 3) return "sh_degree outside [0,3]";
+  if (s->n > 0 && (!s->means || !s->log_scales || !s->quats || !s->opacity_logits || !s->sh || !s->beta))
+    return "NULL splat array";
+  if (s->n > 0 && (reinterpret_cast<uintptr_t>(s->quats) & 15u)) return "quats must be 16-byte aligned";
+  return "";
+}
+
+inline std::string check_params(const ges_raster_params* p) {
+  if (!p) return "params is NULL";
+  if (p->falloff != GES_FALLOFF_PHI && p->falloff != GES_FALLOFF_GEF) return "unknown falloff";
+  if (p->tile_cull != GES_TILES_SQUARE && p->tile_cull != GES_TILES_ELLIPSE) return "unknown tile_cull";
+  if (!std::isfinite(p->rho) || !std::isfinite(p->bg[0]) || !std::isfinite(p->bg[1]) || !std::isfinite(p->bg[2]))
+    return "non-finite raster parameter";
+  return "";
+}
+
+// Fill the camera / scene / parameter part of a view descriptor.  Derived camera values use the same
+// binary32 operation order as the per-splat preprocess.
+inline void fill_view(ViewDesc& V, const ges_splats* s, const ges_camera* c, const ges_raster_params* p) {
+  std::memset(&V, 0, sizeof(V));
+  V.means = s->means; V.log_scales = s->log_scales; V.quats = s->quats; V.logits = s->opacity_logits;
+  V.sh = s->sh; V.beta = s->beta; V.n = s->n; V.sh_degree = s->sh_degree;
+  V.sh_coeffs = (s->sh_degree + 1) * (s->sh_degree + 1);
+  for (int k = 0; k < 9; ++k) V.R[k] = c->R[k];
+  for (int k = 0; k < 3; ++k) V.t[k] = c->t[k];
+  for (int j = 0; j < 3; ++j) {   // camera centre -R^T t
+    volatile float acc = c->R[j] * c->t[0];
+    acc = acc + c->R[3 + j] * c->t[1];
+    acc = acc + c->R[6 + j] * c->t[2];
+    V.campos[j] = -acc;
+  }
+  V.fx = c->fx; V.fy = c->fy; V.cx = c->cx; V.cy = c->cy; V.near_z = c->near_z;
+  volatile float lx = 0.5f * (float)c->width;
+  lx = lx / c->fx;
+  lx = 1.3f * lx;
+  volatile float ly = 0.5f * (float)c->height;
+  ly = ly / c->fy;
+  ly = 1.3f * ly;
+  V.limx = lx; V.limy = ly;
+  V.width = c->width; V.height = c->height;
+  V.tiles_x = (c->width + kTile - 1) / kTile;
+  V.tiles_y = (c->height + kTile - 1) / kTile;
+  V.falloff = p->falloff; V.tile_cull = p->tile_cull; V.rho = p->rho;
+  for (int k = 0; k < 3; ++k) V.bg[k] = p->bg[k];
+}
+
+inline void attach_splat_ws(ViewDesc& V, const FramePlan& fp, void* splat_ws) {
+  char* b = reinterpret_cast<char*>(splat_ws);
+  V.rec = reinterpret_cast<float4*>(b + fp.off_rec);
+  V.grad2d = reinterpret_cast<float*>(b + fp.off_grad);
+  V.bin_counts = reinterpret_cast<uint32_t*>(b + fp.off_counts);
+  V.tile_total = reinterpret_cast<uint32_t*>(b + fp.off_total);
+  V.ranges = reinterpret_cast<uint2*>(b + fp.off_ranges);
+  V.header = reinterpret_cast<unsigned long long*>(b + fp.off_hdr);
+  V.bin_blocks = fp.bin_blocks;
+  V.bin_chunk = fp.bin_chunk;
+}
+
+}  // namespace ges

@@ -1,0 +1,124 @@
+// ges_internal.h -- device-side data layout and launchers of the GES rasterizer (gfx950).
+//
+// One "view" is one camera looking at one scene.  Every kernel takes an array of views so that a
+// single launch can serve a batch of render requests (continuous batching); the plain render path
+// is a batch of one.  All per-view buffers live in caller-provided workspaces.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/ges.h"
+
+namespace ges {
+
+constexpr int kTile = GES_TILE;          // 16 x 16 pixel tiles
+constexpr int kTilePx = kTile * kTile;   // 256 pixels, 4 per lane of one wave64
+constexpr int kRecWords = 16;            // 64-byte per-splat record
+constexpr int kGradStride = 12;          // floats per splat in the 2-D gradient accumulator
+constexpr int kMaxViews = 64;
+constexpr int kBinBlockThreads = 512;
+constexpr int kMaxBinBlocks = 256;       // splat chunks per view for the tile histogram
+constexpr int kBinLdsTiles = 12288;      // tiles per LDS window of the histogram (48 KB)
+constexpr int kSortCap = 4096;           // per-tile lists up to this length sort entirely in LDS
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+
+// Record words (see ges.h)
+enum : int {
+  R_U = 0, R_V, R_A, R_B, R_C, R_QMAX, R_OPA, R_BETA, R_CR, R_CG, R_CB, R_DEPTH, R_RADFLAGS, R_RECT0, R_RECT1, R_TOUCHED
+};
+
+struct ViewDesc {
+  // scene
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* logits;
+  const float* sh;
+  const float* beta;
+  int64_t n;
+  int32_t sh_degree;
+  int32_t sh_coeffs;             // (D+1)^2
+  // camera
+  float R[9];
+  float t[3];
+  float campos[3];
+  float fx, fy, cx, cy, near_z;
+  float limx, limy;              // 1.3 * tan(half FoV) guard of the perspective Jacobian
+  int32_t width, height, tiles_x, tiles_y;
+  // raster parameters
+  int32_t falloff, tile_cull;
+  float rho;
+  float bg[3];
+  // workspaces (device)
+  float4* rec;                   // [n] x 4 float4
+  uint32_t* bin_counts;          // [bin_blocks][tiles] per-chunk tile counts, then exclusive column prefix
+  uint32_t* tile_total;          // [tiles] entries per tile
+  uint2* ranges;                 // [tiles] [start,end) into the key arrays (global positions)
+  unsigned long long* header;    // [0] keys of this view, [1] error flags
+  float* grad2d;                 // [n][kGradStride]
+  float* final_T;                // [h*w]
+  uint32_t* n_contrib;           // [h*w]
+  float* out_rgb;                // [h*w*3]
+  const float* dL_drgb;          // [h*w*3] (backward only)
+  int32_t bin_blocks;            // number of splat chunks (histogram rows)
+  int32_t bin_chunk;             // splats per chunk
+  int64_t tile_base;             // first tile of this view in the batch's global tile numbering
+  int64_t pre_block_base;        // first block of this view in the preprocess grid
+  int64_t bin_block_base;        // first block of this view in the binning grids
+};
+
+struct Batch {
+  int32_t nviews;
+  int32_t falloff;               // shared by every view of a batch
+  int64_t total_tiles;
+  int64_t pre_blocks;
+  int64_t bin_blocks;
+  uint32_t* keys_total;          // device: total keys of the batch (u32 saturating counter)
+  uint2* pairs;                  // [key capacity] (depth bits, splat index) bucketed by tile
+  uint2* pairs_tmp;              // [key capacity] second buffer for large-list sorts
+  uint32_t* sorted_ids;          // [key capacity]
+  uint64_t key_capacity;
+};
+
+// Device view table and per-batch constants, copied to the device by the host before launches.
+// The prefix tables come first so that only the views in use need to be copied.
+struct DeviceBatch {
+  int64_t pre_prefix[kMaxViews + 1];
+  int64_t bin_prefix[kMaxViews + 1];
+  int64_t tile_prefix[kMaxViews + 1];
+  int32_t nviews;
+  int32_t pad_;
+  ViewDesc views[kMaxViews];
+};
+inline size_t device_batch_bytes(int nviews) { return offsetof(DeviceBatch, views) + (size_t)nviews * sizeof(ViewDesc); }
+
+// --------------------------------------------------------------------------------------------
+// launchers (implemented in the .hip files); all enqueue on `stream` and return hipError_t
+hipError_t launch_preprocess(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+hipError_t launch_bin_count(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+hipError_t launch_bin_scan(const DeviceBatch* dbatch, const Batch& b, const int32_t* tiles_per_view, hipStream_t stream);
+hipError_t launch_bin_scatter(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+hipError_t launch_raster_backward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+hipError_t launch_preprocess_backward(const DeviceBatch* dbatch, const Batch& b, const ges_splat_grads* grads,
+                                      hipStream_t stream);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
+
+hipError_t launch_freq_mask(const float* target, int w, int h, float omega, void* scratch, uint8_t* mask,
+                            hipStream_t stream);
+size_t freq_mask_scratch_bytes(int w, int h);
+size_t loss_scratch_bytes();
+hipError_t launch_loss(const float* img, const float* target, const uint8_t* mask, int w, int h, float lam_l1,
+                       float lam_w, void* scratch, float* loss_out, float* dL_dimg, hipStream_t stream);
+
+// Which view owns global block `blk` given a prefix table (linear scan: at most kMaxViews entries).
+__device__ inline int view_of_block(const int64_t* prefix, int nviews, int64_t blk) {
+  int v = 0;
+  while (v + 1 < nviews && prefix[v + 1] <= blk) ++v;
+  return v;
+}
+
+}  // namespace ges

@@ -1,0 +1,317 @@
+// raster.hip -- per-tile front-to-back compositing of GES splats and its reverse-mode pass.
+//
+// Compositing is the discrete form of the volume-rendering integral (GES Sec. 4.2, Eq. transimttance):
+// for every pixel, over its tile's splats in (depth, index) order,
+//   q = a dx^2 + 2 b dx dy + c dy^2 with (dx,dy) = mean2D - pixel centre   (binary32, fixed order:
+//       t = fma(a, dx, (2b) dy); q = fma(t, dx, (c dy) dy) -- identical on every machine)
+//   skip unless q <= q_max (alpha >= 1/255);   falloff G = exp(-q/2) (PHI) or exp(-q^(beta/2)/2) (GEF)
+//   alpha = min(0.99, o G);  t = T (1 - alpha);  stop before compositing when t < 1e-4
+//   C += alpha T rgb;  T = t.
+// Launch shape (gfx950): one wave64 per 16x16 tile, each lane owning 4 pixels of one column
+// (rows y, y+4, y+8, y+12), so each splat read from LDS is used four times per lane.  Splats are
+// staged 64 at a time: lane l gathers record l of the batch into LDS, then every lane reads the batch
+// back as broadcasts.  The wave stops as soon as no lane has a live pixel (ballot).  Tiles are
+// assigned to blocks so that each of the 8 XCDs walks a contiguous band of tiles (neighbouring tiles
+// share splats in that XCD's L2).
+// The backward pass walks each pixel's contributors back to front, recovering the transmittance
+// before splat j as T_j = T_(j+1) / (1 - alpha_j) from the stored final T, so no per-pixel lists are
+// kept.  Per splat, the 4 pixels of a lane are summed in registers, the 64 lanes by DPP row and
+// broadcast steps, and one lane per gradient component adds the total with a float atomic.
+#include "ges_internal.h"
+
+namespace ges {
+
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;   // -log2(e)/2: exp(-q/2) = 2^(kNegHalfLog2e q)
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ float pair_q(float u, float v, float a, float bb, float c, float px, float py,
+                                        float& dx, float& dy) {
+  dx = u - px;
+  dy = v - py;
+  float t = bb * dy;
+  t = __builtin_fmaf(a, dx, t);
+  float w = c * dy;
+  w = w * dy;
+  return __builtin_fmaf(t, dx, w);
+}
+
+// Map a block to a global tile so that blocks landing on one XCD (block index mod 8) cover a
+// contiguous band of tiles.
+__device__ __forceinline__ int64_t xcd_tile(int64_t blk, int64_t per_xcd) { return (blk & 7) * per_xcd + (blk >> 3); }
+
+template <int FALLOFF>
+__global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* __restrict__ db,
+                                                            const uint32_t* __restrict__ sorted_ids,
+                                                            int64_t total_tiles, int64_t per_xcd,
+                                                            uint64_t capacity) {
+  __shared__ float4 sA[64], sB[64], sC[64];
+  const int64_t gt = xcd_tile(blockIdx.x, per_xcd);
+  if (gt >= total_tiles) return;
+  const int v = view_of_block(db->tile_prefix, db->nviews, gt);
+  const ViewDesc& V = db->views[v];
+  const int lt = (int)(gt - db->tile_prefix[v]);
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int lane = threadIdx.x;
+  const int px = tx * kTile + (lane & 15);
+  const int py0 = ty * kTile + (lane >> 4);
+  const float pxf = (float)px;
+  float pyf[4];
+  uint32_t alive = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    pyf[k] = (float)(py0 + 4 * k);
+    if (px < V.width && py0 + 4 * k < V.height) alive |= 1u << k;
+  }
+  float T[4] = {1.f, 1.f, 1.f, 1.f};
+  float C[4][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  uint32_t last[4] = {0u, 0u, 0u, 0u};
+  const uint2 rg = V.ranges[lt];
+  // a range beyond the key buffer (inconsistent key count) renders as background
+  const int n = (uint64_t)rg.y <= capacity ? (int)(rg.y - rg.x) : 0;
+  const float4* rec = V.rec;
+  for (int base = 0; base < n; base += 64) {
+    if (!__any(alive != 0)) break;
+    const int cnt = min(64, n - base);
+    if (lane < cnt) {
+      const uint32_t id = sorted_ids[rg.x + base + lane];
+      const float4 a = rec[4 * (size_t)id];
+      const float4 b = rec[4 * (size_t)id + 1];
+      const float4 c = rec[4 * (size_t)id + 2];
+      sA[lane] = make_float4(a.x, a.y, a.z, a.w + a.w);
+      sB[lane] = b;
+      sC[lane] = c;
+    }
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const float4 A = sA[j];
+      const float4 B = sB[j];
+      const float4 Cc = sC[j];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (!(alive & (1u << k))) continue;
+        float dx, dy;
+        float q = pair_q(A.x, A.y, A.z, A.w, B.x, pxf, pyf[k], dx, dy);
+        if (!(q <= B.y)) continue;
+        q = fmaxf(q, 0.f);
+        float G;
+        if (FALLOFF == GES_FALLOFF_PHI) {
+          G = fast_exp2(kNegHalfLog2e * q);
+        } else {
+          const float qb = fast_exp2(0.5f * B.w * fast_log2(q));
+          G = fast_exp2(kNegHalfLog2e * qb);
+        }
+        const float alpha = fminf(kAlphaMax, B.z * G);
+        const float t = T[k] * (1.f - alpha);
+        if (t < kTMin) { alive &= ~(1u << k); continue; }
+        const float w = alpha * T[k];
+        C[k][0] = __builtin_fmaf(w, Cc.x, C[k][0]);
+        C[k][1] = __builtin_fmaf(w, Cc.y, C[k][1]);
+        C[k][2] = __builtin_fmaf(w, Cc.z, C[k][2]);
+        T[k] = t;
+        last[k] = (uint32_t)(base + j + 1);
+      }
+      if (!__any(alive != 0)) break;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int py = py0 + 4 * k;
+    if (px >= V.width || py >= V.height) continue;
+    const size_t pix = (size_t)py * V.width + px;
+    V.out_rgb[3 * pix + 0] = __builtin_fmaf(T[k], V.bg[0], C[k][0]);
+    V.out_rgb[3 * pix + 1] = __builtin_fmaf(T[k], V.bg[1], C[k][1]);
+    V.out_rgb[3 * pix + 2] = __builtin_fmaf(T[k], V.bg[2], C[k][2]);
+    if (V.final_T) V.final_T[pix] = T[k];
+    if (V.n_contrib) V.n_contrib[pix] = last[k];
+  }
+}
+
+// ---- wave64 sum with DPP: quad swaps, row rotations, then row broadcasts 15 and 31 into lane 63
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float x) {
+  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false);
+  return x + __int_as_float(y);
+}
+
+__device__ __forceinline__ float wave_sum_to_63(float x) {
+  x = dpp_add<0xB1, 0xf>(x);    // quad_perm [1,0,3,2]
+  x = dpp_add<0x4E, 0xf>(x);    // quad_perm [2,3,0,1]
+  x = dpp_add<0x124, 0xf>(x);   // row_ror:4
+  x = dpp_add<0x128, 0xf>(x);   // row_ror:8
+  x = dpp_add<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x = dpp_add<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+template <int FALLOFF>
+__global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* __restrict__ db,
+                                                             const uint32_t* __restrict__ sorted_ids,
+                                                             int64_t total_tiles, int64_t per_xcd) {
+  __shared__ float4 sA[64], sB[64], sC[64];
+  const int64_t gt = xcd_tile(blockIdx.x, per_xcd);
+  if (gt >= total_tiles) return;
+  const int v = view_of_block(db->tile_prefix, db->nviews, gt);
+  const ViewDesc& V = db->views[v];
+  const int lt = (int)(gt - db->tile_prefix[v]);
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int lane = threadIdx.x;
+  const int px = tx * kTile + (lane & 15);
+  const int py0 = ty * kTile + (lane >> 4);
+  const float pxf = (float)px;
+  float pyf[4], T[4], Tf[4], g[4][3], bgg[4], S[4][3];
+  uint32_t last[4];
+  uint32_t maxlast = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int py = py0 + 4 * k;
+    pyf[k] = (float)py;
+    S[k][0] = S[k][1] = S[k][2] = 0.f;
+    if (px < V.width && py < V.height) {
+      const size_t pix = (size_t)py * V.width + px;
+      T[k] = V.final_T[pix];
+      last[k] = V.n_contrib[pix];
+      g[k][0] = V.dL_drgb[3 * pix];
+      g[k][1] = V.dL_drgb[3 * pix + 1];
+      g[k][2] = V.dL_drgb[3 * pix + 2];
+    } else {
+      T[k] = 1.f;
+      last[k] = 0u;
+      g[k][0] = g[k][1] = g[k][2] = 0.f;
+    }
+    Tf[k] = T[k];
+    bgg[k] = V.bg[0] * g[k][0] + V.bg[1] * g[k][1] + V.bg[2] * g[k][2];
+    maxlast = max(maxlast, last[k]);
+  }
+  // wave max of the last contributor position
+  for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, off, 64));
+  const uint2 rg = V.ranges[lt];
+  const float4* rec = V.rec;
+  float* grad2d = V.grad2d;
+  for (int hi = (int)maxlast; hi > 0; hi -= 64) {
+    const int lo = max(0, hi - 64);
+    const int cnt = hi - lo;
+    if (lane < cnt) {
+      const uint32_t id = sorted_ids[rg.x + lo + lane];
+      const float4 a = rec[4 * (size_t)id];
+      const float4 b = rec[4 * (size_t)id + 1];
+      const float4 c = rec[4 * (size_t)id + 2];
+      sA[lane] = make_float4(a.x, a.y, a.z, a.w);
+      sB[lane] = b;
+      sC[lane] = make_float4(c.x, c.y, c.z, __uint_as_float(id));
+    }
+    __syncthreads();
+    for (int j = cnt - 1; j >= 0; --j) {
+      const float4 A = sA[j];
+      const float4 B = sB[j];
+      const float4 Cc = sC[j];
+      const uint32_t pos = (uint32_t)(lo + j);
+      const float bb = A.w + A.w;
+      float pu = 0.f, pv = 0.f, pa = 0.f, pb = 0.f, pc = 0.f, po = 0.f, pr = 0.f, pg = 0.f, pbl = 0.f, pbeta = 0.f;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (pos >= last[k]) continue;
+        float dx, dy;
+        const float q0 = pair_q(A.x, A.y, A.z, bb, B.x, pxf, pyf[k], dx, dy);
+        if (!(q0 <= B.y)) continue;
+        const float q = fmaxf(q0, 0.f);
+        float G, qb = 0.f, lq = 0.f;
+        if (FALLOFF == GES_FALLOFF_PHI) {
+          G = fast_exp2(kNegHalfLog2e * q);
+        } else {
+          lq = fast_log2(q);
+          qb = fast_exp2(0.5f * B.w * lq);
+          G = fast_exp2(kNegHalfLog2e * qb);
+        }
+        const float oG = B.z * G;
+        const bool clamped = oG > kAlphaMax;
+        const float alpha = clamped ? kAlphaMax : oG;
+        const float inv = fast_rcp(1.f - alpha);
+        T[k] = T[k] * inv;                 // transmittance before this splat
+        const float w = alpha * T[k];
+        pr = __builtin_fmaf(w, g[k][0], pr);
+        pg = __builtin_fmaf(w, g[k][1], pg);
+        pbl = __builtin_fmaf(w, g[k][2], pbl);
+        float dalpha = (Cc.x - S[k][0]) * g[k][0] + (Cc.y - S[k][1]) * g[k][1] + (Cc.z - S[k][2]) * g[k][2];
+        dalpha = dalpha * T[k] - Tf[k] * bgg[k] * inv;
+        S[k][0] = __builtin_fmaf(alpha, Cc.x - S[k][0], S[k][0]);
+        S[k][1] = __builtin_fmaf(alpha, Cc.y - S[k][1], S[k][1]);
+        S[k][2] = __builtin_fmaf(alpha, Cc.z - S[k][2], S[k][2]);
+        any = true;
+        if (clamped) continue;
+        const float dG = B.z * dalpha;
+        po = __builtin_fmaf(G, dalpha, po);
+        float dq;
+        if (FALLOFF == GES_FALLOFF_PHI) {
+          dq = q0 >= 0.f ? -0.5f * G * dG : 0.f;
+        } else {
+          // dG/dq = -(beta/4) q^(beta/2 - 1) G  (q floored at 1e-12);  dG/dbeta = -(1/4) q^(beta/2) ln q G
+          const float qf = fmaxf(q, 1e-12f);
+          const float qpow = fast_exp2((0.5f * B.w - 1.f) * fast_log2(qf));
+          dq = q0 >= 0.f ? -0.25f * B.w * qpow * G * dG : 0.f;
+          if (q > 0.f) pbeta = __builtin_fmaf(-0.25f * qb * (lq * 0.69314718055994531f) * G, dG, pbeta);
+        }
+        const float tx2 = dq * 2.f;
+        pu = __builtin_fmaf(tx2, __builtin_fmaf(A.z, dx, A.w * dy), pu);
+        pv = __builtin_fmaf(tx2, __builtin_fmaf(A.w, dx, B.x * dy), pv);
+        pa = __builtin_fmaf(dq * dx, dx, pa);
+        pb = __builtin_fmaf(tx2 * dx, dy, pb);
+        pc = __builtin_fmaf(dq * dy, dy, pc);
+      }
+      if (!__any(any)) continue;
+      const float su = wave_sum_to_63(pu), sv = wave_sum_to_63(pv), sa = wave_sum_to_63(pa);
+      const float sb = wave_sum_to_63(pb), sc = wave_sum_to_63(pc), so = wave_sum_to_63(po);
+      const float sr = wave_sum_to_63(pr), sg = wave_sum_to_63(pg), sbl = wave_sum_to_63(pbl);
+      const float sbeta = FALLOFF == GES_FALLOFF_GEF ? wave_sum_to_63(pbeta) : 0.f;
+      const int ncomp = FALLOFF == GES_FALLOFF_GEF ? 10 : 9;
+      if (lane < ncomp) {
+        float val = su;
+        val = lane == 1 ? sv : val;
+        val = lane == 2 ? sa : val;
+        val = lane == 3 ? sb : val;
+        val = lane == 4 ? sc : val;
+        val = lane == 5 ? so : val;
+        val = lane == 6 ? sr : val;
+        val = lane == 7 ? sg : val;
+        val = lane == 8 ? sbl : val;
+        val = lane == 9 ? sbeta : val;
+        const uint32_t id = __float_as_uint(Cc.w);
+        if (val != 0.f) atomicAdd(&grad2d[(size_t)id * kGradStride + lane], val);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {
+  if (b.total_tiles == 0) return hipSuccess;
+  const int64_t per_xcd = (b.total_tiles + 7) / 8;
+  const dim3 grid((unsigned)(per_xcd * 8));
+  // every view of a batch shares the falloff (the server fixes it per instance)
+  if (b.falloff == GES_FALLOFF_PHI)
+    hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_PHI>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
+                       b.total_tiles, per_xcd, b.key_capacity);
+  else
+    hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_GEF>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
+                       b.total_tiles, per_xcd, b.key_capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_backward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {
+  if (b.total_tiles == 0) return hipSuccess;
+  const int64_t per_xcd = (b.total_tiles + 7) / 8;
+  const dim3 grid((unsigned)(per_xcd * 8));
+  if (b.falloff == GES_FALLOFF_PHI)
+    hipLaunchKernelGGL(raster_backward_kernel<GES_FALLOFF_PHI>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
+                       b.total_tiles, per_xcd);
+  else
+    hipLaunchKernelGGL(raster_backward_kernel<GES_FALLOFF_GEF>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
+                       b.total_tiles, per_xcd);
+  return hipGetLastError();
+}
+
+}  // namespace ges

@@ -1,0 +1,298 @@
+"""ctypes binding of libges.so (include/ges.h).
+
+Argument marshalling only: every function here converts torch tensors to device
+pointers and calls the C entry point of the same name; all arithmetic runs in the
+HIP kernels.  The library must have been built (``paper_2402_10128_amd.build``);
+importing this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libges.so")
+
+GES_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "CAPACITY", 3: "OUT_OF_MEMORY", 4: "DEVICE", 5: "BUSY",
+                6: "NOT_FOUND", 7: "INTERNAL"}
+FALLOFF_PHI, FALLOFF_GEF = 0, 1
+TILES_SQUARE, TILES_ELLIPSE = 0, 1
+TILE = 16
+
+
+class GESError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ges_splats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("means", C.c_void_p), ("log_scales", C.c_void_p),
+                ("quats", C.c_void_p), ("opacity_logits", C.c_void_p), ("sh", C.c_void_p), ("beta", C.c_void_p)]
+
+
+class ges_camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("R", C.c_float * 9), ("t", C.c_float * 3),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float), ("near_z", C.c_float)]
+
+
+class ges_raster_params(C.Structure):
+    _fields_ = [("falloff", C.c_int32), ("tile_cull", C.c_int32), ("rho", C.c_float), ("bg", C.c_float * 3)]
+
+
+class ges_splat_grads(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "beta")]
+
+
+class ges_frame_view(C.Structure):
+    _fields_ = [("records", C.c_void_p), ("tile_ranges", C.c_void_p), ("sorted_ids", C.c_void_p),
+                ("bucket_pairs", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
+                ("grad2d", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32)]
+
+
+class ges_serve_config(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("queue_capacity", C.c_int32), ("falloff", C.c_int32),
+                ("tile_cull", C.c_int32), ("rho", C.c_float), ("bg", C.c_float * 3), ("sequential", C.c_int32)]
+
+
+class ges_request_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("t_submit_ns", C.c_uint64), ("t_start_ns", C.c_uint64),
+                ("t_done_ns", C.c_uint64), ("num_keys", C.c_uint64), ("batch_size", C.c_int32)]
+
+
+# exported entry points and their argument types
+_SIGS = {
+    "ges_abi_version": (C.c_uint32, []),
+    "ges_last_error": (C.c_char_p, []),
+    "ges_workspace_query": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "ges_key_workspace_query": (C.c_int, [C.c_uint64, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "ges_preprocess": (C.c_int, [C.POINTER(ges_splats), C.POINTER(ges_camera), C.POINTER(ges_raster_params),
+                                 C.c_void_p, C.c_size_t, C.POINTER(C.c_uint64), C.c_void_p]),
+    "ges_render_forward": (C.c_int, [C.POINTER(ges_splats), C.POINTER(ges_camera), C.POINTER(ges_raster_params),
+                                     C.c_void_p, C.c_void_p, C.c_size_t, C.c_uint64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
+    "ges_render_backward": (C.c_int, [C.POINTER(ges_splats), C.POINTER(ges_camera), C.POINTER(ges_raster_params),
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(ges_splat_grads),
+                                      C.c_void_p]),
+    "ges_frame_view_get": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64,
+                                     C.c_void_p, C.POINTER(ges_frame_view)]),
+    "ges_mask_scratch_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "ges_freq_mask": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ges_loss_scratch_bytes": (C.c_size_t, []),
+    "ges_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_float,
+                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ges_serve_create": (C.c_int, [C.POINTER(ges_serve_config), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "ges_serve_add_scene": (C.c_int, [C.c_void_p, C.POINTER(ges_splats), C.POINTER(C.c_int32)]),
+    "ges_serve_submit": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(ges_camera), C.c_void_p, C.POINTER(C.c_uint64)]),
+    "ges_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ges_request_info)]),
+    "ges_serve_drain": (C.c_int, [C.c_void_p]),
+    "ges_serve_destroy": (C.c_int, [C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libges.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2402_10128_amd.build.build()")
+        _lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(_lib, name, None)
+            if f is None:
+                continue
+            f.restype = res
+            f.argtypes = args
+    return _lib
+
+
+def _check(status):
+    if status != GES_OK:
+        raise GESError(status, lib().ges_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def camera_struct(cam) -> ges_camera:
+    c = ges_camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.R[:] = [float(x) for x in np.asarray(cam.R, np.float32).ravel()]
+    c.t[:] = [float(x) for x in np.asarray(cam.t, np.float32).ravel()]
+    c.fx, c.fy, c.cx, c.cy, c.near_z = (float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy, cam.near))
+    return c
+
+
+def params_struct(falloff=FALLOFF_PHI, tile_cull=TILES_SQUARE, rho=0.1, bg=(0.0, 0.0, 0.0)) -> ges_raster_params:
+    p = ges_raster_params()
+    p.falloff, p.tile_cull, p.rho = int(falloff), int(tile_cull), float(rho)
+    p.bg[:] = [float(b) for b in bg]
+    return p
+
+
+def splats_struct(means, log_scales, quats, opacity_logits, sh, beta) -> ges_splats:
+    s = ges_splats()
+    s.n = int(means.shape[0])
+    k = int(sh.shape[1]) if sh.dim() == 3 else 1
+    deg = {1: 0, 4: 1, 9: 2, 16: 3}[k]
+    s.sh_degree = deg
+    for name, t in (("means", means), ("log_scales", log_scales), ("quats", quats),
+                    ("opacity_logits", opacity_logits), ("sh", sh), ("beta", beta)):
+        if t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+        setattr(s, name, t.data_ptr())
+    return s
+
+
+# ---- thin wrappers with the C names --------------------------------------------------------------------
+def ges_abi_version() -> int:
+    return lib().ges_abi_version()
+
+
+def ges_workspace_query(n, width, height):
+    a, b = C.c_size_t(0), C.c_size_t(0)
+    _check(lib().ges_workspace_query(int(n), int(width), int(height), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def ges_key_workspace_query(num_keys, n, width, height):
+    a = C.c_size_t(0)
+    _check(lib().ges_key_workspace_query(int(num_keys), int(n), int(width), int(height), C.byref(a)))
+    return a.value
+
+
+def ges_preprocess(splats, cam, params, splat_ws, read_num_keys=True, stream=None):
+    k = C.c_uint64(0)
+    _check(lib().ges_preprocess(C.byref(splats), C.byref(cam), C.byref(params), _ptr(splat_ws),
+                                splat_ws.numel(), C.byref(k) if read_num_keys else None, _stream(stream)))
+    return k.value if read_num_keys else None
+
+
+def ges_render_forward(splats, cam, params, splat_ws, key_ws, num_keys, pixel_ws, out_rgb, stream=None):
+    _check(lib().ges_render_forward(C.byref(splats), C.byref(cam), C.byref(params), _ptr(splat_ws), _ptr(key_ws),
+                                    0 if key_ws is None else key_ws.numel(), int(num_keys), _ptr(pixel_ws),
+                                    _ptr(out_rgb), _stream(stream)))
+
+
+def ges_render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads: dict, stream=None):
+    g = ges_splat_grads()
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "beta"):
+        t = grads.get(k)
+        setattr(g, k, None if t is None else t.data_ptr())
+    _check(lib().ges_render_backward(C.byref(splats), C.byref(cam), C.byref(params), _ptr(splat_ws), _ptr(key_ws),
+                                     _ptr(pixel_ws), _ptr(dL_drgb), C.byref(g), _stream(stream)))
+
+
+def ges_frame_view_get(n, width, height, splat_ws, key_ws, num_keys, pixel_ws) -> ges_frame_view:
+    v = ges_frame_view()
+    _check(lib().ges_frame_view_get(int(n), int(width), int(height), _ptr(splat_ws), _ptr(key_ws), int(num_keys),
+                                    _ptr(pixel_ws), C.byref(v)))
+    return v
+
+
+def ges_freq_mask(target, omega, mask=None, stream=None):
+    H, W = int(target.shape[0]), int(target.shape[1])
+    scratch = torch.empty(lib().ges_mask_scratch_bytes(W, H), dtype=torch.uint8, device=target.device)
+    if mask is None:
+        mask = torch.empty((H, W), dtype=torch.uint8, device=target.device)
+    _check(lib().ges_freq_mask(_ptr(target), W, H, float(omega), _ptr(scratch), _ptr(mask), _stream(stream)))
+    return mask
+
+
+def ges_loss(img, target, mask, lam_l1, lam_w, dL_dimg=None, loss_out=None, scratch=None, stream=None):
+    H, W = int(img.shape[0]), int(img.shape[1])
+    if dL_dimg is None:
+        dL_dimg = torch.empty_like(img)
+    if loss_out is None:
+        loss_out = torch.empty((), dtype=torch.float32, device=img.device)
+    if scratch is None:
+        scratch = torch.empty(lib().ges_loss_scratch_bytes(), dtype=torch.uint8, device=img.device)
+    _check(lib().ges_loss(_ptr(img), _ptr(target), _ptr(mask), W, H, float(lam_l1), float(lam_w), _ptr(scratch),
+                          _ptr(loss_out), _ptr(dL_dimg), _stream(stream)))
+    return loss_out, dL_dimg
+
+
+# ---- a frame: owns the workspaces of one (scene, camera) render --------------------------------------
+@dataclass
+class Frame:
+    """Workspaces and results of one render; re-usable across calls with the same sizes."""
+    n: int
+    width: int
+    height: int
+    splat_ws: torch.Tensor
+    pixel_ws: torch.Tensor
+    key_ws: torch.Tensor | None = None
+    num_keys: int = 0
+
+    @staticmethod
+    def create(n, width, height, device="cuda"):
+        sb, pb = ges_workspace_query(n, width, height)
+        return Frame(n, width, height, torch.empty(sb, dtype=torch.uint8, device=device),
+                     torch.empty(pb, dtype=torch.uint8, device=device))
+
+    def ensure_keys(self, num_keys):
+        need = ges_key_workspace_query(num_keys, self.n, self.width, self.height)
+        if self.key_ws is None or self.key_ws.numel() < need:
+            # grow with headroom so that small changes of the key count do not reallocate
+            self.key_ws = torch.empty(max(need, int(need * 1.25)), dtype=torch.uint8, device=self.splat_ws.device)
+        self.num_keys = num_keys
+
+    def view(self) -> ges_frame_view:
+        return ges_frame_view_get(self.n, self.width, self.height, self.splat_ws, self.key_ws, self.num_keys,
+                                  self.pixel_ws)
+
+
+def frame_arrays(frame: Frame, n: int) -> dict:
+    """Copies of a frame's inspection arrays as numpy (tests)."""
+    v = frame.view()
+    out = {}
+    ws = frame.splat_ws
+
+    def sl(ptr, nbytes, tensor):
+        off = ptr - tensor.data_ptr()
+        return tensor[off:off + nbytes]
+
+    out["records"] = sl(v.records, 64 * n, ws).view(torch.float32).reshape(n, 16).cpu().numpy()
+    T = v.tiles_x * v.tiles_y
+    out["ranges"] = sl(v.tile_ranges, 8 * T, ws).view(torch.int32).reshape(T, 2).cpu().numpy().view(np.uint32)
+    out["grad2d"] = sl(v.grad2d, 48 * n, ws).view(torch.float32).reshape(n, 12).cpu().numpy()
+    if frame.key_ws is not None and frame.num_keys > 0:
+        K = frame.num_keys
+        out["sorted_ids"] = sl(v.sorted_ids, 4 * K, frame.key_ws).view(torch.int32).cpu().numpy().view(np.uint32)
+        out["bucket_pairs"] = sl(v.bucket_pairs, 8 * K, frame.key_ws).view(torch.int32).reshape(K, 2).cpu().numpy().view(
+            np.uint32)
+    px = frame.width * frame.height
+    out["final_T"] = sl(v.final_T, 4 * px, frame.pixel_ws).view(torch.float32).reshape(frame.height, frame.width).cpu().numpy()
+    out["n_contrib"] = sl(v.n_contrib, 4 * px, frame.pixel_ws).view(torch.int32).reshape(
+        frame.height, frame.width).cpu().numpy().view(np.uint32)
+    return out
+
+
+def render(scene: dict, cam, falloff=FALLOFF_PHI, tile_cull=TILES_SQUARE, rho=0.1, bg=(0.0, 0.0, 0.0), frame=None,
+           out=None, stream=None):
+    """Preprocess + forward render of one view.  scene: dict of CUDA float32 tensors."""
+    s = splats_struct(scene["means"], scene["log_scales"], scene["quats"], scene["opacity_logits"], scene["sh"],
+                      scene["beta"])
+    c = camera_struct(cam)
+    p = params_struct(falloff, tile_cull, rho, bg)
+    if frame is None:
+        frame = Frame.create(s.n, c.width, c.height, scene["means"].device)
+    k = ges_preprocess(s, c, p, frame.splat_ws, True, stream)
+    frame.ensure_keys(k)
+    if out is None:
+        out = torch.empty((c.height, c.width, 3), dtype=torch.float32, device=scene["means"].device)
+    ges_render_forward(s, c, p, frame.splat_ws, frame.key_ws, k, frame.pixel_ws, out, stream)
+    return out, frame

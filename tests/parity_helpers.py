@@ -1,0 +1,134 @@
+"""Helpers for the GPU-vs-oracle parity tests: run both sides on the same seeded inputs and compare.
+
+Tolerances (stated per result):
+  * per-splat records, keys, sort order, tile ranges: bit-exact (mismatch count must be 0);
+  * image: <= 1e-5 absolute per FP32 channel on pixels whose termination decision is not within
+    1e-3 (relative) of the 1e-4 threshold; flagged pixels must match one of the two branches;
+  * gradients: |g - r| / max(|r|, 1e-2 * rms(r)) <= 1e-3 per tensor.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle import oracle as O
+from oracle import preprocess_f64 as PF
+from paper_2402_10128_amd import ges as G
+
+IMG_ATOL = 1e-5
+GRAD_RTOL = 1e-3
+GRAD_FLOOR = 1e-2
+
+
+def to_device(arrays: dict, device="cuda"):
+    return {k: torch.as_tensor(np.ascontiguousarray(v, np.float32)).to(device) for k, v in arrays.items()}
+
+
+def gpu_render(arrays, sh_degree, cam, falloff=0, tile_cull=0, rho=0.1, bg=(0.0, 0.0, 0.0), dL=None):
+    """Forward (+ optional backward) on the GPU; returns numpy results and the frame arrays."""
+    sc = to_device(arrays)
+    s = G.splats_struct(sc["means"], sc["log_scales"], sc["quats"], sc["opacity_logits"], sc["sh"], sc["beta"])
+    c = G.camera_struct(cam)
+    p = G.params_struct(falloff, tile_cull, rho, bg)
+    frame = G.Frame.create(s.n, c.width, c.height)
+    k = G.ges_preprocess(s, c, p, frame.splat_ws, True)
+    frame.ensure_keys(k)
+    out = torch.empty((c.height, c.width, 3), dtype=torch.float32, device="cuda")
+    G.ges_render_forward(s, c, p, frame.splat_ws, frame.key_ws, k, frame.pixel_ws, out)
+    res = dict(img=out.cpu().numpy(), num_keys=k)
+    if dL is not None:
+        grads = {kk: torch.empty_like(sc[kk]) for kk in ("means", "log_scales", "quats", "opacity_logits", "sh", "beta")}
+        G.ges_render_backward(s, c, p, frame.splat_ws, frame.key_ws, frame.pixel_ws,
+                              torch.as_tensor(np.ascontiguousarray(dL, np.float32)).cuda(), grads)
+        res["grads"] = {kk: v.cpu().numpy() for kk, v in grads.items()}
+    torch.cuda.synchronize()
+    res.update(G.frame_arrays(frame, s.n))
+    return res
+
+
+RECORD_FIELDS = [("u", 0), ("v", 1), ("a", 2), ("b", 3), ("c", 4), ("qmax", 5), ("opacity", 6), ("beta", 7),
+                 ("r", 8), ("g", 9), ("b_", 10), ("depth", 11)]
+
+
+def record_mismatches(gpu_rec: np.ndarray, orc: O.Record) -> dict:
+    """Mismatch counts per record field, binary32 bits vs the oracle's F32 record (visible splats)."""
+    vis = orc.tiles_touched > 0
+    gvis = gpu_rec[:, 15].view(np.uint32) > 0
+    out = {"visible": int((vis != gvis).sum())}
+    ref = {"u": orc.u, "v": orc.v, "a": orc.conic[:, 0], "b": orc.conic[:, 1], "c": orc.conic[:, 2],
+           "qmax": orc.qmax, "opacity": orc.opacity, "beta": orc.beta, "r": orc.rgb[:, 0], "g": orc.rgb[:, 1],
+           "b_": orc.rgb[:, 2], "depth": orc.depth}
+    both = vis & gvis
+    for name, col in RECORD_FIELDS:
+        g = gpu_rec[both, col].view(np.uint32)
+        r = ref[name][both].astype(np.float32).view(np.uint32)
+        out[name] = int((g != r).sum())
+    words = gpu_rec.view(np.uint32)
+    radius = (words[:, 12] & 0xFFFFFF).astype(np.int64)
+    flags = (words[:, 12] >> 24).astype(np.int64)
+    out["radius"] = int((radius[both] != orc.radius[both]).sum())
+    out["flags"] = int((flags[both] != orc.clamp_bits[both]).sum())
+    rect = np.stack([words[:, 13] & 0xFFFF, words[:, 13] >> 16, words[:, 14] & 0xFFFF, words[:, 14] >> 16], 1)
+    out["rect"] = int((rect[both] != orc.rect[both]).any(axis=1).sum())
+    out["tiles_touched"] = int((words[both, 15].astype(np.int64) != orc.tiles_touched[both]).sum())
+    return out
+
+
+def image_compare(gpu_img, orc_out, pixels_mask=None):
+    """Max error on unflagged pixels, and whether every flagged pixel matches one branch."""
+    ref, alt, fl = orc_out["img"], orc_out["alt"], orc_out["flags"].astype(bool)
+    if pixels_mask is None:
+        pixels_mask = np.ones(fl.shape, bool)
+    err = np.abs(gpu_img.astype(np.float64) - ref).max(axis=2)
+    unf = pixels_mask & ~fl
+    flagged = pixels_mask & fl
+    err_alt = np.abs(gpu_img.astype(np.float64) - alt).max(axis=2)
+    flag_ok = np.minimum(err, err_alt)[flagged]
+    return dict(max_err=float(err[unf].max()) if unf.any() else 0.0,
+                p99_err=float(np.percentile(err[unf], 99)) if unf.any() else 0.0,
+                flagged=int(flagged.sum()),
+                flagged_max_err=float(flag_ok.max()) if flagged.any() else 0.0)
+
+
+def grad_rel_err(g, r):
+    g = np.asarray(g, np.float64).ravel()
+    r = np.asarray(r, np.float64).ravel()
+    rms = np.sqrt(np.mean(r * r)) if r.size else 0.0
+    floor = max(GRAD_FLOOR * rms, 1e-30)
+    rel = np.abs(g - r) / np.maximum(np.abs(r), floor)
+    nrm = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
+    return dict(max=float(rel.max()) if rel.size else 0.0, p99=float(np.percentile(rel, 99)) if rel.size else 0.0,
+                norm=float(nrm))
+
+
+def grad2d_check(g, r, delta):
+    """2-D accumulators: error beyond the ambiguous-decision allowance, relative to max(|r|, floor)."""
+    g = np.asarray(g, np.float64)
+    r = np.asarray(r, np.float64)
+    floor = np.maximum(GRAD_FLOOR * np.sqrt(np.mean(r * r, axis=0, keepdims=True)), 1e-30)
+    excess = np.maximum(np.abs(g - r) - delta, 0.0) / np.maximum(np.abs(r), floor)
+    return dict(max=float(excess.max()) if excess.size else 0.0, ambiguous_entries=int((delta > 0).sum()))
+
+
+def ambiguous_splats(r2d, delta):
+    """Splats whose 2-D gradient may legitimately move by at least a tenth of the tolerance because of a
+    floating-point-ambiguous decision in one of their pixels (see grad2d_check).  Their parameter
+    gradients are reported but not held to the strict bound, since the allowance passes through the
+    preprocess chain rule unbounded by a simple per-component factor."""
+    floor = np.maximum(GRAD_FLOOR * np.sqrt(np.mean(r2d * r2d, axis=0, keepdims=True)), 1e-30)
+    return (delta > 0.1 * GRAD_RTOL * np.maximum(np.abs(r2d), floor)).any(axis=1)
+
+
+def oracle_full(arrays, sh_degree, cam, falloff=0, tile_cull=0, rho=0.1, bg=(0.0, 0.0, 0.0), dL=None):
+    orc = O.Oracle(arrays, sh_degree, cam, falloff=falloff, tile_cull=tile_cull, rho=rho, bg=bg)
+    rec = orc.preprocess(O.MODE_F32)
+    keys, vals, ranges = orc.build_keys(rec)
+    out = orc.render(rec, vals, ranges)
+    res = dict(orc=orc, rec=rec, keys=keys, values=vals, ranges=ranges, out=out)
+    if dL is not None:
+        g2d, delta, _ = orc.backward2d(rec, dL, vals, ranges, with_delta=True)
+        res["g2d"] = g2d
+        res["delta"] = delta
+        res["grads"] = PF.chain_to_params(arrays, sh_degree, cam, g2d, rec.tiles_touched > 0, rec.clamp_bits,
+                                          falloff, rho)
+    return res

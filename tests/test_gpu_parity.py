@@ -1,0 +1,155 @@
+"""GPU (HIP, through the C ABI) vs CPU oracle on the same seeded inputs.
+
+Sizes small enough for the oracle to finish in seconds while spanning several tiles, ragged image
+edges and both falloffs / tile rules.  Tolerances are defined in parity_helpers.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2402_10128_amd import synth
+
+from .parity_helpers import (GRAD_RTOL, IMG_ATOL, ambiguous_splats, gpu_render, grad2d_check, grad_rel_err,
+                             image_compare, oracle_full, record_mismatches)
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (name, workload, n, width, height, falloff, tile_cull)
+    ("w0_phi_square", 0, 1000, None, None, O.FALLOFF_PHI, O.TILES_SQUARE),
+    ("w0_gef_ellipse", 0, 1000, None, None, O.FALLOFF_GEF, O.TILES_ELLIPSE),
+    ("w0_phi_ellipse_ragged", 0, 800, 71, 45, O.FALLOFF_PHI, O.TILES_ELLIPSE),
+    ("w1_small_sh3", 1, 20000, 200, 136, O.FALLOFF_PHI, O.TILES_SQUARE),
+    ("w1_small_sh3_gef", 1, 20000, 200, 136, O.FALLOFF_GEF, O.TILES_ELLIPSE),
+]
+
+
+def _inputs(workload, n, w, h):
+    cfg = synth.make_config(workload, n_override=n)
+    sc, cam = cfg["scene"], cfg["camera"]
+    if w is not None:
+        cam = synth.pinhole(w, h, (0.0, 0.0, -4.0)) if workload == 0 else synth.orbit_camera(
+            np.random.default_rng(7), w, h)
+    return sc, cam
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_forward_parity(case):
+    name, wl, n, w, h, falloff, cull = case
+    sc, cam = _inputs(wl, n, w, h)
+    print(f"[parity] {name} n={n} {cam.width}x{cam.height}", flush=True)
+    gpu = gpu_render(sc.arrays(), sc.sh_degree, cam, falloff, cull)
+    ref = oracle_full(sc.arrays(), sc.sh_degree, cam, falloff, cull)
+    mm = record_mismatches(gpu["records"], ref["rec"])
+    print("  record mismatches", mm)
+    assert all(v == 0 for v in mm.values()), mm
+    assert gpu["num_keys"] == len(ref["keys"])
+    r = ref["ranges"]
+    assert np.array_equal(gpu["ranges"].astype(np.int64), r), "tile ranges differ"
+    assert np.array_equal(gpu["sorted_ids"], ref["values"]), "sorted order differs"
+    cmp = image_compare(gpu["img"], ref["out"])
+    print("  image", cmp)
+    assert cmp["max_err"] <= IMG_ATOL and cmp["flagged_max_err"] <= IMG_ATOL, cmp
+    fl = ref["out"]["flags"].astype(bool)
+    assert np.array_equal(gpu["n_contrib"][~fl], ref["out"]["n_contrib"][~fl].astype(np.uint32))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_backward_parity(case):
+    name, wl, n, w, h, falloff, cull = case
+    sc, cam = _inputs(wl, n, w, h)
+    dL = np.random.default_rng(99).standard_normal((cam.height, cam.width, 3)).astype(np.float32)
+    print(f"[parity-bwd] {name}", flush=True)
+    gpu = gpu_render(sc.arrays(), sc.sh_degree, cam, falloff, cull, dL=dL)
+    ref = oracle_full(sc.arrays(), sc.sh_degree, cam, falloff, cull, dL=dL.astype(np.float64))
+    # 2-D accumulators first (u, v, a, b, c, opacity, rgb, beta), within the allowance of decisions that
+    # binary32 may take either way (termination near 1e-4, alpha clamp near 0.99)
+    ncol = 10 if falloff == O.FALLOFF_GEF else 9
+    e2 = grad2d_check(gpu["grad2d"][:, :ncol], ref["g2d"][:, :ncol], ref["delta"][:, :ncol])
+    print("  grad2d", e2, "plain", grad_rel_err(gpu["grad2d"][:, :ncol], ref["g2d"][:, :ncol]))
+    amb = ambiguous_splats(ref["g2d"][:, :ncol], ref["delta"][:, :ncol])
+    print(f"  splats with an ambiguous decision: {int(amb.sum())} of {len(amb)}")
+    errs = {k: grad_rel_err(gpu["grads"][k][~amb], ref["grads"][k][~amb]) for k in gpu["grads"]}
+    for k, e in errs.items():
+        print(f"  d{k}: max {e['max']:.2e} p99 {e['p99']:.2e} norm {e['norm']:.2e}")
+    assert e2["max"] <= GRAD_RTOL, e2
+    for k, e in errs.items():
+        assert e["max"] <= GRAD_RTOL, (k, e)
+
+
+def test_empty_scene_renders_background():
+    cam = synth.pinhole(40, 33, (0.0, 0.0, -4.0))
+    arr = dict(means=np.zeros((0, 3), np.float32), log_scales=np.zeros((0, 3), np.float32),
+               quats=np.zeros((0, 4), np.float32), opacity_logits=np.zeros(0, np.float32),
+               sh=np.zeros((0, 1, 3), np.float32), beta=np.zeros(0, np.float32))
+    gpu = gpu_render(arr, 0, cam, bg=(0.25, 0.5, 0.75))
+    assert gpu["num_keys"] == 0
+    assert np.all(gpu["img"] == np.array([0.25, 0.5, 0.75], np.float32))
+
+
+def test_culled_and_degenerate_splats():
+    """NaN inputs, a zero quaternion, splats behind the camera and opacity below 1/255 are culled."""
+    sc, cam = _inputs(0, 64, None, None)
+    arr = {k: v.copy() for k, v in sc.arrays().items()}
+    arr["means"][0, 0] = np.nan
+    arr["quats"][1] = 0.0
+    arr["means"][2] = [0.0, 0.0, -10.0]
+    arr["opacity_logits"][3] = -8.0
+    arr["sh"][4, 0, 1] = np.inf
+    gpu = gpu_render(arr, 0, cam)
+    ref = oracle_full(arr, 0, cam)
+    assert np.all(gpu["records"][:5, 15].view(np.uint32) == 0)
+    mm = record_mismatches(gpu["records"], ref["rec"])
+    assert all(v == 0 for v in mm.values()), mm
+    cmp = image_compare(gpu["img"], ref["out"])
+    assert cmp["max_err"] <= IMG_ATOL
+
+
+def test_equal_depth_ties_sorted_by_index():
+    """Many splats at one depth: the per-tile order must break ties by splat index (long runs too)."""
+    rng = np.random.default_rng(3)
+    n = 300
+    means = np.zeros((n, 3), np.float32)
+    means[:, :2] = rng.uniform(-0.3, 0.3, (n, 2))
+    means[:, 2] = 0.0
+    cam = synth.Camera(48, 48, np.eye(3, dtype=np.float32), np.array([0, 0, 3.0], np.float32), 50.0, 50.0, 23.5,
+                       23.5, 0.2)
+    arr = dict(means=means, log_scales=rng.normal(-3.0, 0.3, (n, 3)).astype(np.float32),
+               quats=np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)),
+               opacity_logits=rng.normal(-1, 1, n).astype(np.float32),
+               sh=rng.uniform(-1, 1, (n, 1, 3)).astype(np.float32), beta=np.full(n, 2.0, np.float32))
+    gpu = gpu_render(arr, 0, cam)
+    ref = oracle_full(arr, 0, cam)
+    assert np.array_equal(gpu["sorted_ids"], ref["values"])
+    cmp = image_compare(gpu["img"], ref["out"])
+    assert cmp["max_err"] <= IMG_ATOL, cmp
+
+
+def test_long_tile_lists_global_sort_path():
+    """A tile list longer than the LDS capacity (4096) goes through the global-memory sort."""
+    rng = np.random.default_rng(5)
+    n = 9000
+    means = np.zeros((n, 3), np.float32)
+    means[:, :2] = rng.uniform(-0.02, 0.02, (n, 2))
+    means[:, 2] = rng.uniform(-0.5, 0.5, n)
+    cam = synth.Camera(32, 32, np.eye(3, dtype=np.float32), np.array([0, 0, 4.0], np.float32), 40.0, 40.0, 15.5,
+                       15.5, 0.2)
+    arr = dict(means=means, log_scales=np.full((n, 3), -4.0, np.float32),
+               quats=np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)),
+               opacity_logits=np.full(n, -3.0, np.float32),
+               sh=rng.uniform(-1, 1, (n, 1, 3)).astype(np.float32), beta=np.full(n, 2.0, np.float32))
+    gpu = gpu_render(arr, 0, cam)
+    ref = oracle_full(arr, 0, cam)
+    lens = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+    assert lens.max() > 4096
+    assert np.array_equal(gpu["sorted_ids"], ref["values"])
+    cmp = image_compare(gpu["img"], ref["out"])
+    assert cmp["max_err"] <= IMG_ATOL, cmp
+
+
+def test_forward_is_deterministic():
+    sc, cam = _inputs(1, 20000, 200, 136)
+    a = gpu_render(sc.arrays(), 3, cam)
+    b = gpu_render(sc.arrays(), 3, cam)
+    assert np.array_equal(a["img"], b["img"])
+    assert np.array_equal(a["sorted_ids"], b["sorted_ids"])
