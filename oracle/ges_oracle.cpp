@@ -188,12 +188,13 @@ void sh_basis(S x, S y, S z, int degree, S* Y) {
 // form over the tile's box of pixel centres, less a rounding allowance of 1e-3 times the magnitude of
 // its terms, does not exceed q_max.  The minimum over a box lies at an interior point only if the
 // centre is inside; otherwise on one of the four edges, where it is a 1-D quadratic minimised at the
-// clamped stationary point.
+// clamped stationary point -b e / c (resp. -b e / a), evaluated with the reciprocals 1/c and 1/a
+// formed once per splat.
 // ------------------------------------------------------------------------------------------------
 template <class S>
-S edge_min(S a, S b, S c, S e, S lo, S hi) {
+S edge_min(S a, S b, S c, S inv_c, S e, S lo, S hi) {
   S y = b * e;
-  y = y / c;
+  y = y * inv_c;
   y = -y;
   y = std::max(y, lo);
   y = std::min(y, hi);
@@ -213,10 +214,11 @@ bool ellipse_hits_tile(S u, S v, S a, S b, S c, S qm, int tx, int ty, int W, int
   S y0 = (S)(ty * OC_TILE), y1 = (S)std::min(ty * OC_TILE + OC_TILE - 1, H - 1);
   S dxlo = u - x1, dxhi = u - x0, dylo = v - y1, dyhi = v - y0;
   if (dxlo <= (S)0 && dxhi >= (S)0 && dylo <= (S)0 && dyhi >= (S)0) return true;
-  S m1 = edge_min(a, b, c, dxlo, dylo, dyhi);
-  S m2 = edge_min(a, b, c, dxhi, dylo, dyhi);
-  S m3 = edge_min(c, b, a, dylo, dxlo, dxhi);
-  S m4 = edge_min(c, b, a, dyhi, dxlo, dxhi);
+  const S inv_a = (S)1 / a, inv_c = (S)1 / c;
+  S m1 = edge_min(a, b, c, inv_c, dxlo, dylo, dyhi);
+  S m2 = edge_min(a, b, c, inv_c, dxhi, dylo, dyhi);
+  S m3 = edge_min(c, b, a, inv_a, dylo, dxlo, dxhi);
+  S m4 = edge_min(c, b, a, inv_a, dyhi, dxlo, dxhi);
   S m = std::min(std::min(m1, m2), std::min(m3, m4));
   return m <= qm;
 }
