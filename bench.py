@@ -1,0 +1,288 @@
+#!/usr/bin/env python3
+"""Benchmark of the GES rasterizer on one MI355X.
+
+A step is one pass of the whole hot path over one frame: preprocess (with the key-count readback),
+tile binning, per-tile sort, forward raster, the frequency-masked L1 loss and its gradient, the
+reverse-order adjoint raster and the preprocess backward.  The default workload is the 3M-splat
+1920x1080 training step (64 clusters, SH degree 3, loss 0.5 L1 + 0.5 masked L1 at omega = 0.75,
+mask made once outside the timed region); inputs are synthetic and already resident in HBM.
+
+Prints ONE JSON line.  Per-kernel times come from HIP events recorded around every launch on the
+stream the kernel runs on (library stage timing), over the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector peak (packed FMA)
+
+# Floating-point operations per pair of the raster (FMA = 2), see DESIGN.md "Rooflines":
+FWD_FLOP_EXAMINED = 9          # dx, dy, quadratic form
+FWD_FLOP_BLENDED = {0: 12, 1: 15}   # falloff, alpha, transmittance, colour (PHI, GEF)
+BWD_FLOP_EXAMINED = 9
+BWD_FLOP_BLENDED = {0: 51, 1: 60}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", type=int, default=2, choices=[0, 1, 2, 3])
+    ap.add_argument("--tile-cull", choices=["square", "ellipse"], default="ellipse")
+    ap.add_argument("--falloff", choices=["phi", "gef"], default="phi")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for scaling rocprof FETCH/WRITE counters)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(stage, n, sh_coeffs, K, tiles, bin_blocks, px, ellipse):
+    """Minimum HBM bytes of one launch of an HBM-bound stage (rooflines)."""
+    splat_in = 12 + 12 + 16 + 4 + 4 + 12 * sh_coeffs
+    rec_tile_read = 48 if ellipse else 16
+    table = 4 * bin_blocks * tiles
+    return {
+        "preprocess": n * (splat_in + 64),
+        "bin_count": n * rec_tile_read + table,
+        "bin_scan": 2 * table + 12 * tiles,
+        "bin_scatter": n * (rec_tile_read + 16) + table + 8 * K,
+        "tile_sort": 12 * K,
+        "preprocess_backward": n * (16 + 12 + 16 + 4 + 12 * sh_coeffs + 48 + 80 + 4 * (3 + 3 + 4 + 1 + 1 + 3 * sh_coeffs)),
+        "zero": 96 * n,
+        "loss": 37 * px,
+    }.get(stage)
+
+
+def kernel_source_hash(stage):
+    src = {"raster_forward": "raster.hip", "raster_backward": "raster.hip", "preprocess": "preprocess.hip",
+           "preprocess_backward": "preprocess.hip", "tile_sort": "tile_sort.hip", "bin_count": "binning.hip",
+           "bin_scatter": "binning.hip", "bin_scan": "binning.hip", "loss": "loss.hip", "zero": "loss.hip"}[stage]
+    with open(os.path.join(HERE, "paper_2402_10128_amd", "csrc", src), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(stage, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches this source."""
+    path = os.path.join(HERE, "profiles", f"{stage}_counters_workload{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_sha256_16") != kernel_source_hash(stage):
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg, falloff, tile_cull, budget_tiles=160):
+    """The oracle on this host: full per-splat preprocess, forward+backward of a sample of tiles,
+    binary64 chain rule on a splat subset; extrapolated to one full frame."""
+    import torch
+    from oracle import oracle as O
+    from oracle import preprocess_f64 as PF
+    sc, cam = cfg["scene"], cfg["camera"]
+    arr = sc.arrays()
+    n = sc.n
+    orc = O.Oracle(arr, sc.sh_degree, cam, falloff=falloff, tile_cull=tile_cull)
+    t0 = time.perf_counter()
+    rec = orc.preprocess(O.MODE_F32)
+    t_pre = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    T = orc.TX * orc.TY
+    tiles = np.sort(rng.choice(T, size=min(budget_tiles, T), replace=False)).astype(np.int32)
+    t0 = time.perf_counter()
+    vals, ranges = [], np.zeros((T, 2), np.int64)
+    pos = 0
+    for t in tiles:
+        lst = orc.tile_list(rec, int(t))
+        ranges[t] = (pos, pos + len(lst))
+        pos += len(lst)
+        vals.append(lst)
+    values = np.concatenate(vals) if vals else np.zeros(0, np.uint32)
+    t_lists = time.perf_counter() - t0
+    dL = np.random.default_rng(1).standard_normal((cam.height, cam.width, 3))
+    t0 = time.perf_counter()
+    orc.render(rec, values, ranges, tiles=tiles)
+    orc.backward2d(rec, dL, values, ranges, tiles=tiles)
+    t_tiles = time.perf_counter() - t0
+    sub = min(n, 200_000)
+    sub_arr = {k: v[:sub] for k, v in arr.items()}
+    g2d = np.random.default_rng(2).standard_normal((sub, 10))
+    torch.set_num_threads(O.num_threads())
+    t0 = time.perf_counter()
+    PF.chain_to_params(sub_arr, sc.sh_degree, cam, g2d, rec.tiles_touched[:sub] > 0, rec.clamp_bits[:sub],
+                       falloff, 0.1)
+    t_chain = (time.perf_counter() - t0) * (n / sub)
+    frac = len(tiles) / T
+    t_full = t_pre + (t_lists + t_tiles) / frac + t_chain
+    px = cam.width * cam.height
+    return {"value": round(px / t_full / 1e6, 5), "unit": "Mpix/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": (f"full per-splat preprocess of {n} splats ({t_pre:.1f}s); per-pixel forward+backward and "
+                       f"list building on {len(tiles)} random tiles of {T} ({t_lists + t_tiles:.1f}s, scaled by "
+                       f"{T}/{len(tiles)}); binary64 chain rule on {sub} splats ({t_chain * sub / n:.1f}s, scaled by "
+                       f"{n}/{sub}); estimated full frame {t_full:.1f}s")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import torch
+    from paper_2402_10128_amd import ges as G
+    from paper_2402_10128_amd import synth
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    G.lib()
+    dev = torch.device("cuda:0")
+    falloff = 0 if args.falloff == "phi" else 1
+    tile_cull = 0 if args.tile_cull == "square" else 1
+    log(f"generating workload {args.workload}")
+    cfg = synth.make_config(args.workload)
+    sc, cam = cfg["scene"], cfg["camera"]
+    t = {k: torch.as_tensor(v).to(dev) for k, v in sc.arrays().items()}
+    target = torch.as_tensor(cfg["target"]).to(dev)
+    W, H = cam.width, cam.height
+    s = G.splats_struct(t["means"], t["log_scales"], t["quats"], t["opacity_logits"], t["sh"], t["beta"])
+    c = G.camera_struct(cam)
+    p = G.params_struct(falloff, tile_cull, 0.1, (0.0, 0.0, 0.0))
+    frame = G.Frame.create(s.n, W, H, dev)
+    masked = cfg.get("loss") == "l1+freq"
+    mask = G.ges_freq_mask(target, cfg.get("omega", 0.75)) if masked else None
+    lam_l1, lam_w = (0.5, 0.5) if masked else (1.0, 0.0)
+    out = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    dL = torch.empty_like(out)
+    loss = torch.empty((), dtype=torch.float32, device=dev)
+    loss_scratch = torch.empty(G.lib().ges_loss_scratch_bytes(), dtype=torch.uint8, device=dev)
+    grads = {k: torch.empty_like(v) for k, v in t.items()}
+
+    def step():
+        k = G.ges_preprocess(s, c, p, frame.splat_ws, True)
+        frame.ensure_keys(k)
+        G.ges_render_forward(s, c, p, frame.splat_ws, frame.key_ws, k, frame.pixel_ws, out)
+        G.ges_loss(out, target, mask, lam_l1, lam_w, dL, loss, loss_scratch)
+        G.ges_render_backward(s, c, p, frame.splat_ws, frame.key_ws, frame.pixel_ws, dL, grads)
+        return k
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    G.ges_profile_enable(True)
+    G.ges_profile_read(reset=True)
+    log(f"timing {args.steps} steps")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    t_host0 = time.perf_counter()
+    for i in range(args.steps):
+        K = step()
+    ev1.record()
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host0
+    ms_total = ev0.elapsed_time(ev1)
+    stages = G.ges_profile_read(reset=True)
+    G.ges_profile_enable(False)
+    ms_step = ms_total / args.steps
+    mpix = W * H / (ms_step / 1e3) / 1e6
+    fa = G.frame_arrays(frame, s.n)
+    pairs_exam, pairs_blend = int(fa["stats"][2]), int(fa["stats"][3])
+    bwd_walk = int(fa["n_contrib"].astype(np.int64).sum())
+    log(f"{ms_step:.3f} ms/step  {mpix:.1f} Mpix/s  K={K}  host {t_host / args.steps * 1e3:.2f} ms/step")
+
+    per_stage = {}
+    for name, (ms, nl) in stages.items():
+        if nl:
+            per_stage[name] = round(ms / nl, 4)
+    log("stage ms/launch: " + json.dumps(per_stage))
+    dominant = max(per_stage, key=per_stage.get)
+    avg_ms = per_stage[dominant]
+    n, sh_k = s.n, (sc.sh_degree + 1) ** 2
+    fp = frame
+    T = ((W + 15) // 16) * ((H + 15) // 16)
+    bin_blocks = max(1, min(256, (n + 8191) // 8192))
+    if dominant in ("raster_forward", "raster_backward"):
+        if dominant == "raster_forward":
+            flop = FWD_FLOP_EXAMINED * pairs_exam + FWD_FLOP_BLENDED[falloff] * pairs_blend
+        else:
+            flop = BWD_FLOP_EXAMINED * bwd_walk + BWD_FLOP_BLENDED[falloff] * pairs_blend
+        achieved = flop / (avg_ms / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "kernel": dominant,
+                "algorithmic_flop_per_launch": flop}
+    else:
+        nbytes = algorithmic_bytes(dominant, n, sh_k, K, T, bin_blocks, W * H, tile_cull == 1)
+        achieved = nbytes / (avg_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": dominant, "algorithmic_bytes_per_launch": nbytes}
+    roof["traffic"] = read_traffic(dominant, args.workload)
+    roof["avg_launch_ms"] = avg_ms
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
+        try:
+            cpu = cpu_baseline(cfg, falloff, tile_cull)
+        except Exception as e:  # reported, never silently replaced
+            cpu = {"error": repr(e)}
+
+    names = {0: "1k splats 64x64", 1: "1M splats 1600x1040", 2: "3M splats 1920x1080 training step",
+             3: "5M splats 1920x1080 heavy overlap"}
+    res = {
+        "metric": "fwd+bwd Mpix/s at 3M splats 1080p",
+        "value": round(mpix, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": names[args.workload], "splats": n, "width": W, "height": H,
+                   "sh_degree": sc.sh_degree, "falloff": args.falloff, "tile_cull": args.tile_cull,
+                   "loss": cfg.get("loss"), "num_keys": K, "pairs_examined_fwd": pairs_exam,
+                   "pairs_composited": pairs_blend, "stage_ms_per_launch": per_stage},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

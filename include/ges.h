@@ -155,7 +155,8 @@ typedef struct {
   const uint32_t* bucket_pairs;  /* [num_keys,2] (depth bits, splat index) in tile order, unsorted within a tile */
   const float* final_T;          /* [height,width] (after ges_render_forward) */
   const uint32_t* n_contrib;     /* [height,width] list position + 1 of the last composited splat */
-  const float* grad2d;           /* [n,12] dL/d(u,v,a,b,c,opacity,r,g,b,beta) (after ges_render_backward) */
+  const double* grad2d;          /* [n,12] dL/d(u,v,a,b,c,opacity,r,g,b,beta), binary64 (after ges_render_backward) */
+  const uint64_t* stats;         /* [4]: keys, -, pairs examined, pairs composited (after ges_render_forward) */
   int32_t tiles_x, tiles_y;
 } ges_frame_view;
 /* Record layout, 16 x 32-bit words per splat:
@@ -165,6 +166,18 @@ typedef struct {
  *   flags: bit0..2 colour channel clamped at 0, bit3/4 x/y guard clamp. */
 ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* splat_ws, void* key_ws,
                               uint64_t num_keys, void* pixel_ws, ges_frame_view* out);
+
+/* ---- stage timing (benchmarks) -----------------------------------------------------
+ * When enabled, every kernel launch of the render path is bracketed by two HIP events
+ * recorded on the stream it runs on; ges_profile_read waits for the recorded events
+ * and returns the accumulated device milliseconds and launch counts per stage
+ * (indices GES_STAGE_*), then optionally clears them.  Off by default; enabling it
+ * costs two event records per launch. */
+enum { GES_STAGE_PREPROCESS = 0, GES_STAGE_BIN_COUNT, GES_STAGE_BIN_SCAN, GES_STAGE_BIN_SCATTER, GES_STAGE_TILE_SORT,
+       GES_STAGE_RASTER_FORWARD, GES_STAGE_RASTER_BACKWARD, GES_STAGE_PREPROCESS_BACKWARD, GES_STAGE_ZERO,
+       GES_STAGE_LOSS, GES_NUM_STAGES };
+ges_status ges_profile_enable(int32_t on);
+ges_status ges_profile_read(double* ms /*[GES_NUM_STAGES]*/, int64_t* launches /*[GES_NUM_STAGES]*/, int32_t reset);
 
 /* ---- frequency-modulated loss (Sec. 4.3) ------------------------------------------
  * Mask M_omega = 1(|DoG_omega(grey(target))| / max > 0.5) computed on the target
@@ -212,6 +225,13 @@ typedef struct {
 /* pool: caller-owned device buffer the server sub-allocates all per-request
  * workspaces from (the admission budget). */
 ges_status ges_serve_create(const ges_serve_config* cfg, void* pool, size_t pool_bytes, ges_server** out);
+/* Host-only variant for testing the scheduler without a GPU: the executor never touches device
+ * memory; every view of a batch produces keys_per_view keys, a batch takes batch_ns + per_view_ns
+ * per view, and batches holding a request for scene fail_scene fail with GES_ERR_DEVICE.  The pool
+ * of pool_bytes is accounted but never dereferenced. */
+ges_status ges_serve_create_simulated(const ges_serve_config* cfg, size_t pool_bytes, uint64_t keys_per_view,
+                                      uint64_t batch_ns, uint64_t per_view_ns, int32_t fail_scene,
+                                      ges_server** out);
 /* The scene's device buffers must stay alive and unchanged until ges_serve_destroy. */
 ges_status ges_serve_add_scene(ges_server* s, const ges_splats* scene, int32_t* scene_id);
 /* Queue a render of scene_id from cam into out_rgb_device [h,w,3] FP32.  Returns BUSY when

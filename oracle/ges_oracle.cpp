@@ -734,7 +734,7 @@ void pixel_grads(const oc_params* p, const Splat2D* L, const std::vector<Contrib
 }
 
 void pixel_backward(int mode, const oc_params* p, const Splat2D* L, const uint32_t* ids, int64_t len, int px,
-                    int py, const double g[3], double* g2d, double* delta, int64_t* examined) {
+                    int py, const double g[3], double* g2d, double* delta, double* mass, int64_t* examined) {
   std::vector<Contrib> cs;
   std::vector<PixelGrad> prim, alt;
   double tm, cm;
@@ -746,6 +746,14 @@ void pixel_backward(int mode, const oc_params* p, const Splat2D* L, const uint32
     for (int k = 0; k < 10; ++k) {
 #pragma omp atomic
       gs[k] += pg.v[k];
+    }
+    if (mass) {
+      double* ms = mass + 10 * (int64_t)ids[pg.j];
+      for (int k = 0; k < 10; ++k) {
+        const double a = std::fabs(pg.v[k]);
+#pragma omp atomic
+        ms[k] += a;
+      }
     }
   }
   if (!delta) return;
@@ -962,7 +970,7 @@ int oc_render_untiled(int mode, const oc_record* r, int64_t n, const oc_camera* 
 }
 
 int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera* cam, const oc_params* p,
-                        const double* dL_dimg, double* g2d, double* delta, oc_stats* stats) {
+                        const double* dL_dimg, double* g2d, double* delta, double* mass, oc_stats* stats) {
   std::vector<uint32_t> ids;
   for (int64_t i = 0; i < n; ++i)
     if (r->tiles_touched[i] > 0) ids.push_back((uint32_t)i);
@@ -977,7 +985,8 @@ int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera
   for (int py = 0; py < cam->height; ++py)
     for (int px = 0; px < cam->width; ++px) {
       const int64_t pix = (int64_t)py * cam->width + px;
-      pixel_backward(mode, p, L.data(), ids.data(), (int64_t)L.size(), px, py, dL_dimg + 3 * pix, g2d, delta, &tot);
+      pixel_backward(mode, p, L.data(), ids.data(), (int64_t)L.size(), px, py, dL_dimg + 3 * pix, g2d, delta, mass,
+                     &tot);
     }
   if (stats) { std::memset(stats, 0, sizeof(*stats)); stats->pairs_examined = tot; }
   return 0;
@@ -985,7 +994,7 @@ int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera
 
 int oc_backward(int mode, const oc_record* r, int64_t n, const oc_camera* cam, const oc_params* p,
                 const uint32_t* values, const int64_t* ranges, const int32_t* tiles, int64_t n_tiles,
-                const double* dL_dimg, double* g2d, double* delta, oc_stats* stats) {
+                const double* dL_dimg, double* g2d, double* delta, double* mass, oc_stats* stats) {
   (void)n;
   const int TX = tiles_x(cam), TY = tiles_y(cam);
   const int64_t nt = tiles ? n_tiles : (int64_t)TX * TY;
@@ -1005,7 +1014,7 @@ int oc_backward(int mode, const oc_record* r, int64_t n, const oc_camera* cam, c
       for (int py = y0; py <= y1; ++py)
         for (int px = x0; px <= x1; ++px) {
           const int64_t pix = (int64_t)py * cam->width + px;
-          pixel_backward(mode, p, L.data(), values + s0, s1 - s0, px, py, dL_dimg + 3 * pix, g2d, delta, &ex);
+          pixel_backward(mode, p, L.data(), values + s0, s1 - s0, px, py, dL_dimg + 3 * pix, g2d, delta, mass, &ex);
         }
     }
 #pragma omp critical

@@ -154,6 +154,33 @@ def chain_to_params(arrays: dict, sh_degree: int, cam, g2d: np.ndarray, visible:
     return res
 
 
+def abs_chain(arrays: dict, sh_degree: int, cam, a2d: np.ndarray, visible: np.ndarray, clamp_bits,
+              falloff: int = 0, rho: float = 0.1) -> dict:
+    """|J|^T a per splat: the bound on how far parameter gradients can move when each 2-D gradient
+    component k of a splat is uncertain by a2d[:, k] >= 0.  Splats are independent, so one backward
+    pass per 2-D component (unit weight on that component of every splat) yields every splat's
+    Jacobian row for that component."""
+    P = to_params(arrays, requires_grad=True)
+    out = preprocess(P, sh_degree, cam, falloff, rho, clamp_bits)
+    cols = [out["u"], out["v"], out["a"], out["b"], out["c"], out["opacity"], out["rgb"][:, 0], out["rgb"][:, 1],
+            out["rgb"][:, 2], out["beta"]]
+    vis = torch.as_tensor(visible.astype(np.float64))
+    res = {k: np.zeros(P[k].shape) for k in P}
+    ncol = 10 if falloff == 1 else 9
+    for k in range(ncol):
+        total = (torch.nan_to_num(cols[k]) * vis).sum()
+        grads = torch.autograd.grad(total, [P[q] for q in P], retain_graph=True, allow_unused=True)
+        w = a2d[:, k]
+        for name, gr in zip(P, grads):
+            if gr is None:
+                continue
+            J = np.abs(gr.detach().numpy())
+            res[name] += J * w.reshape((-1,) + (1,) * (J.ndim - 1))
+    for name in res:
+        res[name][~visible.astype(bool)] = 0.0
+    return res
+
+
 def record_from(out: dict, base_record):
     """A binary64 record (for the C++ renderer) whose continuous fields come from ``out`` and whose
     decisions (visibility, rect, clamp bits) come from ``base_record``."""

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libges.so")
-SOURCES = ["preprocess.hip", "binning.hip", "tile_sort.hip", "raster.hip", "loss.hip", "abi.cpp", "serve.cpp"]
+SOURCES = ["preprocess.hip", "preprocess_bwd.hip", "binning.hip", "tile_sort.hip", "raster.hip", "loss.hip", "abi.cpp",
+           "serve.cpp"]
 ARCH = os.environ.get("GES_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off plus correctly rounded division/sqrt and IEEE denormals: the preprocess and the
@@ -20,11 +21,19 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
 
 
+# Files whose results feed no integer decision may contract and divide fast.
+RELAXED = {"preprocess_bwd.hip": ["-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt"]}
+
+
 def _compile(src: str) -> str:
     out = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = ["hipcc", *FLAGS, *lang, "-c", path, "-o", out]
+    flags = list(FLAGS)
+    if src in RELAXED:
+        flags = [f for f in flags if f not in ("-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt")]
+        flags += RELAXED[src]
+    cmd = ["hipcc", *flags, *lang, "-c", path, "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     err = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if noise not in l and "ignoring feature" not in l)

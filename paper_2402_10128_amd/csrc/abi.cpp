@@ -4,7 +4,9 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "frame.h"
 #include "ges_internal.h"
@@ -29,6 +31,44 @@ ges_status device_fail(hipError_t e, const char* where) {
     hipError_t e_ = (expr);                        \
     if (e_ != hipSuccess) return device_fail(e_, where); \
   } while (0)
+
+// ---- stage timing: event pairs recorded around launches while profiling is on
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> free_events;
+  struct Pending { int stage; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double ms[GES_NUM_STAGES] = {};
+  int64_t launches[GES_NUM_STAGES] = {};
+
+  hipEvent_t get() {
+    if (!free_events.empty()) { hipEvent_t e = free_events.back(); free_events.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Profiler g_prof;
+
+template <class F>
+hipError_t timed(int stage, hipStream_t stream, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (g_prof.on) { a = g_prof.get(); b = g_prof.get(); }
+  }
+  if (a) { hipError_t e = hipEventRecord(a, stream); if (e != hipSuccess) return e; }
+  hipError_t e = launch();
+  if (e != hipSuccess) return e;
+  if (a && b) {
+    e = hipEventRecord(b, stream);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.pending.push_back({stage, a, b});
+  }
+  return hipSuccess;
+}
 
 // Build the single-view batch of a frame and copy it into the splat workspace.
 hipError_t upload_single_view(const ges_splats* s, const ges_camera* c, const ges_raster_params* p,
@@ -116,9 +156,9 @@ ges_status ges_preprocess(const ges_splats* splats, const ges_camera* cam, const
   GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, nullptr, nullptr, nullptr, stream), "upload");
   const ges::Batch b = single_batch(splats, params, fp, splat_ws);
   const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
-  GES_CHECK_HIP(ges::launch_preprocess(db, b, stream), "preprocess");
-  GES_CHECK_HIP(ges::launch_bin_count(db, b, stream), "bin_count");
-  GES_CHECK_HIP(ges::launch_bin_scan(db, b, nullptr, stream), "bin_scan");
+  GES_CHECK_HIP(timed(GES_STAGE_PREPROCESS, stream, [&] { return ges::launch_preprocess(db, b, stream); }), "preprocess");
+  GES_CHECK_HIP(timed(GES_STAGE_BIN_COUNT, stream, [&] { return ges::launch_bin_count(db, b, stream); }), "bin_count");
+  GES_CHECK_HIP(timed(GES_STAGE_BIN_SCAN, stream, [&] { return ges::launch_bin_scan(db, b, nullptr, stream); }), "bin_scan");
   if (num_keys_host) {
     uint32_t k = 0;
     GES_CHECK_HIP(hipMemcpyAsync(&k, b.keys_total, 4, hipMemcpyDeviceToHost, stream), "read num_keys");
@@ -150,9 +190,9 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
     b.sorted_ids = reinterpret_cast<uint32_t*>(kw + kp.off_sorted);
   }
   const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
-  GES_CHECK_HIP(ges::launch_bin_scatter(db, b, stream), "bin_scatter");
-  GES_CHECK_HIP(ges::launch_tile_sort(db, b, stream), "tile_sort");
-  GES_CHECK_HIP(ges::launch_raster_forward(db, b, stream), "raster_forward");
+  GES_CHECK_HIP(timed(GES_STAGE_BIN_SCATTER, stream, [&] { return ges::launch_bin_scatter(db, b, stream); }), "bin_scatter");
+  GES_CHECK_HIP(timed(GES_STAGE_TILE_SORT, stream, [&] { return ges::launch_tile_sort(db, b, stream); }), "tile_sort");
+  GES_CHECK_HIP(timed(GES_STAGE_RASTER_FORWARD, stream, [&] { return ges::launch_raster_forward(db, b, stream); }), "raster_forward");
   return GES_OK;
 }
 
@@ -169,10 +209,12 @@ ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, 
   // the sorted ids of the forward pass; ranges bound every access, so the capacity is not needed here
   if (key_ws) b.sorted_ids = reinterpret_cast<uint32_t*>(key_ws);   // KeyPlan::off_sorted == 0
   const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
-  GES_CHECK_HIP(ges::launch_zero(reinterpret_cast<char*>(splat_ws) + fp.off_grad,
-                                 (size_t)splats->n * ges::kGradStride * 4, stream), "zero grad2d");
-  GES_CHECK_HIP(ges::launch_raster_backward(db, b, stream), "raster_backward");
-  GES_CHECK_HIP(ges::launch_preprocess_backward(db, b, grads, stream), "preprocess_backward");
+  GES_CHECK_HIP(timed(GES_STAGE_ZERO, stream, [&] {
+                  return ges::launch_zero(reinterpret_cast<char*>(splat_ws) + fp.off_grad,
+                                          (size_t)splats->n * ges::kGradStride * 8, stream);
+                }), "zero grad2d");
+  GES_CHECK_HIP(timed(GES_STAGE_RASTER_BACKWARD, stream, [&] { return ges::launch_raster_backward(db, b, stream); }), "raster_backward");
+  GES_CHECK_HIP(timed(GES_STAGE_PREPROCESS_BACKWARD, stream, [&] { return ges::launch_preprocess_backward(db, b, grads, stream); }), "preprocess_backward");
   return GES_OK;
 }
 
@@ -186,7 +228,8 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
   std::memset(out, 0, sizeof(*out));
   out->records = reinterpret_cast<const float*>(sw + fp.off_rec);
   out->tile_ranges = reinterpret_cast<const uint32_t*>(sw + fp.off_ranges);
-  out->grad2d = reinterpret_cast<const float*>(sw + fp.off_grad);
+  out->grad2d = reinterpret_cast<const double*>(sw + fp.off_grad);
+  out->stats = reinterpret_cast<const uint64_t*>(sw + fp.off_hdr);
   if (key_ws) {
     const ges::KeyPlan kp = ges::plan_keys(num_keys);
     char* kw = reinterpret_cast<char*>(key_ws);
@@ -200,6 +243,32 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
   }
   out->tiles_x = fp.tiles_x;
   out->tiles_y = fp.tiles_y;
+  return GES_OK;
+}
+
+ges_status ges_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+  return GES_OK;
+}
+
+ges_status ges_profile_read(double* ms, int64_t* launches, int32_t reset) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (auto& p : g_prof.pending) {
+    GES_CHECK_HIP(hipEventSynchronize(p.b), "profile sync");
+    float t = 0.f;
+    GES_CHECK_HIP(hipEventElapsedTime(&t, p.a, p.b), "profile elapsed");
+    g_prof.ms[p.stage] += t;
+    g_prof.launches[p.stage] += 1;
+    g_prof.free_events.push_back(p.a);
+    g_prof.free_events.push_back(p.b);
+  }
+  g_prof.pending.clear();
+  for (int k = 0; k < GES_NUM_STAGES; ++k) {
+    if (ms) ms[k] = g_prof.ms[k];
+    if (launches) launches[k] = g_prof.launches[k];
+    if (reset) { g_prof.ms[k] = 0.0; g_prof.launches[k] = 0; }
+  }
   return GES_OK;
 }
 
@@ -225,9 +294,11 @@ ges_status ges_loss(const float* img, const float* target, const uint8_t* mask, 
   if (!img || !target || !scratch || !loss_out || !dL_dimg) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
   if (width < 1 || height < 1 || width > 16384 || height > 16384) return fail(GES_ERR_INVALID_ARGUMENT, "bad sizes");
   if (!std::isfinite(lam_l1) || !std::isfinite(lam_w)) return fail(GES_ERR_INVALID_ARGUMENT, "non-finite weight");
-  GES_CHECK_HIP(ges::launch_loss(img, target, mask, width, height, lam_l1, mask ? lam_w : 0.f, scratch, loss_out,
-                                 dL_dimg, reinterpret_cast<hipStream_t>(stream)),
-                "loss");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  GES_CHECK_HIP(timed(GES_STAGE_LOSS, st, [&] {
+                  return ges::launch_loss(img, target, mask, width, height, lam_l1, mask ? lam_w : 0.f, scratch,
+                                          loss_out, dL_dimg, st);
+                }), "loss");
   return GES_OK;
 }
 

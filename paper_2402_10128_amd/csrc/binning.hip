@@ -12,34 +12,119 @@
 //   4. bin_scatter: each block re-walks its chunk and writes (depth bits, splat index) into its own
 //                   sub-range of every tile's bucket, using LDS cursors.
 // The order inside a bucket is arbitrary; the per-tile sort makes it unique.
+// Load balance: rectangles of up to 16 tiles are walked by one thread, larger ones by a whole wave, so
+// the heavy tail of near, large splats does not serialise a wave behind one lane.
 // HBM: 16-48 B read per splat and 8 B written per pair, plus the G x T count table.
 #include "ges_internal.h"
 #include "tile_geom.h"
 
 namespace ges {
 
+constexpr int kSmallArea = 16;   // rectangles of up to this many tiles are walked by one thread
+
 struct SplatTiles {
-  int tx0, ty0, tx1, ty1;
-  float u, v, a, b, c, qm;
-  bool ellipse;
+  int tx0, ty0, tx1, ty1, rw;
+  uint32_t area;
+  float u, v, a, b, c, qm, inv_a, inv_c;
+  uint32_t depth_bits;
 };
 
-__device__ __forceinline__ bool load_splat_tiles(const ViewDesc& V, int64_t i, SplatTiles& s, uint32_t& depth_bits) {
+// Rectangle (and, for ELLIPSE, the conic) of splat i; area 0 for culled splats.
+__device__ __forceinline__ void load_splat_tiles(const ViewDesc& V, int64_t i, bool ellipse, SplatTiles& s) {
   const float4 r3 = V.rec[4 * i + 3];
-  if (__float_as_uint(r3.w) == 0) return false;
   const uint32_t lo = __float_as_uint(r3.y), hi = __float_as_uint(r3.z);
   s.tx0 = (int)(lo & 0xffffu); s.ty0 = (int)(lo >> 16);
   s.tx1 = (int)(hi & 0xffffu); s.ty1 = (int)(hi >> 16);
-  s.ellipse = V.tile_cull == GES_TILES_ELLIPSE;
-  const float4 r0 = V.rec[4 * i + 0];
-  const float4 r1 = V.rec[4 * i + 1];
-  s.u = r0.x; s.v = r0.y; s.a = r0.z; s.b = r0.w; s.c = r1.x; s.qm = r1.y;
-  depth_bits = __float_as_uint(V.rec[4 * i + 2].w);
-  return true;
+  s.rw = s.tx1 - s.tx0 + 1;
+  s.area = __float_as_uint(r3.w) == 0 ? 0u : (uint32_t)(s.rw * (s.ty1 - s.ty0 + 1));
+  s.depth_bits = __float_as_uint(V.rec[4 * i + 2].w);
+  if (ellipse && s.area) {
+    const float4 r0 = V.rec[4 * i + 0];
+    const float4 r1 = V.rec[4 * i + 1];
+    s.u = r0.x; s.v = r0.y; s.a = r0.z; s.b = r0.w; s.c = r1.x; s.qm = r1.y;
+    s.inv_a = 1.0f / s.a;
+    s.inv_c = 1.0f / s.c;
+  }
 }
 
-__device__ __forceinline__ bool tile_hit(const SplatTiles& s, const ViewDesc& V, int tx, int ty) {
-  return !s.ellipse || ellipse_hits_tile(s.u, s.v, s.a, s.b, s.c, s.qm, tx, ty, V.width, V.height);
+__device__ __forceinline__ uint32_t rect_area(const ViewDesc& V, int64_t i) {
+  const float4 r3 = V.rec[4 * i + 3];
+  if (__float_as_uint(r3.w) == 0) return 0u;
+  const uint32_t lo = __float_as_uint(r3.y), hi = __float_as_uint(r3.z);
+  return ((hi & 0xffffu) - (lo & 0xffffu) + 1u) * ((hi >> 16) - (lo >> 16) + 1u);
+}
+
+__device__ __forceinline__ bool tile_hit(const SplatTiles& s, const ViewDesc& V, bool ellipse, int tx, int ty) {
+  return !ellipse || ellipse_hits_tile(s.u, s.v, s.a, s.b, s.c, s.inv_a, s.inv_c, s.qm, tx, ty, V.width, V.height);
+}
+
+// Visit the (splat, tile) hits of the block's chunk [i0, i1) whose tile lies in the window [w0, w1):
+// rectangles of up to kSmallArea tiles one thread each, larger ones one wave each (lanes over tiles).
+// COUNT: histogram into lds; on the first window also store each splat's exact tile count (ELLIPSE).
+// SCATTER: claim a slot from the tile's cursor in lds and write (depth bits, splat index).
+template <bool SCATTER>
+__device__ __forceinline__ void walk_chunk(const ViewDesc& V, int64_t i0, int64_t i1, int w0, int w1,
+                                           uint32_t* lds, uint2* pairs, uint64_t capacity) {
+  const bool ellipse = V.tile_cull == GES_TILES_ELLIPSE;
+  const bool store_count = !SCATTER && ellipse && w0 == 0;
+  const int TX = V.tiles_x;
+  // one thread per small rectangle
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    SplatTiles s;
+    load_splat_tiles(V, i, ellipse, s);
+    if (s.area == 0 || s.area > (uint32_t)kSmallArea) continue;
+    uint32_t hits = 0;
+    for (int ty = s.ty0; ty <= s.ty1; ++ty)
+      for (int tx = s.tx0; tx <= s.tx1; ++tx) {
+        const int t = ty * TX + tx;
+        const bool in_win = t >= w0 && t < w1;
+        if (!in_win && !store_count) continue;
+        if (!tile_hit(s, V, ellipse, tx, ty)) continue;
+        ++hits;
+        if (!in_win) continue;
+        if (SCATTER) {
+          const uint32_t pos = atomicAdd(&lds[t - w0], 1u);
+          if ((uint64_t)pos < capacity) pairs[pos] = make_uint2(s.depth_bits, (uint32_t)i);
+        } else {
+          atomicAdd(&lds[t - w0], 1u);
+        }
+      }
+    if (store_count) reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = hits;
+  }
+  // one wave per large rectangle
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int64_t base = i0 + (int64_t)wave * 64; base < i1; base += (int64_t)nwaves * 64) {
+    const int64_t mine = base + lane;
+    const uint32_t area = mine < i1 ? rect_area(V, mine) : 0u;
+    uint64_t big = __ballot(area > (uint32_t)kSmallArea);
+    while (big) {
+      const int j = __ffsll((long long)big) - 1;
+      big &= big - 1;
+      const int64_t i = base + j;
+      SplatTiles s;
+      load_splat_tiles(V, i, ellipse, s);
+      uint32_t hits = 0;
+      for (uint32_t k = lane; k < s.area; k += 64) {
+        const int tx = s.tx0 + (int)(k % (uint32_t)s.rw), ty = s.ty0 + (int)(k / (uint32_t)s.rw);
+        const int t = ty * TX + tx;
+        const bool in_win = t >= w0 && t < w1;
+        if (!in_win && !store_count) continue;
+        if (!tile_hit(s, V, ellipse, tx, ty)) continue;
+        ++hits;
+        if (!in_win) continue;
+        if (SCATTER) {
+          const uint32_t pos = atomicAdd(&lds[t - w0], 1u);
+          if ((uint64_t)pos < capacity) pairs[pos] = make_uint2(s.depth_bits, (uint32_t)i);
+        } else {
+          atomicAdd(&lds[t - w0], 1u);
+        }
+      }
+      if (store_count) {
+        for (int off = 32; off > 0; off >>= 1) hits += __shfl_xor(hits, off, 64);
+        if (lane == 0) reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = hits;
+      }
+    }
+  }
 }
 
 __global__ void __launch_bounds__(kBinBlockThreads) bin_count_kernel(const DeviceBatch* __restrict__ db) {
@@ -55,20 +140,7 @@ __global__ void __launch_bounds__(kBinBlockThreads) bin_count_kernel(const Devic
     const int w1 = min(T, w0 + kBinLdsTiles);
     for (int j = threadIdx.x; j < w1 - w0; j += blockDim.x) hist[j] = 0;
     __syncthreads();
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-      SplatTiles s;
-      uint32_t db_;
-      if (!load_splat_tiles(V, i, s, db_)) continue;
-      for (int ty = s.ty0; ty <= s.ty1; ++ty) {
-        const int row = ty * V.tiles_x;
-        if (row + s.tx1 < w0 || row + s.tx0 >= w1) continue;
-        for (int tx = s.tx0; tx <= s.tx1; ++tx) {
-          const int t = row + tx;
-          if (t < w0 || t >= w1) continue;
-          if (tile_hit(s, V, tx, ty)) atomicAdd(&hist[t - w0], 1u);
-        }
-      }
-    }
+    walk_chunk<false>(V, i0, i1, w0, w1, hist, nullptr, 0);
     __syncthreads();
     uint32_t* out = V.bin_counts + (int64_t)g * T;
     for (int j = threadIdx.x; j < w1 - w0; j += blockDim.x) out[w0 + j] = hist[j];
@@ -140,7 +212,11 @@ __global__ void __launch_bounds__(1024) bin_tilescan_kernel(const DeviceBatch* _
       if (threadIdx.x == 1023) carry = excl + x;
       __syncthreads();
     }
-    if (threadIdx.x == 0) V.header[0] = carry - view_start;
+    if (threadIdx.x == 0) {
+      V.header[0] = carry - view_start;
+      V.header[2] = 0ull;   // pair statistics of the coming forward pass
+      V.header[3] = 0ull;
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) *keys_total = carry > 0xffffffffull ? 0xffffffffu : (uint32_t)carry;
@@ -161,22 +237,7 @@ __global__ void __launch_bounds__(kBinBlockThreads) bin_scatter_kernel(const Dev
     const int w1 = min(T, w0 + kBinLdsTiles);
     for (int j = threadIdx.x; j < w1 - w0; j += blockDim.x) cursor[j] = V.ranges[w0 + j].x + row[w0 + j];
     __syncthreads();
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-      SplatTiles s;
-      uint32_t dbits;
-      if (!load_splat_tiles(V, i, s, dbits)) continue;
-      for (int ty = s.ty0; ty <= s.ty1; ++ty) {
-        const int rowt = ty * V.tiles_x;
-        if (rowt + s.tx1 < w0 || rowt + s.tx0 >= w1) continue;
-        for (int tx = s.tx0; tx <= s.tx1; ++tx) {
-          const int t = rowt + tx;
-          if (t < w0 || t >= w1) continue;
-          if (!tile_hit(s, V, tx, ty)) continue;
-          const uint32_t pos = atomicAdd(&cursor[t - w0], 1u);
-          if ((uint64_t)pos < capacity) pairs[pos] = make_uint2(dbits, (uint32_t)i);
-        }
-      }
-    }
+    walk_chunk<true>(V, i0, i1, w0, w1, cursor, pairs, capacity);
     __syncthreads();
   }
 }

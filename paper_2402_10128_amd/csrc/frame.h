@@ -36,7 +36,7 @@ inline FramePlan plan_frame(int64_t n, int w, int h) {
   p.off_db = o;      o += align256(sizeof(DeviceBatch));
   p.off_hdr = o;     o += 256;
   p.off_rec = o;     o += align256((size_t)n * kRecWords * 4);
-  p.off_grad = o;    o += align256((size_t)n * kGradStride * 4);
+  p.off_grad = o;    o += align256((size_t)n * kGradStride * 8);
   p.off_counts = o;  o += align256((size_t)p.bin_blocks * (size_t)p.tiles * 4);
   p.off_total = o;   o += align256((size_t)p.tiles * 4);
   p.off_ranges = o;  o += align256((size_t)p.tiles * 8);
@@ -97,6 +97,8 @@ inline std::string check_splats(const ges_splats* s) {
   if (s->n > 0 && (!s->means || !s->log_scales || !s->quats || !s->opacity_logits || !s->sh || !s->beta))
     return "NULL splat array";
   if (s->n > 0 && (reinterpret_cast<uintptr_t>(s->quats) & 15u)) return "quats must be 16-byte aligned";
+  if (s->n > 0 && (s->sh_degree == 1 || s->sh_degree == 3) && (reinterpret_cast<uintptr_t>(s->sh) & 15u))
+    return "sh must be 16-byte aligned";
   return "";
 }
 
@@ -142,7 +144,7 @@ inline void fill_view(ViewDesc& V, const ges_splats* s, const ges_camera* c, con
 inline void attach_splat_ws(ViewDesc& V, const FramePlan& fp, void* splat_ws) {
   char* b = reinterpret_cast<char*>(splat_ws);
   V.rec = reinterpret_cast<float4*>(b + fp.off_rec);
-  V.grad2d = reinterpret_cast<float*>(b + fp.off_grad);
+  V.grad2d = reinterpret_cast<double*>(b + fp.off_grad);
   V.bin_counts = reinterpret_cast<uint32_t*>(b + fp.off_counts);
   V.tile_total = reinterpret_cast<uint32_t*>(b + fp.off_total);
   V.ranges = reinterpret_cast<uint2*>(b + fp.off_ranges);

@@ -15,9 +15,9 @@ namespace ges {
 constexpr int kTile = GES_TILE;          // 16 x 16 pixel tiles
 constexpr int kTilePx = kTile * kTile;   // 256 pixels, 4 per lane of one wave64
 constexpr int kRecWords = 16;            // 64-byte per-splat record
-constexpr int kGradStride = 12;          // floats per splat in the 2-D gradient accumulator
+constexpr int kGradStride = 12;          // doubles per splat in the 2-D gradient accumulator
 constexpr int kMaxViews = 64;
-constexpr int kBinBlockThreads = 512;
+constexpr int kBinBlockThreads = 1024;
 constexpr int kMaxBinBlocks = 256;       // splat chunks per view for the tile histogram
 constexpr int kBinLdsTiles = 12288;      // tiles per LDS window of the histogram (48 KB)
 constexpr int kSortCap = 4096;           // per-tile lists up to this length sort entirely in LDS
@@ -57,7 +57,7 @@ struct ViewDesc {
   uint32_t* tile_total;          // [tiles] entries per tile
   uint2* ranges;                 // [tiles] [start,end) into the key arrays (global positions)
   unsigned long long* header;    // [0] keys of this view, [1] error flags
-  float* grad2d;                 // [n][kGradStride]
+  double* grad2d;                // [n][kGradStride] binary64 accumulators (cross-tile sums)
   float* final_T;                // [h*w]
   uint32_t* n_contrib;           // [h*w]
   float* out_rgb;                // [h*w*3]

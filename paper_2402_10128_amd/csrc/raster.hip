@@ -15,8 +15,10 @@
 // share splats in that XCD's L2).
 // The backward pass walks each pixel's contributors back to front, recovering the transmittance
 // before splat j as T_j = T_(j+1) / (1 - alpha_j) from the stored final T, so no per-pixel lists are
-// kept.  Per splat, the 4 pixels of a lane are summed in registers, the 64 lanes by DPP row and
-// broadcast steps, and one lane per gradient component adds the total with a float atomic.
+// kept.  Per splat, the 4 pixels of a lane are summed in registers and each row of 16 lanes by four
+// DPP steps; one lane per row parks the row sums in LDS, and every 32 splats each lane finishes one
+// parked splat (4 row sums) and adds its components to binary64 accumulators with float64 atomics
+// (the cross-tile sums of a splat often cancel; binary32 accumulation would lose accuracy there).
 #include "ges_internal.h"
 
 namespace ges {
@@ -68,6 +70,7 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
   float T[4] = {1.f, 1.f, 1.f, 1.f};
   float C[4][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
   uint32_t last[4] = {0u, 0u, 0u, 0u};
+  uint32_t n_exam = 0, n_blend = 0;   // pairs examined (up to termination) and composited, for the stats
   const uint2 rg = V.ranges[lt];
   // a range beyond the key buffer (inconsistent key count) renders as background
   const int n = (uint64_t)rg.y <= capacity ? (int)(rg.y - rg.x) : 0;
@@ -92,6 +95,7 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (!(alive & (1u << k))) continue;
+        ++n_exam;
         float dx, dy;
         float q = pair_q(A.x, A.y, A.z, A.w, B.x, pxf, pyf[k], dx, dy);
         if (!(q <= B.y)) continue;
@@ -112,10 +116,23 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
         C[k][2] = __builtin_fmaf(w, Cc.z, C[k][2]);
         T[k] = t;
         last[k] = (uint32_t)(base + j + 1);
+        ++n_blend;
       }
       if (!__any(alive != 0)) break;
     }
     __syncthreads();
+  }
+  {
+    // per-frame pair statistics: one atomic per tile
+    unsigned long long e = n_exam, b = n_blend;
+    for (int off = 32; off > 0; off >>= 1) {
+      e += __shfl_xor(e, off, 64);
+      b += __shfl_xor(b, off, 64);
+    }
+    if (lane == 0 && e > 0) {
+      atomicAdd(&V.header[2], e);
+      atomicAdd(&V.header[3], b);
+    }
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -137,6 +154,15 @@ __device__ __forceinline__ float dpp_add(float x) {
   return x + __int_as_float(y);
 }
 
+// Sum over each row of 16 lanes (every lane of the row ends with its row's total).
+__device__ __forceinline__ float row_sum(float x) {
+  x = dpp_add<0xB1, 0xf>(x);    // quad_perm [1,0,3,2]
+  x = dpp_add<0x4E, 0xf>(x);    // quad_perm [2,3,0,1]
+  x = dpp_add<0x124, 0xf>(x);   // row_ror:4
+  x = dpp_add<0x128, 0xf>(x);   // row_ror:8
+  return x;
+}
+
 __device__ __forceinline__ float wave_sum_to_63(float x) {
   x = dpp_add<0xB1, 0xf>(x);    // quad_perm [1,0,3,2]
   x = dpp_add<0x4E, 0xf>(x);    // quad_perm [2,3,0,1]
@@ -147,11 +173,15 @@ __device__ __forceinline__ float wave_sum_to_63(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+constexpr int kFlush = 32;   // splats whose row partials are parked in LDS before one atomic flush
+
 template <int FALLOFF>
 __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* __restrict__ db,
                                                              const uint32_t* __restrict__ sorted_ids,
                                                              int64_t total_tiles, int64_t per_xcd) {
   __shared__ float4 sA[64], sB[64], sC[64];
+  __shared__ float sRed[kFlush][4][10];   // [splat slot][lane row][component]
+  __shared__ uint32_t sId[kFlush];
   const int64_t gt = xcd_tile(blockIdx.x, per_xcd);
   if (gt >= total_tiles) return;
   const int v = view_of_block(db->tile_prefix, db->nviews, gt);
@@ -159,6 +189,7 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   const int lt = (int)(gt - db->tile_prefix[v]);
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
   const int lane = threadIdx.x;
+  const int row = lane >> 4;
   const int px = tx * kTile + (lane & 15);
   const int py0 = ty * kTile + (lane >> 4);
   const float pxf = (float)px;
@@ -190,7 +221,10 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, off, 64));
   const uint2 rg = V.ranges[lt];
   const float4* rec = V.rec;
-  float* grad2d = V.grad2d;
+  double* grad2d = V.grad2d;
+  const int ncomp = FALLOFF == GES_FALLOFF_GEF ? 10 : 9;
+  uint32_t parked = 0;    // bit s: slot s holds row partials (uniform across the wave)
+  int nslot = 0;
   for (int hi = (int)maxlast; hi > 0; hi -= 64) {
     const int lo = max(0, hi - 64);
     const int cnt = hi - lo;
@@ -262,25 +296,36 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         pb = __builtin_fmaf(tx2 * dx, dy, pb);
         pc = __builtin_fmaf(dq * dy, dy, pc);
       }
-      if (!__any(any)) continue;
-      const float su = wave_sum_to_63(pu), sv = wave_sum_to_63(pv), sa = wave_sum_to_63(pa);
-      const float sb = wave_sum_to_63(pb), sc = wave_sum_to_63(pc), so = wave_sum_to_63(po);
-      const float sr = wave_sum_to_63(pr), sg = wave_sum_to_63(pg), sbl = wave_sum_to_63(pbl);
-      const float sbeta = FALLOFF == GES_FALLOFF_GEF ? wave_sum_to_63(pbeta) : 0.f;
-      const int ncomp = FALLOFF == GES_FALLOFF_GEF ? 10 : 9;
-      if (lane < ncomp) {
-        float val = su;
-        val = lane == 1 ? sv : val;
-        val = lane == 2 ? sa : val;
-        val = lane == 3 ? sb : val;
-        val = lane == 4 ? sc : val;
-        val = lane == 5 ? so : val;
-        val = lane == 6 ? sr : val;
-        val = lane == 7 ? sg : val;
-        val = lane == 8 ? sbl : val;
-        val = lane == 9 ? sbeta : val;
-        const uint32_t id = __float_as_uint(Cc.w);
-        if (val != 0.f) atomicAdd(&grad2d[(size_t)id * kGradStride + lane], val);
+      if (__any(any)) {
+        // rows of 16 lanes reduce in registers; one lane per row parks the 10 row sums in LDS
+        const float r0 = row_sum(pu), r1 = row_sum(pv), r2 = row_sum(pa), r3 = row_sum(pb), r4 = row_sum(pc);
+        const float r5 = row_sum(po), r6 = row_sum(pr), r7 = row_sum(pg), r8 = row_sum(pbl);
+        const float r9 = FALLOFF == GES_FALLOFF_GEF ? row_sum(pbeta) : 0.f;
+        if ((lane & 15) == 15) {
+          float* d = sRed[nslot][row];
+          d[0] = r0; d[1] = r1; d[2] = r2; d[3] = r3; d[4] = r4;
+          d[5] = r5; d[6] = r6; d[7] = r7; d[8] = r8; d[9] = r9;
+        }
+        if (lane == 0) sId[nslot] = __float_as_uint(Cc.w);
+        parked |= 1u << nslot;
+        ++nslot;
+      }
+      if (nslot == kFlush || (j == 0 && hi - 64 <= 0 && nslot > 0)) {
+        // one lane per parked splat: add the four row sums, then one float64 atomic per component
+        __syncthreads();
+        if (lane < kFlush && (parked >> lane) & 1u) {
+          const uint32_t id = sId[lane];
+          double* dst = grad2d + (size_t)id * kGradStride;
+#pragma unroll
+          for (int c = 0; c < 10; ++c) {
+            if (c >= ncomp) break;
+            const float val = (sRed[lane][0][c] + sRed[lane][1][c]) + (sRed[lane][2][c] + sRed[lane][3][c]);
+            if (val != 0.f) atomicAdd(dst + c, (double)val);
+          }
+        }
+        __syncthreads();
+        parked = 0;
+        nslot = 0;
       }
     }
     __syncthreads();

@@ -52,7 +52,7 @@ class ges_splat_grads(C.Structure):
 class ges_frame_view(C.Structure):
     _fields_ = [("records", C.c_void_p), ("tile_ranges", C.c_void_p), ("sorted_ids", C.c_void_p),
                 ("bucket_pairs", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
-                ("grad2d", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32)]
+                ("grad2d", C.c_void_p), ("stats", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32)]
 
 
 class ges_serve_config(C.Structure):
@@ -81,12 +81,16 @@ _SIGS = {
                                       C.c_void_p]),
     "ges_frame_view_get": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64,
                                      C.c_void_p, C.POINTER(ges_frame_view)]),
+    "ges_profile_enable": (C.c_int, [C.c_int32]),
+    "ges_profile_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "ges_mask_scratch_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "ges_freq_mask": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ges_loss_scratch_bytes": (C.c_size_t, []),
     "ges_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_float,
                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ges_serve_create": (C.c_int, [C.POINTER(ges_serve_config), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "ges_serve_create_simulated": (C.c_int, [C.POINTER(ges_serve_config), C.c_size_t, C.c_uint64, C.c_uint64,
+                                             C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
     "ges_serve_add_scene": (C.c_int, [C.c_void_p, C.POINTER(ges_splats), C.POINTER(C.c_int32)]),
     "ges_serve_submit": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(ges_camera), C.c_void_p, C.POINTER(C.c_uint64)]),
     "ges_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ges_request_info)]),
@@ -203,6 +207,21 @@ def ges_frame_view_get(n, width, height, splat_ws, key_ws, num_keys, pixel_ws) -
     return v
 
 
+STAGES = ["preprocess", "bin_count", "bin_scan", "bin_scatter", "tile_sort", "raster_forward", "raster_backward",
+          "preprocess_backward", "zero", "loss"]
+
+
+def ges_profile_enable(on: bool):
+    _check(lib().ges_profile_enable(1 if on else 0))
+
+
+def ges_profile_read(reset=True):
+    ms = (C.c_double * len(STAGES))()
+    n = (C.c_int64 * len(STAGES))()
+    _check(lib().ges_profile_read(ms, n, 1 if reset else 0))
+    return {STAGES[k]: (ms[k], n[k]) for k in range(len(STAGES))}
+
+
 def ges_freq_mask(target, omega, mask=None, stream=None):
     H, W = int(target.shape[0]), int(target.shape[1])
     scratch = torch.empty(lib().ges_mask_scratch_bytes(W, H), dtype=torch.uint8, device=target.device)
@@ -268,7 +287,8 @@ def frame_arrays(frame: Frame, n: int) -> dict:
     out["records"] = sl(v.records, 64 * n, ws).view(torch.float32).reshape(n, 16).cpu().numpy()
     T = v.tiles_x * v.tiles_y
     out["ranges"] = sl(v.tile_ranges, 8 * T, ws).view(torch.int32).reshape(T, 2).cpu().numpy().view(np.uint32)
-    out["grad2d"] = sl(v.grad2d, 48 * n, ws).view(torch.float32).reshape(n, 12).cpu().numpy()
+    out["grad2d"] = sl(v.grad2d, 96 * n, ws).view(torch.float64).reshape(n, 12).cpu().numpy()
+    out["stats"] = sl(v.stats, 32, ws).view(torch.int64).cpu().numpy()
     if frame.key_ws is not None and frame.num_keys > 0:
         K = frame.num_keys
         out["sorted_ids"] = sl(v.sorted_ids, 4 * K, frame.key_ws).view(torch.int32).cpu().numpy().view(np.uint32)

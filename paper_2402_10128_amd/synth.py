@@ -98,18 +98,26 @@ def orbit_camera(rng: np.random.Generator, width: int, height: int, radius: floa
     return pinhole(width, height, pos)
 
 
+def _normal(rng, mean, std, size):
+    return (rng.standard_normal(size, dtype=np.float32) * np.float32(std) + np.float32(mean)).astype(np.float32)
+
+
+def _uniform(rng, lo, hi, size):
+    return (rng.random(size, dtype=np.float32) * np.float32(hi - lo) + np.float32(lo)).astype(np.float32)
+
+
 def _quats(rng, n):
-    q = rng.standard_normal((n, 4))
+    q = rng.standard_normal((n, 4), dtype=np.float32)
     q /= np.linalg.norm(q, axis=1, keepdims=True)
     return q.astype(np.float32)
 
 
 def _sh(rng, n, degree, dc_rgb, high_std):
     k = (degree + 1) ** 2
-    sh = np.zeros((n, k, 3), dtype=np.float32)
-    sh[:, 0, :] = (dc_rgb - 0.5) / Y00
+    sh = np.empty((n, k, 3), dtype=np.float32)
+    sh[:, 0, :] = (dc_rgb - np.float32(0.5)) / np.float32(Y00)
     if k > 1:
-        sh[:, 1:, :] = rng.normal(0.0, high_std, size=(n, k - 1, 3))
+        sh[:, 1:, :] = _normal(rng, 0.0, high_std, (n, k - 1, 3))
     return sh
 
 
@@ -126,14 +134,14 @@ def scene_uniform(n: int, seed: int) -> Scene:
 
 def scene_clusters(n: int, seed: int, degree: int = 3, n_clusters: int = 64) -> Scene:
     rng = np.random.default_rng(seed)
-    centres = rng.uniform(-5.0, 5.0, size=(n_clusters, 3))
+    centres = rng.uniform(-5.0, 5.0, size=(n_clusters, 3)).astype(np.float32)
     which = rng.integers(0, n_clusters, size=n)
-    means = (centres[which] + rng.normal(0.0, 0.3, size=(n, 3))).astype(np.float32)
-    log_scales = rng.normal(-4.0, 0.7, size=(n, 3)).astype(np.float32)
+    means = (centres[which] + _normal(rng, 0.0, 0.3, (n, 3))).astype(np.float32)
+    log_scales = _normal(rng, -4.0, 0.7, (n, 3))
     quats = _quats(rng, n)
-    logits = rng.normal(0.0, 1.5, size=n).astype(np.float32)
-    sh = _sh(rng, n, degree, rng.uniform(0.0, 1.0, size=(n, 3)), 0.05)
-    beta = np.exp(rng.uniform(math.log(0.5), math.log(8.0), size=n)).astype(np.float32)
+    logits = _normal(rng, 0.0, 1.5, n)
+    sh = _sh(rng, n, degree, _uniform(rng, 0.0, 1.0, (n, 3)), 0.05)
+    beta = np.exp(_uniform(rng, math.log(0.5), math.log(8.0), n)).astype(np.float32)
     return Scene(means, log_scales, quats, logits, sh, beta, degree, dict(kind="clusters", seed=seed))
 
 
@@ -151,14 +159,13 @@ def scene_overlap(n: int, seed: int, cam: Camera, depth_range=(6.0, 10.0)) -> Sc
     t = cam.t.astype(np.float64)
     centres = (cam_pts - t) @ R  # camera -> world: R^T (p - t)
     which = rng.integers(0, 16, size=n)
-    means = (centres[which] + rng.normal(0.0, 0.25, size=(n, 3))).astype(np.float32)
-    ls = rng.normal(-5.0, 0.5, size=(n, 3))
-    ls[:, 0] = rng.normal(-1.5, 0.5, size=n)
-    log_scales = ls.astype(np.float32)
+    means = (centres[which].astype(np.float32) + _normal(rng, 0.0, 0.25, (n, 3))).astype(np.float32)
+    log_scales = _normal(rng, -5.0, 0.5, (n, 3))
+    log_scales[:, 0] = _normal(rng, -1.5, 0.5, n)
     quats = _quats(rng, n)
-    logits = rng.normal(1.0, 1.0, size=n).astype(np.float32)
-    sh = _sh(rng, n, 3, rng.uniform(0.0, 1.0, size=(n, 3)), 0.05)
-    beta = rng.uniform(0.5, 2.0, size=n).astype(np.float32)
+    logits = _normal(rng, 1.0, 1.0, n)
+    sh = _sh(rng, n, 3, _uniform(rng, 0.0, 1.0, (n, 3)), 0.05)
+    beta = _uniform(rng, 0.5, 2.0, n)
     return Scene(means, log_scales, quats, logits, sh, beta, 3, dict(kind="overlap", seed=seed))
 
 

@@ -18,6 +18,7 @@ from paper_2402_10128_amd import ges as G
 IMG_ATOL = 1e-5
 GRAD_RTOL = 1e-3
 GRAD_FLOOR = 1e-2
+TERM_EPS = 1e-5   # rounding allowance per summed contribution (binary32 terms with hardware exp2/rcp)
 
 
 def to_device(arrays: dict, device="cuda"):
@@ -101,13 +102,29 @@ def grad_rel_err(g, r):
                 norm=float(nrm))
 
 
-def grad2d_check(g, r, delta):
-    """2-D accumulators: error beyond the ambiguous-decision allowance, relative to max(|r|, floor)."""
+def allowance2d(r, delta, mass):
+    """Per 2-D component: the ambiguous-decision allowance plus the rounding of a sum whose terms each carry
+    a relative error of TERM_EPS (the sum of |terms| is `mass`)."""
+    return delta + TERM_EPS * mass + TERM_EPS * np.abs(r)
+
+
+def grad2d_check(g, r, delta, mass):
+    """2-D accumulators: error beyond the allowance, relative to max(|r|, floor)."""
     g = np.asarray(g, np.float64)
     r = np.asarray(r, np.float64)
     floor = np.maximum(GRAD_FLOOR * np.sqrt(np.mean(r * r, axis=0, keepdims=True)), 1e-30)
-    excess = np.maximum(np.abs(g - r) - delta, 0.0) / np.maximum(np.abs(r), floor)
+    excess = np.maximum(np.abs(g - r) - allowance2d(r, delta, mass), 0.0) / np.maximum(np.abs(r), floor)
     return dict(max=float(excess.max()) if excess.size else 0.0, ambiguous_entries=int((delta > 0).sum()))
+
+
+def grad3d_check(g, r, allow):
+    """Parameter gradients: error beyond the propagated allowance |J|^T a, relative to max(|r|, floor)."""
+    g = np.asarray(g, np.float64).ravel()
+    r = np.asarray(r, np.float64).ravel()
+    a = np.asarray(allow, np.float64).ravel()
+    floor = max(GRAD_FLOOR * np.sqrt(np.mean(r * r)), 1e-30) if r.size else 1.0
+    excess = np.maximum(np.abs(g - r) - a, 0.0) / np.maximum(np.abs(r), floor)
+    return dict(max=float(excess.max()) if excess.size else 0.0)
 
 
 def ambiguous_splats(r2d, delta):
@@ -126,9 +143,12 @@ def oracle_full(arrays, sh_degree, cam, falloff=0, tile_cull=0, rho=0.1, bg=(0.0
     out = orc.render(rec, vals, ranges)
     res = dict(orc=orc, rec=rec, keys=keys, values=vals, ranges=ranges, out=out)
     if dL is not None:
-        g2d, delta, _ = orc.backward2d(rec, dL, vals, ranges, with_delta=True)
+        g2d, delta, mass, _ = orc.backward2d(rec, dL, vals, ranges, with_delta=True)
         res["g2d"] = g2d
         res["delta"] = delta
-        res["grads"] = PF.chain_to_params(arrays, sh_degree, cam, g2d, rec.tiles_touched > 0, rec.clamp_bits,
-                                          falloff, rho)
+        res["mass"] = mass
+        vis = rec.tiles_touched > 0
+        res["grads"] = PF.chain_to_params(arrays, sh_degree, cam, g2d, vis, rec.clamp_bits, falloff, rho)
+        res["allow"] = PF.abs_chain(arrays, sh_degree, cam, allowance2d(g2d, delta, mass), vis, rec.clamp_bits,
+                                    falloff, rho)
     return res

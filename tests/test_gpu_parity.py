@@ -9,8 +9,8 @@ import pytest
 from oracle import oracle as O
 from paper_2402_10128_amd import synth
 
-from .parity_helpers import (GRAD_RTOL, IMG_ATOL, ambiguous_splats, gpu_render, grad2d_check, grad_rel_err,
-                             image_compare, oracle_full, record_mismatches)
+from .parity_helpers import (GRAD_RTOL, IMG_ATOL, ambiguous_splats, gpu_render, grad2d_check, grad3d_check,
+                             grad_rel_err, image_compare, oracle_full, record_mismatches)
 
 pytestmark = pytest.mark.gpu
 
@@ -62,16 +62,19 @@ def test_backward_parity(case):
     print(f"[parity-bwd] {name}", flush=True)
     gpu = gpu_render(sc.arrays(), sc.sh_degree, cam, falloff, cull, dL=dL)
     ref = oracle_full(sc.arrays(), sc.sh_degree, cam, falloff, cull, dL=dL.astype(np.float64))
-    # 2-D accumulators first (u, v, a, b, c, opacity, rgb, beta), within the allowance of decisions that
-    # binary32 may take either way (termination near 1e-4, alpha clamp near 0.99)
+    # 2-D accumulators (u, v, a, b, c, opacity, rgb, beta): within the allowance for decisions binary32 may
+    # take either way (termination near 1e-4, alpha clamp near 0.99) and for the rounding of sums whose
+    # terms cancel; parameter gradients: within that allowance propagated through |J|^T of the preprocess.
     ncol = 10 if falloff == O.FALLOFF_GEF else 9
-    e2 = grad2d_check(gpu["grad2d"][:, :ncol], ref["g2d"][:, :ncol], ref["delta"][:, :ncol])
+    e2 = grad2d_check(gpu["grad2d"][:, :ncol], ref["g2d"][:, :ncol], ref["delta"][:, :ncol], ref["mass"][:, :ncol])
     print("  grad2d", e2, "plain", grad_rel_err(gpu["grad2d"][:, :ncol], ref["g2d"][:, :ncol]))
     amb = ambiguous_splats(ref["g2d"][:, :ncol], ref["delta"][:, :ncol])
-    print(f"  splats with an ambiguous decision: {int(amb.sum())} of {len(amb)}")
-    errs = {k: grad_rel_err(gpu["grads"][k][~amb], ref["grads"][k][~amb]) for k in gpu["grads"]}
-    for k, e in errs.items():
-        print(f"  d{k}: max {e['max']:.2e} p99 {e['p99']:.2e} norm {e['norm']:.2e}")
+    print(f"  splats touched by an ambiguous decision: {int(amb.sum())} of {len(amb)}")
+    errs = {k: grad3d_check(gpu["grads"][k], ref["grads"][k], ref["allow"][k]) for k in gpu["grads"]}
+    for k in gpu["grads"]:
+        e = grad_rel_err(gpu["grads"][k], ref["grads"][k])
+        print(f"  d{k}: beyond allowance {errs[k]['max']:.2e}; plain max {e['max']:.2e} p99 {e['p99']:.2e} "
+              f"norm {e['norm']:.2e}")
     assert e2["max"] <= GRAD_RTOL, e2
     for k, e in errs.items():
         assert e["max"] <= GRAD_RTOL, (k, e)
@@ -125,10 +128,10 @@ def test_equal_depth_ties_sorted_by_index():
     assert cmp["max_err"] <= IMG_ATOL, cmp
 
 
-def test_long_tile_lists_global_sort_path():
-    """A tile list longer than the LDS capacity (4096) goes through the global-memory sort."""
+@pytest.mark.parametrize("n", [9000, 20000], ids=["lds1024", "global"])
+def test_long_tile_lists_large_sort_paths(n):
+    """Tile lists longer than 4,096 use the 1,024-thread LDS sort; longer than 16,384 the global path."""
     rng = np.random.default_rng(5)
-    n = 9000
     means = np.zeros((n, 3), np.float32)
     means[:, :2] = rng.uniform(-0.02, 0.02, (n, 2))
     means[:, 2] = rng.uniform(-0.5, 0.5, n)
@@ -141,7 +144,7 @@ def test_long_tile_lists_global_sort_path():
     gpu = gpu_render(arr, 0, cam)
     ref = oracle_full(arr, 0, cam)
     lens = ref["ranges"][:, 1] - ref["ranges"][:, 0]
-    assert lens.max() > 4096
+    assert lens.max() > (16384 if n > 16384 else 4096)
     assert np.array_equal(gpu["sorted_ids"], ref["values"])
     cmp = image_compare(gpu["img"], ref["out"])
     assert cmp["max_err"] <= IMG_ATOL, cmp
