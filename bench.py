@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--tile-cull", choices=["square", "ellipse"], default="ellipse")
     ap.add_argument("--falloff", choices=["phi", "gef"], default="phi")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof FETCH/WRITE counters)")
     return ap.parse_args()
@@ -144,6 +146,73 @@ def cpu_baseline(cfg, falloff, tile_cull, budget_tiles=160):
                        f"list building on {len(tiles)} random tiles of {T} ({t_lists + t_tiles:.1f}s, scaled by "
                        f"{T}/{len(tiles)}); binary64 chain rule on {sub} splats ({t_chain * sub / n:.1f}s, scaled by "
                        f"{n}/{sub}); estimated full frame {t_full:.1f}s")}
+
+
+def serving_bench(dev, n_req, log_fn):
+    """Batched vs one-request-at-a-time serving over 8 resident scenes (13.7M splats, SH degree 3) at
+    mixed resolutions: closed-loop capacity of each, then Poisson arrivals at 0.5, 0.9 and 1.2 times
+    the sequential capacity (0.9 is the headline).  Both servers run the same kernels."""
+    import torch
+    from paper_2402_10128_amd import synth
+    from paper_2402_10128_amd.serve import Server, run_stream
+    scenes = [synth.scene_clusters_device(n, 1004 + 10 * i, dev) for i, n in enumerate(synth.SERVING_SIZES)]
+    torch.cuda.synchronize()
+    res = list(synth.SERVING_RESOLUTIONS)
+    reqs = synth.serving_requests(n_req, len(scenes), res, seed=2000)
+    sizes = [c.width * c.height * 3 for _, c in reqs]
+    flat = torch.zeros(sum(sizes), dtype=torch.float32, device=dev)
+    outs, o = [], 0
+    for (_, c), sz in zip(reqs, sizes):
+        outs.append(flat[o:o + sz].view(c.height, c.width, 3))
+        o += sz
+    pool_bytes = 8 << 30
+
+    def server(sequential):
+        s = Server(pool_bytes, max_slots=16, queue_capacity=max(4096, n_req + 16), sequential=sequential,
+                   device=dev)
+        ids = [s.add_scene(sc) for sc in scenes]
+        return s, [(ids[k], cam) for k, cam in reqs]
+
+    def summary(r):
+        return {k: round(r[k], 3) for k in ("p50_ms", "p99_ms", "mean_ms", "mpix_s", "mean_batch")}
+
+    out = {"workload": "8 resident scenes of 0.2/0.5/1/1/2/2/3/4M splats (64 clusters, SH degree 3), "
+                       "orbit cameras, resolution uniform over 256x256/512x512/1280x720/1920x1080",
+           "requests_per_rate": n_req, "pool_bytes": pool_bytes, "max_slots": 16}
+    sat = {}
+    n_sat = min(n_req, 400)
+    for mode in ("sequential", "batched"):
+        s, rq = server(mode == "sequential")
+        with s:
+            run_stream(s, rq[:32], outs[:32], None)    # warm-up
+            r = run_stream(s, rq[:n_sat], outs[:n_sat], None)
+        t_s = (max(x["t_done_ns"] for x in r["infos"]) - min(x["t_submit_ns"] for x in r["infos"])) / 1e9
+        sat[mode] = dict(summary(r), req_s=round(n_sat / t_s, 2))
+        log_fn(f"serving saturation {mode}: {sat[mode]}")
+    mu_seq = sat["sequential"]["req_s"]
+    out["saturation"] = sat
+    out["mu_seq_req_s"] = mu_seq
+    rates = []
+    for f in (0.5, 0.9, 1.2):
+        row = {"load": f, "rate_req_s": round(f * mu_seq, 2)}
+        for mode in ("sequential", "batched"):
+            s, rq = server(mode == "sequential")
+            with s:
+                r = run_stream(s, rq, outs, f * mu_seq, seed=int(f * 100))
+            assert r["all_done"], f"serving run at load {f} ({mode}) did not complete every request"
+            row[mode] = summary(r)
+            log_fn(f"serving load {f} {mode}: {row[mode]}")
+        rates.append(row)
+    out["poisson"] = rates
+    head = next(r for r in rates if r["load"] == 0.9)
+    out["headline_load_0.9"] = {"batched_p50_ms": head["batched"]["p50_ms"], "batched_p99_ms": head["batched"]["p99_ms"],
+                                "batched_mpix_s": head["batched"]["mpix_s"],
+                                "sequential_p50_ms": head["sequential"]["p50_ms"],
+                                "sequential_p99_ms": head["sequential"]["p99_ms"],
+                                "sequential_mpix_s": head["sequential"]["mpix_s"]}
+    del flat, outs, scenes
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -251,6 +320,13 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    del frame, t, grads, out, dL
+    torch.cuda.empty_cache()
+    serving = None
+    if not args.no_serving:
+        log("serving (workload 4)")
+        serving = serving_bench(dev, args.serve_requests, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
@@ -262,7 +338,7 @@ def main():
     names = {0: "1k splats 64x64", 1: "1M splats 1600x1040", 2: "3M splats 1920x1080 training step",
              3: "5M splats 1920x1080 heavy overlap"}
     res = {
-        "metric": "fwd+bwd Mpix/s at 3M splats 1080p",
+        "metric": "fwd+bwd Mpix/s at 3M splats 1080p; render p50/p99 ms under batched load",
         "value": round(mpix, 3),
         "unit": "Mpix/s",
         "n_gpus": 1,
@@ -280,6 +356,7 @@ def main():
                    "pairs_composited": pairs_blend, "stage_ms_per_launch": per_stage},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(res), flush=True)
 

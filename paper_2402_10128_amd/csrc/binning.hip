@@ -12,15 +12,13 @@
 //   4. bin_scatter: each block re-walks its chunk and writes (depth bits, splat index) into its own
 //                   sub-range of every tile's bucket, using LDS cursors.
 // The order inside a bucket is arbitrary; the per-tile sort makes it unique.
-// Load balance: rectangles of up to 16 tiles are walked by one thread, larger ones by a whole wave, so
-// the heavy tail of near, large splats does not serialise a wave behind one lane.
+// Load balance: each wave expands 64 splats at a time into their (splat, tile) candidates and tests
+// them one per lane, so the heavy tail of near, large splats keeps every lane busy.
 // HBM: 16-48 B read per splat and 8 B written per pair, plus the G x T count table.
 #include "ges_internal.h"
 #include "tile_geom.h"
 
 namespace ges {
-
-constexpr int kSmallArea = 16;   // rectangles of up to this many tiles are walked by one thread
 
 struct SplatTiles {
   int tx0, ty0, tx1, ty1, rw;
@@ -47,88 +45,106 @@ __device__ __forceinline__ void load_splat_tiles(const ViewDesc& V, int64_t i, b
   }
 }
 
-__device__ __forceinline__ uint32_t rect_area(const ViewDesc& V, int64_t i) {
-  const float4 r3 = V.rec[4 * i + 3];
-  if (__float_as_uint(r3.w) == 0) return 0u;
-  const uint32_t lo = __float_as_uint(r3.y), hi = __float_as_uint(r3.z);
-  return ((hi & 0xffffu) - (lo & 0xffffu) + 1u) * ((hi >> 16) - (lo >> 16) + 1u);
+// Per-wave LDS staging of 64 splats for the flattened candidate walk.
+struct WaveSplats {
+  uint32_t excl[64];     // exclusive prefix of the rectangle areas
+  uint32_t rect[64];     // tx0 | ty0 << 16
+  int32_t rw[64];
+  float inv_rw[64];
+  float u[64], v[64], a[64], b[64], c[64], qm[64], inv_a[64], inv_c[64];
+  uint32_t depth[64];
+  uint32_t hits[64];
+};
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ bool tile_hit(const SplatTiles& s, const ViewDesc& V, bool ellipse, int tx, int ty) {
-  return !ellipse || ellipse_hits_tile(s.u, s.v, s.a, s.b, s.c, s.inv_a, s.inv_c, s.qm, tx, ty, V.width, V.height);
-}
-
-// Visit the (splat, tile) hits of the block's chunk [i0, i1) whose tile lies in the window [w0, w1):
-// rectangles of up to kSmallArea tiles one thread each, larger ones one wave each (lanes over tiles).
+// Visit the (splat, tile) hits of the block's chunk [i0, i1) whose tile lies in the window [w0, w1).
+// Each wave takes 64 consecutive splats at a time, scans their rectangle areas and walks the
+// flattened list of (splat, rectangle tile) candidates 64 at a time, one candidate per lane, so that
+// large rectangles do not serialise a wave.
 // COUNT: histogram into lds; on the first window also store each splat's exact tile count (ELLIPSE).
 // SCATTER: claim a slot from the tile's cursor in lds and write (depth bits, splat index).
 template <bool SCATTER>
 __device__ __forceinline__ void walk_chunk(const ViewDesc& V, int64_t i0, int64_t i1, int w0, int w1,
-                                           uint32_t* lds, uint2* pairs, uint64_t capacity) {
+                                           uint32_t* lds, WaveSplats* wave_lds, uint2* pairs, uint64_t capacity) {
   const bool ellipse = V.tile_cull == GES_TILES_ELLIPSE;
   const bool store_count = !SCATTER && ellipse && w0 == 0;
   const int TX = V.tiles_x;
-  // one thread per small rectangle
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    SplatTiles s;
-    load_splat_tiles(V, i, ellipse, s);
-    if (s.area == 0 || s.area > (uint32_t)kSmallArea) continue;
-    uint32_t hits = 0;
-    for (int ty = s.ty0; ty <= s.ty1; ++ty)
-      for (int tx = s.tx0; tx <= s.tx1; ++tx) {
-        const int t = ty * TX + tx;
-        const bool in_win = t >= w0 && t < w1;
-        if (!in_win && !store_count) continue;
-        if (!tile_hit(s, V, ellipse, tx, ty)) continue;
-        ++hits;
-        if (!in_win) continue;
-        if (SCATTER) {
-          const uint32_t pos = atomicAdd(&lds[t - w0], 1u);
-          if ((uint64_t)pos < capacity) pairs[pos] = make_uint2(s.depth_bits, (uint32_t)i);
-        } else {
-          atomicAdd(&lds[t - w0], 1u);
-        }
-      }
-    if (store_count) reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = hits;
-  }
-  // one wave per large rectangle
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  WaveSplats& W = wave_lds[wave];
   for (int64_t base = i0 + (int64_t)wave * 64; base < i1; base += (int64_t)nwaves * 64) {
-    const int64_t mine = base + lane;
-    const uint32_t area = mine < i1 ? rect_area(V, mine) : 0u;
-    uint64_t big = __ballot(area > (uint32_t)kSmallArea);
-    while (big) {
-      const int j = __ffsll((long long)big) - 1;
-      big &= big - 1;
-      const int64_t i = base + j;
-      SplatTiles s;
-      load_splat_tiles(V, i, ellipse, s);
-      uint32_t hits = 0;
-      for (uint32_t k = lane; k < s.area; k += 64) {
-        const int tx = s.tx0 + (int)(k % (uint32_t)s.rw), ty = s.ty0 + (int)(k / (uint32_t)s.rw);
-        const int t = ty * TX + tx;
-        const bool in_win = t >= w0 && t < w1;
-        if (!in_win && !store_count) continue;
-        if (!tile_hit(s, V, ellipse, tx, ty)) continue;
-        ++hits;
-        if (!in_win) continue;
-        if (SCATTER) {
-          const uint32_t pos = atomicAdd(&lds[t - w0], 1u);
-          if ((uint64_t)pos < capacity) pairs[pos] = make_uint2(s.depth_bits, (uint32_t)i);
-        } else {
-          atomicAdd(&lds[t - w0], 1u);
-        }
-      }
-      if (store_count) {
-        for (int off = 32; off > 0; off >>= 1) hits += __shfl_xor(hits, off, 64);
-        if (lane == 0) reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = hits;
+    const int64_t i = base + lane;
+    SplatTiles s;
+    s.area = 0u;
+    if (i < i1) load_splat_tiles(V, i, ellipse, s);
+    // inclusive wave scan of the areas
+    uint32_t incl = s.area;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    const uint32_t total = __shfl(incl, 63, 64);
+    wave_lds_fence();
+    W.excl[lane] = incl - s.area;
+    W.hits[lane] = 0u;
+    if (s.area) {
+      W.rect[lane] = (uint32_t)s.tx0 | ((uint32_t)s.ty0 << 16);
+      W.rw[lane] = s.rw;
+      W.inv_rw[lane] = 1.0f / (float)s.rw;
+      W.depth[lane] = s.depth_bits;
+      if (ellipse) {
+        W.u[lane] = s.u; W.v[lane] = s.v; W.a[lane] = s.a; W.b[lane] = s.b; W.c[lane] = s.c;
+        W.qm[lane] = s.qm; W.inv_a[lane] = s.inv_a; W.inv_c[lane] = s.inv_c;
       }
     }
+    wave_lds_fence();
+    for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+      const uint32_t c = c0 + (uint32_t)lane;
+      if (c < total) {
+        // owner: the last splat whose range starts at or before c (its area is then non-zero)
+        int j = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+          if (W.excl[j + step] <= c) j += step;
+        const uint32_t k = c - W.excl[j];
+        const int rw = W.rw[j];
+        int row = (int)((float)k * W.inv_rw[j]);
+        int col = (int)k - row * rw;
+        if (col < 0) { --row; col += rw; }
+        if (col >= rw) { ++row; col -= rw; }
+        const uint32_t r0 = W.rect[j];
+        const int tx = (int)(r0 & 0xffffu) + col, ty = (int)(r0 >> 16) + row;
+        const int t = ty * TX + tx;
+        const bool in_win = t >= w0 && t < w1;
+        if (in_win || store_count) {
+          const bool hit = !ellipse || ellipse_hits_tile(W.u[j], W.v[j], W.a[j], W.b[j], W.c[j], W.inv_a[j],
+                                                          W.inv_c[j], W.qm[j], tx, ty, V.width, V.height);
+          if (hit) {
+            if (store_count) atomicAdd(&W.hits[j], 1u);
+            if (in_win) {
+              if (SCATTER) {
+                const uint32_t pos = atomicAdd(&lds[t - w0], 1u);
+                if ((uint64_t)pos < capacity) pairs[pos] = make_uint2(W.depth[j], (uint32_t)(base + j));
+              } else {
+                atomicAdd(&lds[t - w0], 1u);
+              }
+            }
+          }
+        }
+      }
+    }
+    wave_lds_fence();
+    if (store_count && s.area) reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = W.hits[lane];
   }
 }
 
 __global__ void __launch_bounds__(kBinBlockThreads) bin_count_kernel(const DeviceBatch* __restrict__ db) {
   __shared__ uint32_t hist[kBinLdsTiles];
+  __shared__ WaveSplats wave_lds[kBinBlockThreads / 64];
   const int64_t blk = blockIdx.x;
   const int v = view_of_block(db->bin_prefix, db->nviews, blk);
   const ViewDesc& V = db->views[v];
@@ -140,7 +156,7 @@ __global__ void __launch_bounds__(kBinBlockThreads) bin_count_kernel(const Devic
     const int w1 = min(T, w0 + kBinLdsTiles);
     for (int j = threadIdx.x; j < w1 - w0; j += blockDim.x) hist[j] = 0;
     __syncthreads();
-    walk_chunk<false>(V, i0, i1, w0, w1, hist, nullptr, 0);
+    walk_chunk<false>(V, i0, i1, w0, w1, hist, wave_lds, nullptr, 0);
     __syncthreads();
     uint32_t* out = V.bin_counts + (int64_t)g * T;
     for (int j = threadIdx.x; j < w1 - w0; j += blockDim.x) out[w0 + j] = hist[j];
@@ -225,6 +241,7 @@ __global__ void __launch_bounds__(1024) bin_tilescan_kernel(const DeviceBatch* _
 __global__ void __launch_bounds__(kBinBlockThreads) bin_scatter_kernel(const DeviceBatch* __restrict__ db, uint2* pairs,
                                                                        uint64_t capacity) {
   __shared__ uint32_t cursor[kBinLdsTiles];
+  __shared__ WaveSplats wave_lds[kBinBlockThreads / 64];
   const int64_t blk = blockIdx.x;
   const int v = view_of_block(db->bin_prefix, db->nviews, blk);
   const ViewDesc& V = db->views[v];
@@ -237,7 +254,7 @@ __global__ void __launch_bounds__(kBinBlockThreads) bin_scatter_kernel(const Dev
     const int w1 = min(T, w0 + kBinLdsTiles);
     for (int j = threadIdx.x; j < w1 - w0; j += blockDim.x) cursor[j] = V.ranges[w0 + j].x + row[w0 + j];
     __syncthreads();
-    walk_chunk<true>(V, i0, i1, w0, w1, cursor, pairs, capacity);
+    walk_chunk<true>(V, i0, i1, w0, w1, cursor, wave_lds, pairs, capacity);
     __syncthreads();
   }
 }

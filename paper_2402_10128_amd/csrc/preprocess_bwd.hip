@@ -2,15 +2,48 @@
 //
 // From the accumulated gradients of a splat's 2-D quantities (mean2D, conic a/b/c, opacity, colour and,
 // with the GEF falloff, beta) to its mean, log-scale, quaternion, opacity logit, SH coefficients and
-// beta.  Forward quantities are recomputed in binary32; the decisions (culling, guard clamp of the
-// Jacobian, colour clamp) come from the record.  Nothing here feeds a decision, so this file is built
-// with contraction and fast division allowed.
+// beta.  The chain runs in binary64: forward quantities (scales, opacity, rotation, covariance, the
+// conic, the view direction) are recomputed in binary64 from the binary32 inputs, and only the decisions
+// (culling, guard clamp of the Jacobian, colour clamp) come from the record.  Several of the sums cancel
+// (e.g. the scale gradient of an axis along the view ray), and binary32 there leaves an error
+// proportional to the splat's whole gradient; the FP64 vector rate of gfx950 equals its non-packed FP32
+// rate and the kernel is HBM-bound, so binary64 costs little.  Nothing here feeds a decision, so this
+// file is built with contraction allowed.
 // Memory: ~600 B per splat at SH degree 3 (parameters, record, 2-D gradients in; parameter gradients
 // out): HBM-bound.
 #include "ges_internal.h"
-#include "sh_basis.h"
 
 namespace ges {
+
+// Real SH normalisations in binary64 (same values as the forward's binary32 constants, unrounded).
+constexpr double kD0 = 0.28209479177387814;   // 1/(2 sqrt(pi))
+constexpr double kD1 = 0.4886025119029199;    // sqrt(3/pi)/2
+constexpr double kD2a = 1.0925484305920792;   // sqrt(15/pi)/2
+constexpr double kD2b = 0.31539156525252005;  // sqrt(5/pi)/4
+constexpr double kD2c = 0.5462742152960396;   // sqrt(15/pi)/4
+constexpr double kD3a = 0.5900435899266435;   // sqrt(35/(2 pi))/4
+constexpr double kD3b = 2.890611442640554;    // sqrt(105/pi)/2
+constexpr double kD3c = 0.4570457994644658;   // sqrt(21/(2 pi))/4
+constexpr double kD3d = 0.3731763325901154;   // sqrt(7/pi)/4
+constexpr double kD3e = 1.445305721320277;    // sqrt(105/pi)/4
+
+__device__ __forceinline__ void sh_basis_f64(double x, double y, double z, int degree, double* Y) {
+  Y[0] = kD0;
+  if (degree < 1) return;
+  Y[1] = -kD1 * y; Y[2] = kD1 * z; Y[3] = -kD1 * x;
+  if (degree < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = kD2a * x * y; Y[5] = -kD2a * y * z; Y[6] = kD2b * (2.0 * zz - xx - yy); Y[7] = -kD2a * x * z;
+  Y[8] = kD2c * (xx - yy);
+  if (degree < 3) return;
+  Y[9] = -kD3a * y * (3.0 * xx - yy);
+  Y[10] = kD3b * x * y * z;
+  Y[11] = -kD3c * y * (4.0 * zz - xx - yy);
+  Y[12] = kD3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+  Y[13] = -kD3c * x * (4.0 * zz - xx - yy);
+  Y[14] = kD3e * z * (xx - yy);
+  Y[15] = -kD3a * x * (xx - 3.0 * yy);
+}
 
 template <int D>
 __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_splat_grads& G, int64_t i) {
@@ -27,88 +60,96 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
     return;
   }
   const uint32_t flags = (uint32_t)__float_as_int(r3.x) >> 24;
-  const float4 r0 = V.rec[4 * i + 0];
-  const float4 r1 = V.rec[4 * i + 1];
   const double2* gp = reinterpret_cast<const double2*>(V.grad2d + (int64_t)kGradStride * i);
   const double2 g01 = gp[0], g23 = gp[1], g45 = gp[2], g67 = gp[3], g89 = gp[4];
-  const float gu = (float)g01.x, gv = (float)g01.y, ga = (float)g23.x, gb = (float)g23.y;
-  const float gc = (float)g45.x, gop = (float)g45.y;
-  const float grgb[3] = {(float)g67.x, (float)g67.y, (float)g89.x};
-  const float gbeta2 = (float)g89.y;
+  const double gu = g01.x, gv = g01.y, ga = g23.x, gb = g23.y, gc = g45.x, gop = g45.y;
+  const double grgb[3] = {g67.x, g67.y, g89.x};
+  const double gbeta2 = g89.y;
 
   const float* mu = V.means + 3 * i;
-  const float mx = mu[0], my = mu[1], mz = mu[2];
+  const double mx = mu[0], my = mu[1], mz = mu[2];
   const float4 qv = reinterpret_cast<const float4*>(V.quats)[i];
-  const float beta = V.beta[i];
-  const float* R = V.R;
-  float p[3];
-  for (int r = 0; r < 3; ++r) p[r] = R[3 * r] * mx + R[3 * r + 1] * my + R[3 * r + 2] * mz + V.t[r];
-  const float z = p[2];
-  const float s[3] = {__expf(V.log_scales[3 * i]), __expf(V.log_scales[3 * i + 1]), __expf(V.log_scales[3 * i + 2])};
-  const float op = r1.z;
+  const double beta = V.beta[i];
+  double R[9];
+  for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+  double p[3];
+  for (int r = 0; r < 3; ++r) p[r] = R[3 * r] * mx + R[3 * r + 1] * my + R[3 * r + 2] * mz + (double)V.t[r];
+  const double z = p[2];
+  const double s[3] = {exp((double)V.log_scales[3 * i]), exp((double)V.log_scales[3 * i + 1]),
+                       exp((double)V.log_scales[3 * i + 2])};
+  const double op = 1.0 / (1.0 + exp(-(double)V.logits[i]));
 
   // quaternion
-  const float nn = qv.x * qv.x + qv.y * qv.y + qv.z * qv.z + qv.w * qv.w;
-  const float nr = sqrtf(nn);
-  const float qw = qv.x / nr, qx = qv.y / nr, qy = qv.z / nr, qz = qv.w / nr;
-  float Q[9];
-  Q[0] = 1.f - 2.f * (qy * qy + qz * qz); Q[1] = 2.f * (qx * qy - qw * qz); Q[2] = 2.f * (qx * qz + qw * qy);
-  Q[3] = 2.f * (qx * qy + qw * qz); Q[4] = 1.f - 2.f * (qx * qx + qz * qz); Q[5] = 2.f * (qy * qz - qw * qx);
-  Q[6] = 2.f * (qx * qz - qw * qy); Q[7] = 2.f * (qy * qz + qw * qx); Q[8] = 1.f - 2.f * (qx * qx + qy * qy);
-  float phi = 1.f;
-  if (V.falloff == GES_FALLOFF_PHI) phi = 2.f / (1.f + __expf(-(V.rho * beta - 2.f * V.rho)));
-  const float S[3] = {phi * s[0], phi * s[1], phi * s[2]};
-  float Mm[9];
+  const double q0 = qv.x, q1 = qv.y, q2 = qv.z, q3 = qv.w;
+  const double nr = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  const double qw = q0 / nr, qx = q1 / nr, qy = q2 / nr, qz = q3 / nr;
+  double Q[9];
+  Q[0] = 1.0 - 2.0 * (qy * qy + qz * qz); Q[1] = 2.0 * (qx * qy - qw * qz); Q[2] = 2.0 * (qx * qz + qw * qy);
+  Q[3] = 2.0 * (qx * qy + qw * qz); Q[4] = 1.0 - 2.0 * (qx * qx + qz * qz); Q[5] = 2.0 * (qy * qz - qw * qx);
+  Q[6] = 2.0 * (qx * qz - qw * qy); Q[7] = 2.0 * (qy * qz + qw * qx); Q[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+  double phi = 1.0;
+  const double rho = V.rho;
+  if (V.falloff == GES_FALLOFF_PHI) phi = 2.0 / (1.0 + exp(-(rho * beta - 2.0 * rho)));
+  const double S[3] = {phi * s[0], phi * s[1], phi * s[2]};
+  double Mm[9];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) Mm[3 * r + c] = Q[3 * r + c] * S[c];
-  float Sig[9];
+  double Sig[9];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) Sig[3 * r + c] = Mm[3 * r] * Mm[3 * c] + Mm[3 * r + 1] * Mm[3 * c + 1] + Mm[3 * r + 2] * Mm[3 * c + 2];
 
-  const float fx = V.fx, fy = V.fy;
+  // perspective Jacobian at p; the guard clamp of x/z, y/z is the forward's decision (record flags)
+  const double fx = V.fx, fy = V.fy;
   const bool clx = (flags & 8u) != 0, cly = (flags & 16u) != 0;
-  float txz = p[0] / z, tyz = p[1] / z;
-  txz = fminf(V.limx, fmaxf(-V.limx, txz));
-  tyz = fminf(V.limy, fmaxf(-V.limy, tyz));
-  const float xc = clx ? txz * z : p[0];
-  const float yc = cly ? tyz * z : p[1];
-  const float iz = 1.f / z, iz2 = iz * iz, iz3 = iz2 * iz;
-  const float J00 = fx * iz, J11 = fy * iz, J02 = -fx * xc * iz2, J12 = -fy * yc * iz2;
-  float T[6];
+  const double limx = 1.3 * (0.5 * (double)V.width / fx), limy = 1.3 * (0.5 * (double)V.height / fy);
+  const double txz = clx ? copysign(limx, p[0] / z) : p[0] / z;
+  const double tyz = cly ? copysign(limy, p[1] / z) : p[1] / z;
+  const double xc = txz * z, yc = tyz * z;
+  const double iz = 1.0 / z, iz2 = iz * iz, iz3 = iz2 * iz;
+  const double J00 = fx * iz, J11 = fy * iz, J02 = -fx * xc * iz2, J12 = -fy * yc * iz2;
+  double T[6];
   for (int c = 0; c < 3; ++c) {
     T[c] = J00 * R[c] + J02 * R[6 + c];
     T[3 + c] = J11 * R[3 + c] + J12 * R[6 + c];
   }
+  // 2-D covariance and its inverse (the conic), recomputed in binary64
+  double TS[6];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c) TS[3 * r + c] = T[3 * r] * Sig[c] + T[3 * r + 1] * Sig[3 + c] + T[3 * r + 2] * Sig[6 + c];
+  const double c00 = TS[0] * T[0] + TS[1] * T[1] + TS[2] * T[2] + 0.3;
+  const double c01 = TS[0] * T[3] + TS[1] * T[4] + TS[2] * T[5];
+  const double c11 = TS[3] * T[3] + TS[4] * T[4] + TS[5] * T[5] + 0.3;
+  const double det = c00 * c11 - c01 * c01;
+  const double ca = c11 / det, cb = -c01 / det, cc = c00 / det;
 
   // conic -> covariance: dL/dcov = -C G_C C with C = conic, G_C the symmetric gradient
-  const float ca = r0.z, cb = r0.w, cc = r1.x;
-  const float gx = -(ca * ca * ga + ca * cb * gb + cb * cb * gc);
-  const float gy = -(2.f * ca * cb * ga + (ca * cc + cb * cb) * gb + 2.f * cb * cc * gc);
-  const float gz = -(cb * cb * ga + cb * cc * gb + cc * cc * gc);
+  const double gx = -(ca * ca * ga + ca * cb * gb + cb * cb * gc);
+  const double gy = -(2.0 * ca * cb * ga + (ca * cc + cb * cb) * gb + 2.0 * cb * cc * gc);
+  const double gz = -(cb * cb * ga + cb * cc * gb + cc * cc * gc);
   // G2: gradient w.r.t. the full symmetric 2x2 covariance (off-diagonal split in half)
-  const float G2[4] = {gx, 0.5f * gy, 0.5f * gy, gz};
+  const double G2[4] = {gx, 0.5 * gy, 0.5 * gy, gz};
 
   // cov = T Sigma T^T: dL/dSigma = T^T G2 T (symmetric), dL/dT = 2 G2 T Sigma
-  float GT[6];   // G2 T (2x3)
+  double GT[6];   // G2 T (2x3)
   for (int c = 0; c < 3; ++c) {
     GT[c] = G2[0] * T[c] + G2[1] * T[3 + c];
     GT[3 + c] = G2[2] * T[c] + G2[3] * T[3 + c];
   }
-  float GS[9];   // T^T (G2 T)
+  double GS[9];   // T^T (G2 T)
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) GS[3 * r + c] = T[r] * GT[c] + T[3 + r] * GT[3 + c];
-  float gT[6];
+  double gT[6];
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 3; ++c)
-      gT[3 * r + c] = 2.f * (GT[3 * r] * Sig[c] + GT[3 * r + 1] * Sig[3 + c] + GT[3 * r + 2] * Sig[6 + c]);
+      gT[3 * r + c] = 2.0 * (GT[3 * r] * Sig[c] + GT[3 * r + 1] * Sig[3 + c] + GT[3 * r + 2] * Sig[6 + c]);
   // T = J W: dL/dJ = dL/dT W^T
-  const float gJ00 = gT[0] * R[0] + gT[1] * R[1] + gT[2] * R[2];
-  const float gJ02 = gT[0] * R[6] + gT[1] * R[7] + gT[2] * R[8];
-  const float gJ11 = gT[3] * R[3] + gT[4] * R[4] + gT[5] * R[5];
-  const float gJ12 = gT[3] * R[6] + gT[4] * R[7] + gT[5] * R[8];
-  float gp0 = 0.f, gp1 = 0.f, gz_ = 0.f;
-  gz_ += -fx * iz2 * gJ00 + 2.f * fx * xc * iz3 * gJ02 - fy * iz2 * gJ11 + 2.f * fy * yc * iz3 * gJ12;
-  const float gxc = -fx * iz2 * gJ02, gyc = -fy * iz2 * gJ12;
+  const double gJ00 = gT[0] * R[0] + gT[1] * R[1] + gT[2] * R[2];
+  const double gJ02 = gT[0] * R[6] + gT[1] * R[7] + gT[2] * R[8];
+  const double gJ11 = gT[3] * R[3] + gT[4] * R[4] + gT[5] * R[5];
+  const double gJ12 = gT[3] * R[6] + gT[4] * R[7] + gT[5] * R[8];
+  double gp0 = 0.0, gp1 = 0.0, gz_ = 0.0;
+  gz_ += -fx * iz2 * gJ00 + 2.0 * fx * xc * iz3 * gJ02 - fy * iz2 * gJ11 + 2.0 * fy * yc * iz3 * gJ12;
+  const double gxc = -fx * iz2 * gJ02, gyc = -fy * iz2 * gJ12;
   if (clx) gz_ += gxc * txz; else gp0 += gxc;
   if (cly) gz_ += gyc * tyz; else gp1 += gyc;
   // mean2D
@@ -117,81 +158,83 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
   gz_ += -(gu * fx * p[0] + gv * fy * p[1]) * iz2;
 
   // Sigma = M M^T: dL/dM = 2 GS M
-  float gM[9];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) gM[3 * r + c] = 2.f * (GS[3 * r] * Mm[c] + GS[3 * r + 1] * Mm[3 + c] + GS[3 * r + 2] * Mm[6 + c]);
-  float gS[3] = {0.f, 0.f, 0.f};
-  float gQ[9];
+  double gS[3] = {0.0, 0.0, 0.0};
+  double gQ[9];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) {
-      gS[c] += gM[3 * r + c] * Q[3 * r + c];
-      gQ[3 * r + c] = gM[3 * r + c] * S[c];
+      const double gM = 2.0 * (GS[3 * r] * Mm[c] + GS[3 * r + 1] * Mm[3 + c] + GS[3 * r + 2] * Mm[6 + c]);
+      gS[c] += gM * Q[3 * r + c];
+      gQ[3 * r + c] = gM * S[c];
     }
-  float gphi = gS[0] * s[0] + gS[1] * s[1] + gS[2] * s[2];
+  const double gphi = gS[0] * s[0] + gS[1] * s[1] + gS[2] * s[2];
   if (G.log_scales)
-    for (int c = 0; c < 3; ++c) G.log_scales[3 * i + c] = gS[c] * phi * s[c];
+    for (int c = 0; c < 3; ++c) G.log_scales[3 * i + c] = (float)(gS[c] * phi * s[c]);
   if (G.beta) {
-    float gb_ = 0.f;
-    if (V.falloff == GES_FALLOFF_PHI) gb_ = gphi * V.rho * phi * (1.f - 0.5f * phi);
+    double gb_ = 0.0;
+    if (V.falloff == GES_FALLOFF_PHI) gb_ = gphi * rho * phi * (1.0 - 0.5 * phi);
     else gb_ = gbeta2;
-    G.beta[i] = gb_;
+    G.beta[i] = (float)gb_;
   }
   // rotation -> unit quaternion -> quaternion
   {
-    const float w = qw, x = qx, y = qy, zq = qz;
-    float gw = 2.f * (-zq * gQ[1] + y * gQ[2] + zq * gQ[3] - x * gQ[5] - y * gQ[6] + x * gQ[7]);
-    float gxq = 2.f * (y * gQ[1] + zq * gQ[2] + y * gQ[3] - 2.f * x * gQ[4] - w * gQ[5] + zq * gQ[6] + w * gQ[7] - 2.f * x * gQ[8]);
-    float gyq = 2.f * (-2.f * y * gQ[0] + x * gQ[1] + w * gQ[2] + x * gQ[3] + zq * gQ[5] - w * gQ[6] + zq * gQ[7] - 2.f * y * gQ[8]);
-    float gzq = 2.f * (-2.f * zq * gQ[0] - w * gQ[1] + x * gQ[2] + w * gQ[3] - 2.f * zq * gQ[4] + y * gQ[5] + x * gQ[6] + y * gQ[7]);
-    const float dot = gw * w + gxq * x + gyq * y + gzq * zq;
+    const double w = qw, x = qx, y = qy, zq = qz;
+    const double gw = 2.0 * (-zq * gQ[1] + y * gQ[2] + zq * gQ[3] - x * gQ[5] - y * gQ[6] + x * gQ[7]);
+    const double gxq = 2.0 * (y * gQ[1] + zq * gQ[2] + y * gQ[3] - 2.0 * x * gQ[4] - w * gQ[5] + zq * gQ[6] + w * gQ[7] - 2.0 * x * gQ[8]);
+    const double gyq = 2.0 * (-2.0 * y * gQ[0] + x * gQ[1] + w * gQ[2] + x * gQ[3] + zq * gQ[5] - w * gQ[6] + zq * gQ[7] - 2.0 * y * gQ[8]);
+    const double gzq = 2.0 * (-2.0 * zq * gQ[0] - w * gQ[1] + x * gQ[2] + w * gQ[3] - 2.0 * zq * gQ[4] + y * gQ[5] + x * gQ[6] + y * gQ[7]);
+    const double dot = gw * w + gxq * x + gyq * y + gzq * zq;
     if (G.quats)
       reinterpret_cast<float4*>(G.quats)[i] =
-          make_float4((gw - w * dot) / nr, (gxq - x * dot) / nr, (gyq - y * dot) / nr, (gzq - zq * dot) / nr);
+          make_float4((float)((gw - w * dot) / nr), (float)((gxq - x * dot) / nr), (float)((gyq - y * dot) / nr),
+                      (float)((gzq - zq * dot) / nr));
   }
-  if (G.opacity_logits) G.opacity_logits[i] = gop * op * (1.f - op);
+  if (G.opacity_logits) G.opacity_logits[i] = (float)(gop * op * (1.0 - op));
 
   // colour: SH coefficients and the view direction
-  float gmu[3] = {0.f, 0.f, 0.f};
+  double gmu[3] = {0.0, 0.0, 0.0};
   {
-    const float e0 = mx - V.campos[0], e1 = my - V.campos[1], e2 = mz - V.campos[2];
-    const float len = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
-    const float x = e0 / len, y = e1 / len, zz_ = e2 / len;
-    float Y[16];
-    sh_basis(x, y, zz_, D, Y);
-    float gc3[3];
-    for (int ch = 0; ch < 3; ++ch) gc3[ch] = (flags & (1u << ch)) ? 0.f : grgb[ch];
+    double cpos[3];
+    for (int j = 0; j < 3; ++j) cpos[j] = -(R[j] * (double)V.t[0] + R[3 + j] * (double)V.t[1] + R[6 + j] * (double)V.t[2]);
+    const double e0 = mx - cpos[0], e1 = my - cpos[1], e2 = mz - cpos[2];
+    const double len = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    const double x = e0 / len, y = e1 / len, zz_ = e2 / len;
+    double Y[16];
+    sh_basis_f64(x, y, zz_, D, Y);
+    double gc3[3];
+    for (int ch = 0; ch < 3; ++ch) gc3[ch] = (flags & (1u << ch)) ? 0.0 : grgb[ch];
     const float* shc = V.sh + (int64_t)3 * K * i;
     if (G.sh)
       for (int k = 0; k < K; ++k)
-        for (int ch = 0; ch < 3; ++ch) G.sh[(int64_t)3 * K * i + 3 * k + ch] = Y[k] * gc3[ch];
+        for (int ch = 0; ch < 3; ++ch) G.sh[(int64_t)3 * K * i + 3 * k + ch] = (float)(Y[k] * gc3[ch]);
     if (D > 0) {
       // dL/dY_k = sum_ch gc3[ch] sh[k][ch]
-      float gY[16];
-      for (int k = 0; k < K; ++k) gY[k] = gc3[0] * shc[3 * k] + gc3[1] * shc[3 * k + 1] + gc3[2] * shc[3 * k + 2];
-      float gdx = 0.f, gdy = 0.f, gdz = 0.f;
-      gdy += -kC1 * gY[1]; gdz += kC1 * gY[2]; gdx += -kC1 * gY[3];
+      double gY[16];
+      for (int k = 0; k < K; ++k)
+        gY[k] = gc3[0] * (double)shc[3 * k] + gc3[1] * (double)shc[3 * k + 1] + gc3[2] * (double)shc[3 * k + 2];
+      double gdx = 0.0, gdy = 0.0, gdz = 0.0;
+      gdy += -kD1 * gY[1]; gdz += kD1 * gY[2]; gdx += -kD1 * gY[3];
       if (D > 1) {
-        const float xx = x * x, yy = y * y, z2v = zz_ * zz_;
-        gdx += kC2a * y * gY[4]; gdy += kC2a * x * gY[4];
-        gdy += -kC2a * zz_ * gY[5]; gdz += -kC2a * y * gY[5];
-        gdx += -2.f * kC2b * x * gY[6]; gdy += -2.f * kC2b * y * gY[6]; gdz += 4.f * kC2b * zz_ * gY[6];
-        gdx += -kC2a * zz_ * gY[7]; gdz += -kC2a * x * gY[7];
-        gdx += 2.f * kC2c * x * gY[8]; gdy += -2.f * kC2c * y * gY[8];
+        const double xx = x * x, yy = y * y, z2v = zz_ * zz_;
+        gdx += kD2a * y * gY[4]; gdy += kD2a * x * gY[4];
+        gdy += -kD2a * zz_ * gY[5]; gdz += -kD2a * y * gY[5];
+        gdx += -2.0 * kD2b * x * gY[6]; gdy += -2.0 * kD2b * y * gY[6]; gdz += 4.0 * kD2b * zz_ * gY[6];
+        gdx += -kD2a * zz_ * gY[7]; gdz += -kD2a * x * gY[7];
+        gdx += 2.0 * kD2c * x * gY[8]; gdy += -2.0 * kD2c * y * gY[8];
         if (D > 2) {
-          gdx += -kC3a * 6.f * x * y * gY[9]; gdy += -kC3a * (3.f * xx - 3.f * yy) * gY[9];
-          gdx += kC3b * y * zz_ * gY[10]; gdy += kC3b * x * zz_ * gY[10]; gdz += kC3b * x * y * gY[10];
-          gdx += 2.f * kC3c * x * y * gY[11]; gdy += -kC3c * (4.f * z2v - xx - 3.f * yy) * gY[11];
-          gdz += -8.f * kC3c * y * zz_ * gY[11];
-          gdx += -6.f * kC3d * x * zz_ * gY[12]; gdy += -6.f * kC3d * y * zz_ * gY[12];
-          gdz += kC3d * (6.f * z2v - 3.f * xx - 3.f * yy) * gY[12];
-          gdx += -kC3c * (4.f * z2v - 3.f * xx - yy) * gY[13]; gdy += 2.f * kC3c * x * y * gY[13];
-          gdz += -8.f * kC3c * x * zz_ * gY[13];
-          gdx += 2.f * kC3e * x * zz_ * gY[14]; gdy += -2.f * kC3e * y * zz_ * gY[14]; gdz += kC3e * (xx - yy) * gY[14];
-          gdx += -kC3a * (3.f * xx - 3.f * yy) * gY[15]; gdy += 6.f * kC3a * x * y * gY[15];
+          gdx += -kD3a * 6.0 * x * y * gY[9]; gdy += -kD3a * (3.0 * xx - 3.0 * yy) * gY[9];
+          gdx += kD3b * y * zz_ * gY[10]; gdy += kD3b * x * zz_ * gY[10]; gdz += kD3b * x * y * gY[10];
+          gdx += 2.0 * kD3c * x * y * gY[11]; gdy += -kD3c * (4.0 * z2v - xx - 3.0 * yy) * gY[11];
+          gdz += -8.0 * kD3c * y * zz_ * gY[11];
+          gdx += -6.0 * kD3d * x * zz_ * gY[12]; gdy += -6.0 * kD3d * y * zz_ * gY[12];
+          gdz += kD3d * (6.0 * z2v - 3.0 * xx - 3.0 * yy) * gY[12];
+          gdx += -kD3c * (4.0 * z2v - 3.0 * xx - yy) * gY[13]; gdy += 2.0 * kD3c * x * y * gY[13];
+          gdz += -8.0 * kD3c * x * zz_ * gY[13];
+          gdx += 2.0 * kD3e * x * zz_ * gY[14]; gdy += -2.0 * kD3e * y * zz_ * gY[14]; gdz += kD3e * (xx - yy) * gY[14];
+          gdx += -kD3a * (3.0 * xx - 3.0 * yy) * gY[15]; gdy += 6.0 * kD3a * x * y * gY[15];
         }
       }
       // d = e/|e|: dL/de = (dL/dd - d (d . dL/dd)) / |e|
-      const float dd = gdx * x + gdy * y + gdz * zz_;
+      const double dd = gdx * x + gdy * y + gdz * zz_;
       gmu[0] += (gdx - x * dd) / len;
       gmu[1] += (gdy - y * dd) / len;
       gmu[2] += (gdz - zz_ * dd) / len;
@@ -199,7 +242,8 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
   }
   // p = W mu + t
   if (G.means) {
-    for (int c = 0; c < 3; ++c) G.means[3 * i + c] = gmu[c] + R[c] * gp0 + R[3 + c] * gp1 + R[6 + c] * gz_;
+    for (int c = 0; c < 3; ++c)
+      G.means[3 * i + c] = (float)(gmu[c] + R[c] * gp0 + R[3 + c] * gp1 + R[6 + c] * gz_);
   }
 }
 

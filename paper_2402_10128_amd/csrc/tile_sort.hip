@@ -3,14 +3,16 @@
 // Every tile's bucket holds (depth bits, splat index) pairs in arbitrary order.  One block per tile
 // sorts them ascending by depth (camera z > 0, so the IEEE bits order like the values), ties broken by
 // the splat index, which makes the order unique and equal to a stable sort of the pairs in splat-index
-// order.  Method: LSD radix sort with 8-bit digits, each pass a stable counting sort in which a wave
-// ranks equal digits with eight ballots; digits that are constant across the tile (known from an
-// AND/OR reduction) are skipped.  Runs of equal depth are then ordered by index: runs of at most 32 by
-// insertion sort, longer ones (only in degenerate scenes) by extra index passes placed before the
+// order.  Method: LSD radix sort with 8-bit digits; digits that are constant across the tile (known from
+// an AND/OR reduction) are skipped.  Each pass is a stable counting sort ranked wave by wave: a wave owns
+// a contiguous segment of the list, ranks its elements 64 at a time with eight ballots against
+// wave-private digit counters in LDS, and only the scatter needs block barriers (five per pass,
+// independent of the list length).  Runs of equal depth are then ordered by index: runs of at most 32
+// by insertion sort, longer ones (only in degenerate scenes) by extra index passes placed before the
 // depth passes.
-// Two LDS-resident shapes: 256 threads for lists of up to 4,096 pairs (38 KB of LDS, several blocks
-// per CU) and 1,024 threads for lists of up to 16,384 pairs (146 KB: gfx950 gives a workgroup up to
-// 160 KB).  Longer lists stream through global memory with the same passes.
+// Shapes: 256 threads for lists of up to 4,096 pairs (36 KB of LDS, several blocks per CU) and 1,024
+// threads for up to 16,384 (144 KB; gfx950 gives a workgroup up to 160 KB).  Longer lists stream
+// through global memory in chunks of 16,384 with the same ranking.
 #include "ges_internal.h"
 
 namespace ges {
@@ -21,11 +23,12 @@ constexpr int kLargeCap = 16384;
 template <int CAP, int THREADS>
 struct SortShared {
   static constexpr int kWaves = THREADS / 64;
+  static constexpr int kR = CAP / THREADS;   // elements per lane
   uint32_t key[CAP];
   uint32_t val[CAP];
-  uint32_t hist[256];
-  uint32_t run[256];
-  uint32_t wcnt[kWaves][256];
+  uint32_t cnt[kWaves][256];   // per-wave digit counters, then per-wave scatter bases
+  uint32_t carry[256];         // streamed lists: base of every digit for the next chunk
+  uint32_t wsum[kWaves];
   uint32_t kand, kor, vand, vor;
   uint32_t long_run;
 };
@@ -35,11 +38,17 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Stable rank of one element per thread within the current round: returns its destination given the
-// running digit offsets; updates the offsets for the next round.  `valid` lanes participate.
-template <class SS>
-__device__ __forceinline__ uint32_t rank_round(SS& S, bool valid, uint32_t dg) {
-  const int w = threadIdx.x >> 6;
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t digit_of(uint32_t k, uint32_t v, bool by_key, int shift) {
+  return ((by_key ? k : v) >> shift) & 0xffu;
+}
+
+// Lanes of this wave holding the same digit (valid lanes only).
+__device__ __forceinline__ uint64_t match_digit(bool valid, uint32_t dg) {
   uint64_t peers = __ballot(valid);
 #pragma unroll
   for (int bit = 0; bit < 8; ++bit) {
@@ -47,93 +56,117 @@ __device__ __forceinline__ uint32_t rank_round(SS& S, bool valid, uint32_t dg) {
     const uint64_t m = __ballot(valid && b);
     peers &= b ? m : ~m;
   }
-  const uint32_t lrank = (uint32_t)__popcll(peers & lanemask_lt());
-  const bool leader = valid && (peers & lanemask_lt()) == 0;
-  if (leader) S.wcnt[w][dg] = (uint32_t)__popcll(peers);
-  __syncthreads();
-  uint32_t pos = 0;
-  if (valid) {
-    uint32_t pre = 0;
-    for (int k = 0; k < w; ++k) pre += S.wcnt[k][dg];
-    pos = S.run[dg] + pre + lrank;
-  }
-  __syncthreads();
-  if (threadIdx.x < 256) {
-    const int d = threadIdx.x;
-    uint32_t add = 0;
-#pragma unroll
-    for (int k = 0; k < SS::kWaves; ++k) { add += S.wcnt[k][d]; S.wcnt[k][d] = 0; }
-    S.run[d] += add;
-  }
-  __syncthreads();
-  return pos;
+  return peers;
 }
 
-// Exclusive scan of S.hist into S.run (256 digits, held by threads 0..255).
+// Rank of an element among the wave's elements of the same digit seen so far (in element order);
+// advances the wave's counter of that digit.
 template <class SS>
-__device__ __forceinline__ void scan_hist(SS& S) {
+__device__ __forceinline__ uint32_t wave_rank(SS& S, bool valid, uint32_t dg) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t peers = match_digit(valid, dg);
+  uint32_t r = 0;
+  if (valid) {
+    const uint32_t before = S.cnt[w][dg];
+    r = before + (uint32_t)__popcll(peers & lanemask_lt());
+    if ((peers >> lane) == 1ull) S.cnt[w][dg] = before + (uint32_t)__popcll(peers);   // last peer
+  }
+  wave_lds_fence();
+  return r;
+}
+
+// After every wave has counted: turn the per-wave counts into scatter bases, digit-major then
+// wave-major, offset by `base[d]` (streamed lists) or by the exclusive digit scan (LDS lists).
+// For streamed lists also advance base[d] by the chunk's count of digit d.
+template <class SS>
+__device__ __forceinline__ void counts_to_bases(SS& S, bool streamed) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  uint32_t x = 0, s = 0;
+  uint32_t tot = 0;
   if (t < 256) {
-    x = S.hist[t];
-    s = x;
+#pragma unroll
+    for (int k = 0; k < SS::kWaves; ++k) { const uint32_t c = S.cnt[k][t]; S.cnt[k][t] = tot; tot += c; }
+  }
+  uint32_t start = 0;
+  if (streamed) {
+    if (t < 256) { start = S.carry[t]; S.carry[t] = start + tot; }
+  } else {
+    uint32_t s = tot;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const uint32_t y = __shfl_up(s, d, 64);
       if (lane >= d) s += y;
     }
-    if (lane == 63) S.wcnt[w][0] = s;
+    if (t < 256 && lane == 63) S.wsum[w] = s;
+    __syncthreads();
+    if (t < 256) {
+      start = s - tot;
+      for (int k = 0; k < w; ++k) start += S.wsum[k];
+    }
   }
-  __syncthreads();
-  uint32_t pre = 0;
-  if (t < 256)
-    for (int k = 0; k < w; ++k) pre += S.wcnt[k][0];
-  __syncthreads();
   if (t < 256) {
-    S.run[t] = pre + s - x;
-    S.wcnt[w][0] = 0;
+#pragma unroll
+    for (int k = 0; k < SS::kWaves; ++k) S.cnt[k][t] += start;
   }
   __syncthreads();
 }
 
 template <class SS>
-__device__ __forceinline__ void init_shared(SS& S) {
-  if (threadIdx.x == 0) { S.kand = 0xffffffffu; S.kor = 0u; S.vand = 0xffffffffu; S.vor = 0u; S.long_run = 0u; }
-  for (int d = threadIdx.x; d < 256; d += blockDim.x)
-    for (int w = 0; w < SS::kWaves; ++w) S.wcnt[w][d] = 0;
+__device__ __forceinline__ void zero_wave_counters(SS& S) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = lane; d < 256; d += 64) S.cnt[w][d] = 0;
+  wave_lds_fence();
 }
 
-// ---------------------------------------------------------------- LDS path
-// Registers hold the elements in round order: element e = r * THREADS + t.
+// Segment of each wave for a list of m elements: a multiple of 64, so rounds never straddle waves.
+template <int THREADS>
+__device__ __forceinline__ int wave_segment(int m) {
+  constexpr int W = THREADS / 64;
+  const int per = (m + W - 1) / W;
+  return (per + 63) & ~63;
+}
+
+// ---------------------------------------------------------------- LDS-resident lists (n <= CAP)
+// Element e of the list lives in the registers of wave e / seg, round (e % seg) / 64, lane e % 64.
 template <int CAP, int THREADS>
 __device__ __forceinline__ void lds_pass(SortShared<CAP, THREADS>& S, uint32_t (&k)[CAP / THREADS],
-                                         uint32_t (&vv)[CAP / THREADS], int n, bool by_key, int shift) {
+                                         uint32_t (&vv)[CAP / THREADS], int n, int seg, bool by_key, int shift) {
   constexpr int R = CAP / THREADS;
-  const int t = threadIdx.x;
-  if (t < 256) S.hist[t] = 0;
-  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e0 = w * seg + lane;
+  uint32_t rank[R];
+  zero_wave_counters(S);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int e = r * THREADS + t;
-    if (e < n) atomicAdd(&S.hist[((by_key ? k[r] : vv[r]) >> shift) & 0xffu], 1u);
+    if (r * 64 >= seg) break;
+    const bool valid = e0 + r * 64 < n;
+    rank[r] = wave_rank(S, valid, valid ? digit_of(k[r], vv[r], by_key, shift) : 0u);
   }
   __syncthreads();
-  scan_hist(S);
+  counts_to_bases(S, false);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    if (r * THREADS >= n) break;
-    const int e = r * THREADS + t;
-    const bool valid = e < n;
-    const uint32_t dg = valid ? (((by_key ? k[r] : vv[r]) >> shift) & 0xffu) : 0u;
-    const uint32_t pos = rank_round(S, valid, dg);
-    if (valid) { S.key[pos] = k[r]; S.val[pos] = vv[r]; }
+    if (r * 64 >= seg) break;
+    if (e0 + r * 64 < n) {
+      const uint32_t pos = S.cnt[w][digit_of(k[r], vv[r], by_key, shift)] + rank[r];
+      S.key[pos] = k[r];
+      S.val[pos] = vv[r];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int e = r * THREADS + t;
+    if (r * 64 >= seg) break;
+    const int e = e0 + r * 64;
     if (e < n) { k[r] = S.key[e]; vv[r] = S.val[e]; }
   }
+  __syncthreads();
+}
+
+template <class SS>
+__device__ __forceinline__ void reduce_bits(SS& S, uint32_t kand, uint32_t kor, uint32_t vand, uint32_t vor) {
+  if (threadIdx.x == 0) { S.kand = 0xffffffffu; S.kor = 0u; S.vand = 0xffffffffu; S.vor = 0u; S.long_run = 0u; }
+  __syncthreads();
+  atomicAnd(&S.kand, kand); atomicOr(&S.kor, kor); atomicAnd(&S.vand, vand); atomicOr(&S.vor, vor);
   __syncthreads();
 }
 
@@ -141,31 +174,31 @@ template <int CAP, int THREADS>
 __device__ void sort_lds(SortShared<CAP, THREADS>& S, const uint2* __restrict__ in, uint32_t* __restrict__ out_ids,
                          int n) {
   constexpr int R = CAP / THREADS;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int seg = wave_segment<THREADS>(n);
+  const int e0 = w * seg + lane;
   uint32_t k[R], vv[R];
   uint32_t kand = 0xffffffffu, kor = 0u, vand = 0xffffffffu, vor = 0u;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int e = r * THREADS + t;
+    k[r] = 0u; vv[r] = 0u;
+    if (r * 64 >= seg) continue;
+    const int e = e0 + r * 64;
     if (e < n) {
       const uint2 p = in[e];
       k[r] = p.x; vv[r] = p.y;
       kand &= p.x; kor |= p.x; vand &= p.y; vor |= p.y;
-    } else {
-      k[r] = 0u; vv[r] = 0u;
     }
   }
-  init_shared(S);
-  __syncthreads();
-  atomicAnd(&S.kand, kand); atomicOr(&S.kor, kor); atomicAnd(&S.vand, vand); atomicOr(&S.vor, vor);
-  __syncthreads();
+  reduce_bits(S, kand, kor, vand, vor);
   const uint32_t kdiff = S.kand ^ S.kor, vdiff = S.vand ^ S.vor;
   for (int shift = 0; shift < 32; shift += 8)
-    if ((kdiff >> shift) & 0xffu) lds_pass(S, k, vv, n, true, shift);
+    if ((kdiff >> shift) & 0xffu) lds_pass(S, k, vv, n, seg, true, shift);
   // publish, then look for runs of equal depth
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int e = r * THREADS + t;
+    if (r * 64 >= seg) break;
+    const int e = e0 + r * 64;
     if (e < n) { S.key[e] = k[r]; S.val[e] = vv[r]; }
   }
   __syncthreads();
@@ -190,17 +223,19 @@ __device__ void sort_lds(SortShared<CAP, THREADS>& S, const uint2* __restrict__ 
     // composite order: stable index passes first, then the depth passes again
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int e = r * THREADS + t;
+      if (r * 64 >= seg) break;
+      const int e = e0 + r * 64;
       if (e < n) { k[r] = S.key[e]; vv[r] = S.val[e]; }
     }
     __syncthreads();
     for (int shift = 0; shift < 32; shift += 8)
-      if ((vdiff >> shift) & 0xffu) lds_pass(S, k, vv, n, false, shift);
+      if ((vdiff >> shift) & 0xffu) lds_pass(S, k, vv, n, seg, false, shift);
     for (int shift = 0; shift < 32; shift += 8)
-      if ((kdiff >> shift) & 0xffu) lds_pass(S, k, vv, n, true, shift);
+      if ((kdiff >> shift) & 0xffu) lds_pass(S, k, vv, n, seg, true, shift);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int e = r * THREADS + t;
+      if (r * 64 >= seg) break;
+      const int e = e0 + r * 64;
       if (e < n) S.val[e] = vv[r];
     }
     __syncthreads();
@@ -208,49 +243,79 @@ __device__ void sort_lds(SortShared<CAP, THREADS>& S, const uint2* __restrict__ 
   for (int e = t; e < n; e += THREADS) out_ids[e] = S.val[e];
 }
 
-// ---------------------------------------------------------------- global path (n > kLargeCap)
-template <class SS>
-__device__ void global_pass(SS& S, const uint2* __restrict__ src, uint2* __restrict__ dst, int64_t n, bool by_key,
-                            int shift) {
-  const int t = threadIdx.x;
-  if (t < 256) S.hist[t] = 0;
+// ---------------------------------------------------------------- streamed lists (n > CAP)
+template <int CAP, int THREADS>
+__device__ void stream_pass(SortShared<CAP, THREADS>& S, const uint2* __restrict__ src, uint2* __restrict__ dst,
+                            int64_t n, bool by_key, int shift) {
+  constexpr int R = CAP / THREADS;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // digit histogram of the whole list, scanned into the first chunk's bases
+  for (int d = t; d < 256; d += THREADS) S.carry[d] = 0;
   __syncthreads();
-  for (int64_t e = t; e < n; e += blockDim.x) {
+  for (int64_t e = t; e < n; e += THREADS) {
     const uint2 p = src[e];
-    atomicAdd(&S.hist[((by_key ? p.x : p.y) >> shift) & 0xffu], 1u);
+    atomicAdd(&S.carry[digit_of(p.x, p.y, by_key, shift)], 1u);
   }
   __syncthreads();
-  scan_hist(S);
-  for (int64_t base = 0; base < n; base += blockDim.x) {
-    const int64_t e = base + t;
-    const bool valid = e < n;
-    const uint2 p = valid ? src[e] : make_uint2(0u, 0u);
-    const uint32_t dg = valid ? (((by_key ? p.x : p.y) >> shift) & 0xffu) : 0u;
-    const uint32_t pos = rank_round(S, valid, dg);
-    if (valid) dst[pos] = p;
+  {
+    uint32_t x = t < 256 ? S.carry[t] : 0u, s = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(s, d, 64);
+      if (lane >= d) s += y;
+    }
+    if (t < 256 && lane == 63) S.wsum[w] = s;
+    __syncthreads();
+    if (t < 256) {
+      uint32_t pre = s - x;
+      for (int k = 0; k < w; ++k) pre += S.wsum[k];
+      S.carry[t] = pre;
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  for (int64_t c0 = 0; c0 < n; c0 += CAP) {
+    const int m = (int)min<int64_t>(CAP, n - c0);
+    const int seg = wave_segment<THREADS>(m);
+    const int e0 = w * seg + lane;
+    uint2 p[R];
+    uint32_t rank[R];
+    zero_wave_counters(S);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r * 64 >= seg) break;
+      const bool valid = e0 + r * 64 < m;
+      p[r] = valid ? src[c0 + e0 + r * 64] : make_uint2(0u, 0u);
+      rank[r] = wave_rank(S, valid, valid ? digit_of(p[r].x, p[r].y, by_key, shift) : 0u);
+    }
+    __syncthreads();
+    counts_to_bases(S, true);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r * 64 >= seg) break;
+      if (e0 + r * 64 < m) dst[S.cnt[w][digit_of(p[r].x, p[r].y, by_key, shift)] + rank[r]] = p[r];
+    }
+    __syncthreads();
+  }
 }
 
-template <class SS>
-__device__ void sort_global(SS& S, uint2* __restrict__ a, uint2* __restrict__ b, uint32_t* __restrict__ out_ids,
-                            int64_t n) {
+template <int CAP, int THREADS>
+__device__ void sort_stream(SortShared<CAP, THREADS>& S, uint2* __restrict__ a, uint2* __restrict__ b,
+                            uint32_t* __restrict__ out_ids, int64_t n) {
   const int t = threadIdx.x;
   uint32_t kand = 0xffffffffu, kor = 0u, vand = 0xffffffffu, vor = 0u;
-  for (int64_t e = t; e < n; e += blockDim.x) {
+  for (int64_t e = t; e < n; e += THREADS) {
     const uint2 p = a[e];
     kand &= p.x; kor |= p.x; vand &= p.y; vor |= p.y;
   }
-  init_shared(S);
-  __syncthreads();
-  atomicAnd(&S.kand, kand); atomicOr(&S.kor, kor); atomicAnd(&S.vand, vand); atomicOr(&S.vor, vor);
-  __syncthreads();
+  reduce_bits(S, kand, kor, vand, vor);
   const uint32_t kdiff = S.kand ^ S.kor, vdiff = S.vand ^ S.vor;
   uint2* src = a;
   uint2* dst = b;
   for (int shift = 0; shift < 32; shift += 8)
-    if ((kdiff >> shift) & 0xffu) { global_pass(S, src, dst, n, true, shift); uint2* x = src; src = dst; dst = x; }
-  for (int64_t e = t; e < n; e += blockDim.x) {
+    if ((kdiff >> shift) & 0xffu) { stream_pass(S, src, dst, n, true, shift); uint2* x = src; src = dst; dst = x; }
+  __threadfence_block();
+  __syncthreads();
+  for (int64_t e = t; e < n; e += THREADS) {
     if ((e == 0 || src[e - 1].x != src[e].x) && e + 1 < n && src[e + 1].x == src[e].x) {
       int len = 1;
       while (e + len < n && src[e + len].x == src[e].x && len <= kShortRun) ++len;
@@ -270,14 +335,16 @@ __device__ void sort_global(SS& S, uint2* __restrict__ a, uint2* __restrict__ b,
   __syncthreads();
   if (S.long_run) {
     for (int shift = 0; shift < 32; shift += 8)
-      if ((vdiff >> shift) & 0xffu) { global_pass(S, src, dst, n, false, shift); uint2* x = src; src = dst; dst = x; }
+      if ((vdiff >> shift) & 0xffu) { stream_pass(S, src, dst, n, false, shift); uint2* x = src; src = dst; dst = x; }
     for (int shift = 0; shift < 32; shift += 8)
-      if ((kdiff >> shift) & 0xffu) { global_pass(S, src, dst, n, true, shift); uint2* x = src; src = dst; dst = x; }
+      if ((kdiff >> shift) & 0xffu) { stream_pass(S, src, dst, n, true, shift); uint2* x = src; src = dst; dst = x; }
+    __threadfence_block();
+    __syncthreads();
   }
-  for (int64_t e = t; e < n; e += blockDim.x) out_ids[e] = src[e].y;
+  for (int64_t e = t; e < n; e += THREADS) out_ids[e] = src[e].y;
 }
 
-// LOW < n <= CAP: sort in LDS; with CAP == kLargeCap also n > CAP (global path, same block shape).
+// LOW < n <= CAP: sort in LDS; with CAP == kLargeCap also n > CAP (streamed, same block shape).
 template <int CAP, int THREADS, int LOW>
 __global__ void __launch_bounds__(THREADS) tile_sort_kernel(const DeviceBatch* __restrict__ db, uint2* pairs,
                                                             uint2* pairs_tmp, uint32_t* sorted_ids,
@@ -297,7 +364,7 @@ __global__ void __launch_bounds__(THREADS) tile_sort_kernel(const DeviceBatch* _
     return;
   }
   if (n <= CAP) sort_lds(S, pairs + rg.x, sorted_ids + rg.x, (int)n);
-  else sort_global(S, pairs + rg.x, pairs_tmp + rg.x, sorted_ids + rg.x, n);
+  else sort_stream(S, pairs + rg.x, pairs_tmp + rg.x, sorted_ids + rg.x, n);
 }
 
 hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {

@@ -145,6 +145,33 @@ def scene_clusters(n: int, seed: int, degree: int = 3, n_clusters: int = 64) -> 
     return Scene(means, log_scales, quats, logits, sh, beta, degree, dict(kind="clusters", seed=seed))
 
 
+def scene_clusters_device(n: int, seed: int, device, degree: int = 3, n_clusters: int = 64) -> dict:
+    """The ``clusters`` recipe drawn by torch's generator on ``device`` (a dict of float32 tensors).
+
+    Same distributions as :func:`scene_clusters`, different random stream: used where millions of
+    resident splats are needed quickly and no oracle looks at them (the serving benchmark).
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f32 = dict(dtype=torch.float32, device=device, generator=g)
+    centres = torch.rand((n_clusters, 3), **f32) * 10.0 - 5.0
+    which = torch.randint(0, n_clusters, (n,), device=device, generator=g)
+    means = centres[which] + 0.3 * torch.randn((n, 3), **f32)
+    log_scales = -4.0 + 0.7 * torch.randn((n, 3), **f32)
+    quats = torch.randn((n, 4), **f32)
+    quats = quats / quats.norm(dim=1, keepdim=True)
+    logits = 1.5 * torch.randn((n,), **f32)
+    k = (degree + 1) ** 2
+    sh = torch.empty((n, k, 3), dtype=torch.float32, device=device)
+    sh[:, 0, :] = (torch.rand((n, 3), **f32) - 0.5) / Y00
+    if k > 1:
+        sh[:, 1:, :] = 0.05 * torch.randn((n, k - 1, 3), **f32)
+    beta = torch.exp(math.log(0.5) + (math.log(8.0) - math.log(0.5)) * torch.rand((n,), **f32))
+    return dict(means=means.contiguous(), log_scales=log_scales.contiguous(), quats=quats.contiguous(),
+                opacity_logits=logits.contiguous(), sh=sh, beta=beta.contiguous())
+
+
 def scene_overlap(n: int, seed: int, cam: Camera, depth_range=(6.0, 10.0)) -> Scene:
     """Heavy-overlap scene: 16 dense clusters laid out in front of ``cam``."""
     rng = np.random.default_rng(seed)
@@ -174,6 +201,9 @@ def random_target(rng: np.random.Generator, width: int, height: int) -> np.ndarr
 
 
 # ---- the five workloads -------------------------------------------------------------------
+
+SERVING_SIZES = (200_000, 500_000, 1_000_000, 1_000_000, 2_000_000, 2_000_000, 3_000_000, 4_000_000)
+SERVING_RESOLUTIONS = ((256, 256), (512, 512), (1280, 720), (1920, 1080))
 
 CONFIG_NAMES = {
     0: "fwd+bwd 1k splats 64x64 (uniform cube, SH0)",
@@ -210,11 +240,11 @@ def make_config(k: int, n_override: int | None = None, seed: int | None = None):
         tgt = random_target(np.random.default_rng(seed + 7), 1920, 1080)
         return dict(scene=sc, camera=cam, target=tgt, loss="l1")
     if k == 4:
-        sizes = [200_000, 500_000, 1_000_000, 1_000_000, 2_000_000, 2_000_000, 3_000_000, 4_000_000]
+        sizes = list(SERVING_SIZES)
         if n_override is not None:
             sizes = [max(1, int(s * n_override / 4_000_000)) for s in sizes]
         scenes = [scene_clusters(s, seed + 10 * i) for i, s in enumerate(sizes)]
-        return dict(scenes=scenes, resolutions=[(256, 256), (512, 512), (1280, 720), (1920, 1080)])
+        return dict(scenes=scenes, resolutions=list(SERVING_RESOLUTIONS))
     raise ValueError(f"unknown workload {k}")
 
 
