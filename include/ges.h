@@ -108,7 +108,10 @@ const char* ges_last_error(void);
 ges_status ges_workspace_query(int64_t n, int32_t width, int32_t height, size_t* splat_ws_bytes,
                                size_t* pixel_ws_bytes);
 
-/* Size of the key workspace for num_keys (tile, splat) pairs of a frame with n splats. */
+/* Size of the key workspace for num_keys (tile, splat) pairs of a width x height frame with n splats:
+ * sorted splat ids (4 B per pair), bucketed pairs (8 B), a second pair buffer for lists beyond the
+ * LDS sort (8 B) and the list of long-list tiles (4 B per tile).  Width/height outside [1,16384]:
+ * GES_ERR_INVALID_ARGUMENT; num_keys >= 2^32-1: GES_ERR_CAPACITY. */
 ges_status ges_key_workspace_query(uint64_t num_keys, int64_t n, int32_t width, int32_t height,
                                    size_t* key_ws_bytes);
 

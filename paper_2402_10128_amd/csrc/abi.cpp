@@ -104,6 +104,7 @@ ges::Batch single_batch(const ges_splats* s, const ges_raster_params* p, const g
   b.pre_blocks = (s->n + 255) / 256;
   b.bin_blocks = fp.bin_blocks;
   b.keys_total = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(splat_ws) + fp.off_hdr + 128);
+  b.sort_queue = b.keys_total + 1;
   return b;
 }
 
@@ -138,10 +139,12 @@ ges_status ges_workspace_query(int64_t n, int32_t width, int32_t height, size_t*
 }
 
 ges_status ges_key_workspace_query(uint64_t num_keys, int64_t n, int32_t width, int32_t height, size_t* key_ws_bytes) {
-  (void)n; (void)width; (void)height;
+  (void)n;
   if (!key_ws_bytes) return fail(GES_ERR_INVALID_ARGUMENT, "key_ws_bytes is NULL");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(GES_ERR_INVALID_ARGUMENT, "width/height outside [1,16384]");
   if (num_keys >= 0xffffffffull) return fail(GES_ERR_CAPACITY, "more than 2^32-2 keys");
-  *key_ws_bytes = ges::plan_keys(num_keys).bytes;
+  *key_ws_bytes = ges::plan_keys(num_keys, ges::plan_frame(0, width, height).tiles).bytes;
   return GES_OK;
 }
 
@@ -176,9 +179,9 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
   if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
   if (!splat_ws || !pixel_ws || !out_rgb) return fail(GES_ERR_INVALID_ARGUMENT, "NULL workspace or output");
   if (num_keys >= 0xffffffffull) return fail(GES_ERR_CAPACITY, "more than 2^32-2 keys");
-  const ges::KeyPlan kp = ges::plan_keys(num_keys);
-  if (num_keys > 0 && (!key_ws || key_ws_bytes < kp.bytes)) return fail(GES_ERR_CAPACITY, "key workspace too small");
   const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
+  const ges::KeyPlan kp = ges::plan_keys(num_keys, fp.tiles);
+  if (num_keys > 0 && (!key_ws || key_ws_bytes < kp.bytes)) return fail(GES_ERR_CAPACITY, "key workspace too small");
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
   GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, out_rgb, nullptr, stream), "upload");
   ges::Batch b = single_batch(splats, params, fp, splat_ws);
@@ -188,6 +191,7 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
     b.pairs = reinterpret_cast<uint2*>(kw + kp.off_pairs);
     b.pairs_tmp = reinterpret_cast<uint2*>(kw + kp.off_tmp);
     b.sorted_ids = reinterpret_cast<uint32_t*>(kw + kp.off_sorted);
+    b.long_list = reinterpret_cast<uint32_t*>(kw + kp.off_list);
   }
   const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
   GES_CHECK_HIP(timed(GES_STAGE_BIN_SCATTER, stream, [&] { return ges::launch_bin_scatter(db, b, stream); }), "bin_scatter");
@@ -231,7 +235,7 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
   out->grad2d = reinterpret_cast<const double*>(sw + fp.off_grad);
   out->stats = reinterpret_cast<const uint64_t*>(sw + fp.off_hdr);
   if (key_ws) {
-    const ges::KeyPlan kp = ges::plan_keys(num_keys);
+    const ges::KeyPlan kp = ges::plan_keys(num_keys, fp.tiles);
     char* kw = reinterpret_cast<char*>(key_ws);
     out->sorted_ids = reinterpret_cast<const uint32_t*>(kw + kp.off_sorted);
     out->bucket_pairs = reinterpret_cast<const uint32_t*>(kw + kp.off_pairs);

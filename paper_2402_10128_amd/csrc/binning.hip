@@ -239,10 +239,11 @@ __global__ void __launch_bounds__(1024) bin_tilescan_kernel(const DeviceBatch* _
 }
 
 __global__ void __launch_bounds__(kBinBlockThreads) bin_scatter_kernel(const DeviceBatch* __restrict__ db, uint2* pairs,
-                                                                       uint64_t capacity) {
+                                                                       uint64_t capacity, uint32_t* sort_queue) {
   __shared__ uint32_t cursor[kBinLdsTiles];
   __shared__ WaveSplats wave_lds[kBinBlockThreads / 64];
   const int64_t blk = blockIdx.x;
+  if (blk == 0 && threadIdx.x < 2) sort_queue[threadIdx.x] = 0u;   // the long-list queue of the coming sort
   const int v = view_of_block(db->bin_prefix, db->nviews, blk);
   const ViewDesc& V = db->views[v];
   const int g = (int)(blk - db->bin_prefix[v]);
@@ -279,8 +280,9 @@ hipError_t launch_bin_scan(const DeviceBatch* dbatch, const Batch& b, const int3
 
 hipError_t launch_bin_scatter(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {
   if (b.bin_blocks == 0 || b.key_capacity == 0) return hipSuccess;
+  if (!b.sort_queue) return hipErrorInvalidValue;
   hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)b.bin_blocks), dim3(kBinBlockThreads), 0, stream, dbatch,
-                     b.pairs, b.key_capacity);
+                     b.pairs, b.key_capacity, b.sort_queue);
   return hipGetLastError();
 }
 

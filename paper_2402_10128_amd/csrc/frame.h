@@ -49,17 +49,19 @@ inline FramePlan plan_frame(int64_t n, int w, int h) {
   return p;
 }
 
-// The sorted ids come first so that the backward pass can find them without the key count.
+// The sorted ids come first so that the backward pass can find them without the key count; the
+// last region lists the tiles whose lists go to the long-list sort (one u32 per tile of the batch).
 struct KeyPlan {
-  size_t off_sorted = 0, off_pairs = 0, off_tmp = 0, bytes = 0;
+  size_t off_sorted = 0, off_pairs = 0, off_tmp = 0, off_list = 0, bytes = 0;
 };
 
-inline KeyPlan plan_keys(uint64_t k) {
+inline KeyPlan plan_keys(uint64_t k, int64_t tiles) {
   KeyPlan p;
   size_t o = 0;
   p.off_sorted = o; o += align256((size_t)k * 4);
   p.off_pairs = o;  o += align256((size_t)k * 8);
   p.off_tmp = o;    o += align256((size_t)k * 8);
+  p.off_list = o;   o += align256((size_t)tiles * 4);
   p.bytes = o;
   return p;
 }

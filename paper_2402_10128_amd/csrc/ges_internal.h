@@ -20,7 +20,8 @@ constexpr int kMaxViews = 64;
 constexpr int kBinBlockThreads = 1024;
 constexpr int kMaxBinBlocks = 256;       // splat chunks per view for the tile histogram
 constexpr int kBinLdsTiles = 12288;      // tiles per LDS window of the histogram (48 KB)
-constexpr int kSortCap = 4096;           // per-tile lists up to this length sort entirely in LDS
+constexpr int kSortCap = 4096;           // per-tile lists up to this length: one 256-thread block per tile
+constexpr int kLongSortBlocks = 256;     // persistent blocks of the long-list sort (one per CU)
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 
@@ -76,6 +77,8 @@ struct Batch {
   int64_t pre_blocks;
   int64_t bin_blocks;
   uint32_t* keys_total;          // device: total keys of the batch (u32 saturating counter)
+  uint32_t* sort_queue;          // device: [0] long lists found, [1] long lists claimed (keys_total + 1)
+  uint32_t* long_list;           // [total tiles] tiles whose lists exceed kSortCap (key workspace)
   uint2* pairs;                  // [key capacity] (depth bits, splat index) bucketed by tile
   uint2* pairs_tmp;              // [key capacity] second buffer for large-list sorts
   uint32_t* sorted_ids;          // [key capacity]

@@ -157,11 +157,18 @@ __global__ void __launch_bounds__(kLossThreads) loss_kernel(const float* __restr
   }
 }
 
-__global__ void loss_final_kernel(const float* __restrict__ partial, int nb, float scale, float* __restrict__ out) {
-  if (threadIdx.x != 0) return;
+// Sum of the block partials in binary64, in a fixed order: 256 strided partial sums, then a fixed
+// butterfly within each wave and the four wave sums in order.
+__global__ void __launch_bounds__(256) loss_final_kernel(const float* __restrict__ partial, int nb, float scale,
+                                                         float* __restrict__ out) {
+  __shared__ double wsum[4];
   double s = 0.0;
-  for (int k = 0; k < nb; ++k) s += (double)partial[k];
-  *out = (float)(s * (double)scale);
+  for (int k = threadIdx.x; k < nb; k += 256) s += (double)partial[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (float)((((wsum[0] + wsum[1]) + wsum[2]) + wsum[3]) * (double)scale);
 }
 
 size_t loss_scratch_bytes() { return kLossBlocks * sizeof(float); }
@@ -173,7 +180,7 @@ hipError_t launch_loss(const float* img, const float* target, const uint8_t* mas
   const int nb = (int)std::min<int64_t>(kLossBlocks, (npix + kLossThreads - 1) / kLossThreads);
   hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(kLossThreads), 0, stream, img, target, mask, npix, lam_l1, lam_w,
                      dL_dimg, partial);
-  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, stream, partial, nb, 1.f / (3.f * (float)npix), loss_out);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, stream, partial, nb, 1.f / (3.f * (float)npix), loss_out);
   return hipGetLastError();
 }
 

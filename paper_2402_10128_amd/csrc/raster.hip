@@ -19,6 +19,7 @@
 // DPP steps; one lane per row parks the row sums in LDS, and every 32 splats each lane finishes one
 // parked splat (4 row sums) and adds its components to binary64 accumulators with float64 atomics
 // (the cross-tile sums of a splat often cancel; binary32 accumulation would lose accuracy there).
+// Factors of 2 common to a splat's terms (the mean2D and b gradients) are applied once per (tile, splat).
 #include "ges_internal.h"
 
 namespace ges {
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   const int px = tx * kTile + (lane & 15);
   const int py0 = ty * kTile + (lane >> 4);
   const float pxf = (float)px;
-  float pyf[4], T[4], Tf[4], g[4][3], bgg[4], S[4][3];
+  float pyf[4], T[4], TfB[4], g[4][3], S[4][3];
   uint32_t last[4];
   uint32_t maxlast = 0;
 #pragma unroll
@@ -213,8 +214,8 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
       last[k] = 0u;
       g[k][0] = g[k][1] = g[k][2] = 0.f;
     }
-    Tf[k] = T[k];
-    bgg[k] = V.bg[0] * g[k][0] + V.bg[1] * g[k][1] + V.bg[2] * g[k][2];
+    // T_final (bg . g): the background's share of dL/dalpha, divided by (1 - alpha) per splat
+    TfB[k] = T[k] * (V.bg[0] * g[k][0] + V.bg[1] * g[k][1] + V.bg[2] * g[k][2]);
     maxlast = max(maxlast, last[k]);
   }
   // wave max of the last contributor position
@@ -222,7 +223,6 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   const uint2 rg = V.ranges[lt];
   const float4* rec = V.rec;
   double* grad2d = V.grad2d;
-  const int ncomp = FALLOFF == GES_FALLOFF_GEF ? 10 : 9;
   uint32_t parked = 0;    // bit s: slot s holds row partials (uniform across the wave)
   int nslot = 0;
   for (int hi = (int)maxlast; hi > 0; hi -= 64) {
@@ -244,7 +244,10 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
       const float4 Cc = sC[j];
       const uint32_t pos = (uint32_t)(lo + j);
       const float bb = A.w + A.w;
-      float pu = 0.f, pv = 0.f, pa = 0.f, pb = 0.f, pc = 0.f, po = 0.f, pr = 0.f, pg = 0.f, pbl = 0.f, pbeta = 0.f;
+      // per lane: sums over its pixels of dq (a dx + b dy), dq (b dx + c dy), dq dx^2, dq dx dy, dq dy^2
+      // (dq = dL/dq; halves of the mean2D and b gradients), of G dL/dalpha (opacity), of alpha T g
+      // (colour) and, for GEF, of dL/dbeta
+      float su = 0.f, sv = 0.f, pa = 0.f, pb = 0.f, pc = 0.f, po = 0.f, pr = 0.f, pg = 0.f, pbl = 0.f, pbeta = 0.f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -270,35 +273,37 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         pr = __builtin_fmaf(w, g[k][0], pr);
         pg = __builtin_fmaf(w, g[k][1], pg);
         pbl = __builtin_fmaf(w, g[k][2], pbl);
-        float dalpha = (Cc.x - S[k][0]) * g[k][0] + (Cc.y - S[k][1]) * g[k][1] + (Cc.z - S[k][2]) * g[k][2];
-        dalpha = dalpha * T[k] - Tf[k] * bgg[k] * inv;
-        S[k][0] = __builtin_fmaf(alpha, Cc.x - S[k][0], S[k][0]);
-        S[k][1] = __builtin_fmaf(alpha, Cc.y - S[k][1], S[k][1]);
-        S[k][2] = __builtin_fmaf(alpha, Cc.z - S[k][2], S[k][2]);
+        const float d0 = Cc.x - S[k][0], d1 = Cc.y - S[k][1], d2 = Cc.z - S[k][2];
+        float dalpha = __builtin_fmaf(d0, g[k][0], __builtin_fmaf(d1, g[k][1], d2 * g[k][2]));
+        dalpha = __builtin_fmaf(dalpha, T[k], -TfB[k] * inv);
+        S[k][0] = __builtin_fmaf(alpha, d0, S[k][0]);
+        S[k][1] = __builtin_fmaf(alpha, d1, S[k][1]);
+        S[k][2] = __builtin_fmaf(alpha, d2, S[k][2]);
         any = true;
         if (clamped) continue;
-        const float dG = B.z * dalpha;
         po = __builtin_fmaf(G, dalpha, po);
+        // G dL/dG = alpha dL/dalpha below the clamp
+        const float adal = alpha * dalpha;
         float dq;
         if (FALLOFF == GES_FALLOFF_PHI) {
-          dq = q0 >= 0.f ? -0.5f * G * dG : 0.f;
+          dq = q0 >= 0.f ? -0.5f * adal : 0.f;
         } else {
           // dG/dq = -(beta/4) q^(beta/2 - 1) G  (q floored at 1e-12);  dG/dbeta = -(1/4) q^(beta/2) ln q G
           const float qf = fmaxf(q, 1e-12f);
           const float qpow = fast_exp2((0.5f * B.w - 1.f) * fast_log2(qf));
-          dq = q0 >= 0.f ? -0.25f * B.w * qpow * G * dG : 0.f;
-          if (q > 0.f) pbeta = __builtin_fmaf(-0.25f * qb * (lq * 0.69314718055994531f) * G, dG, pbeta);
+          dq = q0 >= 0.f ? (-0.25f * B.w) * qpow * adal : 0.f;
+          if (q > 0.f) pbeta = __builtin_fmaf(-0.25f * qb * (lq * 0.69314718055994531f), adal, pbeta);
         }
-        const float tx2 = dq * 2.f;
-        pu = __builtin_fmaf(tx2, __builtin_fmaf(A.z, dx, A.w * dy), pu);
-        pv = __builtin_fmaf(tx2, __builtin_fmaf(A.w, dx, B.x * dy), pv);
-        pa = __builtin_fmaf(dq * dx, dx, pa);
-        pb = __builtin_fmaf(tx2 * dx, dy, pb);
-        pc = __builtin_fmaf(dq * dy, dy, pc);
+        const float dqdx = dq * dx, dqdy = dq * dy;
+        su = __builtin_fmaf(dq, __builtin_fmaf(A.z, dx, A.w * dy), su);
+        sv = __builtin_fmaf(dq, __builtin_fmaf(A.w, dx, B.x * dy), sv);
+        pa = __builtin_fmaf(dqdx, dx, pa);
+        pb = __builtin_fmaf(dqdx, dy, pb);
+        pc = __builtin_fmaf(dqdy, dy, pc);
       }
       if (__any(any)) {
         // rows of 16 lanes reduce in registers; one lane per row parks the 10 row sums in LDS
-        const float r0 = row_sum(pu), r1 = row_sum(pv), r2 = row_sum(pa), r3 = row_sum(pb), r4 = row_sum(pc);
+        const float r0 = row_sum(su), r1 = row_sum(sv), r2 = row_sum(pa), r3 = row_sum(pb), r4 = row_sum(pc);
         const float r5 = row_sum(po), r6 = row_sum(pr), r7 = row_sum(pg), r8 = row_sum(pbl);
         const float r9 = FALLOFF == GES_FALLOFF_GEF ? row_sum(pbeta) : 0.f;
         if ((lane & 15) == 15) {
@@ -315,13 +320,18 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         __syncthreads();
         if (lane < kFlush && (parked >> lane) & 1u) {
           const uint32_t id = sId[lane];
-          double* dst = grad2d + (size_t)id * kGradStride;
+          float val[10];
 #pragma unroll
-          for (int c = 0; c < 10; ++c) {
-            if (c >= ncomp) break;
-            const float val = (sRed[lane][0][c] + sRed[lane][1][c]) + (sRed[lane][2][c] + sRed[lane][3][c]);
-            if (val != 0.f) atomicAdd(dst + c, (double)val);
-          }
+          for (int c = 0; c < 10; ++c)
+            val[c] = (sRed[lane][0][c] + sRed[lane][1][c]) + (sRed[lane][2][c] + sRed[lane][3][c]);
+          val[0] = 2.f * val[0];   // dL/du = 2 sum dq (a dx + b dy)
+          val[1] = 2.f * val[1];   // dL/dv = 2 sum dq (b dx + c dy)
+          val[3] = 2.f * val[3];   // dL/db = 2 sum dq dx dy
+          double* dst = grad2d + (size_t)id * kGradStride;
+          constexpr int ncomp = FALLOFF == GES_FALLOFF_GEF ? 10 : 9;
+#pragma unroll
+          for (int c = 0; c < ncomp; ++c)
+            if (val[c] != 0.f) atomicAdd(dst + c, (double)val[c]);
         }
         __syncthreads();
         parked = 0;

@@ -114,6 +114,8 @@ struct BatchWork {
   uint64_t sim_done_ns = 0;
 };
 
+int64_t batch_tiles(const BatchWork& b) { return b.host ? b.host->tile_prefix[b.host->nviews] : 0; }
+
 }  // namespace
 
 // ---- executors: the GPU one, and a simulated one for host-only tests of the scheduler ------------
@@ -229,12 +231,14 @@ class GpuExecutor : public Executor {
     bt.pre_blocks = h.pre_prefix[h.nviews];
     bt.bin_blocks = h.bin_prefix[h.nviews];
     bt.keys_total = reinterpret_cast<uint32_t*>(pool + b.table_off + align256(device_batch_bytes(kMaxViews)));
+    bt.sort_queue = bt.keys_total + 1;
     if (b.has_keys && b.keys > 0) {
-      const KeyPlan kp = plan_keys(b.keys);
+      const KeyPlan kp = plan_keys(b.keys, bt.total_tiles);
       char* kw = pool + b.key_off;
       bt.sorted_ids = reinterpret_cast<uint32_t*>(kw + kp.off_sorted);
       bt.pairs = reinterpret_cast<uint2*>(kw + kp.off_pairs);
       bt.pairs_tmp = reinterpret_cast<uint2*>(kw + kp.off_tmp);
+      bt.long_list = reinterpret_cast<uint32_t*>(kw + kp.off_list);
       bt.key_capacity = b.keys;
     }
     return bt;
@@ -404,7 +408,7 @@ void worker_loop(ges_server* s) {
     // ---- 3. key buffer under the budget: wait for older batches, then give back the newest views
     bool placed = false;
     for (;;) {
-      const size_t kb = plan_keys(b.keys).bytes;
+      const size_t kb = plan_keys(b.keys, batch_tiles(b)).bytes;
       if (b.keys == 0 || s->alloc->alloc(kb, &b.key_off)) {
         b.key_bytes = kb;
         b.has_keys = b.keys > 0;

@@ -10,9 +10,13 @@
 // independent of the list length).  Runs of equal depth are then ordered by index: runs of at most 32
 // by insertion sort, longer ones (only in degenerate scenes) by extra index passes placed before the
 // depth passes.
-// Shapes: 256 threads for lists of up to 4,096 pairs (36 KB of LDS, several blocks per CU) and 1,024
-// threads for up to 16,384 (144 KB; gfx950 gives a workgroup up to 160 KB).  Longer lists stream
-// through global memory in chunks of 16,384 with the same ranking.
+// Shapes: 256 threads, one block per tile, for lists of up to 4,096 pairs (37 KB of LDS, four blocks per
+// CU); longer lists go to a persistent grid of 1,024-thread blocks (one per CU, 145 KB of LDS; gfx950
+// gives a workgroup up to 160 KB) fed by a work queue, so that no CU slot is spent on a block that
+// finds a short list.  Lists beyond 16,384 pairs stream through global memory in chunks of 16,384 with
+// the same ranking.
+#include <algorithm>
+
 #include "ges_internal.h"
 
 namespace ges {
@@ -164,9 +168,19 @@ __device__ __forceinline__ void lds_pass(SortShared<CAP, THREADS>& S, uint32_t (
 
 template <class SS>
 __device__ __forceinline__ void reduce_bits(SS& S, uint32_t kand, uint32_t kor, uint32_t vand, uint32_t vor) {
+  // reduce within the wave first, so that only one lane per wave touches the shared words
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    kand &= (uint32_t)__shfl_xor((int)kand, off, 64);
+    kor |= (uint32_t)__shfl_xor((int)kor, off, 64);
+    vand &= (uint32_t)__shfl_xor((int)vand, off, 64);
+    vor |= (uint32_t)__shfl_xor((int)vor, off, 64);
+  }
   if (threadIdx.x == 0) { S.kand = 0xffffffffu; S.kor = 0u; S.vand = 0xffffffffu; S.vor = 0u; S.long_run = 0u; }
   __syncthreads();
-  atomicAnd(&S.kand, kand); atomicOr(&S.kor, kor); atomicAnd(&S.vand, vand); atomicOr(&S.vor, vor);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAnd(&S.kand, kand); atomicOr(&S.kor, kor); atomicAnd(&S.vand, vand); atomicOr(&S.vor, vor);
+  }
   __syncthreads();
 }
 
@@ -344,38 +358,72 @@ __device__ void sort_stream(SortShared<CAP, THREADS>& S, uint2* __restrict__ a, 
   for (int64_t e = t; e < n; e += THREADS) out_ids[e] = src[e].y;
 }
 
-// LOW < n <= CAP: sort in LDS; with CAP == kLargeCap also n > CAP (streamed, same block shape).
-template <int CAP, int THREADS, int LOW>
-__global__ void __launch_bounds__(THREADS) tile_sort_kernel(const DeviceBatch* __restrict__ db, uint2* pairs,
-                                                            uint2* pairs_tmp, uint32_t* sorted_ids,
-                                                            int64_t total_tiles, uint64_t capacity) {
-  __shared__ SortShared<CAP, THREADS> S;
+// Lists of 2..kSortCap pairs: one block per tile.  A longer list is appended to the long-list queue
+// (whose counters the scatter kernel has reset).
+__global__ void __launch_bounds__(256) tile_sort_short_kernel(const DeviceBatch* __restrict__ db, const uint2* pairs,
+                                                              uint32_t* sorted_ids, int64_t total_tiles,
+                                                              uint64_t capacity, uint32_t* queue,
+                                                              uint32_t* long_list) {
+  __shared__ SortShared<kSortCap, 256> S;
   const int64_t gt = blockIdx.x;
   if (gt >= total_tiles) return;
   const int v = view_of_block(db->tile_prefix, db->nviews, gt);
   const ViewDesc& V = db->views[v];
   const uint2 rg = V.ranges[gt - db->tile_prefix[v]];
   if (rg.y <= rg.x || (uint64_t)rg.y > capacity) return;
-  const int64_t n = (int64_t)(rg.y - rg.x);
-  if (n <= LOW) return;                       // handled by the smaller shape
-  if (CAP != kLargeCap && n > CAP) return;    // handled by the larger shape
+  const int n = (int)(rg.y - rg.x);
+  if (n > kSortCap) {
+    if (threadIdx.x == 0) {
+      const uint32_t slot = atomicAdd(&queue[0], 1u);
+      if ((int64_t)slot < total_tiles) long_list[slot] = (uint32_t)gt;
+    }
+    return;
+  }
   if (n == 1) {
     if (threadIdx.x == 0) sorted_ids[rg.x] = pairs[rg.x].y;
     return;
   }
-  if (n <= CAP) sort_lds(S, pairs + rg.x, sorted_ids + rg.x, (int)n);
-  else sort_stream(S, pairs + rg.x, pairs_tmp + rg.x, sorted_ids + rg.x, n);
+  sort_lds(S, pairs + rg.x, sorted_ids + rg.x, n);
+}
+
+// Lists longer than kSortCap: a persistent grid (one 1,024-thread block per CU) claims the queued tiles
+// one at a time and sorts them in LDS (up to kLargeCap) or streamed.  Every block leaves once the
+// claims have passed the number of queued tiles.
+__global__ void __launch_bounds__(1024) tile_sort_long_kernel(const DeviceBatch* __restrict__ db, uint2* pairs,
+                                                              uint2* pairs_tmp, uint32_t* sorted_ids,
+                                                              int64_t total_tiles, uint64_t capacity,
+                                                              uint32_t* queue, const uint32_t* long_list) {
+  __shared__ SortShared<kLargeCap, 1024> S;
+  __shared__ uint32_t s_idx;
+  const uint32_t found = (uint32_t)min<int64_t>((int64_t)queue[0], total_tiles);
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(&queue[1], 1u);
+    __syncthreads();
+    const uint32_t idx = s_idx;
+    __syncthreads();   // every thread has read s_idx before the next claim overwrites it
+    if (idx >= found) break;
+    const int64_t gt = long_list[idx];
+    if (gt >= total_tiles) continue;
+    const int v = view_of_block(db->tile_prefix, db->nviews, gt);
+    const uint2 rg = db->views[v].ranges[gt - db->tile_prefix[v]];
+    if (rg.y <= rg.x || (uint64_t)rg.y > capacity) continue;
+    const int64_t n = (int64_t)(rg.y - rg.x);
+    if (n <= kLargeCap) sort_lds(S, pairs + rg.x, sorted_ids + rg.x, (int)n);
+    else sort_stream(S, pairs + rg.x, pairs_tmp + rg.x, sorted_ids + rg.x, n);
+    __syncthreads();
+  }
 }
 
 hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {
   if (b.total_tiles == 0 || b.key_capacity == 0) return hipSuccess;
-  const dim3 grid((unsigned)b.total_tiles);
-  hipLaunchKernelGGL((tile_sort_kernel<kSortCap, 256, 0>), grid, dim3(256), 0, stream, dbatch, b.pairs, b.pairs_tmp,
-                     b.sorted_ids, b.total_tiles, b.key_capacity);
+  if (!b.sort_queue || !b.long_list) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tile_sort_short_kernel, dim3((unsigned)b.total_tiles), dim3(256), 0, stream, dbatch, b.pairs,
+                     b.sorted_ids, b.total_tiles, b.key_capacity, b.sort_queue, b.long_list);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((tile_sort_kernel<kLargeCap, 1024, kSortCap>), grid, dim3(1024), 0, stream, dbatch, b.pairs,
-                     b.pairs_tmp, b.sorted_ids, b.total_tiles, b.key_capacity);
+  const int64_t blocks = std::min<int64_t>(kLongSortBlocks, b.total_tiles);
+  hipLaunchKernelGGL(tile_sort_long_kernel, dim3((unsigned)blocks), dim3(1024), 0, stream, dbatch, b.pairs,
+                     b.pairs_tmp, b.sorted_ids, b.total_tiles, b.key_capacity, b.sort_queue, b.long_list);
   return hipGetLastError();
 }
 
