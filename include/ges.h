@@ -36,6 +36,7 @@ extern "C" {
 
 #define GES_ABI_VERSION 1u
 #define GES_TILE 16
+#define GES_GRAD2D_STRIDE 12   /* binary64 slots per splat in the 2-D gradient rows */
 
 typedef enum {
   GES_OK = 0,
@@ -67,9 +68,10 @@ typedef struct {
   int32_t sh_degree;             /* 0..3; (sh_degree+1)^2 coefficients per colour channel */
   const float* means;            /* [n,3] world position */
   const float* log_scales;       /* [n,3] log of the per-axis scale */
-  const float* quats;            /* [n,4] rotation (w,x,y,z), normalised internally */
+  const float* quats;            /* [n,4] rotation (w,x,y,z), normalised internally; 16-byte aligned */
   const float* opacity_logits;   /* [n] opacity = sigmoid(logit) */
-  const float* sh;               /* [n,(D+1)^2,3] real SH coefficients, m-ordered, Condon-Shortley phase */
+  const float* sh;               /* [n,(D+1)^2,3] real SH coefficients, m-ordered, Condon-Shortley phase;
+                                    16-byte aligned at degree 1 or 3 (rows move as float4) */
   const float* beta;             /* [n] shape parameter beta (2 = Gaussian), the true value */
 } ges_splats;
 
@@ -143,8 +145,10 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
  * contributors back to front recovering the transmittance by division, accumulates
  * the gradient of each splat's 2-D quantities (mean2D, conic, opacity, colour and,
  * with the GEF falloff, beta), then maps them to the parameters through the
- * preprocess chain rule.  Every gradient buffer of `grads` is overwritten; NULL
- * members are skipped.  Must follow the ges_render_forward of the same frame. */
+ * preprocess chain rule (evaluated in binary64).  Every gradient buffer of `grads`
+ * is overwritten; NULL members are skipped.  grads->quats, and grads->sh at SH degree
+ * 1 or 3, must be 16-byte aligned (INVALID_ARGUMENT otherwise), like the inputs.
+ * Must follow the ges_render_forward of the same frame. */
 ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
                                void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
                                const ges_splat_grads* grads, void* stream);
@@ -158,7 +162,8 @@ typedef struct {
   const uint32_t* bucket_pairs;  /* [num_keys,2] (depth bits, splat index) in tile order, unsorted within a tile */
   const float* final_T;          /* [height,width] (after ges_render_forward) */
   const uint32_t* n_contrib;     /* [height,width] list position + 1 of the last composited splat */
-  const double* grad2d;          /* [n,12] dL/d(u,v,a,b,c,opacity,r,g,b,beta), binary64 (after ges_render_backward) */
+  const double* grad2d;          /* [n,GES_GRAD2D_STRIDE] dL/d(u,v,a,b,c,opacity,r,g,b,beta) in slots 0..9, binary64
+                                    (after ges_render_backward) */
   const uint64_t* stats;         /* [4]: keys, -, pairs examined, pairs composited (after ges_render_forward) */
   int32_t tiles_x, tiles_y;
 } ges_frame_view;

@@ -206,6 +206,10 @@ ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, 
   const std::string e = check_all(splats, cam, params);
   if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
   if (!splat_ws || !pixel_ws || !dL_drgb || !grads) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (grads->quats && (reinterpret_cast<uintptr_t>(grads->quats) & 15u))
+    return fail(GES_ERR_INVALID_ARGUMENT, "grads->quats must be 16-byte aligned");
+  if (grads->sh && (splats->sh_degree == 1 || splats->sh_degree == 3) && (reinterpret_cast<uintptr_t>(grads->sh) & 15u))
+    return fail(GES_ERR_INVALID_ARGUMENT, "grads->sh must be 16-byte aligned");
   const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
   GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, nullptr, dL_drgb, stream), "upload");

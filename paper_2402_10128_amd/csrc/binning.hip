@@ -25,6 +25,7 @@ struct SplatTiles {
   uint32_t area;
   float u, v, a, b, c, qm, inv_a, inv_c;
   uint32_t depth_bits;
+  uint32_t flags;
 };
 
 // Rectangle (and, for ELLIPSE, the conic) of splat i; area 0 for culled splats.
@@ -34,6 +35,7 @@ __device__ __forceinline__ void load_splat_tiles(const ViewDesc& V, int64_t i, b
   s.tx0 = (int)(lo & 0xffffu); s.ty0 = (int)(lo >> 16);
   s.tx1 = (int)(hi & 0xffffu); s.ty1 = (int)(hi >> 16);
   s.rw = s.tx1 - s.tx0 + 1;
+  s.flags = (uint32_t)__float_as_int(r3.x) >> 24;
   s.area = __float_as_uint(r3.w) == 0 ? 0u : (uint32_t)(s.rw * (s.ty1 - s.ty0 + 1));
   s.depth_bits = __float_as_uint(V.rec[4 * i + 2].w);
   if (ellipse && s.area) {
@@ -138,7 +140,11 @@ __device__ __forceinline__ void walk_chunk(const ViewDesc& V, int64_t i0, int64_
       }
     }
     wave_lds_fence();
-    if (store_count && s.area) reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = W.hits[lane];
+    if (store_count && s.area) {
+      const uint32_t hits = W.hits[lane];
+      reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = hits;
+      V.vis[i] = (hits ? kVisBit : 0u) | s.flags;
+    }
   }
 }
 

@@ -16,7 +16,8 @@ struct FramePlan {
   int64_t tiles = 0;
   int bin_blocks = 1, bin_chunk = 0;
   // splat workspace
-  size_t off_db = 0, off_hdr = 0, off_rec = 0, off_grad = 0, off_counts = 0, off_total = 0, off_ranges = 0;
+  size_t off_db = 0, off_hdr = 0, off_rec = 0, off_grad = 0, off_vis = 0, off_counts = 0, off_total = 0,
+         off_ranges = 0;
   size_t splat_bytes = 0;
   // pixel workspace
   size_t off_final_T = 0, off_n_contrib = 0, pixel_bytes = 0;
@@ -37,6 +38,7 @@ inline FramePlan plan_frame(int64_t n, int w, int h) {
   p.off_hdr = o;     o += 256;
   p.off_rec = o;     o += align256((size_t)n * kRecWords * 4);
   p.off_grad = o;    o += align256((size_t)n * kGradStride * 8);
+  p.off_vis = o;     o += align256((size_t)n * 4);
   p.off_counts = o;  o += align256((size_t)p.bin_blocks * (size_t)p.tiles * 4);
   p.off_total = o;   o += align256((size_t)p.tiles * 4);
   p.off_ranges = o;  o += align256((size_t)p.tiles * 8);
@@ -147,6 +149,7 @@ inline void attach_splat_ws(ViewDesc& V, const FramePlan& fp, void* splat_ws) {
   char* b = reinterpret_cast<char*>(splat_ws);
   V.rec = reinterpret_cast<float4*>(b + fp.off_rec);
   V.grad2d = reinterpret_cast<double*>(b + fp.off_grad);
+  V.vis = reinterpret_cast<uint32_t*>(b + fp.off_vis);
   V.bin_counts = reinterpret_cast<uint32_t*>(b + fp.off_counts);
   V.tile_total = reinterpret_cast<uint32_t*>(b + fp.off_total);
   V.ranges = reinterpret_cast<uint2*>(b + fp.off_ranges);

@@ -15,7 +15,7 @@ namespace ges {
 constexpr int kTile = GES_TILE;          // 16 x 16 pixel tiles
 constexpr int kTilePx = kTile * kTile;   // 256 pixels, 4 per lane of one wave64
 constexpr int kRecWords = 16;            // 64-byte per-splat record
-constexpr int kGradStride = 12;          // doubles per splat in the 2-D gradient accumulator
+constexpr int kGradStride = GES_GRAD2D_STRIDE;   // doubles per splat in the 2-D gradient accumulator
 constexpr int kMaxViews = 64;
 constexpr int kBinBlockThreads = 1024;
 constexpr int kMaxBinBlocks = 256;       // splat chunks per view for the tile histogram
@@ -26,6 +26,8 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 
 // Record words (see ges.h)
+constexpr uint32_t kVisBit = 0x80000000u;
+
 enum : int {
   R_U = 0, R_V, R_A, R_B, R_C, R_QMAX, R_OPA, R_BETA, R_CR, R_CG, R_CB, R_DEPTH, R_RADFLAGS, R_RECT0, R_RECT1, R_TOUCHED
 };
@@ -59,6 +61,7 @@ struct ViewDesc {
   uint2* ranges;                 // [tiles] [start,end) into the key arrays (global positions)
   unsigned long long* header;    // [0] keys of this view, [1] error flags
   double* grad2d;                // [n][kGradStride] binary64 accumulators (cross-tile sums)
+  uint32_t* vis;                 // [n] bit 31: the splat touches a tile; bits 0..4: its clamp flags
   float* final_T;                // [h*w]
   uint32_t* n_contrib;           // [h*w]
   float* out_rgb;                // [h*w*3]

@@ -21,7 +21,9 @@ namespace ges {
 __device__ __forceinline__ float max_c(float a, float b) { return geom_max(a, b); }
 __device__ __forceinline__ float min_c(float a, float b) { return geom_min(a, b); }
 
-__device__ __forceinline__ void write_culled(float4* rec, int64_t i) {
+__device__ __forceinline__ void write_culled(const ViewDesc& V, int64_t i) {
+  float4* rec = V.rec;
+  V.vis[i] = 0u;
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   rec[4 * i + 0] = z;
   rec[4 * i + 1] = z;
@@ -49,21 +51,7 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
   bool ok = finite3(mu) && finite3(ls) && __builtin_isfinite(qv.x) && __builtin_isfinite(qv.y) &&
             __builtin_isfinite(qv.z) && __builtin_isfinite(qv.w) && __builtin_isfinite(logit) &&
             __builtin_isfinite(beta);
-  float shv[3 * K];
-  if constexpr ((3 * K) % 4 == 0) {
-    // rows of 12 K bytes are 16-byte aligned (the base pointer is checked on the host)
-#pragma unroll
-    for (int k = 0; k < 3 * K / 4; ++k) {
-      const float4 x = reinterpret_cast<const float4*>(shc)[k];
-      shv[4 * k] = x.x; shv[4 * k + 1] = x.y; shv[4 * k + 2] = x.z; shv[4 * k + 3] = x.w;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 3 * K; ++k) shv[k] = shc[k];
-  }
-#pragma unroll
-  for (int k = 0; k < 3 * K; ++k) ok = ok && __builtin_isfinite(shv[k]);
-  if (!ok) { write_culled(rec, i); return; }
+  if (!ok) { write_culled(V, i); return; }
 
   // 1. camera-space position
   float p[3];
@@ -75,7 +63,7 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
     p[r] = acc + V.t[r];
   }
   const float z = p[2];
-  if (!(z > V.near_z)) { write_culled(rec, i); return; }
+  if (!(z > V.near_z)) { write_culled(V, i); return; }
 
   // 2. activations
   const float s0 = canon_exp(l0), s1 = canon_exp(l1), s2 = canon_exp(l2);
@@ -83,12 +71,12 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
   const float den = 1.0f + en;
   const float op = 1.0f / den;
   const float o255 = 255.0f * op;
-  if (!(o255 > 1.0f)) { write_culled(rec, i); return; }
+  if (!(o255 > 1.0f)) { write_culled(V, i); return; }
 
   // 3. quaternion -> rotation
   float qw = qv.x, qx = qv.y, qy = qv.z, qz = qv.w;
   float nn = qw * qw; nn = nn + qx * qx; nn = nn + qy * qy; nn = nn + qz * qz;
-  if (!(nn > 0.0f)) { write_culled(rec, i); return; }
+  if (!(nn > 0.0f)) { write_culled(V, i); return; }
   const float nr = __builtin_sqrtf(nn);
   qw = qw / nr; qx = qx / nr; qy = qy / nr; qz = qz / nr;
   float Q[9];
@@ -115,7 +103,7 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
     float d = 1.0f + e;
     phi = 2.0f / d;
   } else {
-    if (!(beta > 0.0f)) { write_culled(rec, i); return; }
+    if (!(beta > 0.0f)) { write_culled(V, i); return; }
     phi = 1.0f;
   }
   const float sc[3] = {phi * s0, phi * s1, phi * s2};
@@ -177,7 +165,7 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
   cv2 = cv2 + 0.3f;
   float det = cv0 * cv2;
   det = det - cv1 * cv1;
-  if (!(det > 0.0f)) { write_culled(rec, i); return; }
+  if (!(det > 0.0f)) { write_culled(V, i); return; }
   const float ca = cv2 / det;
   float cb = cv1 / det; cb = -cb;
   const float cc = cv0 / det;
@@ -198,7 +186,7 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
     e = e * lgl;
     qm = canon_exp(e);
   }
-  if (!__builtin_isfinite(qm)) { write_culled(rec, i); return; }
+  if (!__builtin_isfinite(qm)) { write_culled(V, i); return; }
 
   // 9. radius
   float mid = cv0 + cv2; mid = 0.5f * mid;
@@ -219,13 +207,31 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
   float yh = vv + fr; yh = __builtin_floorf(yh);
   xl = max_c(xl, 0.0f); xh = min_c(xh, (float)(V.width - 1));
   yl = max_c(yl, 0.0f); yh = min_c(yh, (float)(V.height - 1));
-  if (!(xl <= xh) || !(yl <= yh)) { write_culled(rec, i); return; }
+  if (!(xl <= xh) || !(yl <= yh)) { write_culled(V, i); return; }
   const int tx0 = (int)xl / kTile, tx1 = (int)xh / kTile;
   const int ty0 = (int)yl / kTile, ty1 = (int)yh / kTile;
   // SQUARE: every tile of the rectangle.  ELLIPSE: the rectangle's area here; the tile histogram
   // pass replaces it by the exact number of tiles the ellipse meets (possibly 0).
   const uint32_t touched = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
 
+  float shv[3 * K];
+  if constexpr ((3 * K) % 4 == 0) {
+    // rows of 12 K bytes are 16-byte aligned (the base pointer is checked on the host); read only
+    // for splats that survived culling
+#pragma unroll
+    for (int k = 0; k < 3 * K / 4; ++k) {
+      const float4 x = reinterpret_cast<const float4*>(shc)[k];
+      shv[4 * k] = x.x; shv[4 * k + 1] = x.y; shv[4 * k + 2] = x.z; shv[4 * k + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) shv[k] = shc[k];
+  }
+  // a non-finite SH coefficient culls the splat like any other non-finite parameter
+  bool sh_ok = true;
+#pragma unroll
+  for (int k = 0; k < 3 * K; ++k) sh_ok = sh_ok && __builtin_isfinite(shv[k]);
+  if (!sh_ok) { write_culled(V, i); return; }
   // 11. colour
   float d0 = mx - V.campos[0], d1 = my - V.campos[1], d2 = mz - V.campos[2];
   float len = d0 * d0; len = len + d1 * d1; len = len + d2 * d2;
@@ -244,6 +250,9 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
     rgb[ch] = acc;
   }
 
+  // visibility and clamp flags for the backward pass (ELLIPSE: the histogram pass clears the bit of a
+  // splat whose ellipse meets no tile)
+  V.vis[i] = (touched ? kVisBit : 0u) | bits;
   rec[4 * i + 0] = make_float4(u, vv, ca, cb);
   rec[4 * i + 1] = make_float4(cc, qm, op, beta);
   rec[4 * i + 2] = make_float4(rgb[0], rgb[1], rgb[2], z);

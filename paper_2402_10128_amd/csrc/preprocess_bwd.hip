@@ -4,13 +4,14 @@
 // with the GEF falloff, beta) to its mean, log-scale, quaternion, opacity logit, SH coefficients and
 // beta.  The chain runs in binary64: forward quantities (scales, opacity, rotation, covariance, the
 // conic, the view direction) are recomputed in binary64 from the binary32 inputs, and only the decisions
-// (culling, guard clamp of the Jacobian, colour clamp) come from the record.  Several of the sums cancel
-// (e.g. the scale gradient of an axis along the view ray), and binary32 there leaves an error
-// proportional to the splat's whole gradient; the FP64 vector rate of gfx950 equals its non-packed FP32
-// rate and the kernel is HBM-bound, so binary64 costs little.  Nothing here feeds a decision, so this
-// file is built with contraction allowed.
-// Memory: ~600 B per splat at SH degree 3 (parameters, record, 2-D gradients in; parameter gradients
-// out): HBM-bound.
+// (visibility, guard clamp of the Jacobian, colour clamp) come from the forward pass, through a 4-byte
+// visibility word per splat.  Several of the sums cancel (e.g. the scale gradient of an axis along the
+// view ray), and binary32 there leaves an error proportional to the splat's whole gradient; the FP64
+// vector rate of gfx950 equals its non-packed FP32 rate and the kernel is memory-bound, so binary64
+// costs little.  Nothing here feeds a decision, so this file is built with contraction allowed.
+// Memory: per visible splat the 2-D gradient row, the parameters (240 B at SH degree 3) and the
+// parameter gradients (240 B); per culled splat the visibility word and zero gradients.  The SH rows
+// (192 B at degree 3) of a wave's 64 splats are staged in LDS and written as one contiguous block.
 #include "ges_internal.h"
 
 namespace ges {
@@ -45,25 +46,34 @@ __device__ __forceinline__ void sh_basis_f64(double x, double y, double z, int d
   Y[15] = -kD3a * x * (xx - 3.0 * yy);
 }
 
+constexpr int kRowPad = 13;   // float4 slots per staged SH-gradient row (12 used at degree 3; 13 spreads LDS banks)
+
+// Chain rule of splat i.  SH-gradient rows of degrees 1 and 3 (whole float4s) go to `row` in LDS; other
+// degrees are written straight to memory.
 template <int D>
-__device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_splat_grads& G, int64_t i) {
+__device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_splat_grads& G, int64_t i, float4* row) {
   constexpr int K = (D + 1) * (D + 1);
-  const float4 r3 = V.rec[4 * i + 3];
-  const uint32_t touched = __float_as_uint(r3.w);
-  if (touched == 0) {
+  const uint32_t vis = V.vis[i];
+  float* gsh = G.sh ? G.sh + (int64_t)3 * K * i : nullptr;
+  if (!(vis & kVisBit)) {
     if (G.means) { G.means[3 * i] = 0.f; G.means[3 * i + 1] = 0.f; G.means[3 * i + 2] = 0.f; }
     if (G.log_scales) { G.log_scales[3 * i] = 0.f; G.log_scales[3 * i + 1] = 0.f; G.log_scales[3 * i + 2] = 0.f; }
     if (G.quats) reinterpret_cast<float4*>(G.quats)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (G.opacity_logits) G.opacity_logits[i] = 0.f;
-    if (G.sh) for (int k = 0; k < 3 * K; ++k) G.sh[(int64_t)3 * K * i + k] = 0.f;
     if (G.beta) G.beta[i] = 0.f;
+    if constexpr ((3 * K) % 4 == 0) {
+#pragma unroll
+      for (int m = 0; m < 3 * K / 4; ++m) row[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      if (gsh) for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.f;
+    }
     return;
   }
-  const uint32_t flags = (uint32_t)__float_as_int(r3.x) >> 24;
+  const uint32_t flags = vis & 0xffu;
   const double2* gp = reinterpret_cast<const double2*>(V.grad2d + (int64_t)kGradStride * i);
   const double2 g01 = gp[0], g23 = gp[1], g45 = gp[2], g67 = gp[3], g89 = gp[4];
-  const double gu = g01.x, gv = g01.y, ga = g23.x, gb = g23.y, gc = g45.x, gop = g45.y;
   const double grgb[3] = {g67.x, g67.y, g89.x};
+  const double gu = g01.x, gv = g01.y, ga = g23.x, gb = g23.y, gc = g45.x, gop = g45.y;
   const double gbeta2 = g89.y;
 
   const float* mu = V.means + 3 * i;
@@ -192,53 +202,78 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
 
   // colour: SH coefficients and the view direction
   double gmu[3] = {0.0, 0.0, 0.0};
-  {
-    double cpos[3];
-    for (int j = 0; j < 3; ++j) cpos[j] = -(R[j] * (double)V.t[0] + R[3 + j] * (double)V.t[1] + R[6 + j] * (double)V.t[2]);
-    const double e0 = mx - cpos[0], e1 = my - cpos[1], e2 = mz - cpos[2];
-    const double len = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-    const double x = e0 / len, y = e1 / len, zz_ = e2 / len;
-    double Y[16];
-    sh_basis_f64(x, y, zz_, D, Y);
-    double gc3[3];
-    for (int ch = 0; ch < 3; ++ch) gc3[ch] = (flags & (1u << ch)) ? 0.0 : grgb[ch];
-    const float* shc = V.sh + (int64_t)3 * K * i;
-    if (G.sh)
-      for (int k = 0; k < K; ++k)
-        for (int ch = 0; ch < 3; ++ch) G.sh[(int64_t)3 * K * i + 3 * k + ch] = (float)(Y[k] * gc3[ch]);
-    if (D > 0) {
-      // dL/dY_k = sum_ch gc3[ch] sh[k][ch]
-      double gY[16];
-      for (int k = 0; k < K; ++k)
-        gY[k] = gc3[0] * (double)shc[3 * k] + gc3[1] * (double)shc[3 * k + 1] + gc3[2] * (double)shc[3 * k + 2];
-      double gdx = 0.0, gdy = 0.0, gdz = 0.0;
-      gdy += -kD1 * gY[1]; gdz += kD1 * gY[2]; gdx += -kD1 * gY[3];
-      if (D > 1) {
-        const double xx = x * x, yy = y * y, z2v = zz_ * zz_;
-        gdx += kD2a * y * gY[4]; gdy += kD2a * x * gY[4];
-        gdy += -kD2a * zz_ * gY[5]; gdz += -kD2a * y * gY[5];
-        gdx += -2.0 * kD2b * x * gY[6]; gdy += -2.0 * kD2b * y * gY[6]; gdz += 4.0 * kD2b * zz_ * gY[6];
-        gdx += -kD2a * zz_ * gY[7]; gdz += -kD2a * x * gY[7];
-        gdx += 2.0 * kD2c * x * gY[8]; gdy += -2.0 * kD2c * y * gY[8];
-        if (D > 2) {
-          gdx += -kD3a * 6.0 * x * y * gY[9]; gdy += -kD3a * (3.0 * xx - 3.0 * yy) * gY[9];
-          gdx += kD3b * y * zz_ * gY[10]; gdy += kD3b * x * zz_ * gY[10]; gdz += kD3b * x * y * gY[10];
-          gdx += 2.0 * kD3c * x * y * gY[11]; gdy += -kD3c * (4.0 * z2v - xx - 3.0 * yy) * gY[11];
-          gdz += -8.0 * kD3c * y * zz_ * gY[11];
-          gdx += -6.0 * kD3d * x * zz_ * gY[12]; gdy += -6.0 * kD3d * y * zz_ * gY[12];
-          gdz += kD3d * (6.0 * z2v - 3.0 * xx - 3.0 * yy) * gY[12];
-          gdx += -kD3c * (4.0 * z2v - 3.0 * xx - yy) * gY[13]; gdy += 2.0 * kD3c * x * y * gY[13];
-          gdz += -8.0 * kD3c * x * zz_ * gY[13];
-          gdx += 2.0 * kD3e * x * zz_ * gY[14]; gdy += -2.0 * kD3e * y * zz_ * gY[14]; gdz += kD3e * (xx - yy) * gY[14];
-          gdx += -kD3a * (3.0 * xx - 3.0 * yy) * gY[15]; gdy += 6.0 * kD3a * x * y * gY[15];
-        }
+  double gc3[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) gc3[ch] = (flags & (1u << ch)) ? 0.0 : grgb[ch];
+  double cpos[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    cpos[j] = -(R[j] * (double)V.t[0] + R[3 + j] * (double)V.t[1] + R[6 + j] * (double)V.t[2]);
+  const double e0 = mx - cpos[0], e1 = my - cpos[1], e2 = mz - cpos[2];
+  const double len = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+  const double x = e0 / len, y = e1 / len, zz_ = e2 / len;
+  double Y[16];
+  sh_basis_f64(x, y, zz_, D, Y);
+  const float* shc = V.sh + (int64_t)3 * K * i;
+  // dL/dc_k,ch = Y_k gc3[ch]; dL/dY_k = sum_ch gc3[ch] c_k,ch.  Rows of 3K floats; for degrees 1 and 3
+  // they are 16-byte aligned (checked on the host), so they move as float4.
+  double gY[16];
+#pragma unroll
+  for (int k = 0; k < K; ++k) gY[k] = 0.0;
+  if constexpr ((3 * K) % 4 == 0) {
+    const float4* s4 = reinterpret_cast<const float4*>(shc);
+    float4 xv[3 * K / 4];
+#pragma unroll
+    for (int m = 0; m < 3 * K / 4; ++m) xv[m] = s4[m];
+#pragma unroll
+    for (int m = 0; m < 3 * K / 4; ++m) {
+      const float xs[4] = {xv[m].x, xv[m].y, xv[m].z, xv[m].w};
+      float ys[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = (4 * m + e) / 3, ch = (4 * m + e) % 3;
+        gY[k] += gc3[ch] * (double)xs[e];
+        ys[e] = (float)(Y[k] * gc3[ch]);
       }
-      // d = e/|e|: dL/de = (dL/dd - d (d . dL/dd)) / |e|
-      const double dd = gdx * x + gdy * y + gdz * zz_;
-      gmu[0] += (gdx - x * dd) / len;
-      gmu[1] += (gdy - y * dd) / len;
-      gmu[2] += (gdz - zz_ * dd) / len;
+      row[m] = make_float4(ys[0], ys[1], ys[2], ys[3]);
     }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        gY[k] += gc3[ch] * (double)shc[3 * k + ch];
+        if (gsh) gsh[3 * k + ch] = (float)(Y[k] * gc3[ch]);
+      }
+  }
+  if (D > 0) {
+    double gdx = 0.0, gdy = 0.0, gdz = 0.0;
+    gdy += -kD1 * gY[1]; gdz += kD1 * gY[2]; gdx += -kD1 * gY[3];
+    if (D > 1) {
+      const double xx = x * x, yy = y * y, z2v = zz_ * zz_;
+      gdx += kD2a * y * gY[4]; gdy += kD2a * x * gY[4];
+      gdy += -kD2a * zz_ * gY[5]; gdz += -kD2a * y * gY[5];
+      gdx += -2.0 * kD2b * x * gY[6]; gdy += -2.0 * kD2b * y * gY[6]; gdz += 4.0 * kD2b * zz_ * gY[6];
+      gdx += -kD2a * zz_ * gY[7]; gdz += -kD2a * x * gY[7];
+      gdx += 2.0 * kD2c * x * gY[8]; gdy += -2.0 * kD2c * y * gY[8];
+      if (D > 2) {
+        gdx += -kD3a * 6.0 * x * y * gY[9]; gdy += -kD3a * (3.0 * xx - 3.0 * yy) * gY[9];
+        gdx += kD3b * y * zz_ * gY[10]; gdy += kD3b * x * zz_ * gY[10]; gdz += kD3b * x * y * gY[10];
+        gdx += 2.0 * kD3c * x * y * gY[11]; gdy += -kD3c * (4.0 * z2v - xx - 3.0 * yy) * gY[11];
+        gdz += -8.0 * kD3c * y * zz_ * gY[11];
+        gdx += -6.0 * kD3d * x * zz_ * gY[12]; gdy += -6.0 * kD3d * y * zz_ * gY[12];
+        gdz += kD3d * (6.0 * z2v - 3.0 * xx - 3.0 * yy) * gY[12];
+        gdx += -kD3c * (4.0 * z2v - 3.0 * xx - yy) * gY[13]; gdy += 2.0 * kD3c * x * y * gY[13];
+        gdz += -8.0 * kD3c * x * zz_ * gY[13];
+        gdx += 2.0 * kD3e * x * zz_ * gY[14]; gdy += -2.0 * kD3e * y * zz_ * gY[14]; gdz += kD3e * (xx - yy) * gY[14];
+        gdx += -kD3a * (3.0 * xx - 3.0 * yy) * gY[15]; gdy += 6.0 * kD3a * x * y * gY[15];
+      }
+    }
+    // d = e/|e|: dL/de = (dL/dd - d (d . dL/dd)) / |e|
+    const double dd = gdx * x + gdy * y + gdz * zz_;
+    gmu[0] = (gdx - x * dd) / len;
+    gmu[1] = (gdy - y * dd) / len;
+    gmu[2] = (gdz - zz_ * dd) / len;
   }
   // p = W mu + t
   if (G.means) {
@@ -247,18 +282,39 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
   }
 }
 
+template <int D>
+__device__ __forceinline__ void backward_wave(const ViewDesc& V, const ges_splat_grads& G, int64_t w0, float4* rows) {
+  constexpr int K = (D + 1) * (D + 1);
+  constexpr int F4 = 3 * K / 4;   // float4s per SH-gradient row (degrees 1 and 3)
+  const int lane = threadIdx.x & 63;
+  const int64_t i = w0 + lane;
+  if (i < V.n) backward_splat<D>(V, G, i, rows + lane * kRowPad);
+  if constexpr ((3 * K) % 4 == 0) {
+    if (!G.sh) return;
+    const int cnt = (int)min<int64_t>(64, V.n - w0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float4* out = reinterpret_cast<float4*>(G.sh + (int64_t)3 * K * w0);
+    for (int m = lane; m < cnt * F4; m += 64) out[m] = rows[(m / F4) * kRowPad + (m % F4)];
+  }
+}
+
 __global__ void __launch_bounds__(256) preprocess_backward_kernel(const DeviceBatch* __restrict__ db,
                                                                    ges_splat_grads G) {
+  __shared__ float4 sRows[4 * 64 * kRowPad];
   const int64_t blk = blockIdx.x;
   const int v = view_of_block(db->pre_prefix, db->nviews, blk);
   const ViewDesc& V = db->views[v];
-  const int64_t i = (blk - db->pre_prefix[v]) * 256 + threadIdx.x;
-  if (i >= V.n) return;
-  switch (V.sh_degree) {
-    case 0: backward_splat<0>(V, G, i); break;
-    case 1: backward_splat<1>(V, G, i); break;
-    case 2: backward_splat<2>(V, G, i); break;
-    default: backward_splat<3>(V, G, i); break;
+  const int wave = threadIdx.x >> 6;
+  const int64_t w0 = (blk - db->pre_prefix[v]) * 256 + wave * 64;
+  if (w0 >= V.n) return;
+  float4* rows = sRows + wave * 64 * kRowPad;
+  switch (V.sh_degree) {   // uniform per block: one view per block
+    case 0: backward_wave<0>(V, G, w0, rows); break;
+    case 1: backward_wave<1>(V, G, w0, rows); break;
+    case 2: backward_wave<2>(V, G, w0, rows); break;
+    default: backward_wave<3>(V, G, w0, rows); break;
   }
 }
 

@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libges.so")
 
 GES_OK = 0
+GRAD2D_STRIDE = 12   # GES_GRAD2D_STRIDE: binary64 slots per splat in the 2-D gradient rows
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "CAPACITY", 3: "OUT_OF_MEMORY", 4: "DEVICE", 5: "BUSY",
                 6: "NOT_FOUND", 7: "INTERNAL"}
 FALLOFF_PHI, FALLOFF_GEF = 0, 1
@@ -287,7 +288,7 @@ def frame_arrays(frame: Frame, n: int) -> dict:
     out["records"] = sl(v.records, 64 * n, ws).view(torch.float32).reshape(n, 16).cpu().numpy()
     T = v.tiles_x * v.tiles_y
     out["ranges"] = sl(v.tile_ranges, 8 * T, ws).view(torch.int32).reshape(T, 2).cpu().numpy().view(np.uint32)
-    out["grad2d"] = sl(v.grad2d, 96 * n, ws).view(torch.float64).reshape(n, 12).cpu().numpy()
+    out["grad2d"] = sl(v.grad2d, 8 * GRAD2D_STRIDE * n, ws).view(torch.float64).reshape(n, GRAD2D_STRIDE).cpu().numpy()
     out["stats"] = sl(v.stats, 32, ws).view(torch.int64).cpu().numpy()
     if frame.key_ws is not None and frame.num_keys > 0:
         K = frame.num_keys
