@@ -21,14 +21,42 @@
 namespace ges {
 
 struct SplatTiles {
-  int tx0, ty0, tx1, ty1, rw;
-  uint32_t area;
+  int tx0, ty0, tx1, ty1, rw;    // tiles to enumerate (ELLIPSE: the rectangle cut to the ellipse's box)
+  uint32_t area;                 // number of tiles to enumerate (0: none)
+  bool live;                     // the record lists the splat (its rectangle is not empty)
   float u, v, a, b, c, qm, inv_a, inv_c;
   uint32_t depth_bits;
   uint32_t flags;
 };
 
-// Rectangle (and, for ELLIPSE, the conic) of splat i; area 0 for culled splats.
+// ELLIPSE: narrow the rectangle to the tiles whose pixel-centre box can meet the accepted region of the
+// exact test.  That test accepts a point when q - 1e-3 m <= q_max, with m = a dx^2 + c dy^2 + |2 b dx dy|
+// <= 2 q / (1 - rho), rho = |b| / sqrt(a c) < 1; so accepted points satisfy q <= q_max / (1 - 2e-3 / (1 - rho)),
+// an ellipse with half-extents X = sqrt(q' c / det), Y = sqrt(q' a / det).  Enlarged by 2.5e-3 instead
+// of 2e-3, 1% and half a pixel (covering binary32 rounding here and in the test); near-degenerate
+// conics (rho close to 1) keep the whole rectangle.  A superset only: the exact test decides.
+__device__ __forceinline__ void narrow_to_ellipse_box(SplatTiles& s) {
+  const float ac = s.a * s.c;
+  const float det = ac - s.b * s.b;
+  const float gap = 1.f - __builtin_fabsf(s.b) / __builtin_sqrtf(ac);
+  if (!(det > 0.f) || !(gap > 0.f)) return;
+  const float grow = 2.5e-3f / gap;
+  if (!(grow < 0.25f)) return;
+  const float q2 = s.qm / (1.f - grow);
+  const float X = __builtin_sqrtf(q2 * s.c / det) * 1.01f + 0.5f;
+  const float Y = __builtin_sqrtf(q2 * s.a / det) * 1.01f + 0.5f;
+  if (!(X < 1e7f) || !(Y < 1e7f)) return;
+  // tile tx can meet [u - X, u + X] when 16 tx + 15 >= u - X and 16 tx <= u + X
+  s.tx0 = max(s.tx0, (int)__builtin_ceilf((s.u - X - 15.f) * 0.0625f));
+  s.tx1 = min(s.tx1, (int)__builtin_floorf((s.u + X) * 0.0625f));
+  s.ty0 = max(s.ty0, (int)__builtin_ceilf((s.v - Y - 15.f) * 0.0625f));
+  s.ty1 = min(s.ty1, (int)__builtin_floorf((s.v + Y) * 0.0625f));
+  if (s.tx0 > s.tx1 || s.ty0 > s.ty1) { s.area = 0u; return; }
+  s.rw = s.tx1 - s.tx0 + 1;
+  s.area = (uint32_t)(s.rw * (s.ty1 - s.ty0 + 1));
+}
+
+// Rectangle (and, for ELLIPSE, the conic and the narrowed rectangle) of splat i; area 0 for culled splats.
 __device__ __forceinline__ void load_splat_tiles(const ViewDesc& V, int64_t i, bool ellipse, SplatTiles& s) {
   const float4 r3 = V.rec[4 * i + 3];
   const uint32_t lo = __float_as_uint(r3.y), hi = __float_as_uint(r3.z);
@@ -36,7 +64,8 @@ __device__ __forceinline__ void load_splat_tiles(const ViewDesc& V, int64_t i, b
   s.tx1 = (int)(hi & 0xffffu); s.ty1 = (int)(hi >> 16);
   s.rw = s.tx1 - s.tx0 + 1;
   s.flags = (uint32_t)__float_as_int(r3.x) >> 24;
-  s.area = __float_as_uint(r3.w) == 0 ? 0u : (uint32_t)(s.rw * (s.ty1 - s.ty0 + 1));
+  s.live = __float_as_uint(r3.w) != 0;
+  s.area = s.live ? (uint32_t)(s.rw * (s.ty1 - s.ty0 + 1)) : 0u;
   s.depth_bits = __float_as_uint(V.rec[4 * i + 2].w);
   if (ellipse && s.area) {
     const float4 r0 = V.rec[4 * i + 0];
@@ -44,7 +73,16 @@ __device__ __forceinline__ void load_splat_tiles(const ViewDesc& V, int64_t i, b
     s.u = r0.x; s.v = r0.y; s.a = r0.z; s.b = r0.w; s.c = r1.x; s.qm = r1.y;
     s.inv_a = 1.0f / s.a;
     s.inv_c = 1.0f / s.c;
+    narrow_to_ellipse_box(s);
   }
+}
+
+// Chunk of a view's local block index: blocks are dealt to the 8 XCDs round-robin, so with G a multiple
+// of 8 the XCD of block j owns chunks (j % 8) G/8 .. (j % 8 + 1) G/8 - 1.  A tile's bucket slices of
+// consecutive chunks are adjacent in memory; this way they pass through one XCD's L2, where the partial
+// cache lines of neighbouring slices can merge.  Count and scatter use the same mapping.
+__device__ __forceinline__ int chunk_of_block(int local, int G) {
+  return (G & 7) ? local : (local & 7) * (G >> 3) + (local >> 3);
 }
 
 // Per-wave LDS staging of 64 splats for the flattened candidate walk.
@@ -81,6 +119,7 @@ __device__ __forceinline__ void walk_chunk(const ViewDesc& V, int64_t i0, int64_
     const int64_t i = base + lane;
     SplatTiles s;
     s.area = 0u;
+    s.live = false;
     if (i < i1) load_splat_tiles(V, i, ellipse, s);
     // inclusive wave scan of the areas
     uint32_t incl = s.area;
@@ -140,7 +179,7 @@ __device__ __forceinline__ void walk_chunk(const ViewDesc& V, int64_t i0, int64_
       }
     }
     wave_lds_fence();
-    if (store_count && s.area) {
+    if (store_count && s.live) {
       const uint32_t hits = W.hits[lane];
       reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = hits;
       V.vis[i] = (hits ? kVisBit : 0u) | s.flags;
@@ -154,7 +193,7 @@ __global__ void __launch_bounds__(kBinBlockThreads) bin_count_kernel(const Devic
   const int64_t blk = blockIdx.x;
   const int v = view_of_block(db->bin_prefix, db->nviews, blk);
   const ViewDesc& V = db->views[v];
-  const int g = (int)(blk - db->bin_prefix[v]);
+  const int g = chunk_of_block((int)(blk - db->bin_prefix[v]), V.bin_blocks);
   const int64_t i0 = (int64_t)g * V.bin_chunk;
   const int64_t i1 = min<int64_t>(V.n, i0 + V.bin_chunk);
   const int T = V.tiles_x * V.tiles_y;
@@ -252,7 +291,7 @@ __global__ void __launch_bounds__(kBinBlockThreads) bin_scatter_kernel(const Dev
   if (blk == 0 && threadIdx.x < 2) sort_queue[threadIdx.x] = 0u;   // the long-list queue of the coming sort
   const int v = view_of_block(db->bin_prefix, db->nviews, blk);
   const ViewDesc& V = db->views[v];
-  const int g = (int)(blk - db->bin_prefix[v]);
+  const int g = chunk_of_block((int)(blk - db->bin_prefix[v]), V.bin_blocks);
   const int64_t i0 = (int64_t)g * V.bin_chunk;
   const int64_t i1 = min<int64_t>(V.n, i0 + V.bin_chunk);
   const int T = V.tiles_x * V.tiles_y;
