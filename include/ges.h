@@ -133,8 +133,13 @@ ges_status ges_preprocess(const ges_splats* splats, const ges_camera* cam, const
  * composites front to back per pixel with alpha = min(0.99, opacity * falloff),
  * skipping pairs below the 1/255 alpha floor and stopping a pixel before the splat
  * that would take its transmittance below 1e-4.
- * out_rgb: [height,width,3] FP32, overwritten.  num_keys must be the value returned
- * by ges_preprocess for the same splat_ws; key_ws_bytes >= ges_key_workspace_query().
+ * out_rgb: [height,width,3] FP32, overwritten.  num_keys is the key capacity of key_ws
+ * (key_ws_bytes >= ges_key_workspace_query(num_keys, ...)) and must be at least the key
+ * count of the frame: either the value ges_preprocess returned, or any larger capacity,
+ * in which case no read-back is needed (the kernels take the count from the device).  If
+ * the frame's count exceeds num_keys, tiles beyond the capacity render as background and
+ * bit 0 of the frame's error word (ges_frame_view stats[1]) is set.  The same num_keys
+ * must be passed to ges_frame_view_get.
  * The splat, pixel and key workspaces must stay untouched until the matching
  * ges_render_backward (if any) has been enqueued. */
 ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
@@ -164,7 +169,8 @@ typedef struct {
   const uint32_t* n_contrib;     /* [height,width] list position + 1 of the last composited splat */
   const double* grad2d;          /* [n,GES_GRAD2D_STRIDE] dL/d(u,v,a,b,c,opacity,r,g,b,beta) in slots 0..9, binary64
                                     (after ges_render_backward) */
-  const uint64_t* stats;         /* [4]: keys, -, pairs examined, pairs composited (after ges_render_forward) */
+  const uint64_t* stats;         /* [4]: keys, error word (bit 0: key capacity too small), pairs examined,
+                                    pairs composited (after ges_render_forward) */
   int32_t tiles_x, tiles_y;
 } ges_frame_view;
 /* Record layout, 16 x 32-bit words per splat:
@@ -185,6 +191,8 @@ enum { GES_STAGE_PREPROCESS = 0, GES_STAGE_BIN_COUNT, GES_STAGE_BIN_SCAN, GES_ST
        GES_STAGE_RASTER_FORWARD, GES_STAGE_RASTER_BACKWARD, GES_STAGE_PREPROCESS_BACKWARD, GES_STAGE_ZERO,
        GES_STAGE_LOSS, GES_NUM_STAGES };
 ges_status ges_profile_enable(int32_t on);
+/* Time only the stages whose bit (1 << GES_STAGE_*) is set; 0 switches timing off. */
+ges_status ges_profile_select(uint32_t stage_mask);
 ges_status ges_profile_read(double* ms /*[GES_NUM_STAGES]*/, int64_t* launches /*[GES_NUM_STAGES]*/, int32_t reset);
 
 /* ---- frequency-modulated loss (Sec. 4.3) ------------------------------------------

@@ -36,6 +36,7 @@ ges_status device_fail(hipError_t e, const char* where) {
 struct Profiler {
   std::mutex mu;
   bool on = false;
+  uint32_t mask = ~0u;   // stages timed while on
   std::vector<hipEvent_t> free_events;
   struct Pending { int stage; hipEvent_t a, b; };
   std::vector<Pending> pending;
@@ -56,7 +57,7 @@ hipError_t timed(int stage, hipStream_t stream, F&& launch) {
   hipEvent_t a = nullptr, b = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    if (g_prof.on) { a = g_prof.get(); b = g_prof.get(); }
+    if (g_prof.on && ((g_prof.mask >> stage) & 1u)) { a = g_prof.get(); b = g_prof.get(); }
   }
   if (a) { hipError_t e = hipEventRecord(a, stream); if (e != hipSuccess) return e; }
   hipError_t e = launch();
@@ -257,6 +258,14 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
 ges_status ges_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.on = on != 0;
+  g_prof.mask = ~0u;
+  return GES_OK;
+}
+
+ges_status ges_profile_select(uint32_t stage_mask) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = stage_mask != 0;
+  g_prof.mask = stage_mask;
   return GES_OK;
 }
 

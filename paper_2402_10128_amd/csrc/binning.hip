@@ -275,6 +275,7 @@ __global__ void __launch_bounds__(1024) bin_tilescan_kernel(const DeviceBatch* _
     }
     if (threadIdx.x == 0) {
       V.header[0] = carry - view_start;
+      V.header[1] = 0ull;   // error word of the coming forward pass
       V.header[2] = 0ull;   // pair statistics of the coming forward pass
       V.header[3] = 0ull;
     }
@@ -284,11 +285,14 @@ __global__ void __launch_bounds__(1024) bin_tilescan_kernel(const DeviceBatch* _
 }
 
 __global__ void __launch_bounds__(kBinBlockThreads) bin_scatter_kernel(const DeviceBatch* __restrict__ db, uint2* pairs,
-                                                                       uint64_t capacity, uint32_t* sort_queue) {
+                                                                       uint64_t capacity, uint32_t* sort_queue,
+                                                                       const uint32_t* keys_total) {
   __shared__ uint32_t cursor[kBinLdsTiles];
   __shared__ WaveSplats wave_lds[kBinBlockThreads / 64];
   const int64_t blk = blockIdx.x;
   if (blk == 0 && threadIdx.x < 2) sort_queue[threadIdx.x] = 0u;   // the long-list queue of the coming sort
+  if (blk == 0 && threadIdx.x == 0 && (uint64_t)*keys_total > capacity)
+    db->views[0].header[1] |= 1ull;   // key workspace smaller than the frame's key count
   const int v = view_of_block(db->bin_prefix, db->nviews, blk);
   const ViewDesc& V = db->views[v];
   const int g = chunk_of_block((int)(blk - db->bin_prefix[v]), V.bin_blocks);
@@ -327,7 +331,7 @@ hipError_t launch_bin_scatter(const DeviceBatch* dbatch, const Batch& b, hipStre
   if (b.bin_blocks == 0 || b.key_capacity == 0) return hipSuccess;
   if (!b.sort_queue) return hipErrorInvalidValue;
   hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)b.bin_blocks), dim3(kBinBlockThreads), 0, stream, dbatch,
-                     b.pairs, b.key_capacity, b.sort_queue);
+                     b.pairs, b.key_capacity, b.sort_queue, b.keys_total);
   return hipGetLastError();
 }
 

@@ -71,7 +71,8 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
   float T[4] = {1.f, 1.f, 1.f, 1.f};
   float C[4][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
   uint32_t last[4] = {0u, 0u, 0u, 0u};
-  uint32_t n_exam = 0, n_blend = 0;   // pairs examined (up to termination) and composited, for the stats
+  uint32_t stop[4] = {0u, 0u, 0u, 0u};   // 1 + position of the terminating splat (0: never terminated)
+  uint32_t n_blend = 0;                  // pairs composited, for the statistics
   const uint2 rg = V.ranges[lt];
   // a range beyond the key buffer (inconsistent key count) renders as background
   const int n = (uint64_t)rg.y <= capacity ? (int)(rg.y - rg.x) : 0;
@@ -93,10 +94,10 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
       const float4 A = sA[j];
       const float4 B = sB[j];
       const float4 Cc = sC[j];
+      const uint32_t pos1 = (uint32_t)(base + j + 1);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (!(alive & (1u << k))) continue;
-        ++n_exam;
         float dx, dy;
         float q = pair_q(A.x, A.y, A.z, A.w, B.x, pxf, pyf[k], dx, dy);
         if (!(q <= B.y)) continue;
@@ -110,13 +111,13 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
         }
         const float alpha = fminf(kAlphaMax, B.z * G);
         const float t = T[k] * (1.f - alpha);
-        if (t < kTMin) { alive &= ~(1u << k); continue; }
+        if (t < kTMin) { alive &= ~(1u << k); stop[k] = pos1; continue; }
         const float w = alpha * T[k];
         C[k][0] = __builtin_fmaf(w, Cc.x, C[k][0]);
         C[k][1] = __builtin_fmaf(w, Cc.y, C[k][1]);
         C[k][2] = __builtin_fmaf(w, Cc.z, C[k][2]);
         T[k] = t;
-        last[k] = (uint32_t)(base + j + 1);
+        last[k] = pos1;
         ++n_blend;
       }
       if (!__any(alive != 0)) break;
@@ -124,8 +125,14 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
     __syncthreads();
   }
   {
-    // per-frame pair statistics: one atomic per tile
-    unsigned long long e = n_exam, b = n_blend;
+    // per-frame pair statistics: pairs examined (each pixel up to and including its terminating splat)
+    // and composited; one atomic per tile
+    unsigned long long e = 0, b = n_blend;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool inside = px < V.width && py0 + 4 * k < V.height;
+      e += inside ? (stop[k] ? stop[k] : (uint32_t)n) : 0u;
+    }
     for (int off = 32; off > 0; off >>= 1) {
       e += __shfl_xor(e, off, 64);
       b += __shfl_xor(b, off, 64);
@@ -251,10 +258,12 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
       bool any = false;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (pos >= last[k]) continue;
         float dx, dy;
         const float q0 = pair_q(A.x, A.y, A.z, bb, B.x, pxf, pyf[k], dx, dy);
-        if (!(q0 <= B.y)) continue;
+        const bool valid = (pos < last[k]) && (q0 <= B.y);
+        if (!__any(valid)) continue;   // wave-uniform: no pixel of this row band took the splat
+        // straight-line for every lane; a pixel that did not take the splat gets alpha = 0 (T, S and every
+        // accumulated term are then unchanged: 1/(1 - 0) = 1 exactly)
         const float q = fmaxf(q0, 0.f);
         float G, qb = 0.f, lq = 0.f;
         if (FALLOFF == GES_FALLOFF_PHI) {
@@ -266,9 +275,9 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         }
         const float oG = B.z * G;
         const bool clamped = oG > kAlphaMax;
-        const float alpha = clamped ? kAlphaMax : oG;
-        const float inv = fast_rcp(1.f - alpha);
-        T[k] = T[k] * inv;                 // transmittance before this splat
+        const float alpha = valid ? (clamped ? kAlphaMax : oG) : 0.f;
+        const float inv = valid ? fast_rcp(1.f - alpha) : 1.f;
+        T[k] = valid ? T[k] * inv : T[k];  // transmittance before this splat
         const float w = alpha * T[k];
         pr = __builtin_fmaf(w, g[k][0], pr);
         pg = __builtin_fmaf(w, g[k][1], pg);
@@ -279,11 +288,11 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         S[k][0] = __builtin_fmaf(alpha, d0, S[k][0]);
         S[k][1] = __builtin_fmaf(alpha, d1, S[k][1]);
         S[k][2] = __builtin_fmaf(alpha, d2, S[k][2]);
-        any = true;
-        if (clamped) continue;
-        po = __builtin_fmaf(G, dalpha, po);
-        // G dL/dG = alpha dL/dalpha below the clamp
-        const float adal = alpha * dalpha;
+        any = any || valid;
+        // below the clamp: dL/do = G dL/dalpha and G dL/dG = alpha dL/dalpha; above it both are 0
+        const bool grad = valid && !clamped;
+        po = __builtin_fmaf(grad ? G : 0.f, dalpha, po);
+        const float adal = grad ? alpha * dalpha : 0.f;
         float dq;
         if (FALLOFF == GES_FALLOFF_PHI) {
           dq = q0 >= 0.f ? -0.5f * adal : 0.f;
@@ -291,8 +300,9 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
           // dG/dq = -(beta/4) q^(beta/2 - 1) G  (q floored at 1e-12);  dG/dbeta = -(1/4) q^(beta/2) ln q G
           const float qf = fmaxf(q, 1e-12f);
           const float qpow = fast_exp2((0.5f * B.w - 1.f) * fast_log2(qf));
-          dq = q0 >= 0.f ? (-0.25f * B.w) * qpow * adal : 0.f;
-          if (q > 0.f) pbeta = __builtin_fmaf(-0.25f * qb * (lq * 0.69314718055994531f), adal, pbeta);
+          dq = (grad && q0 >= 0.f) ? (-0.25f * B.w) * qpow * adal : 0.f;
+          const float cb = (grad && q > 0.f) ? -0.25f * qb * (lq * 0.69314718055994531f) : 0.f;
+          pbeta = __builtin_fmaf(cb, adal, pbeta);
         }
         const float dqdx = dq * dx, dqdy = dq * dy;
         su = __builtin_fmaf(dq, __builtin_fmaf(A.z, dx, A.w * dy), su);

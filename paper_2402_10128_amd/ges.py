@@ -83,6 +83,7 @@ _SIGS = {
     "ges_frame_view_get": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64,
                                      C.c_void_p, C.POINTER(ges_frame_view)]),
     "ges_profile_enable": (C.c_int, [C.c_int32]),
+    "ges_profile_select": (C.c_int, [C.c_uint32]),
     "ges_profile_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "ges_mask_scratch_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "ges_freq_mask": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -216,6 +217,14 @@ def ges_profile_enable(on: bool):
     _check(lib().ges_profile_enable(1 if on else 0))
 
 
+def ges_profile_select(stages):
+    """Time only the named stages (names of STAGES); an empty list switches timing off."""
+    mask = 0
+    for st in stages:
+        mask |= 1 << STAGES.index(st)
+    _check(lib().ges_profile_select(mask))
+
+
 def ges_profile_read(reset=True):
     ms = (C.c_double * len(STAGES))()
     n = (C.c_int64 * len(STAGES))()
@@ -255,7 +264,8 @@ class Frame:
     splat_ws: torch.Tensor
     pixel_ws: torch.Tensor
     key_ws: torch.Tensor | None = None
-    num_keys: int = 0
+    num_keys: int = 0        # the key count (or capacity) the frame was rendered with
+    key_capacity: int = 0    # keys the current key workspace holds
 
     @staticmethod
     def create(n, width, height, device="cuda"):
@@ -264,10 +274,12 @@ class Frame:
                      torch.empty(pb, dtype=torch.uint8, device=device))
 
     def ensure_keys(self, num_keys):
-        need = ges_key_workspace_query(num_keys, self.n, self.width, self.height)
-        if self.key_ws is None or self.key_ws.numel() < need:
+        if self.key_ws is None or self.key_capacity < num_keys:
             # grow with headroom so that small changes of the key count do not reallocate
-            self.key_ws = torch.empty(max(need, int(need * 1.25)), dtype=torch.uint8, device=self.splat_ws.device)
+            cap = max(int(num_keys * 1.25), num_keys + 1024)
+            need = ges_key_workspace_query(cap, self.n, self.width, self.height)
+            self.key_ws = torch.empty(need, dtype=torch.uint8, device=self.splat_ws.device)
+            self.key_capacity = cap
         self.num_keys = num_keys
 
     def view(self) -> ges_frame_view:
