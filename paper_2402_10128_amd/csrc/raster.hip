@@ -71,8 +71,8 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
   float T[4] = {1.f, 1.f, 1.f, 1.f};
   float C[4][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
   uint32_t last[4] = {0u, 0u, 0u, 0u};
-  uint32_t stop[4] = {0u, 0u, 0u, 0u};   // 1 + position of the terminating splat (0: never terminated)
-  uint32_t n_blend = 0;                  // pairs composited, for the statistics
+  uint32_t n_exam = 0;    // pairs examined: each terminated pixel adds 1 + its terminating position
+  uint32_t n_blend = 0;   // pairs composited, for the statistics
   const uint2 rg = V.ranges[lt];
   // a range beyond the key buffer (inconsistent key count) renders as background
   const int n = (uint64_t)rg.y <= capacity ? (int)(rg.y - rg.x) : 0;
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
         }
         const float alpha = fminf(kAlphaMax, B.z * G);
         const float t = T[k] * (1.f - alpha);
-        if (t < kTMin) { alive &= ~(1u << k); stop[k] = pos1; continue; }
+        if (t < kTMin) { alive &= ~(1u << k); n_exam += pos1; continue; }
         const float w = alpha * T[k];
         C[k][0] = __builtin_fmaf(w, Cc.x, C[k][0]);
         C[k][1] = __builtin_fmaf(w, Cc.y, C[k][1]);
@@ -127,12 +127,8 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
   {
     // per-frame pair statistics: pairs examined (each pixel up to and including its terminating splat)
     // and composited; one atomic per tile
-    unsigned long long e = 0, b = n_blend;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const bool inside = px < V.width && py0 + 4 * k < V.height;
-      e += inside ? (stop[k] ? stop[k] : (uint32_t)n) : 0u;
-    }
+    // pixels still alive examined the whole list (out-of-image pixels were never alive)
+    unsigned long long e = (unsigned long long)n_exam + (unsigned long long)__popc(alive) * (uint32_t)n, b = n_blend;
     for (int off = 32; off > 0; off >>= 1) {
       e += __shfl_xor(e, off, 64);
       b += __shfl_xor(b, off, 64);
