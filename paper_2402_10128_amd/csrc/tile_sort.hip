@@ -1,7 +1,7 @@
 // tile_sort.hip -- per-tile ordering of the bucketed pairs by (depth, splat index).
 //
-// Every tile's bucket holds (depth bits, splat index) pairs in arbitrary order.  One block per tile
-// sorts them ascending by depth (camera z > 0, so the IEEE bits order like the values), ties broken by
+// Every tile's bucket holds (depth bits, splat index) pairs in arbitrary order.  Each tile's list is
+// sorted ascending by depth (camera z > 0, so the IEEE bits order like the values), ties broken by
 // the splat index, which makes the order unique and equal to a stable sort of the pairs in splat-index
 // order.  Method: LSD radix sort with 8-bit digits; digits that are constant across the tile (known from
 // an AND/OR reduction) are skipped.  Each pass is a stable counting sort ranked wave by wave: a wave owns
@@ -10,8 +10,8 @@
 // independent of the list length).  Runs of equal depth are then ordered by index: runs of at most 32
 // by insertion sort, longer ones (only in degenerate scenes) by extra index passes placed before the
 // depth passes.
-// Shapes: 256 threads, one block per tile, for lists of up to 4,096 pairs (37 KB of LDS, four blocks per
-// CU); longer lists go to a persistent grid of 1,024-thread blocks (one per CU, 145 KB of LDS; gfx950
+// Shapes: lists of up to 1,024 pairs take one wave each (four tiles per 256-thread block, no block
+// barriers); up to 4,096 pairs one 256-thread block per tile (37 KB of LDS); longer lists go to a persistent grid of 1,024-thread blocks (one per CU, 145 KB of LDS; gfx950
 // gives a workgroup up to 160 KB) fed by a work queue, so that no CU slot is spent on a block that
 // finds a short list.  Lists beyond 16,384 pairs stream through global memory in chunks of 16,384 with
 // the same ranking.
@@ -51,14 +51,18 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t k, uint32_t v, bool by_key
   return ((by_key ? k : v) >> shift) & 0xffu;
 }
 
-// Lanes of this wave holding the same digit (valid lanes only).
-__device__ __forceinline__ uint64_t match_digit(bool valid, uint32_t dg) {
+// Lanes of this wave holding the same digit (valid lanes only), from eight ballots.  The per-lane choice
+// between a ballot and its complement is an XOR with the lane's sign-extended bit, so each bit costs a
+// few 32-bit operations.
+__device__ __forceinline__ uint64_t match_digit_ballot(bool valid, uint32_t dg) {
   uint64_t peers = __ballot(valid);
 #pragma unroll
   for (int bit = 0; bit < 8; ++bit) {
-    const bool b = (dg >> bit) & 1u;
-    const uint64_t m = __ballot(valid && b);
-    peers &= b ? m : ~m;
+    const uint32_t b = (dg >> bit) & 1u;
+    const uint64_t m = __ballot(b != 0u);
+    const uint32_t flip = b - 1u;   // 0 if the lane's bit is set, all ones if not
+    const uint32_t lo = (uint32_t)m ^ flip, hi = (uint32_t)(m >> 32) ^ flip;
+    peers &= ((uint64_t)hi << 32) | lo;
   }
   return peers;
 }
@@ -68,7 +72,7 @@ __device__ __forceinline__ uint64_t match_digit(bool valid, uint32_t dg) {
 template <class SS>
 __device__ __forceinline__ uint32_t wave_rank(SS& S, bool valid, uint32_t dg) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t peers = match_digit(valid, dg);
+  const uint64_t peers = match_digit_ballot(valid, dg);
   uint32_t r = 0;
   if (valid) {
     const uint32_t before = S.cnt[w][dg];
@@ -358,7 +362,166 @@ __device__ void sort_stream(SortShared<CAP, THREADS>& S, uint2* __restrict__ a, 
   for (int64_t e = t; e < n; e += THREADS) out_ids[e] = src[e].y;
 }
 
-// Lists of 2..kSortCap pairs: one block per tile.  A longer list is appended to the long-list queue
+// ---------------------------------------------------------------- one wave per tile (n <= kWaveCap)
+// Short lists need no block: a wave owns a tile, holds its elements in registers (element e = r * 64 +
+// lane) and a 9 KB slice of LDS, and uses wave fences only.
+constexpr int kWaveCap = 1024;
+constexpr int kWaveR = kWaveCap / 64;
+
+struct WaveSortShared {
+  uint32_t key[kWaveCap];
+  uint32_t val[kWaveCap];
+  uint32_t cnt[256];              // digit counters, then digit bases
+};
+
+__device__ __forceinline__ void wave_pass(WaveSortShared& S, uint32_t (&k)[kWaveR], uint32_t (&vv)[kWaveR], int n,
+                                          bool by_key, int shift) {
+  const int lane = threadIdx.x & 63;
+  uint32_t rank[kWaveR];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) S.cnt[lane * 4 + d] = 0u;
+  wave_lds_fence();
+#pragma unroll
+  for (int r = 0; r < kWaveR; ++r) {
+    if (r * 64 >= n) break;
+    const bool valid = r * 64 + lane < n;
+    const uint32_t dg = valid ? digit_of(k[r], vv[r], by_key, shift) : 0u;
+    const uint64_t peers = match_digit_ballot(valid, dg);
+    uint32_t rr = 0;
+    if (valid) {
+      const uint32_t before = S.cnt[dg];
+      rr = before + (uint32_t)__popcll(peers & lanemask_lt());
+      if ((peers >> lane) == 1ull) S.cnt[dg] = before + (uint32_t)__popcll(peers);   // last peer
+    }
+    wave_lds_fence();
+    rank[r] = rr;
+  }
+  // exclusive scan of the 256 counters: lane l owns digits 4l .. 4l+3
+  uint32_t c[4], sum = 0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) { c[d] = S.cnt[lane * 4 + d]; sum += c[d]; }
+  uint32_t incl = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  uint32_t run = incl - sum;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) { S.cnt[lane * 4 + d] = run; run += c[d]; }
+  wave_lds_fence();
+#pragma unroll
+  for (int r = 0; r < kWaveR; ++r) {
+    if (r * 64 >= n) break;
+    if (r * 64 + lane < n) {
+      const uint32_t pos = S.cnt[digit_of(k[r], vv[r], by_key, shift)] + rank[r];
+      S.key[pos] = k[r];
+      S.val[pos] = vv[r];
+    }
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int r = 0; r < kWaveR; ++r) {
+    if (r * 64 >= n) break;
+    const int e = r * 64 + lane;
+    if (e < n) { k[r] = S.key[e]; vv[r] = S.val[e]; }
+  }
+  wave_lds_fence();
+}
+
+__device__ void wave_sort(WaveSortShared& S, const uint2* __restrict__ in, uint32_t* __restrict__ out_ids, int n) {
+  const int lane = threadIdx.x & 63;
+  uint32_t k[kWaveR], vv[kWaveR];
+  uint32_t kand = 0xffffffffu, kor = 0u, vand = 0xffffffffu, vor = 0u;
+#pragma unroll
+  for (int r = 0; r < kWaveR; ++r) {
+    k[r] = 0u; vv[r] = 0u;
+    const int e = r * 64 + lane;
+    if (e < n) {
+      const uint2 p = in[e];
+      k[r] = p.x; vv[r] = p.y;
+      kand &= p.x; kor |= p.x; vand &= p.y; vor |= p.y;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    kand &= (uint32_t)__shfl_xor((int)kand, off, 64);
+    kor |= (uint32_t)__shfl_xor((int)kor, off, 64);
+    vand &= (uint32_t)__shfl_xor((int)vand, off, 64);
+    vor |= (uint32_t)__shfl_xor((int)vor, off, 64);
+  }
+  const uint32_t kdiff = kand ^ kor, vdiff = vand ^ vor;
+  for (int shift = 0; shift < 32; shift += 8)
+    if ((kdiff >> shift) & 0xffu) wave_pass(S, k, vv, n, true, shift);
+  // publish, then order runs of equal depth by index
+#pragma unroll
+  for (int r = 0; r < kWaveR; ++r) {
+    const int e = r * 64 + lane;
+    if (e < n) { S.key[e] = k[r]; S.val[e] = vv[r]; }
+  }
+  wave_lds_fence();
+  bool long_run = false;
+  for (int e = lane; e < n; e += 64) {
+    if ((e == 0 || S.key[e - 1] != S.key[e]) && e + 1 < n && S.key[e + 1] == S.key[e]) {
+      int len = 1;
+      while (e + len < n && S.key[e + len] == S.key[e] && len <= kShortRun) ++len;
+      if (len > kShortRun) {
+        long_run = true;
+      } else {
+        for (int a = e + 1; a < e + len; ++a) {   // insertion sort of the run by index
+          const uint32_t x = S.val[a];
+          int b = a - 1;
+          while (b >= e && S.val[b] > x) { S.val[b + 1] = S.val[b]; --b; }
+          S.val[b + 1] = x;
+        }
+      }
+    }
+  }
+  wave_lds_fence();
+  if (__any(long_run)) {
+    // composite order: stable index passes first, then the depth passes again
+#pragma unroll
+    for (int r = 0; r < kWaveR; ++r) {
+      const int e = r * 64 + lane;
+      if (e < n) { k[r] = S.key[e]; vv[r] = S.val[e]; }
+    }
+    wave_lds_fence();
+    for (int shift = 0; shift < 32; shift += 8)
+      if ((vdiff >> shift) & 0xffu) wave_pass(S, k, vv, n, false, shift);
+    for (int shift = 0; shift < 32; shift += 8)
+      if ((kdiff >> shift) & 0xffu) wave_pass(S, k, vv, n, true, shift);
+#pragma unroll
+    for (int r = 0; r < kWaveR; ++r) {
+      const int e = r * 64 + lane;
+      if (e < n) S.val[e] = vv[r];
+    }
+    wave_lds_fence();
+  }
+  for (int e = lane; e < n; e += 64) out_ids[e] = S.val[e];
+}
+
+// Lists of 1..kWaveCap pairs: four tiles per 256-thread block, one per wave.
+__global__ void __launch_bounds__(256) tile_sort_wave_kernel(const DeviceBatch* __restrict__ db, const uint2* pairs,
+                                                             uint32_t* sorted_ids, int64_t total_tiles,
+                                                             uint64_t capacity) {
+  __shared__ WaveSortShared S[4];
+  const int wave = threadIdx.x >> 6;
+  const int64_t gt = (int64_t)blockIdx.x * 4 + wave;
+  if (gt >= total_tiles) return;
+  const int v = view_of_block(db->tile_prefix, db->nviews, gt);
+  const ViewDesc& V = db->views[v];
+  const uint2 rg = V.ranges[gt - db->tile_prefix[v]];
+  if (rg.y <= rg.x || (uint64_t)rg.y > capacity) return;
+  const int n = (int)(rg.y - rg.x);
+  if (n > kWaveCap) return;   // the block kernels'
+  if (n == 1) {
+    if ((threadIdx.x & 63) == 0) sorted_ids[rg.x] = pairs[rg.x].y;
+    return;
+  }
+  wave_sort(S[wave], pairs + rg.x, sorted_ids + rg.x, n);
+}
+
+// Lists of kWaveCap+1..kSortCap pairs: one block per tile.  A longer list is appended to the long-list queue
 // (whose counters the scatter kernel has reset).
 __global__ void __launch_bounds__(256) tile_sort_short_kernel(const DeviceBatch* __restrict__ db, const uint2* pairs,
                                                               uint32_t* sorted_ids, int64_t total_tiles,
@@ -372,15 +535,12 @@ __global__ void __launch_bounds__(256) tile_sort_short_kernel(const DeviceBatch*
   const uint2 rg = V.ranges[gt - db->tile_prefix[v]];
   if (rg.y <= rg.x || (uint64_t)rg.y > capacity) return;
   const int n = (int)(rg.y - rg.x);
+  if (n <= kWaveCap) return;   // the wave kernel's
   if (n > kSortCap) {
     if (threadIdx.x == 0) {
       const uint32_t slot = atomicAdd(&queue[0], 1u);
       if ((int64_t)slot < total_tiles) long_list[slot] = (uint32_t)gt;
     }
-    return;
-  }
-  if (n == 1) {
-    if (threadIdx.x == 0) sorted_ids[rg.x] = pairs[rg.x].y;
     return;
   }
   sort_lds(S, pairs + rg.x, sorted_ids + rg.x, n);
@@ -417,6 +577,10 @@ __global__ void __launch_bounds__(1024) tile_sort_long_kernel(const DeviceBatch*
 hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {
   if (b.total_tiles == 0 || b.key_capacity == 0) return hipSuccess;
   if (!b.sort_queue || !b.long_list) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tile_sort_wave_kernel, dim3((unsigned)((b.total_tiles + 3) / 4)), dim3(256), 0, stream, dbatch,
+                     b.pairs, b.sorted_ids, b.total_tiles, b.key_capacity);
+  hipError_t e0 = hipGetLastError();
+  if (e0 != hipSuccess) return e0;
   hipLaunchKernelGGL(tile_sort_short_kernel, dim3((unsigned)b.total_tiles), dim3(256), 0, stream, dbatch, b.pairs,
                      b.sorted_ids, b.total_tiles, b.key_capacity, b.sort_queue, b.long_list);
   hipError_t e = hipGetLastError();
