@@ -59,7 +59,8 @@ struct ViewDesc {
   uint32_t* bin_counts;          // [bin_blocks][tiles] per-chunk tile counts, then exclusive column prefix
   uint32_t* tile_total;          // [tiles] entries per tile
   uint2* ranges;                 // [tiles] [start,end) into the key arrays (global positions)
-  unsigned long long* header;    // [0] keys of this view, [1] error flags
+  unsigned long long* header;    // [0] keys of this view, [1] error flags, [2] [3] pair statistics
+  unsigned long long* tile_stats;  // [tiles][2] pairs examined and composited per tile (forward pass)
   double* grad2d;                // [n][kGradStride] binary64 accumulators (cross-tile sums)
   uint32_t* vis;                 // [n] bit 31: the splat touches a tile; bits 0..4: its clamp flags
   float* final_T;                // [h*w]

@@ -132,17 +132,18 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
     __syncthreads();
   }
   {
-    // per-frame pair statistics: pairs examined (each pixel up to and including its terminating splat)
-    // and composited; one atomic per tile
+    // pair statistics of the tile: pairs examined (each pixel up to and including its terminating splat)
+    // and composited, stored per tile and summed by raster_stats_kernel.  (Device-scope atomics from
+    // every tile into one counter serialise across the XCDs: two per tile cost about 50 us per frame.)
     // pixels still alive examined the whole list (out-of-image pixels were never alive)
     unsigned long long e = (unsigned long long)n_exam + (unsigned long long)__popc(alive) * (uint32_t)n, b = n_blend;
     for (int off = 32; off > 0; off >>= 1) {
       e += __shfl_xor(e, off, 64);
       b += __shfl_xor(b, off, 64);
     }
-    if (lane == 0 && e > 0) {
-      atomicAdd(&V.header[2], e);
-      atomicAdd(&V.header[3], b);
+    if (lane == 0) {
+      V.tile_stats[2 * lt] = e;
+      V.tile_stats[2 * lt + 1] = b;
     }
   }
 #pragma unroll
@@ -355,6 +356,34 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   }
 }
 
+// One block: every view's per-tile pair statistics summed into its header ([2] examined, [3] composited).
+__global__ void __launch_bounds__(1024) raster_stats_kernel(const DeviceBatch* __restrict__ db) {
+  __shared__ unsigned long long part[2][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int v = 0; v < db->nviews; ++v) {
+    const ViewDesc& V = db->views[v];
+    const int T = V.tiles_x * V.tiles_y;
+    unsigned long long e = 0, c = 0;
+    for (int t = threadIdx.x; t < T; t += 1024) {
+      e += V.tile_stats[2 * t];
+      c += V.tile_stats[2 * t + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      e += __shfl_xor(e, off, 64);
+      c += __shfl_xor(c, off, 64);
+    }
+    if (lane == 0) { part[0][w] = e; part[1][w] = c; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long se = 0, sc = 0;
+      for (int k = 0; k < 16; ++k) { se += part[0][k]; sc += part[1][k]; }
+      V.header[2] = se;
+      V.header[3] = sc;
+    }
+    __syncthreads();   // part[] is rewritten for the next view
+  }
+}
+
 hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {
   if (b.total_tiles == 0) return hipSuccess;
   const int64_t span = 8 * kXcdGroup;   // the grid covers whole rounds of groups
@@ -366,6 +395,9 @@ hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipS
   else
     hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_GEF>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
                        b.total_tiles, b.key_capacity);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(raster_stats_kernel, dim3(1), dim3(1024), 0, stream, dbatch);
   return hipGetLastError();
 }
 

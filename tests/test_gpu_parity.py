@@ -52,6 +52,13 @@ def test_forward_parity(case):
     assert cmp["max_err"] <= IMG_ATOL and cmp["flagged_max_err"] <= IMG_ATOL, cmp
     fl = ref["out"]["flags"].astype(bool)
     assert np.array_equal(gpu["n_contrib"][~fl], ref["out"]["n_contrib"][~fl].astype(np.uint32))
+    # pair statistics (they price the roofline): pairs examined per pixel up to and including its terminating
+    # splat, and pairs composited; a flagged pixel may end at another position (up to a whole list)
+    ost = ref["out"]["stats"]
+    lens = r[:, 1] - r[:, 0]
+    slack = int(ost["pixels_flagged"]) * int(lens.max(initial=0))
+    assert abs(int(gpu["stats"][2]) - ost["pairs_examined"]) <= slack, (gpu["stats"], ost)
+    assert abs(int(gpu["stats"][3]) - ost["pairs_blended"]) <= slack, (gpu["stats"], ost)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
