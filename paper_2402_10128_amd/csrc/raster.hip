@@ -23,6 +23,18 @@
 
 namespace ges {
 
+// Workspace pointers read from the view descriptor are generic; typed in the global address space, the
+// compiler emits global loads and atomics, which count only against vmcnt, so LDS waits do not wait for
+// them (generic (flat) accesses count against lgkmcnt too).  Records load as native 4-float vectors.
+typedef float Vec4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const Vec4 GlobalRec;
+typedef __attribute__((address_space(1))) double GlobalF64;
+
+__device__ __forceinline__ float4 rec_load(const GlobalRec* rec, size_t i) {
+  const Vec4 v = rec[i];
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;   // -log2(e)/2: exp(-q/2) = 2^(kNegHalfLog2e q)
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -83,15 +95,15 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
   const uint2 rg = V.ranges[lt];
   // a range beyond the key buffer (inconsistent key count) renders as background
   const int n = (uint64_t)rg.y <= capacity ? (int)(rg.y - rg.x) : 0;
-  const float4* rec = V.rec;
+  const GlobalRec* rec = (const GlobalRec*)(V.rec);
   for (int base = 0; base < n; base += 64) {
     if (!__any(alive != 0)) break;
     const int cnt = min(64, n - base);
     if (lane < cnt) {
       const uint32_t id = sorted_ids[rg.x + base + lane];
-      const float4 a = rec[4 * (size_t)id];
-      const float4 b = rec[4 * (size_t)id + 1];
-      const float4 c = rec[4 * (size_t)id + 2];
+      const float4 a = rec_load(rec, 4 * (size_t)id);
+      const float4 b = rec_load(rec, 4 * (size_t)id + 1);
+      const float4 c = rec_load(rec, 4 * (size_t)id + 2);
       sA[lane] = make_float4(a.x, a.y, a.z, a.w + a.w);
       sB[lane] = b;
       sC[lane] = c;
@@ -232,8 +244,10 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   // wave max of the last contributor position
   for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, off, 64));
   const uint2 rg = V.ranges[lt];
-  const float4* rec = V.rec;
-  double* grad2d = V.grad2d;
+  const GlobalRec* rec = (const GlobalRec*)(V.rec);
+  // global address space: the accumulation atomics then count only against vmcnt, and the LDS waits of the
+  // following splats do not wait for them (flat atomics count against lgkmcnt too)
+  GlobalF64* grad2d = (GlobalF64*)(V.grad2d);
   uint32_t parked = 0;    // bit s: slot s holds row partials (uniform across the wave)
   int nslot = 0;
   for (int hi = (int)maxlast; hi > 0; hi -= 64) {
@@ -241,9 +255,9 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
     const int cnt = hi - lo;
     if (lane < cnt) {
       const uint32_t id = sorted_ids[rg.x + lo + lane];
-      const float4 a = rec[4 * (size_t)id];
-      const float4 b = rec[4 * (size_t)id + 1];
-      const float4 c = rec[4 * (size_t)id + 2];
+      const float4 a = rec_load(rec, 4 * (size_t)id);
+      const float4 b = rec_load(rec, 4 * (size_t)id + 1);
+      const float4 c = rec_load(rec, 4 * (size_t)id + 2);
       sA[lane] = make_float4(a.x, a.y, a.z, a.w);
       sB[lane] = b;
       sC[lane] = make_float4(c.x, c.y, c.z, __uint_as_float(id));
@@ -341,11 +355,11 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
           val[0] = 2.f * val[0];   // dL/du = 2 sum dq (a dx + b dy)
           val[1] = 2.f * val[1];   // dL/dv = 2 sum dq (b dx + c dy)
           val[3] = 2.f * val[3];   // dL/db = 2 sum dq dx dy
-          double* dst = grad2d + (size_t)id * kGradStride;
+          GlobalF64* dst = grad2d + (size_t)id * kGradStride;
           constexpr int ncomp = FALLOFF == GES_FALLOFF_GEF ? 10 : 9;
 #pragma unroll
           for (int c = 0; c < ncomp; ++c)
-            if (val[c] != 0.f) atomicAdd(dst + c, (double)val[c]);
+            if (val[c] != 0.f) __hip_atomic_fetch_add(dst + c, (double)val[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
         parked = 0;
