@@ -248,7 +248,6 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   // global address space: the accumulation atomics then count only against vmcnt, and the LDS waits of the
   // following splats do not wait for them (flat atomics count against lgkmcnt too)
   GlobalF64* grad2d = (GlobalF64*)(V.grad2d);
-  uint32_t parked = 0;    // bit s: slot s holds row partials (uniform across the wave)
   int nslot = 0;
   for (int hi = (int)maxlast; hi > 0; hi -= 64) {
     const int lo = max(0, hi - 64);
@@ -340,13 +339,12 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
           d[5] = r5; d[6] = r6; d[7] = r7; d[8] = r8; d[9] = r9;
         }
         if (lane == 0) sId[nslot] = __float_as_uint(Cc.w);
-        parked |= 1u << nslot;
         ++nslot;
       }
       if (nslot == kFlush || (j == 0 && hi - 64 <= 0 && nslot > 0)) {
         // one lane per parked splat: add the four row sums, then one float64 atomic per component
         __syncthreads();
-        if (lane < kFlush && (parked >> lane) & 1u) {
+        if (lane < nslot) {   // slots 0 .. nslot-1 hold row partials
           const uint32_t id = sId[lane];
           float val[10];
 #pragma unroll
@@ -362,7 +360,6 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
             if (val[c] != 0.f) __hip_atomic_fetch_add(dst + c, (double)val[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
-        parked = 0;
         nslot = 0;
       }
     }
