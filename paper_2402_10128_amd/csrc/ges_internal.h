@@ -121,6 +121,20 @@ size_t loss_scratch_bytes();
 hipError_t launch_loss(const float* img, const float* target, const uint8_t* mask, int w, int h, float lam_l1,
                        float lam_w, void* scratch, float* loss_out, float* dL_dimg, hipStream_t stream);
 
+// Workspace pointers read from the view descriptor are generic (flat).  Typed in the global address
+// space, loads, stores and atomics through them become global instructions, which count only against
+// vmcnt; flat ones count against lgkmcnt too, so every LDS wait would also wait for them.  Records load as
+// native 4-float vectors (the float4 class cannot be copied out of another address space).
+typedef float Vec4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const Vec4 GlobalRec;
+typedef __attribute__((address_space(1))) double GlobalF64;
+typedef __attribute__((address_space(1))) uint32_t GlobalU32;
+
+__device__ __forceinline__ float4 rec_load(const GlobalRec* rec, size_t i) {
+  const Vec4 v = rec[i];
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+
 // Which view owns global block `blk` given a prefix table (linear scan: at most kMaxViews entries).
 __device__ inline int view_of_block(const int64_t* prefix, int nviews, int64_t blk) {
   int v = 0;

@@ -23,18 +23,6 @@
 
 namespace ges {
 
-// Workspace pointers read from the view descriptor are generic; typed in the global address space, the
-// compiler emits global loads and atomics, which count only against vmcnt, so LDS waits do not wait for
-// them (generic (flat) accesses count against lgkmcnt too).  Records load as native 4-float vectors.
-typedef float Vec4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(1))) const Vec4 GlobalRec;
-typedef __attribute__((address_space(1))) double GlobalF64;
-
-__device__ __forceinline__ float4 rec_load(const GlobalRec* rec, size_t i) {
-  const Vec4 v = rec[i];
-  return make_float4(v[0], v[1], v[2], v[3]);
-}
-
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;   // -log2(e)/2: exp(-q/2) = 2^(kNegHalfLog2e q)
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
