@@ -517,3 +517,39 @@ def test_loss_gradient_matches_fd():
         Im[idx] -= h
         fd = (OL.loss_and_grad(Ip, T, M, 0.5, 0.5)[0] - OL.loss_and_grad(Im, T, M, 0.5, 0.5)[0]) / (2 * h)
         assert abs(fd - g[idx]) < 1e-6
+
+
+# ---- optimiser (App. B.2): Adam and the position learning-rate schedule
+def test_adam_matches_torch_and_first_step_sign():
+    """The oracle's Adam equals torch.optim.Adam in float64 step for step (a library routine); its first
+    update is -lr sign(g) up to eps (Kingma & Ba, Sec. 2)."""
+    import torch
+    from oracle import optim as OP
+    rng = np.random.default_rng(11)
+    p0 = rng.standard_normal(200)
+    grads = [rng.standard_normal(200) * 10.0 ** rng.uniform(-4, 1, 200) for _ in range(6)]
+    tp = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=0.01, betas=(OP.BETA1, OP.BETA2), eps=OP.EPS)
+    p, m, v = p0.copy(), np.zeros(200), np.zeros(200)
+    for t, g in enumerate(grads, start=1):
+        opt.zero_grad()
+        tp.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        p, m, v = OP.adam_step(p, g, m, v, t, 0.01)
+        assert np.allclose(p, tp.detach().numpy(), rtol=0, atol=1e-13)
+        if t == 1:
+            assert np.allclose(p - p0, -0.01 * np.sign(g), rtol=1e-9, atol=0)
+
+
+def test_position_lr_schedule_endpoints():
+    """Log-linear schedule: the initial rate at step 0, the final rate from max_steps on, the geometric
+    mean halfway; a delay ramps from delay_mult at step 0 to 1 at delay_steps."""
+    from oracle import optim as OP
+    assert OP.position_lr(0) == pytest.approx(0.00016, rel=1e-12)
+    assert OP.position_lr(30000) == pytest.approx(0.0000016, rel=1e-12)
+    assert OP.position_lr(40000) == pytest.approx(0.0000016, rel=1e-12)
+    assert OP.position_lr(15000) == pytest.approx(math.sqrt(0.00016 * 0.0000016), rel=1e-12)
+    lrs = [OP.position_lr(s) for s in range(0, 30001, 1000)]
+    assert all(a > b for a, b in zip(lrs, lrs[1:]))
+    assert OP.expon_lr(0, 1.0, 1.0, 10, delay_steps=100, delay_mult=0.01) == pytest.approx(0.01)
+    assert OP.expon_lr(100, 1.0, 1.0, 10, delay_steps=100, delay_mult=0.01) == pytest.approx(1.0)
