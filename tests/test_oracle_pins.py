@@ -553,3 +553,60 @@ def test_position_lr_schedule_endpoints():
     assert all(a > b for a, b in zip(lrs, lrs[1:]))
     assert OP.expon_lr(0, 1.0, 1.0, 10, delay_steps=100, delay_mult=0.01) == pytest.approx(0.01)
     assert OP.expon_lr(100, 1.0, 1.0, 10, delay_steps=100, delay_mult=0.01) == pytest.approx(1.0)
+
+
+# ---- SSIM term of the training loss (Gaussian-weighted SSIM, Wang et al. 2004)
+def test_ssim_local_mean_is_zero_padded_gaussian_filter():
+    """The 121-tap window sum equals scipy's separable Gaussian filter (sigma 1.5, radius 5, zero padding)."""
+    from scipy.ndimage import gaussian_filter
+    from oracle import ssim as OS
+    a = np.random.default_rng(3).random((23, 31))
+    want = gaussian_filter(a, 1.5, mode="constant", cval=0.0, truncate=5 / 1.5)
+    assert np.allclose(OS.local_mean(a), want, rtol=0, atol=1e-14)
+
+
+def test_ssim_identical_images_and_symmetry():
+    """SSIM(x, x) = 1 at every pixel, so L_ssim = 0 with a zero gradient; SSIM is symmetric in its operands."""
+    from oracle import ssim as OS
+    rng = np.random.default_rng(4)
+    x, y = rng.random((14, 17, 3)), rng.random((14, 17, 3))
+    assert np.allclose(OS.ssim_map(x, x), 1.0, rtol=0, atol=1e-12)
+    loss, g = OS.ssim_loss_and_grad(x, x)
+    assert abs(loss) < 1e-12 and np.abs(g).max() < 1e-12
+    assert np.allclose(OS.ssim_map(x, y), OS.ssim_map(y, x), rtol=0, atol=1e-14)
+
+
+def test_ssim_closed_forms_away_from_the_border():
+    """Constant images a, b: SSIM = (2ab + C1)/(a^2 + b^2 + C1).  A constant image a against y: s_x = s_xy = 0,
+    so SSIM = (2 a mu_y + C1) C2 / ((a^2 + mu_y^2 + C1)(s_y + C2)) with mu_y, s_y from scipy's filter."""
+    from scipy.ndimage import gaussian_filter
+    from oracle import ssim as OS
+    H, W = 25, 27
+    x = np.full((H, W, 3), 0.3)
+    y = np.full((H, W, 3), 0.8)
+    inner = (slice(5, H - 5), slice(5, W - 5))
+    want = (2 * 0.3 * 0.8 + 1e-4) / (0.09 + 0.64 + 1e-4)
+    assert np.allclose(OS.ssim_map(x, y)[inner], want, rtol=1e-12)
+    y = np.random.default_rng(5).random((H, W, 3))
+    f = lambda a: gaussian_filter(a, 1.5, mode="constant", cval=0.0, truncate=5 / 1.5)
+    for c in range(3):
+        mu = f(y[..., c])
+        sy = f(y[..., c] ** 2) - mu * mu
+        want = (2 * 0.3 * mu + 1e-4) * 9e-4 / ((0.09 + mu * mu + 1e-4) * (sy + 9e-4))
+        assert np.allclose(OS.ssim_map(x, y)[..., c][inner], want[inner], rtol=1e-10)
+
+
+def test_ssim_gradient_matches_central_differences():
+    """dL_ssim/dI against central differences of the oracle's loss on a 9x12 image (every pixel within the
+    window's reach of a border, so the zero padding is exercised)."""
+    from oracle import ssim as OS
+    rng = np.random.default_rng(6)
+    x, y = rng.random((9, 12, 3)), rng.random((9, 12, 3))
+    _, g = OS.ssim_loss_and_grad(x, y)
+    h = 1e-6
+    for idx in [(0, 0, 0), (4, 6, 1), (8, 11, 2), (2, 9, 0), (7, 1, 2), (5, 5, 1)]:
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (OS.ssim_loss_and_grad(xp, y)[0] - OS.ssim_loss_and_grad(xm, y)[0]) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-7 * max(1.0, abs(g[idx]) * 1e3), (idx, fd, g[idx])
