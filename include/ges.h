@@ -189,7 +189,7 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
  * costs two event records per launch. */
 enum { GES_STAGE_PREPROCESS = 0, GES_STAGE_BIN_COUNT, GES_STAGE_BIN_SCAN, GES_STAGE_BIN_SCATTER, GES_STAGE_TILE_SORT,
        GES_STAGE_RASTER_FORWARD, GES_STAGE_RASTER_BACKWARD, GES_STAGE_PREPROCESS_BACKWARD, GES_STAGE_ZERO,
-       GES_STAGE_LOSS, GES_NUM_STAGES };
+       GES_STAGE_LOSS, GES_STAGE_ADAM, GES_NUM_STAGES };
 ges_status ges_profile_enable(int32_t on);
 /* Time only the stages whose bit (1 << GES_STAGE_*) is set; 0 switches timing off. */
 ges_status ges_profile_select(uint32_t stage_mask);
@@ -212,6 +212,39 @@ ges_status ges_freq_mask(const float* target, int32_t width, int32_t height, flo
 size_t ges_loss_scratch_bytes(void);
 ges_status ges_loss(const float* img, const float* target, const uint8_t* mask, int32_t width, int32_t height,
                     float lam_l1, float lam_w, void* scratch, float* loss_out, float* dL_dimg, void* stream);
+
+/* ---- optimiser step of training (App. B.2) ---------------------------------------
+ * Adam (Kingma & Ba, 2015, Algorithm 1) applied in place to up to GES_ADAM_MAX_GROUPS
+ * parameter groups in one launch, each with its own learning rate (the paper trains
+ * position, SH features, opacity, shape beta, rotation and scaling at separate rates):
+ *   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
+ *   p <- p - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps),
+ * computed in binary32 (the bias corrections in binary64 on the host).  step counts
+ * from 1; exp_avg and exp_avg_sq must be zero before step 1.  The four arrays of a
+ * group hold `count` floats each and must not overlap each other or another group's
+ * (the result is undefined if they do); 16-byte aligned groups move as float4.
+ * Errors: GES_ERR_INVALID_ARGUMENT for ngroups outside 1..GES_ADAM_MAX_GROUPS, step < 1,
+ * b1 or b2 outside [0,1), eps < 0, a non-finite or negative lr, count < 0, or a NULL
+ * pointer in a group with count > 0. */
+#define GES_ADAM_MAX_GROUPS 8
+typedef struct {
+  float* params;                 /* [count] updated in place */
+  const float* grads;            /* [count] */
+  float* exp_avg;                /* [count] first moment m, updated in place */
+  float* exp_avg_sq;             /* [count] second moment v, updated in place */
+  int64_t count;
+  float lr;
+} ges_adam_group;
+ges_status ges_adam_step(const ges_adam_group* groups, int32_t ngroups, int64_t step, float beta1, float beta2,
+                         float eps, void* stream);
+
+/* Learning rate at `step` of a log-linear decay from lr_init (step 0) to lr_final (step
+ * max_steps, constant afterwards), times a delay factor that rises from delay_mult to 1
+ * along a quarter sine over delay_steps (none when delay_steps <= 0).  The paper decays
+ * the position rate this way (App. B.2).  Host function; returns NaN for lr_init or
+ * lr_final <= 0 or max_steps < 1. */
+double ges_expon_lr(int64_t step, double lr_init, double lr_final, int64_t max_steps, int64_t delay_steps,
+                    double delay_mult);
 
 /* ---- serving: continuous batching of render requests ----------------------------- */
 typedef struct ges_server ges_server;

@@ -2,6 +2,8 @@
 // the launch sequences of one frame.  No allocation happens here: every buffer is the caller's.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -317,6 +319,39 @@ ges_status ges_loss(const float* img, const float* target, const uint8_t* mask, 
                                           loss_out, dL_dimg, st);
                 }), "loss");
   return GES_OK;
+}
+
+ges_status ges_adam_step(const ges_adam_group* groups, int32_t ngroups, int64_t step, float beta1, float beta2,
+                         float eps, void* stream) {
+  if (!groups) return fail(GES_ERR_INVALID_ARGUMENT, "NULL groups");
+  if (ngroups < 1 || ngroups > GES_ADAM_MAX_GROUPS) return fail(GES_ERR_INVALID_ARGUMENT, "ngroups outside 1..8");
+  if (step < 1) return fail(GES_ERR_INVALID_ARGUMENT, "step < 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+    return fail(GES_ERR_INVALID_ARGUMENT, "beta outside [0,1)");
+  if (!(eps >= 0.f) || !std::isfinite(eps)) return fail(GES_ERR_INVALID_ARGUMENT, "bad eps");
+  for (int k = 0; k < ngroups; ++k) {
+    const ges_adam_group& g = groups[k];
+    if (g.count < 0) return fail(GES_ERR_INVALID_ARGUMENT, "negative count");
+    if (!(g.lr >= 0.f) || !std::isfinite(g.lr)) return fail(GES_ERR_INVALID_ARGUMENT, "bad lr");
+    if (g.count > 0 && (!g.params || !g.grads || !g.exp_avg || !g.exp_avg_sq))
+      return fail(GES_ERR_INVALID_ARGUMENT, "NULL array in a group");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  GES_CHECK_HIP(timed(GES_STAGE_ADAM, st, [&] { return ges::launch_adam(groups, ngroups, step, beta1, beta2, eps, st); }),
+                "adam");
+  return GES_OK;
+}
+
+double ges_expon_lr(int64_t step, double lr_init, double lr_final, int64_t max_steps, int64_t delay_steps,
+                    double delay_mult) {
+  if (!(lr_init > 0.0) || !(lr_final > 0.0) || max_steps < 1) return std::nan("");
+  const double tau = std::min(std::max((double)step / (double)max_steps, 0.0), 1.0);
+  double lr = lr_init == lr_final ? lr_init : std::exp((1.0 - tau) * std::log(lr_init) + tau * std::log(lr_final));
+  if (delay_steps > 0) {
+    const double r = std::min(std::max((double)step / (double)delay_steps, 0.0), 1.0);
+    lr *= delay_mult + (1.0 - delay_mult) * std::sin(0.5 * M_PI * r);
+  }
+  return lr;
 }
 
 }  // extern "C"

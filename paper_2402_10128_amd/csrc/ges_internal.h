@@ -121,6 +121,10 @@ size_t loss_scratch_bytes();
 hipError_t launch_loss(const float* img, const float* target, const uint8_t* mask, int w, int h, float lam_l1,
                        float lam_w, void* scratch, float* loss_out, float* dL_dimg, hipStream_t stream);
 
+constexpr int kAdamMaxGroups = GES_ADAM_MAX_GROUPS;
+hipError_t launch_adam(const ges_adam_group* groups, int ngroups, int64_t step, float b1, float b2, float eps,
+                       hipStream_t stream);
+
 // Workspace pointers read from the view descriptor are generic (flat).  Typed in the global address
 // space, loads, stores and atomics through them become global instructions, which count only against
 // vmcnt; flat ones count against lgkmcnt too, so every LDS wait would also wait for them.  Records load as

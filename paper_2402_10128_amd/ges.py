@@ -61,6 +61,11 @@ class ges_serve_config(C.Structure):
                 ("tile_cull", C.c_int32), ("rho", C.c_float), ("bg", C.c_float * 3), ("sequential", C.c_int32)]
 
 
+class ges_adam_group(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("grads", C.c_void_p), ("exp_avg", C.c_void_p), ("exp_avg_sq", C.c_void_p),
+                ("count", C.c_int64), ("lr", C.c_float)]
+
+
 class ges_request_info(C.Structure):
     _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("t_submit_ns", C.c_uint64), ("t_start_ns", C.c_uint64),
                 ("t_done_ns", C.c_uint64), ("num_keys", C.c_uint64), ("batch_size", C.c_int32)]
@@ -90,6 +95,8 @@ _SIGS = {
     "ges_loss_scratch_bytes": (C.c_size_t, []),
     "ges_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_float,
                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ges_adam_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_void_p]),
+    "ges_expon_lr": (C.c_double, [C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_double]),
     "ges_serve_create": (C.c_int, [C.POINTER(ges_serve_config), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
     "ges_serve_create_simulated": (C.c_int, [C.POINTER(ges_serve_config), C.c_size_t, C.c_uint64, C.c_uint64,
                                              C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
@@ -210,7 +217,7 @@ def ges_frame_view_get(n, width, height, splat_ws, key_ws, num_keys, pixel_ws) -
 
 
 STAGES = ["preprocess", "bin_count", "bin_scan", "bin_scatter", "tile_sort", "raster_forward", "raster_backward",
-          "preprocess_backward", "zero", "loss"]
+          "preprocess_backward", "zero", "loss", "adam"]
 
 
 def ges_profile_enable(on: bool):
@@ -252,6 +259,25 @@ def ges_loss(img, target, mask, lam_l1, lam_w, dL_dimg=None, loss_out=None, scra
     _check(lib().ges_loss(_ptr(img), _ptr(target), _ptr(mask), W, H, float(lam_l1), float(lam_w), _ptr(scratch),
                           _ptr(loss_out), _ptr(dL_dimg), _stream(stream)))
     return loss_out, dL_dimg
+
+
+ADAM_MAX_GROUPS = 8
+
+
+def ges_adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    """In-place Adam step; groups: list of (params, grads, exp_avg, exp_avg_sq, lr) with float32 CUDA tensors."""
+    arr = (ges_adam_group * max(1, len(groups)))()
+    for k, (p, g, m, v, lr) in enumerate(groups):
+        for t in (p, g, m, v):
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != p.numel():
+                raise ValueError("Adam groups take contiguous float32 tensors of one size")
+        arr[k] = ges_adam_group(p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), p.numel(), float(lr))
+    _check(lib().ges_adam_step(arr, len(groups), int(step), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def ges_expon_lr(step, lr_init, lr_final, max_steps, delay_steps=0, delay_mult=1.0) -> float:
+    return lib().ges_expon_lr(int(step), float(lr_init), float(lr_final), int(max_steps), int(delay_steps),
+                              float(delay_mult))
 
 
 # ---- a frame: owns the workspaces of one (scene, camera) render --------------------------------------

@@ -87,3 +87,32 @@ def test_loss_and_mask_validate():
     assert lib.ges_loss(None, None, None, 4, 4, 1.0, 0.0, None, None, None, None) == 1
     assert lib.ges_freq_mask(C.c_void_p(1 << 20), 4, 4, 2.0, C.c_void_p(1 << 21), C.c_void_p(1 << 22), None) == 1
     assert lib.ges_mask_scratch_bytes(1920, 1080) > 4 * 384 * 216 * 4
+
+
+def test_expon_lr_matches_oracle_schedule():
+    """The library's host learning-rate schedule equals the oracle's at every 500th step and around the ends."""
+    from oracle import optim as OP
+    steps = list(range(0, 30001, 500)) + [1, 29999, 30001, 45000]
+    for s in steps:
+        assert G.ges_expon_lr(s, 0.00016, 0.0000016, 30000) == pytest.approx(OP.position_lr(s), rel=1e-14)
+        want = OP.expon_lr(s, 0.00016, 0.0000016, 30000, delay_steps=2000, delay_mult=0.01)
+        assert G.ges_expon_lr(s, 0.00016, 0.0000016, 30000, 2000, 0.01) == pytest.approx(want, rel=1e-14)
+    assert np.isnan(G.ges_expon_lr(0, 0.0, 1.0, 10))
+
+
+def test_adam_step_validates_before_any_device_work():
+    lib = G.lib()
+    grp = (G.ges_adam_group * 2)()
+    grp[0] = G.ges_adam_group(1 << 20, 1 << 21, 1 << 22, 1 << 23, 16, 0.01)
+    assert lib.ges_adam_step(None, 1, 1, 0.9, 0.999, 1e-15, None) == 1
+    assert lib.ges_adam_step(grp, 0, 1, 0.9, 0.999, 1e-15, None) == 1
+    assert lib.ges_adam_step(grp, 9, 1, 0.9, 0.999, 1e-15, None) == 1
+    assert lib.ges_adam_step(grp, 1, 0, 0.9, 0.999, 1e-15, None) == 1
+    assert lib.ges_adam_step(grp, 1, 1, 1.0, 0.999, 1e-15, None) == 1
+    assert lib.ges_adam_step(grp, 1, 1, 0.9, 0.999, -1.0, None) == 1
+    grp[1] = G.ges_adam_group(None, None, None, None, 4, 0.01)
+    assert lib.ges_adam_step(grp, 2, 1, 0.9, 0.999, 1e-15, None) == 1
+    grp[1] = G.ges_adam_group(1 << 24, 1 << 25, 1 << 26, 1 << 27, -1, 0.01)
+    assert lib.ges_adam_step(grp, 2, 1, 0.9, 0.999, 1e-15, None) == 1
+    grp[1] = G.ges_adam_group(1 << 24, 1 << 25, 1 << 26, 1 << 27, 4, float("nan"))
+    assert lib.ges_adam_step(grp, 2, 1, 0.9, 0.999, 1e-15, None) == 1
