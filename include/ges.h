@@ -189,7 +189,7 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
  * costs two event records per launch. */
 enum { GES_STAGE_PREPROCESS = 0, GES_STAGE_BIN_COUNT, GES_STAGE_BIN_SCAN, GES_STAGE_BIN_SCATTER, GES_STAGE_TILE_SORT,
        GES_STAGE_RASTER_FORWARD, GES_STAGE_RASTER_BACKWARD, GES_STAGE_PREPROCESS_BACKWARD, GES_STAGE_ZERO,
-       GES_STAGE_LOSS, GES_STAGE_ADAM, GES_NUM_STAGES };
+       GES_STAGE_LOSS, GES_STAGE_ADAM, GES_STAGE_SSIM, GES_NUM_STAGES };
 ges_status ges_profile_enable(int32_t on);
 /* Time only the stages whose bit (1 << GES_STAGE_*) is set; 0 switches timing off. */
 ges_status ges_profile_select(uint32_t stage_mask);
@@ -212,6 +212,20 @@ ges_status ges_freq_mask(const float* target, int32_t width, int32_t height, flo
 size_t ges_loss_scratch_bytes(void);
 ges_status ges_loss(const float* img, const float* target, const uint8_t* mask, int32_t width, int32_t height,
                     float lam_l1, float lam_w, void* scratch, float* loss_out, float* dL_dimg, void* stream);
+
+/* ---- structural-similarity term of the training loss (Sec. 5 loss, lambda_ssim) ------
+ * Gaussian-weighted SSIM (Wang et al., 2004) of img against target, both [h,w,3]:
+ * 11x11 window of sigma 1.5 (unit sum), each channel on its own, zero padding (the
+ * SSIM map has the image's size), C1 = 0.01^2, C2 = 0.03^2; L_ssim = 1 - mean SSIM over
+ * h*w*3 values.  The call ACCUMULATES: *loss_inout += lam_ssim L_ssim and
+ * dL_dimg += lam_ssim dL_ssim/dimg, so it runs after ges_loss (which overwrites both)
+ * to form the full loss 0.3 L1 + 0.2 L_ssim + 0.5 L_omega.  The loss is summed in a
+ * fixed order (deterministic).  scratch: device buffer of ges_ssim_scratch_bytes(w,h)
+ * bytes (nine [h,w] FP32 maps and per-tile sums).  Errors: GES_ERR_INVALID_ARGUMENT for
+ * a NULL pointer, sizes outside 1..16384 or a non-finite lam_ssim. */
+size_t ges_ssim_scratch_bytes(int32_t width, int32_t height);
+ges_status ges_ssim_loss(const float* img, const float* target, int32_t width, int32_t height, float lam_ssim,
+                         void* scratch, float* loss_inout, float* dL_dimg, void* stream);
 
 /* ---- optimiser step of training (App. B.2) ---------------------------------------
  * Adam (Kingma & Ba, 2015, Algorithm 1) applied in place to up to GES_ADAM_MAX_GROUPS

@@ -321,6 +321,23 @@ ges_status ges_loss(const float* img, const float* target, const uint8_t* mask, 
   return GES_OK;
 }
 
+size_t ges_ssim_scratch_bytes(int32_t width, int32_t height) {
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return 0;
+  return ges::ssim_scratch_bytes(width, height);
+}
+
+ges_status ges_ssim_loss(const float* img, const float* target, int32_t width, int32_t height, float lam_ssim,
+                         void* scratch, float* loss_inout, float* dL_dimg, void* stream) {
+  if (!img || !target || !scratch || !loss_inout || !dL_dimg) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return fail(GES_ERR_INVALID_ARGUMENT, "bad sizes");
+  if (!std::isfinite(lam_ssim)) return fail(GES_ERR_INVALID_ARGUMENT, "non-finite weight");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  GES_CHECK_HIP(timed(GES_STAGE_SSIM, st, [&] {
+                  return ges::launch_ssim_loss(img, target, width, height, lam_ssim, scratch, loss_inout, dL_dimg, st);
+                }), "ssim");
+  return GES_OK;
+}
+
 ges_status ges_adam_step(const ges_adam_group* groups, int32_t ngroups, int64_t step, float beta1, float beta2,
                          float eps, void* stream) {
   if (!groups) return fail(GES_ERR_INVALID_ARGUMENT, "NULL groups");

@@ -121,6 +121,10 @@ size_t loss_scratch_bytes();
 hipError_t launch_loss(const float* img, const float* target, const uint8_t* mask, int w, int h, float lam_l1,
                        float lam_w, void* scratch, float* loss_out, float* dL_dimg, hipStream_t stream);
 
+size_t ssim_scratch_bytes(int w, int h);
+hipError_t launch_ssim_loss(const float* img, const float* target, int w, int h, float lam, void* scratch,
+                            float* loss, float* dL, hipStream_t stream);
+
 constexpr int kAdamMaxGroups = GES_ADAM_MAX_GROUPS;
 hipError_t launch_adam(const ges_adam_group* groups, int ngroups, int64_t step, float b1, float b2, float eps,
                        hipStream_t stream);

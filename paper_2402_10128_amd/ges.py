@@ -95,6 +95,9 @@ _SIGS = {
     "ges_loss_scratch_bytes": (C.c_size_t, []),
     "ges_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_float,
                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ges_ssim_scratch_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "ges_ssim_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_void_p]),
     "ges_adam_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "ges_expon_lr": (C.c_double, [C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_double]),
     "ges_serve_create": (C.c_int, [C.POINTER(ges_serve_config), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
@@ -217,7 +220,7 @@ def ges_frame_view_get(n, width, height, splat_ws, key_ws, num_keys, pixel_ws) -
 
 
 STAGES = ["preprocess", "bin_count", "bin_scan", "bin_scatter", "tile_sort", "raster_forward", "raster_backward",
-          "preprocess_backward", "zero", "loss", "adam"]
+          "preprocess_backward", "zero", "loss", "adam", "ssim"]
 
 
 def ges_profile_enable(on: bool):
@@ -259,6 +262,16 @@ def ges_loss(img, target, mask, lam_l1, lam_w, dL_dimg=None, loss_out=None, scra
     _check(lib().ges_loss(_ptr(img), _ptr(target), _ptr(mask), W, H, float(lam_l1), float(lam_w), _ptr(scratch),
                           _ptr(loss_out), _ptr(dL_dimg), _stream(stream)))
     return loss_out, dL_dimg
+
+
+def ges_ssim_loss(img, target, lam_ssim, loss_inout, dL_dimg, scratch=None, stream=None):
+    """loss_inout += lam_ssim (1 - mean SSIM); dL_dimg += lam_ssim dL_ssim/dimg (both accumulated in place)."""
+    H, W = int(img.shape[0]), int(img.shape[1])
+    if scratch is None:
+        scratch = torch.empty(lib().ges_ssim_scratch_bytes(W, H), dtype=torch.uint8, device=img.device)
+    _check(lib().ges_ssim_loss(_ptr(img), _ptr(target), W, H, float(lam_ssim), _ptr(scratch), _ptr(loss_inout),
+                               _ptr(dL_dimg), _stream(stream)))
+    return loss_inout, dL_dimg
 
 
 ADAM_MAX_GROUPS = 8

@@ -116,3 +116,13 @@ def test_adam_step_validates_before_any_device_work():
     assert lib.ges_adam_step(grp, 2, 1, 0.9, 0.999, 1e-15, None) == 1
     grp[1] = G.ges_adam_group(1 << 24, 1 << 25, 1 << 26, 1 << 27, 4, float("nan"))
     assert lib.ges_adam_step(grp, 2, 1, 0.9, 0.999, 1e-15, None) == 1
+
+
+def test_ssim_validates_before_any_device_work():
+    lib = G.lib()
+    assert lib.ges_ssim_scratch_bytes(0, 10) == 0
+    assert lib.ges_ssim_scratch_bytes(1920, 1080) >= 9 * 1920 * 1080 * 4
+    p = C.c_void_p(1 << 20)
+    assert lib.ges_ssim_loss(None, p, 4, 4, 0.2, p, p, p, None) == 1
+    assert lib.ges_ssim_loss(p, p, 0, 4, 0.2, p, p, p, None) == 1
+    assert lib.ges_ssim_loss(p, p, 4, 4, float("inf"), p, p, p, None) == 1
