@@ -1,0 +1,112 @@
+"""One GES optimisation step on the HIP library: frequency mask -> render -> loss -> adjoint -> Adam.
+
+The step follows the paper's training recipe:
+  * loss L = lambda_L1 L1 + lambda_ssim L_ssim + lambda_omega L_omega with lambda_ssim = 0.2,
+    lambda_omega = 0.5 and lambda_L1 = 1 - lambda_ssim - lambda_omega (Sec. 5, loss equation; App. B.2);
+  * the frequency mask M_omega at omega = iteration / total iterations (Sec. 4.3, linear schedule),
+    40,000 iterations in all (App. B.2);
+  * Adam with per-group learning rates, the position rate decaying log-linearly from 1.6e-4 to 1.6e-6
+    over 30,000 steps (App. B.2).
+Every stage runs in the library's kernels; this module only owns buffers and orders the calls on one stream.
+Densification, pruning and the opacity/shape resets of the full training loop are not part of the step.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import ges as G
+
+GROUP_ORDER = ("means", "sh", "opacity_logits", "beta", "quats", "log_scales")
+
+
+@dataclass
+class TrainConfig:
+    total_iterations: int = 40000
+    lam_ssim: float = 0.2
+    lam_omega: float = 0.5
+    lr_pos_init: float = 0.00016
+    lr_pos_final: float = 0.0000016
+    lr_pos_max_steps: int = 30000
+    lr_pos_scale: float = 1.0              # scene extent multiplier of the position rates
+    lr_feature: float = 0.0025
+    lr_opacity: float = 0.05
+    lr_shape: float = 0.001
+    lr_rotation: float = 0.001
+    lr_scaling: float = 0.005
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-15
+    falloff: int = G.FALLOFF_PHI
+    tile_cull: int = G.TILES_ELLIPSE
+    rho: float = 0.1
+    bg: tuple = (0.0, 0.0, 0.0)
+
+
+class TrainStep:
+    """Owns the workspaces of training one scene against one view; ``step(it)`` updates the scene in place.
+
+    scene: dict of contiguous float32 CUDA tensors (means, log_scales, quats, opacity_logits, sh, beta).
+    """
+
+    def __init__(self, scene: dict, cam, target: torch.Tensor, cfg: TrainConfig | None = None):
+        self.cfg = cfg or TrainConfig()
+        self.scene = scene
+        self.cam = cam
+        self.target = target.contiguous()
+        dev = target.device
+        self.s = G.splats_struct(*(scene[k] for k in ("means", "log_scales", "quats", "opacity_logits", "sh",
+                                                      "beta")))
+        self.c = G.camera_struct(cam)
+        self.p = G.params_struct(self.cfg.falloff, self.cfg.tile_cull, self.cfg.rho, self.cfg.bg)
+        H, W = cam.height, cam.width
+        self.frame = G.Frame.create(self.s.n, W, H, dev)
+        self.image = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+        self.dL = torch.empty_like(self.image)
+        self.loss = torch.empty((), dtype=torch.float32, device=dev)
+        self.mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        self.mask_scratch = torch.empty(G.lib().ges_mask_scratch_bytes(W, H), dtype=torch.uint8, device=dev)
+        self.loss_scratch = torch.empty(G.lib().ges_loss_scratch_bytes(), dtype=torch.uint8, device=dev)
+        self.ssim_scratch = torch.empty(G.lib().ges_ssim_scratch_bytes(W, H), dtype=torch.uint8, device=dev)
+        self.grads = {k: torch.empty_like(v) for k, v in scene.items()}
+        self.exp_avg = {k: torch.zeros_like(v) for k, v in scene.items()}
+        self.exp_avg_sq = {k: torch.zeros_like(v) for k, v in scene.items()}
+
+    def omega(self, it: int) -> float:
+        return min(max(it / self.cfg.total_iterations, 0.0), 1.0)
+
+    def learning_rates(self, it: int) -> dict:
+        c = self.cfg
+        pos = c.lr_pos_scale * G.ges_expon_lr(it, c.lr_pos_init, c.lr_pos_final, c.lr_pos_max_steps)
+        return {"means": pos, "sh": c.lr_feature, "opacity_logits": c.lr_opacity, "beta": c.lr_shape,
+                "quats": c.lr_rotation, "log_scales": c.lr_scaling}
+
+    def step(self, it: int, read_num_keys: bool = True):
+        """Iteration ``it`` (counting from 1).  With read_num_keys=False the render takes the key count from
+        the device and the frame's key capacity must already hold it (an overflow is flagged in the frame)."""
+        c = self.cfg
+        _check = G._check
+        L = G.lib()
+        stream = G._stream(None)
+        H, W = self.cam.height, self.cam.width
+        _check(L.ges_freq_mask(G._ptr(self.target), W, H, float(self.omega(it)), G._ptr(self.mask_scratch),
+                               G._ptr(self.mask), stream))
+        if read_num_keys:
+            k = G.ges_preprocess(self.s, self.c, self.p, self.frame.splat_ws, True)
+            self.frame.ensure_keys(k)
+        else:
+            G.ges_preprocess(self.s, self.c, self.p, self.frame.splat_ws, False)
+            k = self.frame.key_capacity
+        self.frame.num_keys = k
+        G.ges_render_forward(self.s, self.c, self.p, self.frame.splat_ws, self.frame.key_ws, k, self.frame.pixel_ws,
+                             self.image)
+        lam_l1 = 1.0 - c.lam_ssim - c.lam_omega
+        G.ges_loss(self.image, self.target, self.mask, lam_l1, c.lam_omega, self.dL, self.loss, self.loss_scratch)
+        G.ges_ssim_loss(self.image, self.target, c.lam_ssim, self.loss, self.dL, self.ssim_scratch)
+        G.ges_render_backward(self.s, self.c, self.p, self.frame.splat_ws, self.frame.key_ws, self.frame.pixel_ws,
+                              self.dL, self.grads)
+        lrs = self.learning_rates(it)
+        groups = [(self.scene[k], self.grads[k], self.exp_avg[k], self.exp_avg_sq[k], lrs[k]) for k in GROUP_ORDER]
+        G.ges_adam_step(groups, it, c.beta1, c.beta2, c.eps)
+        return self.loss

@@ -1,0 +1,87 @@
+"""The composed training step (mask -> render -> L1 + SSIM + frequency loss -> adjoint -> Adam) against the
+oracle's step on the 1,000-splat 64x64 workload, and a short optimisation that must lower the loss.
+
+Each stage has its own parity test; here the stages are chained as the step chains them.  The oracle
+renders in binary64, so its loss gradient and the GPU's agree only where the L1 sign is settled: the seed is
+chosen so that no pixel lies within the image tolerance of its target.  Adam's first step moves each
+parameter by lr g / (|g| + eps), i.e. by lr times the sign of its gradient: where the gradient exceeds
+2e-3 of its group's largest (twice the gradient tolerance) the sign is settled and the moves agree to
+1e-6 lr; elsewhere the GPU's move is at most lr."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import loss as OL
+from oracle import optim as OP
+from oracle import ssim as OS
+from paper_2402_10128_amd import ges as G
+from paper_2402_10128_amd import synth
+from paper_2402_10128_amd.train import GROUP_ORDER, TrainConfig, TrainStep
+
+from .parity_helpers import GRAD_RTOL, IMG_ATOL, oracle_full, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_step(arrays, deg, cam, target, it, cfg):
+    ref = oracle_full(arrays, deg, cam, cfg.falloff, cfg.tile_cull)
+    assert not ref["out"]["flags"].any(), "a pixel has a floating-point-ambiguous decision at this seed"
+    img = ref["out"]["img"]
+    omega = it / cfg.total_iterations
+    mask = OL.freq_mask(target.astype(np.float64), omega)
+    lam_l1 = 1.0 - cfg.lam_ssim - cfg.lam_omega
+    l1, g1 = OL.loss_and_grad(img, target.astype(np.float64), mask, lam_l1, cfg.lam_omega)
+    ls, gs = OS.ssim_loss_and_grad(img, target.astype(np.float64))
+    dL = g1 + cfg.lam_ssim * gs
+    ref = oracle_full(arrays, deg, cam, cfg.falloff, cfg.tile_cull, dL=dL)
+    return dict(img=img, mask=mask, loss=l1 + cfg.lam_ssim * ls, grads=ref["grads"])
+
+
+def test_train_step_matches_oracle_step():
+    cfg_w = synth.make_config(0)
+    sc, cam, target = cfg_w["scene"], cfg_w["camera"], np.asarray(cfg_w["target"], np.float32)
+    arrays = sc.arrays()
+    cfg = TrainConfig()
+    ref = _oracle_step(arrays, sc.sh_degree, cam, target, 1, cfg)
+    assert not np.any(np.abs(ref["img"] - target) <= IMG_ATOL), "an L1 sign is unsettled at this seed"
+    scene = to_device(arrays)
+    p0 = {k: v.clone() for k, v in scene.items()}
+    ts = TrainStep(scene, cam, torch.as_tensor(target).cuda(), cfg)
+    loss = float(ts.step(1).cpu())
+    torch.cuda.synchronize()
+    assert np.array_equal(ts.mask.cpu().numpy(), ref["mask"])
+    assert np.abs(ts.image.cpu().numpy() - ref["img"]).max() <= IMG_ATOL
+    assert abs(loss - ref["loss"]) <= 1e-4, (loss, ref["loss"])
+    lrs = {"means": OP.position_lr(1), "sh": OP.LR["sh"], "opacity_logits": OP.LR["opacity_logits"],
+           "beta": OP.LR["beta"], "quats": OP.LR["quats"], "log_scales": OP.LR["log_scales"]}
+    for k in GROUP_ORDER:
+        g_ref = np.asarray(ref["grads"][k], np.float64).ravel()
+        g_gpu = ts.grads[k].cpu().numpy().astype(np.float64).ravel()
+        gmax = np.abs(g_ref).max()
+        assert np.abs(g_gpu - g_ref).max() <= GRAD_RTOL * gmax, k
+        pr, _, _ = OP.adam_step(p0[k].cpu().numpy().ravel(), g_ref, 0.0, 0.0, 1, lrs[k])
+        move = scene[k].cpu().numpy().astype(np.float64).ravel() - p0[k].cpu().numpy().astype(np.float64).ravel()
+        move_ref = pr - p0[k].cpu().numpy().astype(np.float64).ravel()
+        settled = np.abs(g_ref) > 2 * GRAD_RTOL * gmax
+        tol = 1e-6 * lrs[k] + 2.5e-7 * np.abs(p0[k].cpu().numpy().ravel())
+        assert np.all(np.abs(move - move_ref)[settled] <= tol[settled]), k
+        assert np.all(np.abs(move)[~settled] <= lrs[k] * (1 + 1e-6) + tol[~settled]), k
+
+
+def test_training_lowers_the_loss():
+    """30 steps toward the oracle's image of the same scene with its colours and opacities disturbed."""
+    cfg_w = synth.make_config(0)
+    sc, cam = cfg_w["scene"], cfg_w["camera"]
+    arrays = sc.arrays()
+    target = oracle_full(arrays, sc.sh_degree, cam, 0, 1)["out"]["img"].astype(np.float32)
+    rng = np.random.default_rng(12)
+    start = {k: np.array(v, np.float32) for k, v in arrays.items()}
+    start["sh"] = start["sh"] + rng.normal(0, 0.2, start["sh"].shape).astype(np.float32)
+    start["opacity_logits"] = start["opacity_logits"] + rng.normal(0, 0.5, start["opacity_logits"].shape).astype(
+        np.float32)
+    scene = to_device(start)
+    ts = TrainStep(scene, cam, torch.as_tensor(target).cuda(), TrainConfig())
+    losses = [float(ts.step(it).cpu()) for it in range(1, 31)]
+    print("losses", [round(x, 5) for x in losses])
+    assert all(np.isfinite(losses))
+    assert min(losses[-5:]) < 0.8 * losses[0], losses
