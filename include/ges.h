@@ -252,6 +252,28 @@ typedef struct {
 ges_status ges_adam_step(const ges_adam_group* groups, int32_t ngroups, int64_t step, float beta1, float beta2,
                          float eps, void* stream);
 
+/* Backward pass with the optimiser step fused in: the effect of ges_render_backward followed by
+ * ges_adam_step over the six parameter arrays of `splats` (same arguments and rules as those two
+ * calls), in one pass over the splats: each parameter gradient goes straight into its Adam update
+ * instead of through memory, and is also stored when `grads` is non-NULL.  The parameters, moments
+ * and stored gradients are bit-identical to the two separate calls.  The parameter arrays named by
+ * `splats` are UPDATED IN PLACE: they must be writable device memory (ges_splats declares them const
+ * for the render calls).  Moments k = 0..5 belong to means, log_scales, quats, opacity_logits, sh,
+ * beta, each shaped like its parameter and zero before step 1; the quats moments, and the sh moments
+ * at SH degree 1 or 3, must be 16-byte aligned.  Errors: those of ges_render_backward and of
+ * ges_adam_step, and GES_ERR_INVALID_ARGUMENT for a NULL opt or moment array (with n > 0) or a
+ * misaligned moment array. */
+typedef struct {
+  float* exp_avg[6];             /* first moments m */
+  float* exp_avg_sq[6];          /* second moments v */
+  float lr[6];                   /* learning rate of each parameter array */
+  int64_t step;                  /* Adam step t >= 1 */
+  float beta1, beta2, eps;
+} ges_adam_splats;
+ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                                    void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
+                                    const ges_splat_grads* grads, const ges_adam_splats* opt, void* stream);
+
 /* Learning rate at `step` of a log-linear decay from lr_init (step 0) to lr_final (step
  * max_steps, constant afterwards), times a delay factor that rises from delay_mult to 1
  * along a quarter sine over delay_steps (none when delay_steps <= 0).  The paper decays

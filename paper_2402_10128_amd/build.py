@@ -21,8 +21,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
 
 
-# Files whose results feed no integer decision may contract and divide fast.
-RELAXED = {"preprocess_bwd.hip": ["-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt"]}
+# Files whose results feed no integer decision may contract (binary32 division and sqrt stay correctly
+# rounded: the Adam update fused into the preprocess backward must give the stand-alone kernel's bits).
+RELAXED = {"preprocess_bwd.hip": ["-ffp-contract=fast"]}
 
 
 def _compile(src: str) -> str:
@@ -31,7 +32,7 @@ def _compile(src: str) -> str:
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
     flags = list(FLAGS)
     if src in RELAXED:
-        flags = [f for f in flags if f not in ("-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt")]
+        flags = [f for f in flags if f != "-ffp-contract=off"]
         flags += RELAXED[src]
     cmd = ["hipcc", *flags, *lang, "-c", path, "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)

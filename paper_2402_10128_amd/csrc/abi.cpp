@@ -203,12 +203,14 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
   return GES_OK;
 }
 
-ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
-                               void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
-                               const ges_splat_grads* grads, void* stream_) {
+static ges_status render_backward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                                  void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
+                                  const ges_splat_grads* grads, const ges::AdamSplats* adam, void* stream_) {
   const std::string e = check_all(splats, cam, params);
   if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
-  if (!splat_ws || !pixel_ws || !dL_drgb || !grads) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (!splat_ws || !pixel_ws || !dL_drgb || (!grads && !adam)) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  const ges_splat_grads none{};
+  if (!grads) grads = &none;
   if (grads->quats && (reinterpret_cast<uintptr_t>(grads->quats) & 15u))
     return fail(GES_ERR_INVALID_ARGUMENT, "grads->quats must be 16-byte aligned");
   if (grads->sh && (splats->sh_degree == 1 || splats->sh_degree == 3) && (reinterpret_cast<uintptr_t>(grads->sh) & 15u))
@@ -225,8 +227,52 @@ ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, 
                                           (size_t)splats->n * ges::kGradStride * 8, stream);
                 }), "zero grad2d");
   GES_CHECK_HIP(timed(GES_STAGE_RASTER_BACKWARD, stream, [&] { return ges::launch_raster_backward(db, b, stream); }), "raster_backward");
-  GES_CHECK_HIP(timed(GES_STAGE_PREPROCESS_BACKWARD, stream, [&] { return ges::launch_preprocess_backward(db, b, grads, stream); }), "preprocess_backward");
+  GES_CHECK_HIP(timed(GES_STAGE_PREPROCESS_BACKWARD, stream,
+                      [&] { return ges::launch_preprocess_backward(db, b, grads, stream, adam); }),
+                "preprocess_backward");
   return GES_OK;
+}
+
+ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                               void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
+                               const ges_splat_grads* grads, void* stream) {
+  if (!grads) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, nullptr, stream);
+}
+
+ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                                    void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
+                                    const ges_splat_grads* grads, const ges_adam_splats* opt, void* stream) {
+  if (!opt || !splats) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (opt->step < 1) return fail(GES_ERR_INVALID_ARGUMENT, "step < 1");
+  if (!(opt->beta1 >= 0.f && opt->beta1 < 1.f) || !(opt->beta2 >= 0.f && opt->beta2 < 1.f))
+    return fail(GES_ERR_INVALID_ARGUMENT, "beta outside [0,1)");
+  if (!(opt->eps >= 0.f) || !std::isfinite(opt->eps)) return fail(GES_ERR_INVALID_ARGUMENT, "bad eps");
+  ges::AdamSplats a{};
+  const float* params_in[ges::kNumPar] = {splats->means, splats->log_scales, splats->quats, splats->opacity_logits,
+                                          splats->sh, splats->beta};
+  const double bc1 = 1.0 - std::pow((double)opt->beta1, (double)opt->step);
+  const double bc2 = 1.0 - std::pow((double)opt->beta2, (double)opt->step);
+  for (int k = 0; k < ges::kNumPar; ++k) {
+    if (!(opt->lr[k] >= 0.f) || !std::isfinite(opt->lr[k])) return fail(GES_ERR_INVALID_ARGUMENT, "bad lr");
+    if (splats->n > 0 && (!opt->exp_avg[k] || !opt->exp_avg_sq[k]))
+      return fail(GES_ERR_INVALID_ARGUMENT, "NULL moment array");
+    a.p[k] = const_cast<float*>(params_in[k]);
+    a.m[k] = opt->exp_avg[k];
+    a.v[k] = opt->exp_avg_sq[k];
+    a.step_size[k] = (float)((double)opt->lr[k] / bc1);
+  }
+  const bool sh_vec = splats->sh_degree == 1 || splats->sh_degree == 3;
+  for (int k : {ges::kParQuats, ges::kParSh}) {
+    if (k == ges::kParSh && !sh_vec) continue;
+    if ((reinterpret_cast<uintptr_t>(a.m[k]) | reinterpret_cast<uintptr_t>(a.v[k])) & 15u)
+      return fail(GES_ERR_INVALID_ARGUMENT, "quats/sh moments must be 16-byte aligned");
+  }
+  a.b1 = opt->beta1;
+  a.b2 = opt->beta2;
+  a.eps = opt->eps;
+  a.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(bc2));
+  return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, &a, stream);
 }
 
 ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* splat_ws, void* key_ws, uint64_t num_keys,

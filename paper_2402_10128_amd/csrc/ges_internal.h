@@ -101,6 +101,32 @@ struct DeviceBatch {
 };
 inline size_t device_batch_bytes(int nviews) { return offsetof(DeviceBatch, views) + (size_t)nviews * sizeof(ViewDesc); }
 
+constexpr int kAdamMaxGroups = GES_ADAM_MAX_GROUPS;
+
+// One Adam update in binary32 (Kingma & Ba, Algorithm 1), the bias corrections folded into
+// step_size = lr / (1 - b1^t) and inv_sqrt_bc2 = 1 / sqrt(1 - b2^t).  Shared by the stand-alone step and
+// the update fused into the preprocess backward.  Every multiply-add is an explicit FMA and no product
+// feeds an addition, so no compiler contraction setting can change the result: both give the same bits.
+__device__ __forceinline__ void adam_update(float& p, float g, float& m, float& v, float b1, float b2, float eps,
+                                            float step_size, float inv_sqrt_bc2) {
+  m = __builtin_fmaf(b1, m, (1.f - b1) * g);
+  v = __builtin_fmaf(b2, v, (1.f - b2) * (g * g));
+  const float den = __builtin_fmaf(sqrtf(v), inv_sqrt_bc2, eps);
+  p = p - (step_size * m) / den;
+}
+
+// Parameter arrays of a splat set in the order of ges_adam_splats.
+enum { kParMeans = 0, kParScales = 1, kParQuats = 2, kParOpacity = 3, kParSh = 4, kParBeta = 5, kNumPar = 6 };
+
+// Arguments of the Adam update fused into the preprocess backward (passed by value to the kernel).
+struct AdamSplats {
+  float* p[kNumPar];
+  float* m[kNumPar];
+  float* v[kNumPar];
+  float step_size[kNumPar];
+  float b1, b2, eps, inv_sqrt_bc2;
+};
+
 // --------------------------------------------------------------------------------------------
 // launchers (implemented in the .hip files); all enqueue on `stream` and return hipError_t
 hipError_t launch_preprocess(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
@@ -111,7 +137,7 @@ hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream
 hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_raster_backward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_preprocess_backward(const DeviceBatch* dbatch, const Batch& b, const ges_splat_grads* grads,
-                                      hipStream_t stream);
+                                      hipStream_t stream, const AdamSplats* adam = nullptr);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
 
 hipError_t launch_freq_mask(const float* target, int w, int h, float omega, void* scratch, uint8_t* mask,
@@ -125,7 +151,7 @@ size_t ssim_scratch_bytes(int w, int h);
 hipError_t launch_ssim_loss(const float* img, const float* target, int w, int h, float lam, void* scratch,
                             float* loss, float* dL, hipStream_t stream);
 
-constexpr int kAdamMaxGroups = GES_ADAM_MAX_GROUPS;
+
 hipError_t launch_adam(const ges_adam_group* groups, int ngroups, int64_t step, float b1, float b2, float eps,
                        hipStream_t stream);
 

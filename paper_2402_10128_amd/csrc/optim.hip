@@ -37,13 +37,6 @@ struct AdamArgs {
   float b1, b2, eps, inv_sqrt_bc2;
 };
 
-__device__ __forceinline__ void adam_update(float& p, float g, float& m, float& v, float b1, float b2, float eps,
-                                            float step_size, float inv_sqrt_bc2) {
-  m = b1 * m + (1.f - b1) * g;
-  v = b2 * v + (1.f - b2) * (g * g);
-  p = p - step_size * m / (sqrtf(v) * inv_sqrt_bc2 + eps);
-}
-
 __global__ void __launch_bounds__(kAdamThreads) adam_kernel(const AdamArgs a) {
   const int64_t b = blockIdx.x;
   // pick the group with compile-time indices only (the argument table stays in scalar registers)

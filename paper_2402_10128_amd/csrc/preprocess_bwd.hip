@@ -46,26 +46,61 @@ __device__ __forceinline__ void sh_basis_f64(double x, double y, double z, int d
   Y[15] = -kD3a * x * (xx - 3.0 * yy);
 }
 
+// Output of one parameter gradient: stored when the caller asked for gradients, and with kAdam also
+// applied at once as an Adam update of the parameter (the gradient never goes through memory).
+template <bool kAdam, int P>
+__device__ __forceinline__ void emit(float* g, const AdamSplats& A, int64_t idx, float val) {
+  if (g) g[idx] = val;
+  if constexpr (kAdam) {
+    float p = A.p[P][idx], m = A.m[P][idx], v = A.v[P][idx];
+    adam_update(p, val, m, v, A.b1, A.b2, A.eps, A.step_size[P], A.inv_sqrt_bc2);
+    A.p[P][idx] = p;
+    A.m[P][idx] = m;
+    A.v[P][idx] = v;
+  }
+}
+
+template <bool kAdam, int P>
+__device__ __forceinline__ void emit4(float* g, const AdamSplats& A, int64_t idx4, float4 val) {
+  if (g) reinterpret_cast<float4*>(g)[idx4] = val;
+  if constexpr (kAdam) {
+    float4 p = reinterpret_cast<const float4*>(A.p[P])[idx4];
+    float4 m = reinterpret_cast<const float4*>(A.m[P])[idx4];
+    float4 v = reinterpret_cast<const float4*>(A.v[P])[idx4];
+    adam_update(p.x, val.x, m.x, v.x, A.b1, A.b2, A.eps, A.step_size[P], A.inv_sqrt_bc2);
+    adam_update(p.y, val.y, m.y, v.y, A.b1, A.b2, A.eps, A.step_size[P], A.inv_sqrt_bc2);
+    adam_update(p.z, val.z, m.z, v.z, A.b1, A.b2, A.eps, A.step_size[P], A.inv_sqrt_bc2);
+    adam_update(p.w, val.w, m.w, v.w, A.b1, A.b2, A.eps, A.step_size[P], A.inv_sqrt_bc2);
+    reinterpret_cast<float4*>(A.p[P])[idx4] = p;
+    reinterpret_cast<float4*>(A.m[P])[idx4] = m;
+    reinterpret_cast<float4*>(A.v[P])[idx4] = v;
+  }
+}
+
 constexpr int kRowPad = 13;   // float4 slots per staged SH-gradient row (12 used at degree 3; 13 spreads LDS banks)
 
 // Chain rule of splat i.  SH-gradient rows of degrees 1 and 3 (whole float4s) go to `row` in LDS; other
 // degrees are written straight to memory.
-template <int D>
-__device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_splat_grads& G, int64_t i, float4* row) {
+template <int D, bool kAdam>
+__device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_splat_grads& G, const AdamSplats& A,
+                                               int64_t i, float4* row) {
   constexpr int K = (D + 1) * (D + 1);
   const uint32_t vis = V.vis[i];
-  float* gsh = G.sh ? G.sh + (int64_t)3 * K * i : nullptr;
+  const int64_t sh0 = (int64_t)3 * K * i;
   if (!(vis & kVisBit)) {
-    if (G.means) { G.means[3 * i] = 0.f; G.means[3 * i + 1] = 0.f; G.means[3 * i + 2] = 0.f; }
-    if (G.log_scales) { G.log_scales[3 * i] = 0.f; G.log_scales[3 * i + 1] = 0.f; G.log_scales[3 * i + 2] = 0.f; }
-    if (G.quats) reinterpret_cast<float4*>(G.quats)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (G.opacity_logits) G.opacity_logits[i] = 0.f;
-    if (G.beta) G.beta[i] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      emit<kAdam, kParMeans>(G.means, A, 3 * i + c, 0.f);
+      emit<kAdam, kParScales>(G.log_scales, A, 3 * i + c, 0.f);
+    }
+    emit4<kAdam, kParQuats>(G.quats, A, i, make_float4(0.f, 0.f, 0.f, 0.f));
+    emit<kAdam, kParOpacity>(G.opacity_logits, A, i, 0.f);
+    emit<kAdam, kParBeta>(G.beta, A, i, 0.f);
     if constexpr ((3 * K) % 4 == 0) {
 #pragma unroll
       for (int m = 0; m < 3 * K / 4; ++m) row[m] = make_float4(0.f, 0.f, 0.f, 0.f);
     } else {
-      if (gsh) for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.f;
+      for (int k = 0; k < 3 * K; ++k) emit<kAdam, kParSh>(G.sh, A, sh0 + k, 0.f);
     }
     return;
   }
@@ -177,13 +212,12 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
       gQ[3 * r + c] = gM * S[c];
     }
   const double gphi = gS[0] * s[0] + gS[1] * s[1] + gS[2] * s[2];
-  if (G.log_scales)
-    for (int c = 0; c < 3; ++c) G.log_scales[3 * i + c] = (float)(gS[c] * phi * s[c]);
-  if (G.beta) {
+  for (int c = 0; c < 3; ++c) emit<kAdam, kParScales>(G.log_scales, A, 3 * i + c, (float)(gS[c] * phi * s[c]));
+  {
     double gb_ = 0.0;
     if (V.falloff == GES_FALLOFF_PHI) gb_ = gphi * rho * phi * (1.0 - 0.5 * phi);
     else gb_ = gbeta2;
-    G.beta[i] = (float)gb_;
+    emit<kAdam, kParBeta>(G.beta, A, i, (float)gb_);
   }
   // rotation -> unit quaternion -> quaternion
   {
@@ -193,12 +227,11 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
     const double gyq = 2.0 * (-2.0 * y * gQ[0] + x * gQ[1] + w * gQ[2] + x * gQ[3] + zq * gQ[5] - w * gQ[6] + zq * gQ[7] - 2.0 * y * gQ[8]);
     const double gzq = 2.0 * (-2.0 * zq * gQ[0] - w * gQ[1] + x * gQ[2] + w * gQ[3] - 2.0 * zq * gQ[4] + y * gQ[5] + x * gQ[6] + y * gQ[7]);
     const double dot = gw * w + gxq * x + gyq * y + gzq * zq;
-    if (G.quats)
-      reinterpret_cast<float4*>(G.quats)[i] =
-          make_float4((float)((gw - w * dot) / nr), (float)((gxq - x * dot) / nr), (float)((gyq - y * dot) / nr),
-                      (float)((gzq - zq * dot) / nr));
+    emit4<kAdam, kParQuats>(G.quats, A, i,
+                            make_float4((float)((gw - w * dot) / nr), (float)((gxq - x * dot) / nr),
+                                        (float)((gyq - y * dot) / nr), (float)((gzq - zq * dot) / nr)));
   }
-  if (G.opacity_logits) G.opacity_logits[i] = (float)(gop * op * (1.0 - op));
+  emit<kAdam, kParOpacity>(G.opacity_logits, A, i, (float)(gop * op * (1.0 - op)));
 
   // colour: SH coefficients and the view direction
   double gmu[3] = {0.0, 0.0, 0.0};
@@ -243,7 +276,7 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         gY[k] += gc3[ch] * (double)shc[3 * k + ch];
-        if (gsh) gsh[3 * k + ch] = (float)(Y[k] * gc3[ch]);
+        emit<kAdam, kParSh>(G.sh, A, sh0 + 3 * k + ch, (float)(Y[k] * gc3[ch]));
       }
   }
   if (D > 0) {
@@ -276,32 +309,34 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
     gmu[2] = (gdz - zz_ * dd) / len;
   }
   // p = W mu + t
-  if (G.means) {
-    for (int c = 0; c < 3; ++c)
-      G.means[3 * i + c] = (float)(gmu[c] + R[c] * gp0 + R[3 + c] * gp1 + R[6 + c] * gz_);
-  }
+  for (int c = 0; c < 3; ++c)
+    emit<kAdam, kParMeans>(G.means, A, 3 * i + c, (float)(gmu[c] + R[c] * gp0 + R[3 + c] * gp1 + R[6 + c] * gz_));
 }
 
-template <int D>
-__device__ __forceinline__ void backward_wave(const ViewDesc& V, const ges_splat_grads& G, int64_t w0, float4* rows) {
+template <int D, bool kAdam>
+__device__ __forceinline__ void backward_wave(const ViewDesc& V, const ges_splat_grads& G, const AdamSplats& A,
+                                              int64_t w0, float4* rows) {
   constexpr int K = (D + 1) * (D + 1);
   constexpr int F4 = 3 * K / 4;   // float4s per SH-gradient row (degrees 1 and 3)
   const int lane = threadIdx.x & 63;
   const int64_t i = w0 + lane;
-  if (i < V.n) backward_splat<D>(V, G, i, rows + lane * kRowPad);
+  if (i < V.n) backward_splat<D, kAdam>(V, G, A, i, rows + lane * kRowPad);
   if constexpr ((3 * K) % 4 == 0) {
-    if (!G.sh) return;
+    if (!kAdam && !G.sh) return;
     const int cnt = (int)min<int64_t>(64, V.n - w0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    float4* out = reinterpret_cast<float4*>(G.sh + (int64_t)3 * K * w0);
-    for (int m = lane; m < cnt * F4; m += 64) out[m] = rows[(m / F4) * kRowPad + (m % F4)];
+    // the wave's rows are one contiguous block of float4s starting at splat w0
+    const int64_t base4 = (int64_t)F4 * w0;
+    for (int m = lane; m < cnt * F4; m += 64)
+      emit4<kAdam, kParSh>(G.sh, A, base4 + m, rows[(m / F4) * kRowPad + (m % F4)]);
   }
 }
 
+template <bool kAdam>
 __global__ void __launch_bounds__(256) preprocess_backward_kernel(const DeviceBatch* __restrict__ db,
-                                                                   ges_splat_grads G) {
+                                                                   ges_splat_grads G, AdamSplats A) {
   __shared__ float4 sRows[4 * 64 * kRowPad];
   const int64_t blk = blockIdx.x;
   const int v = view_of_block(db->pre_prefix, db->nviews, blk);
@@ -311,17 +346,24 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(const DeviceBa
   if (w0 >= V.n) return;
   float4* rows = sRows + wave * 64 * kRowPad;
   switch (V.sh_degree) {   // uniform per block: one view per block
-    case 0: backward_wave<0>(V, G, w0, rows); break;
-    case 1: backward_wave<1>(V, G, w0, rows); break;
-    case 2: backward_wave<2>(V, G, w0, rows); break;
-    default: backward_wave<3>(V, G, w0, rows); break;
+    case 0: backward_wave<0, kAdam>(V, G, A, w0, rows); break;
+    case 1: backward_wave<1, kAdam>(V, G, A, w0, rows); break;
+    case 2: backward_wave<2, kAdam>(V, G, A, w0, rows); break;
+    default: backward_wave<3, kAdam>(V, G, A, w0, rows); break;
   }
 }
 
 hipError_t launch_preprocess_backward(const DeviceBatch* dbatch, const Batch& b, const ges_splat_grads* grads,
-                                      hipStream_t stream) {
+                                      hipStream_t stream, const AdamSplats* adam) {
   if (b.pre_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(preprocess_backward_kernel, dim3((unsigned)b.pre_blocks), dim3(256), 0, stream, dbatch, *grads);
+  const ges_splat_grads none{};
+  const ges_splat_grads& g = grads ? *grads : none;
+  if (adam)
+    hipLaunchKernelGGL(preprocess_backward_kernel<true>, dim3((unsigned)b.pre_blocks), dim3(256), 0, stream, dbatch, g,
+                       *adam);
+  else
+    hipLaunchKernelGGL(preprocess_backward_kernel<false>, dim3((unsigned)b.pre_blocks), dim3(256), 0, stream, dbatch,
+                       g, AdamSplats{});
   return hipGetLastError();
 }
 

@@ -29,7 +29,10 @@ constexpr int kSsimT = 32;                       // output tile edge
 constexpr int kSsimIn = kSsimT + 2 * kSsimR;     // staged edge (42)
 constexpr int kSsimPitch = kSsimIn + 1;
 constexpr int kSsimThreads = 256;
-constexpr int kSsimRowsPerThread = kSsimT * kSsimT / kSsimThreads;   // 4 outputs per thread and channel
+constexpr int kSsimStage = (3 * kSsimIn * kSsimIn + kSsimThreads - 1) / kSsimThreads;   // staged values per thread
+constexpr int kSsimGroups = kSsimT / 4;          // 4 neighbouring outputs per thread and pass
+constexpr int kSsimSpan = 4 + 2 * kSsimR;         // staged values those 4 outputs read (14)
+static_assert(kSsimT * kSsimGroups == kSsimThreads, "one 4-output strip per thread in the pass down");
 constexpr float kSsimC1 = 0.01f * 0.01f, kSsimC2 = 0.03f * 0.03f;
 constexpr float kSsimShift = 0.5f;
 
@@ -43,61 +46,94 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_fwd_kernel(const float* __r
                                                                 double* __restrict__ partial) {
   __shared__ float sx[3][kSsimIn][kSsimPitch];
   __shared__ float sy[3][kSsimIn][kSsimPitch];
-  __shared__ float hs[5][kSsimIn][kSsimT];
+  __shared__ __align__(16) float hs[5][kSsimIn][kSsimT];
   __shared__ double red[kSsimThreads / 64];
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * kSsimT - kSsimR, y0 = blockIdx.y * kSsimT - kSsimR;
-  // stage both images (all three channels, rows of 42 interleaved pixels = 126 contiguous floats)
-  for (int e = t; e < kSsimIn * kSsimIn * 3; e += kSsimThreads) {
-    const int r = e / (kSsimIn * 3), j = e - r * (kSsimIn * 3);
-    const int col = j / 3, c = j - col * 3;
-    const int gx = x0 + col, gy = y0 + r;
-    float a = -kSsimShift, b = -kSsimShift;
-    if (gx >= 0 && gx < w && gy >= 0 && gy < h) {
-      const size_t o = 3 * ((size_t)gy * w + gx) + c;
-      a = img[o] - kSsimShift;
-      b = tgt[o] - kSsimShift;
+  // stage both images (all three channels, rows of 42 interleaved pixels = 126 contiguous floats); every
+  // load of a thread is issued before the first LDS store, so their latencies overlap
+  float ra[kSsimStage], rb[kSsimStage];
+#pragma unroll
+  for (int j = 0; j < kSsimStage; ++j) {
+    const int e = t + j * kSsimThreads;
+    ra[j] = 0.f;
+    rb[j] = 0.f;
+    if (e < kSsimIn * kSsimIn * 3) {
+      const int r = e / (kSsimIn * 3), q = e - r * (kSsimIn * 3);
+      const int col = q / 3, c = q - col * 3;
+      const int gx = x0 + col, gy = y0 + r;
+      if (gx >= 0 && gx < w && gy >= 0 && gy < h) {
+        const size_t o = 3 * ((size_t)gy * w + gx) + c;
+        ra[j] = img[o];
+        rb[j] = tgt[o];
+      }
     }
-    sx[c][r][col] = a;
-    sy[c][r][col] = b;
+  }
+#pragma unroll
+  for (int j = 0; j < kSsimStage; ++j) {
+    const int e = t + j * kSsimThreads;
+    if (e < kSsimIn * kSsimIn * 3) {
+      const int r = e / (kSsimIn * 3), q = e - r * (kSsimIn * 3);
+      const int col = q / 3, c = q - col * 3;
+      const int gx = x0 + col, gy = y0 + r;
+      const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;   // padding is 0, i.e. -1/2 after the shift
+      sx[c][r][col] = (in ? ra[j] : 0.f) - kSsimShift;
+      sy[c][r][col] = (in ? rb[j] : 0.f) - kSsimShift;
+    }
   }
   const size_t plane = (size_t)w * h;
   float ssum = 0.f;
   for (int c = 0; c < 3; ++c) {
     __syncthreads();
-    for (int i = t; i < kSsimIn * kSsimT; i += kSsimThreads) {
-      const int r = i / kSsimT, col = i - r * kSsimT;
-      float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
+    // across: row r, columns 4g..4g+3 from the 14 staged values they span
+    for (int i = t; i < kSsimIn * kSsimGroups; i += kSsimThreads) {
+      const int r = i / kSsimGroups, col0 = 4 * (i - r * kSsimGroups);
+      float a[kSsimSpan], b[kSsimSpan];
 #pragma unroll
-      for (int k = 0; k < kSsimTaps; ++k) {
-        const float a = sx[c][r][col + k], b = sy[c][r][col + k], wk = wt.w[k];
-        m0 += wk * a;
-        m1 += wk * b;
-        m2 += wk * (a * a);
-        m3 += wk * (b * b);
-        m4 += wk * (a * b);
+      for (int k = 0; k < kSsimSpan; ++k) {
+        a[k] = sx[c][r][col0 + k];
+        b[k] = sy[c][r][col0 + k];
       }
-      hs[0][r][col] = m0;
-      hs[1][r][col] = m1;
-      hs[2][r][col] = m2;
-      hs[3][r][col] = m3;
-      hs[4][r][col] = m4;
+      float m[5][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSsimTaps; ++k) {
+          const float wk = wt.w[k], av = a[q + k], bv = b[q + k];
+          m0 = __builtin_fmaf(wk, av, m0);
+          m1 = __builtin_fmaf(wk, bv, m1);
+          m2 = __builtin_fmaf(wk, av * av, m2);
+          m3 = __builtin_fmaf(wk, bv * bv, m3);
+          m4 = __builtin_fmaf(wk, av * bv, m4);
+        }
+        m[0][q] = m0; m[1][q] = m1; m[2][q] = m2; m[3][q] = m3; m[4][q] = m4;
+      }
+#pragma unroll
+      for (int s5 = 0; s5 < 5; ++s5)
+        *reinterpret_cast<float4*>(&hs[s5][r][col0]) = make_float4(m[s5][0], m[s5][1], m[s5][2], m[s5][3]);
     }
     __syncthreads();
-    const int ox = t % kSsimT;
+    // down: column ox, rows 4j..4j+3 from the 14 rows they span
+    const int ox = t % kSsimT, oy0 = 4 * (t / kSsimT);
+    float st[5][4];
 #pragma unroll
-    for (int j = 0; j < kSsimRowsPerThread; ++j) {
-      const int oy = t / kSsimT + j * (kSsimThreads / kSsimT);
-      float ex = 0.f, ey = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+    for (int s5 = 0; s5 < 5; ++s5) {
+      float col[kSsimSpan];
 #pragma unroll
-      for (int k = 0; k < kSsimTaps; ++k) {
-        const float wk = wt.w[k];
-        ex += wk * hs[0][oy + k][ox];
-        ey += wk * hs[1][oy + k][ox];
-        exx += wk * hs[2][oy + k][ox];
-        eyy += wk * hs[3][oy + k][ox];
-        exy += wk * hs[4][oy + k][ox];
+      for (int k = 0; k < kSsimSpan; ++k) col[k] = hs[s5][oy0 + k][ox];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSsimTaps; ++k) acc = __builtin_fmaf(wt.w[k], col[q + k], acc);
+        st[s5][q] = acc;
       }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int oy = oy0 + q;
+      const float ex = st[0][q], ey = st[1][q], exx = st[2][q], eyy = st[3][q], exy = st[4][q];
       const int gx = x0 + kSsimR + ox, gy = y0 + kSsimR + oy;
       if (gx >= w || gy >= h) continue;
       // shifted moments -> variances/covariance; means of the unshifted images
@@ -131,7 +167,7 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_bwd_kernel(const float* __r
                                                                 const SsimWeights wt, const float* __restrict__ maps,
                                                                 float scale, float* __restrict__ dL) {
   __shared__ float sm[3][kSsimIn][kSsimPitch];
-  __shared__ float hs[3][kSsimIn][kSsimT];
+  __shared__ __align__(16) float hs[3][kSsimIn][kSsimT];
   const int t = threadIdx.x;
   const int x0 = blockIdx.x * kSsimT - kSsimR, y0 = blockIdx.y * kSsimT - kSsimR;
   const size_t plane = (size_t)w * h;
@@ -139,46 +175,69 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_bwd_kernel(const float* __r
 #pragma unroll 1
   for (int c = 0; c < 3; ++c) {
     if (c > 0) __syncthreads();
-    for (int e = t; e < 3 * kSsimIn * kSsimIn; e += kSsimThreads) {
-      const int m = e / (kSsimIn * kSsimIn), rc = e - m * (kSsimIn * kSsimIn);
-      const int r = rc / kSsimIn, col = rc - r * kSsimIn;
-      const int gx = x0 + col, gy = y0 + r;
-      float v = 0.f;                           // the maps are zero outside the image
-      if (gx >= 0 && gx < w && gy >= 0 && gy < h) v = maps[(m * 3 + c) * plane + (size_t)gy * w + gx];
-      sm[m][r][col] = v;
+    float rv[kSsimStage];
+#pragma unroll
+    for (int j = 0; j < kSsimStage; ++j) {     // all loads first, then the LDS stores
+      const int e = t + j * kSsimThreads;
+      rv[j] = 0.f;                               // the maps are zero outside the image
+      if (e < 3 * kSsimIn * kSsimIn) {
+        const int m = e / (kSsimIn * kSsimIn), rc = e - m * (kSsimIn * kSsimIn);
+        const int r = rc / kSsimIn, col = rc - r * kSsimIn;
+        const int gx = x0 + col, gy = y0 + r;
+        if (gx >= 0 && gx < w && gy >= 0 && gy < h) rv[j] = maps[(m * 3 + c) * plane + (size_t)gy * w + gx];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kSsimStage; ++j) {
+      const int e = t + j * kSsimThreads;
+      if (e < 3 * kSsimIn * kSsimIn) {
+        const int m = e / (kSsimIn * kSsimIn), rc = e - m * (kSsimIn * kSsimIn);
+        const int r = rc / kSsimIn, col = rc - r * kSsimIn;
+        sm[m][r][col] = rv[j];
+      }
     }
     __syncthreads();
-    for (int i = t; i < kSsimIn * kSsimT; i += kSsimThreads) {
-      const int r = i / kSsimT, col = i - r * kSsimT;
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int i = t; i < kSsimIn * kSsimGroups; i += kSsimThreads) {
+      const int r = i / kSsimGroups, col0 = 4 * (i - r * kSsimGroups);
 #pragma unroll
-      for (int k = 0; k < kSsimTaps; ++k) {
-        const float wk = wt.w[k];
-        a0 += wk * sm[0][r][col + k];
-        a1 += wk * sm[1][r][col + k];
-        a2 += wk * sm[2][r][col + k];
+      for (int m = 0; m < 3; ++m) {
+        float v[kSsimSpan];
+#pragma unroll
+        for (int k = 0; k < kSsimSpan; ++k) v[k] = sm[m][r][col0 + k];
+        float o4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < kSsimTaps; ++k) acc = __builtin_fmaf(wt.w[k], v[q + k], acc);
+          o4[q] = acc;
+        }
+        *reinterpret_cast<float4*>(&hs[m][r][col0]) = make_float4(o4[0], o4[1], o4[2], o4[3]);
       }
-      hs[0][r][col] = a0;
-      hs[1][r][col] = a1;
-      hs[2][r][col] = a2;
     }
     __syncthreads();
+    const int oy0 = 4 * (t / kSsimT);
+    float f[3][4];
 #pragma unroll
-    for (int j = 0; j < kSsimRowsPerThread; ++j) {
-      const int oy = t / kSsimT + j * (kSsimThreads / kSsimT);
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int m = 0; m < 3; ++m) {
+      float col[kSsimSpan];
 #pragma unroll
-      for (int k = 0; k < kSsimTaps; ++k) {
-        const float wk = wt.w[k];
-        a0 += wk * hs[0][oy + k][ox];
-        a1 += wk * hs[1][oy + k][ox];
-        a2 += wk * hs[2][oy + k][ox];
+      for (int k = 0; k < kSsimSpan; ++k) col[k] = hs[m][oy0 + k][ox];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSsimTaps; ++k) acc = __builtin_fmaf(wt.w[k], col[q + k], acc);
+        f[m][q] = acc;
       }
-      const int gx = x0 + kSsimR + ox, gy = y0 + kSsimR + oy;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gx = x0 + kSsimR + ox, gy = y0 + kSsimR + oy0 + q;
       if (gx >= w || gy >= h) continue;
       const size_t o = 3 * ((size_t)gy * w + gx) + c;
       const float xs = img[o] - kSsimShift, ys = tgt[o] - kSsimShift;
-      dL[o] = dL[o] - scale * (a0 + 2.f * xs * a1 + ys * a2);
+      dL[o] = dL[o] - scale * (f[0][q] + 2.f * xs * f[1][q] + ys * f[2][q]);
     }
   }
 }

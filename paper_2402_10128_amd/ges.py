@@ -66,6 +66,11 @@ class ges_adam_group(C.Structure):
                 ("count", C.c_int64), ("lr", C.c_float)]
 
 
+class ges_adam_splats(C.Structure):
+    _fields_ = [("exp_avg", C.c_void_p * 6), ("exp_avg_sq", C.c_void_p * 6), ("lr", C.c_float * 6),
+                ("step", C.c_int64), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
 class ges_request_info(C.Structure):
     _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("t_submit_ns", C.c_uint64), ("t_start_ns", C.c_uint64),
                 ("t_done_ns", C.c_uint64), ("num_keys", C.c_uint64), ("batch_size", C.c_int32)]
@@ -98,6 +103,9 @@ _SIGS = {
     "ges_ssim_scratch_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "ges_ssim_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p]),
+    "ges_render_backward_adam": (C.c_int, [C.POINTER(ges_splats), C.POINTER(ges_camera), C.POINTER(ges_raster_params),
+                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.POINTER(ges_splat_grads), C.POINTER(ges_adam_splats), C.c_void_p]),
     "ges_adam_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "ges_expon_lr": (C.c_double, [C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_double]),
     "ges_serve_create": (C.c_int, [C.POINTER(ges_serve_config), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
@@ -286,6 +294,29 @@ def ges_adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
                 raise ValueError("Adam groups take contiguous float32 tensors of one size")
         arr[k] = ges_adam_group(p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), p.numel(), float(lr))
     _check(lib().ges_adam_step(arr, len(groups), int(step), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+SPLAT_PARAMS = ("means", "log_scales", "quats", "opacity_logits", "sh", "beta")
+
+
+def ges_render_backward_adam(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, exp_avg: dict,
+                             exp_avg_sq: dict, lrs: dict, step, beta1=0.9, beta2=0.999, eps=1e-15, grads=None,
+                             stream=None):
+    """Backward pass with Adam fused in: updates the tensors behind ``splats`` and the moments in place."""
+    opt = ges_adam_splats()
+    for k, name in enumerate(SPLAT_PARAMS):
+        opt.exp_avg[k] = exp_avg[name].data_ptr()
+        opt.exp_avg_sq[k] = exp_avg_sq[name].data_ptr()
+        opt.lr[k] = float(lrs[name])
+    opt.step, opt.beta1, opt.beta2, opt.eps = int(step), float(beta1), float(beta2), float(eps)
+    g = ges_splat_grads()
+    if grads is not None:
+        for name in SPLAT_PARAMS:
+            t = grads.get(name)
+            setattr(g, name, None if t is None else t.data_ptr())
+    _check(lib().ges_render_backward_adam(C.byref(splats), C.byref(cam), C.byref(params), _ptr(splat_ws),
+                                          _ptr(key_ws), _ptr(pixel_ws), _ptr(dL_drgb), C.byref(g), C.byref(opt),
+                                          _stream(stream)))
 
 
 def ges_expon_lr(step, lr_init, lr_final, max_steps, delay_steps=0, delay_mult=1.0) -> float:

@@ -8,6 +8,8 @@ The step follows the paper's training recipe:
   * Adam with per-group learning rates, the position rate decaying log-linearly from 1.6e-4 to 1.6e-6
     over 30,000 steps (App. B.2).
 Every stage runs in the library's kernels; this module only owns buffers and orders the calls on one stream.
+By default the Adam update runs inside the backward pass (ges_render_backward_adam), so the parameter
+gradients never go through memory.
 Densification, pruning and the opacity/shape resets of the full training loop are not part of the step.
 """
 from __future__ import annotations
@@ -69,7 +71,7 @@ class TrainStep:
         self.mask_scratch = torch.empty(G.lib().ges_mask_scratch_bytes(W, H), dtype=torch.uint8, device=dev)
         self.loss_scratch = torch.empty(G.lib().ges_loss_scratch_bytes(), dtype=torch.uint8, device=dev)
         self.ssim_scratch = torch.empty(G.lib().ges_ssim_scratch_bytes(W, H), dtype=torch.uint8, device=dev)
-        self.grads = {k: torch.empty_like(v) for k, v in scene.items()}
+        self.grads = None        # parameter gradients, allocated by the first unfused step
         self.exp_avg = {k: torch.zeros_like(v) for k, v in scene.items()}
         self.exp_avg_sq = {k: torch.zeros_like(v) for k, v in scene.items()}
 
@@ -82,9 +84,11 @@ class TrainStep:
         return {"means": pos, "sh": c.lr_feature, "opacity_logits": c.lr_opacity, "beta": c.lr_shape,
                 "quats": c.lr_rotation, "log_scales": c.lr_scaling}
 
-    def step(self, it: int, read_num_keys: bool = True):
+    def step(self, it: int, read_num_keys: bool = True, fused: bool = True):
         """Iteration ``it`` (counting from 1).  With read_num_keys=False the render takes the key count from
-        the device and the frame's key capacity must already hold it (an overflow is flagged in the frame)."""
+        the device and the frame's key capacity must already hold it (an overflow is flagged in the frame).
+        fused=True applies Adam inside the backward pass (the gradients are not stored); fused=False stores
+        the gradients in ``self.grads`` and runs the stand-alone Adam step (the same bits)."""
         c = self.cfg
         _check = G._check
         L = G.lib()
@@ -104,9 +108,17 @@ class TrainStep:
         lam_l1 = 1.0 - c.lam_ssim - c.lam_omega
         G.ges_loss(self.image, self.target, self.mask, lam_l1, c.lam_omega, self.dL, self.loss, self.loss_scratch)
         G.ges_ssim_loss(self.image, self.target, c.lam_ssim, self.loss, self.dL, self.ssim_scratch)
-        G.ges_render_backward(self.s, self.c, self.p, self.frame.splat_ws, self.frame.key_ws, self.frame.pixel_ws,
-                              self.dL, self.grads)
         lrs = self.learning_rates(it)
-        groups = [(self.scene[k], self.grads[k], self.exp_avg[k], self.exp_avg_sq[k], lrs[k]) for k in GROUP_ORDER]
-        G.ges_adam_step(groups, it, c.beta1, c.beta2, c.eps)
+        if fused:
+            G.ges_render_backward_adam(self.s, self.c, self.p, self.frame.splat_ws, self.frame.key_ws,
+                                       self.frame.pixel_ws, self.dL, self.exp_avg, self.exp_avg_sq, lrs, it,
+                                       c.beta1, c.beta2, c.eps)
+        else:
+            if self.grads is None:
+                self.grads = {k: torch.empty_like(v) for k, v in self.scene.items()}
+            G.ges_render_backward(self.s, self.c, self.p, self.frame.splat_ws, self.frame.key_ws,
+                                  self.frame.pixel_ws, self.dL, self.grads)
+            groups = [(self.scene[k], self.grads[k], self.exp_avg[k], self.exp_avg_sq[k], lrs[k])
+                      for k in GROUP_ORDER]
+            G.ges_adam_step(groups, it, c.beta1, c.beta2, c.eps)
         return self.loss

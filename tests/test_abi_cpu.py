@@ -126,3 +126,31 @@ def test_ssim_validates_before_any_device_work():
     assert lib.ges_ssim_loss(None, p, 4, 4, 0.2, p, p, p, None) == 1
     assert lib.ges_ssim_loss(p, p, 0, 4, 0.2, p, p, p, None) == 1
     assert lib.ges_ssim_loss(p, p, 4, 4, float("inf"), p, p, p, None) == 1
+
+
+def test_render_backward_adam_validates_before_any_device_work():
+    lib = G.lib()
+    sc = synth.make_config(0)["scene"]
+    s = G.ges_splats()
+    s.n, s.sh_degree = 10, 0
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "beta"):
+        setattr(s, k, 1 << 20)
+    cam = G.camera_struct(synth.make_config(0)["camera"])
+    p = G.params_struct(0, 0, 0.1, (0.0, 0.0, 0.0))
+    g = G.ges_splat_grads()
+    opt = G.ges_adam_splats()
+    for j in range(6):
+        opt.exp_avg[j], opt.exp_avg_sq[j], opt.lr[j] = 1 << 21, 1 << 22, 0.01
+    opt.step, opt.beta1, opt.beta2, opt.eps = 1, 0.9, 0.999, 1e-15
+    args = lambda o: (C.byref(s), C.byref(cam), C.byref(p), C.c_void_p(1 << 23), None, C.c_void_p(1 << 24),
+                      C.c_void_p(1 << 25), C.byref(g), o, None)
+    assert lib.ges_render_backward_adam(*args(None)) == 1
+    opt.step = 0
+    assert lib.ges_render_backward_adam(*args(C.byref(opt))) == 1
+    opt.step = 1
+    opt.exp_avg[2] = (1 << 21) + 4          # quats moments must be 16-byte aligned
+    assert lib.ges_render_backward_adam(*args(C.byref(opt))) == 1
+    opt.exp_avg[2] = 1 << 21
+    opt.exp_avg_sq[4] = None
+    assert lib.ges_render_backward_adam(*args(C.byref(opt))) == 1
+    del sc

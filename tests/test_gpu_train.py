@@ -21,6 +21,7 @@ from paper_2402_10128_amd.train import GROUP_ORDER, TrainConfig, TrainStep
 from .parity_helpers import GRAD_RTOL, IMG_ATOL, oracle_full, to_device
 
 pytestmark = pytest.mark.gpu
+B1, B2, EPS = (float(np.float32(x)) for x in (OP.BETA1, OP.BETA2, OP.EPS))
 
 
 def _oracle_step(arrays, deg, cam, target, it, cfg):
@@ -37,7 +38,8 @@ def _oracle_step(arrays, deg, cam, target, it, cfg):
     return dict(img=img, mask=mask, loss=l1 + cfg.lam_ssim * ls, grads=ref["grads"])
 
 
-def test_train_step_matches_oracle_step():
+@pytest.mark.parametrize("fused", [True, False], ids=["fused", "two_calls"])
+def test_train_step_matches_oracle_step(fused):
     cfg_w = synth.make_config(0)
     sc, cam, target = cfg_w["scene"], cfg_w["camera"], np.asarray(cfg_w["target"], np.float32)
     arrays = sc.arrays()
@@ -47,7 +49,15 @@ def test_train_step_matches_oracle_step():
     scene = to_device(arrays)
     p0 = {k: v.clone() for k, v in scene.items()}
     ts = TrainStep(scene, cam, torch.as_tensor(target).cuda(), cfg)
-    loss = float(ts.step(1).cpu())
+    loss = float(ts.step(1, fused=False).cpu()) if not fused else None
+    if fused:
+        # the fused step stores no gradients: take them from an unfused backward of the same frame first
+        ts_g = TrainStep({k: v.clone() for k, v in scene.items()}, cam, torch.as_tensor(target).cuda(), cfg)
+        ts_g.step(1, fused=False)
+        grads_gpu = ts_g.grads
+        loss = float(ts.step(1, fused=True).cpu())
+    else:
+        grads_gpu = ts.grads
     torch.cuda.synchronize()
     assert np.array_equal(ts.mask.cpu().numpy(), ref["mask"])
     assert np.abs(ts.image.cpu().numpy() - ref["img"]).max() <= IMG_ATOL
@@ -56,10 +66,10 @@ def test_train_step_matches_oracle_step():
            "beta": OP.LR["beta"], "quats": OP.LR["quats"], "log_scales": OP.LR["log_scales"]}
     for k in GROUP_ORDER:
         g_ref = np.asarray(ref["grads"][k], np.float64).ravel()
-        g_gpu = ts.grads[k].cpu().numpy().astype(np.float64).ravel()
+        g_gpu = grads_gpu[k].cpu().numpy().astype(np.float64).ravel()
         gmax = np.abs(g_ref).max()
         assert np.abs(g_gpu - g_ref).max() <= GRAD_RTOL * gmax, k
-        pr, _, _ = OP.adam_step(p0[k].cpu().numpy().ravel(), g_ref, 0.0, 0.0, 1, lrs[k])
+        pr, _, _ = OP.adam_step(p0[k].cpu().numpy().ravel(), g_ref, 0.0, 0.0, 1, lrs[k], B1, B2, EPS)
         move = scene[k].cpu().numpy().astype(np.float64).ravel() - p0[k].cpu().numpy().astype(np.float64).ravel()
         move_ref = pr - p0[k].cpu().numpy().astype(np.float64).ravel()
         settled = np.abs(g_ref) > 2 * GRAD_RTOL * gmax
@@ -85,3 +95,23 @@ def test_training_lowers_the_loss():
     print("losses", [round(x, 5) for x in losses])
     assert all(np.isfinite(losses))
     assert min(losses[-5:]) < 0.8 * losses[0], losses
+
+
+@pytest.mark.parametrize("workload,n", [(0, None), (1, 200_000)], ids=["1k_64x64", "200k_1600x1040"])
+def test_fused_backward_adam_equals_two_calls(workload, n):
+    """Three steps of the training step with Adam fused into the backward pass and with the stand-alone
+    Adam kernel after a stored-gradient backward: parameters and both moments identical bit for bit."""
+    cfg_w = synth.make_config(workload, n_override=n)
+    sc, cam = cfg_w["scene"], cfg_w["camera"]
+    target = torch.as_tensor(np.asarray(cfg_w["target"], np.float32)).cuda()
+    runs = []
+    for fused in (True, False):
+        scene = to_device(sc.arrays())
+        ts = TrainStep(scene, cam, target, TrainConfig())
+        for it in range(1, 4):
+            ts.step(it, fused=fused)
+        torch.cuda.synchronize()
+        runs.append((scene, ts.exp_avg, ts.exp_avg_sq))
+    for k in GROUP_ORDER:
+        for a, b in zip(runs[0], runs[1]):
+            assert torch.equal(a[k], b[k]), k
