@@ -6,7 +6,10 @@ Definitions:
   down-sampling by 0.2 (App. B.2: the image Laplacian scale factor), the mask then
   up-sampled back with nearest-neighbour lookup.
 * M_omega = 1(|DoG_omega|/max|DoG_omega| > 0.5)  (threshold eps = 0.5).
-* For omega <= 0.5 the mask is 1 - M_(omega + 0.5) (Sec. 4.3, last paragraph).
+* For 0 < omega <= 0.5 the mask is 1 - M_(omega + 0.5) (Sec. 4.3, last paragraph), M_(omega + 0.5) being the
+  direct mask of the range 0.5 < omega + 0.5 <= 1.  omega = 0 is taken as the limit from above,
+  1 - (direct mask at 0.5): the direct definition itself degenerates there (sigma2 = 0.1 gives a response
+  below the flat-image floor on any image).
 * L = lambda_1 mean|I - I_gt| + lambda_omega mean(|I - I_gt| M_omega)  (Eq. laplace, Eq. final;
   the SSIM term is not part of this loss).
 Readings: the blur is a normalised sampled Gaussian of radius ceil(3 sigma) with
@@ -73,7 +76,12 @@ def dog_response(target: np.ndarray, omega: float) -> np.ndarray:
 def freq_mask(target: np.ndarray, omega: float, eps: float = 0.5) -> np.ndarray:
     """M_omega as uint8 [H,W]."""
     if omega <= 0.5:
-        return (1 - freq_mask(target, omega + 0.5, eps)).astype(np.uint8)
+        return (1 - _direct_mask(target, omega + 0.5, eps)).astype(np.uint8)
+    return _direct_mask(target, omega, eps)
+
+
+def _direct_mask(target: np.ndarray, omega: float, eps: float) -> np.ndarray:
+    """1(normalised |DoG_omega| > eps), up-sampled to the target's size."""
     H, W = target.shape[:2]
     low = dog_response(target, omega) > eps
     ys = np.arange(H) // SCALE_INV

@@ -65,7 +65,7 @@ def test_freq_mask_and_loss_vs_oracle():
     tgt = (0.5 + 0.4 * np.sin(xx / 9.0)[..., None] * np.cos(yy / 13.0)[..., None]
            + 0.05 * rng.standard_normal((H, W, 3))).astype(np.float32)
     img = rng.uniform(size=(H, W, 3)).astype(np.float32)
-    for omega in (0.75, 0.3):
+    for omega in (0.75, 0.3, 0.5, 1.0, 0.0, 1 / 40000):
         m_gpu = G.ges_freq_mask(torch.as_tensor(tgt).cuda(), omega).cpu().numpy()
         m_ref = OL.freq_mask(tgt.astype(np.float64), omega)
         # pixels whose normalised response lies within 1e-4 of the threshold may go either way

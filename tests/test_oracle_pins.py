@@ -503,6 +503,27 @@ def test_freq_mask_constant_and_edge():
     assert np.array_equal(m25, 1 - m75)
 
 
+def test_freq_mask_complement_uses_the_direct_mask():
+    """0 < omega <= 0.5 takes the complement of the direct mask at omega + 0.5 (Sec. 4.3), also at omega =
+    0.5 (complement of the direct mask at 1.0) and, as the limit from above, at omega = 0 (complement of the
+    direct mask at 0.5, not a second complement).  On a step edge the direct masks are bands beside the edge
+    whose width grows with omega, so the masks at 0, 0.5 and 1.0 all differ."""
+    img = np.zeros((200, 200, 3))
+    img[:, 100:] = 1.0
+    m0, m_half, m1 = OL.freq_mask(img, 0.0), OL.freq_mask(img, 0.5), OL.freq_mask(img, 1.0)
+    assert np.array_equal(m_half, 1 - m1)
+    assert np.array_equal(m0, OL.freq_mask(img, 1e-9))
+    assert not np.array_equal(m0, m_half) and not np.array_equal(m0, m1)
+    # The direct DoG at 0.5 (sigma2 = 5.1, sigma1 = 10.2) of a step is odd about the edge (x = 19.5 after the
+    # down-sampling): zero at the edge, extreme at 19.5 -/+ d* with d* = sqrt(2 ln 2 / (1/s2^2 - 1/s1^2)).  Its
+    # complement is therefore 1 at the edge and 0 at both extremes.
+    s2, s1 = 5.1, 10.2
+    d = math.sqrt(2 * math.log(2.0) / (1 / s2 ** 2 - 1 / s1 ** 2))
+    for xl in (int(round(19.5 - d)), int(round(19.5 + d))):
+        assert m0[:, 5 * xl:5 * xl + 5].max() == 0, xl
+    assert m0[:, 95:105].min() == 1
+
+
 def test_loss_gradient_matches_fd():
     rng = np.random.default_rng(4)
     I = rng.uniform(size=(8, 9, 3))
