@@ -1,16 +1,17 @@
 // loss.hip -- frequency-modulated L1 loss of GES (Sec. 4.3) and its gradient.
 //
-// Mask (made once per target and omega, outside the training step):
+// Mask (made per target and omega; the training step remakes it every iteration as omega grows):
 //   grey = (r + g + b) / 3, area-down-sampled by 5 (image Laplacian scale 0.2, App. B.2);
 //   DoG = G(grey, sigma1) - G(grey, sigma2), sigma2 = 0.1 + 10 omega, sigma1 = 2 sigma2 (Eq. mask),
 //   separable normalised Gaussians of radius ceil(3 sigma) with replicated borders;
 //   M = |DoG| / max|DoG| > 0.5 (an all-zero mask when max|DoG| <= 1e-5), up-sampled by nearest lookup;
-//   for omega <= 0.5, M = 1 - M_(omega+0.5).
+//   for omega <= 0.5, M = 1 - M_(omega+0.5), M_(omega+0.5) taken directly (omega = 0 as the limit from above).
 // Loss: L = lam_l1 mean|I - T| + lam_w mean(|I - T| M) (Eq. laplace, Eq. final without the SSIM term),
 //   dL/dI = (lam_l1 + lam_w M) sign(I - T) / (3 h w).  The per-block partial sums are added in a
 //   fixed order by one block, so the loss is deterministic.
 // Memory: the loss reads I, T (12 B/px each) and M (1 B/px) and writes dL/dI (12 B/px): HBM-bound.
 #include <algorithm>
+#include <cmath>
 
 #include "ges_internal.h"
 
@@ -19,11 +20,16 @@ namespace ges {
 constexpr int kScale = 5;
 constexpr int kMaxTaps = 2 * 64 + 1;   // supports sigma up to 21 (omega <= 1)
 
-struct MaskScratch {
+// Blur weights of both Gaussians, made on the host and passed by value (they land in the kernel-argument
+// segment and are read with scalar loads).
+struct MaskWeights {
   float w1[kMaxTaps];
   float w2[kMaxTaps];
   int r1, r2;
-  unsigned int maxbits;
+};
+
+struct MaskScratch {
+  unsigned int maxbits;   // largest |DoG| (non-negative floats order like their bits)
 };
 
 size_t freq_mask_scratch_bytes(int w, int h) {
@@ -31,23 +37,23 @@ size_t freq_mask_scratch_bytes(int w, int h) {
   return 256 + ((sizeof(MaskScratch) + 255) / 256) * 256 + 4 * wl * hl * sizeof(float) + 256;
 }
 
-__global__ void mask_weights_kernel(MaskScratch* ms, float s1, float s2) {
-  if (threadIdx.x != 0) return;
+static void mask_weights(MaskWeights& mw, float s1, float s2) {
   for (int which = 0; which < 2; ++which) {
-    const float s = which == 0 ? s1 : s2;
-    const int R = (int)ceilf(3.f * s);
-    float* w = which == 0 ? ms->w1 : ms->w2;
+    const double s = which == 0 ? s1 : s2;
+    const int R = (int)std::ceil(3.0 * (double)(which == 0 ? s1 : s2));
+    float* w = which == 0 ? mw.w1 : mw.w2;
     double sum = 0.0;
-    for (int k = -R; k <= R; ++k) sum += exp(-(double)(k * k) / (2.0 * (double)s * (double)s));
-    for (int k = -R; k <= R; ++k) w[k + R] = (float)(exp(-(double)(k * k) / (2.0 * (double)s * (double)s)) / sum);
-    if (which == 0) ms->r1 = R; else ms->r2 = R;
+    for (int k = -R; k <= R; ++k) sum += std::exp(-(double)(k * k) / (2.0 * s * s));
+    for (int k = -R; k <= R; ++k) w[k + R] = (float)(std::exp(-(double)(k * k) / (2.0 * s * s)) / sum);
+    if (which == 0) mw.r1 = R; else mw.r2 = R;
   }
-  ms->maxbits = 0u;
 }
 
-__global__ void grey_down_kernel(const float* __restrict__ img, int w, int h, float* __restrict__ low, int wl, int hl) {
+__global__ void grey_down_kernel(const float* __restrict__ img, int w, int h, float* __restrict__ low, int wl, int hl,
+                                 MaskScratch* __restrict__ ms) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
+  if (x == 0 && y == 0) ms->maxbits = 0u;   // read only by the later kernels of this mask
   if (x >= wl) return;
   float acc = 0.f;
   int cnt = 0;
@@ -66,31 +72,40 @@ __global__ void grey_down_kernel(const float* __restrict__ img, int w, int h, fl
 }
 
 // horizontal pass of both blurs
-__global__ void blur_h_kernel(const MaskScratch* __restrict__ ms, const float* __restrict__ low, int wl, int hl,
+__global__ void blur_h_kernel(const MaskWeights mw, const float* __restrict__ low, int wl, int hl,
                               float* __restrict__ h1, float* __restrict__ h2) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= wl) return;
   const float* row = low + (size_t)y * wl;
   float a1 = 0.f, a2 = 0.f;
-  for (int k = -ms->r1; k <= ms->r1; ++k) a1 += ms->w1[k + ms->r1] * row[min(max(x + k, 0), wl - 1)];
-  for (int k = -ms->r2; k <= ms->r2; ++k) a2 += ms->w2[k + ms->r2] * row[min(max(x + k, 0), wl - 1)];
+  for (int k = -mw.r1; k <= mw.r1; ++k) a1 += mw.w1[k + mw.r1] * row[min(max(x + k, 0), wl - 1)];
+  for (int k = -mw.r2; k <= mw.r2; ++k) a2 += mw.w2[k + mw.r2] * row[min(max(x + k, 0), wl - 1)];
   h1[(size_t)y * wl + x] = a1;
   h2[(size_t)y * wl + x] = a2;
 }
 
-// vertical pass, |DoG| and its maximum
-__global__ void blur_v_dog_kernel(MaskScratch* __restrict__ ms, const float* __restrict__ h1,
-                                  const float* __restrict__ h2, int wl, int hl, float* __restrict__ dog) {
+// vertical pass, |DoG| and its maximum (a block maximum, then one atomic per block)
+__global__ void __launch_bounds__(128) blur_v_dog_kernel(MaskScratch* __restrict__ ms, const MaskWeights mw,
+                                                         const float* __restrict__ h1, const float* __restrict__ h2,
+                                                         int wl, int hl, float* __restrict__ dog) {
+  __shared__ float wmax[2];
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= wl) return;
-  float a1 = 0.f, a2 = 0.f;
-  for (int k = -ms->r1; k <= ms->r1; ++k) a1 += ms->w1[k + ms->r1] * h1[(size_t)min(max(y + k, 0), hl - 1) * wl + x];
-  for (int k = -ms->r2; k <= ms->r2; ++k) a2 += ms->w2[k + ms->r2] * h2[(size_t)min(max(y + k, 0), hl - 1) * wl + x];
-  const float d = fabsf(a1 - a2);
-  dog[(size_t)y * wl + x] = d;
-  atomicMax(&ms->maxbits, __float_as_uint(d));   // non-negative floats order like their bits
+  float d = 0.f;
+  if (x < wl) {
+    float a1 = 0.f, a2 = 0.f;
+    for (int k = -mw.r1; k <= mw.r1; ++k) a1 += mw.w1[k + mw.r1] * h1[(size_t)min(max(y + k, 0), hl - 1) * wl + x];
+    for (int k = -mw.r2; k <= mw.r2; ++k) a2 += mw.w2[k + mw.r2] * h2[(size_t)min(max(y + k, 0), hl - 1) * wl + x];
+    d = fabsf(a1 - a2);
+    dog[(size_t)y * wl + x] = d;
+  }
+  float m = d;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(&ms->maxbits, __float_as_uint(fmaxf(wmax[0], wmax[1])));
 }
 
 __global__ void mask_up_kernel(const MaskScratch* __restrict__ ms, const float* __restrict__ dog, int wl, int w, int h,
@@ -116,11 +131,12 @@ hipError_t launch_freq_mask(const float* target, int w, int h, float omega, void
   float* h1 = low + (size_t)wl * hl;
   float* h2 = h1 + (size_t)wl * hl;
   float* dog = h2 + (size_t)wl * hl;
-  hipLaunchKernelGGL(mask_weights_kernel, dim3(1), dim3(64), 0, stream, ms, s1, s2);
+  MaskWeights mw;
+  mask_weights(mw, s1, s2);
   const dim3 gl((wl + 127) / 128, hl);
-  hipLaunchKernelGGL(grey_down_kernel, gl, dim3(128), 0, stream, target, w, h, low, wl, hl);
-  hipLaunchKernelGGL(blur_h_kernel, gl, dim3(128), 0, stream, ms, low, wl, hl, h1, h2);
-  hipLaunchKernelGGL(blur_v_dog_kernel, gl, dim3(128), 0, stream, ms, h1, h2, wl, hl, dog);
+  hipLaunchKernelGGL(grey_down_kernel, gl, dim3(128), 0, stream, target, w, h, low, wl, hl, ms);
+  hipLaunchKernelGGL(blur_h_kernel, gl, dim3(128), 0, stream, mw, low, wl, hl, h1, h2);
+  hipLaunchKernelGGL(blur_v_dog_kernel, gl, dim3(128), 0, stream, ms, mw, h1, h2, wl, hl, dog);
   hipLaunchKernelGGL(mask_up_kernel, dim3((w + 255) / 256, h), dim3(256), 0, stream, ms, dog, wl, w, h,
                      invert ? 1 : 0, mask);
   return hipGetLastError();

@@ -15,7 +15,8 @@
 // the cancellation in E[x^2] - E[x]^2.  A final block adds the per-block sums in a fixed order.
 //
 // Memory per pixel and channel: the forward reads x, y (8 B) and writes three maps (12 B); the backward
-// reads the maps (12 B), x, y and the gradient (12 B) and writes the gradient (4 B).  Halo re-reads hit L2.
+// reads the maps (12 B), x, y and the gradient (12 B) and writes the gradient (4 B).  Tiles are dealt to the
+// XCDs in bands so the halo re-reads hit L2.
 #include <algorithm>
 #include <cmath>
 
@@ -40,16 +41,28 @@ struct SsimWeights {
   float w[kSsimTaps];
 };
 
+// Workgroups are dealt to the 8 XCDs in turn (block b runs on XCD b mod 8), and each XCD has its own L2.
+// Block b takes tile (b mod 8) * per + b / 8, so every XCD walks one contiguous band of tile rows and the
+// halos that neighbouring tiles share are read through the same L2.  Returns -1 for the spare blocks.
+__device__ __forceinline__ int ssim_tile(int b, int ntiles) {
+  const int per = (ntiles + 7) / 8;
+  const int j = b >> 3, tile = (b & 7) * per + j;
+  return (j < per && tile < ntiles) ? tile : -1;
+}
+
 __global__ void __launch_bounds__(kSsimThreads) ssim_fwd_kernel(const float* __restrict__ img,
                                                                 const float* __restrict__ tgt, int w, int h,
                                                                 const SsimWeights wt, float* __restrict__ maps,
-                                                                double* __restrict__ partial) {
+                                                                double* __restrict__ partial, int tiles_x,
+                                                                int ntiles) {
   __shared__ float sx[3][kSsimIn][kSsimPitch];
   __shared__ float sy[3][kSsimIn][kSsimPitch];
   __shared__ __align__(16) float hs[5][kSsimIn][kSsimT];
   __shared__ double red[kSsimThreads / 64];
+  const int tile = ssim_tile(blockIdx.x, ntiles);
+  if (tile < 0) return;
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * kSsimT - kSsimR, y0 = blockIdx.y * kSsimT - kSsimR;
+  const int x0 = (tile % tiles_x) * kSsimT - kSsimR, y0 = (tile / tiles_x) * kSsimT - kSsimR;
   // stage both images (all three channels, rows of 42 interleaved pixels = 126 contiguous floats); every
   // load of a thread is issued before the first LDS store, so their latencies overlap
   float ra[kSsimStage], rb[kSsimStage];
@@ -159,19 +172,37 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_fwd_kernel(const float* __r
   for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
   if ((t & 63) == 0) red[t >> 6] = d;
   __syncthreads();
-  if (t == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (t == 0) partial[tile] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 __global__ void __launch_bounds__(kSsimThreads) ssim_bwd_kernel(const float* __restrict__ img,
                                                                 const float* __restrict__ tgt, int w, int h,
                                                                 const SsimWeights wt, const float* __restrict__ maps,
-                                                                float scale, float* __restrict__ dL) {
+                                                                float scale, float* __restrict__ dL, int tiles_x,
+                                                                int ntiles) {
   __shared__ float sm[3][kSsimIn][kSsimPitch];
   __shared__ __align__(16) float hs[3][kSsimIn][kSsimT];
+  const int tile = ssim_tile(blockIdx.x, ntiles);
+  if (tile < 0) return;
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * kSsimT - kSsimR, y0 = blockIdx.y * kSsimT - kSsimR;
+  const int x0 = (tile % tiles_x) * kSsimT - kSsimR, y0 = (tile / tiles_x) * kSsimT - kSsimR;
   const size_t plane = (size_t)w * h;
-  const int ox = t % kSsimT;
+  const int ox = t % kSsimT, oy0 = 4 * (t / kSsimT);
+  const int gx = x0 + kSsimR + ox;
+  // the thread's 4 output pixels (one column, 4 rows): both images read once, all channels
+  float xs[4][3], ys[4][3], gacc[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int gy = y0 + kSsimR + oy0 + q;
+    const bool in = gx < w && gy < h;
+    const size_t o = in ? 3 * ((size_t)gy * w + gx) : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xs[q][c] = in ? img[o + c] - kSsimShift : 0.f;
+      ys[q][c] = in ? tgt[o + c] - kSsimShift : 0.f;
+      gacc[q][c] = 0.f;
+    }
+  }
 #pragma unroll 1
   for (int c = 0; c < 3; ++c) {
     if (c > 0) __syncthreads();
@@ -216,7 +247,6 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_bwd_kernel(const float* __r
       }
     }
     __syncthreads();
-    const int oy0 = 4 * (t / kSsimT);
     float f[3][4];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -231,14 +261,25 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_bwd_kernel(const float* __r
         f[m][q] = acc;
       }
     }
+    // channel c's value of every output (registers picked with constant indices only)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int gx = x0 + kSsimR + ox, gy = y0 + kSsimR + oy0 + q;
-      if (gx >= w || gy >= h) continue;
-      const size_t o = 3 * ((size_t)gy * w + gx) + c;
-      const float xs = img[o] - kSsimShift, ys = tgt[o] - kSsimShift;
-      dL[o] = dL[o] - scale * (f[0][q] + 2.f * xs * f[1][q] + ys * f[2][q]);
+      const float x_ = c == 0 ? xs[q][0] : (c == 1 ? xs[q][1] : xs[q][2]);
+      const float y_ = c == 0 ? ys[q][0] : (c == 1 ? ys[q][1] : ys[q][2]);
+      const float g = f[0][q] + 2.f * x_ * f[1][q] + y_ * f[2][q];
+      if (c == 0) gacc[q][0] = g;
+      else if (c == 1) gacc[q][1] = g;
+      else gacc[q][2] = g;
     }
+  }
+  // one read-modify-write of the three channels of each output pixel
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int gy = y0 + kSsimR + oy0 + q;
+    if (gx >= w || gy >= h) continue;
+    const size_t o = 3 * ((size_t)gy * w + gx);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dL[o + c] = dL[o + c] - scale * gacc[q][c];
   }
 }
 
@@ -280,11 +321,14 @@ hipError_t launch_ssim_loss(const float* img, const float* target, int w, int h,
   float* maps = reinterpret_cast<float*>(scratch);
   const size_t maps_bytes = ((9 * (size_t)w * h * sizeof(float) + 255) / 256) * 256;
   double* partial = reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) + maps_bytes);
-  const dim3 grid((w + kSsimT - 1) / kSsimT, (h + kSsimT - 1) / kSsimT);
+  const int tiles_x = (w + kSsimT - 1) / kSsimT;
+  const int ntiles = (int)ssim_blocks(w, h);
+  const dim3 grid(8 * ((ntiles + 7) / 8));
   const double count = 3.0 * (double)w * (double)h;
-  hipLaunchKernelGGL(ssim_fwd_kernel, grid, dim3(kSsimThreads), 0, stream, img, target, w, h, wt, maps, partial);
+  hipLaunchKernelGGL(ssim_fwd_kernel, grid, dim3(kSsimThreads), 0, stream, img, target, w, h, wt, maps, partial,
+                     tiles_x, ntiles);
   hipLaunchKernelGGL(ssim_bwd_kernel, grid, dim3(kSsimThreads), 0, stream, img, target, w, h, wt,
-                     (const float*)maps, (float)((double)lam / count), dL);
+                     (const float*)maps, (float)((double)lam / count), dL, tiles_x, ntiles);
   hipLaunchKernelGGL(ssim_final_kernel, dim3(1), dim3(256), 0, stream, (const double*)partial,
                      (int)ssim_blocks(w, h), count, lam, loss);
   return hipGetLastError();
