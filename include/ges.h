@@ -213,7 +213,7 @@ size_t ges_loss_scratch_bytes(void);
 ges_status ges_loss(const float* img, const float* target, const uint8_t* mask, int32_t width, int32_t height,
                     float lam_l1, float lam_w, void* scratch, float* loss_out, float* dL_dimg, void* stream);
 
-/* ---- structural-similarity term of the training loss (Sec. 5 loss, lambda_ssim) ------
+/* ---- structural-similarity term of the training loss (Sec. 4.4, Eq. final) --------
  * Gaussian-weighted SSIM (Wang et al., 2004) of img against target, both [h,w,3]:
  * 11x11 window of sigma 1.5 (unit sum), each channel on its own, zero padding (the
  * SSIM map has the image's size), C1 = 0.01^2, C2 = 0.03^2; L_ssim = 1 - mean SSIM over

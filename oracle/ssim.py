@@ -3,7 +3,7 @@
 Only tests/, the package's smoke check and the benchmark's CPU baseline may use this module.
 
 The training loss adds lambda_ssim L_ssim to the L1 and frequency-modulated terms, with lambda_ssim = 0.2 and
-lambda_L1 = 1 - lambda_ssim - lambda_omega (Sec. 5, the loss equation; App. B.2).  The paper does not spell
+lambda_L1 = 1 - lambda_ssim - lambda_omega (Sec. 4.4, Eq. final; App. B.2).  The paper does not spell
 SSIM out; this module takes the Gaussian-weighted SSIM of Wang et al. (2004):
   mu_x = w * x,  s_x = w * x^2 - mu_x^2,  s_xy = w * (x y) - mu_x mu_y   (and likewise for y),
   SSIM = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x + s_y + C2)),

@@ -1,4 +1,4 @@
-// ssim.hip -- SSIM term of the GES training loss (lambda_ssim L_ssim, Sec. 5 loss) and its gradient.
+// ssim.hip -- SSIM term of the GES training loss (lambda_ssim L_ssim, Sec. 4.4, Eq. final) and its gradient.
 //
 // Gaussian-weighted SSIM (Wang et al., 2004): 11x11 window (sigma 1.5, unit sum), each colour channel on its
 // own, zero padding so the map has the image's size, C1 = 0.01^2, C2 = 0.03^2; L_ssim = 1 - mean SSIM over

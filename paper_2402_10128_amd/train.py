@@ -2,7 +2,7 @@
 
 The step follows the paper's training recipe:
   * loss L = lambda_L1 L1 + lambda_ssim L_ssim + lambda_omega L_omega with lambda_ssim = 0.2,
-    lambda_omega = 0.5 and lambda_L1 = 1 - lambda_ssim - lambda_omega (Sec. 5, loss equation; App. B.2);
+    lambda_omega = 0.5 and lambda_L1 = 1 - lambda_ssim - lambda_omega (Sec. 4.4, Eq. final; App. B.2);
   * the frequency mask M_omega at omega = iteration / total iterations (Sec. 4.3, linear schedule),
     40,000 iterations in all (App. B.2);
   * Adam with per-group learning rates, the position rate decaying log-linearly from 1.6e-4 to 1.6e-6

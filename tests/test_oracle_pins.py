@@ -631,3 +631,48 @@ def test_ssim_gradient_matches_central_differences():
         xm[idx] -= h
         fd = (OS.ssim_loss_and_grad(xp, y)[0] - OS.ssim_loss_and_grad(xm, y)[0]) / (2 * h)
         assert abs(fd - g[idx]) <= 1e-7 * max(1.0, abs(g[idx]) * 1e3), (idx, fd, g[idx])
+
+
+# ---- shape/opacity pruning and shape reset (Sec. 4.4, Sec. 5.2, App. B.2)
+def test_prune_hand_example_and_logit_bound():
+    """Five splats worked by hand at min_opacity 0.005 (logit bound ln(0.005/0.995) = -5.2933) and
+    min_beta 0.5: splat 0 too transparent, 1 too small a beta, 4 too transparent; 2 and 3 survive, in order,
+    with their moments."""
+    from oracle import prune as OPR
+    assert abs(OPR.opacity_logit_bound(0.005) - (-5.293304824724492)) < 1e-12
+    assert abs(1 / (1 + math.exp(-OPR.opacity_logit_bound(0.005))) - 0.005) < 1e-15
+    arrays = {"means": np.arange(15, dtype=np.float32).reshape(5, 3), "log_scales": np.zeros((5, 3), np.float32),
+              "quats": np.ones((5, 4), np.float32), "opacity_logits": np.array([-6, 0, 2, -5.0, -5.5], np.float32),
+              "sh": np.arange(5 * 4 * 3, dtype=np.float32).reshape(5, 4, 3),
+              "beta": np.array([2, 0.4, 0.6, 2, 2], np.float32)}
+    mom = {k: v + 100 for k, v in arrays.items()}
+    out, (outm,), keep = OPR.prune(arrays, [mom], 0.005, 0.5)
+    assert list(np.nonzero(keep)[0]) == [2, 3]
+    assert np.array_equal(out["means"], np.array([[6, 7, 8], [9, 10, 11]], np.float32))
+    assert np.array_equal(outm["sh"], arrays["sh"][[2, 3]] + 100)
+
+
+def test_prune_matches_sigmoid_brute_force_and_is_idempotent():
+    from oracle import prune as OPR
+    rng = np.random.default_rng(3)
+    n = 5000
+    logits = rng.normal(-3, 3, n).astype(np.float32)
+    beta = rng.uniform(0, 3, n).astype(np.float32)
+    keep = OPR.keep_mask(logits, beta, 0.005, 0.5)
+    op = 1 / (1 + np.exp(-logits.astype(np.float64)))
+    want = (op >= 0.005) & (beta >= 0.5)
+    settled = np.abs(op - 0.005) > 1e-12
+    assert np.array_equal(keep[settled], want[settled])
+    arrays = {"opacity_logits": logits, "beta": beta, "means": rng.normal(size=(n, 3)).astype(np.float32)}
+    once, _, _ = OPR.prune(arrays, [], 0.005, 0.5)
+    twice, _, k2 = OPR.prune(once, [], 0.005, 0.5)
+    assert k2.all() and all(np.array_equal(once[k], twice[k]) for k in once)
+    # order kept: the surviving means appear in their original order
+    idx = np.nonzero(keep)[0]
+    assert np.array_equal(once["means"], arrays["means"][idx])
+
+
+def test_shape_reset_restores_gaussian_and_clears_moments():
+    from oracle import prune as OPR
+    b, m, v = OPR.shape_reset(np.array([0.3, 5.0], np.float32), np.ones(2, np.float32), np.ones(2, np.float32))
+    assert list(b) == [2.0, 2.0] and not m.any() and not v.any()
