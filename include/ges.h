@@ -274,6 +274,40 @@ ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* 
                                     void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
                                     const ges_splat_grads* grads, const ges_adam_splats* opt, void* stream);
 
+/* ---- shape/opacity pruning and shape reset (Sec. 4.4, Sec. 5.2, App. B.2) --------
+ * The paper prunes splats on their shape every 100 iterations (threshold 0.5 in Sec. 5.2,
+ * 0.005 in App. B.2), keeps the opacity pruning of Gaussian splatting (0.005) and resets
+ * the shape every 1,000 iterations.
+ *
+ * ges_prune_splats removes every splat whose opacity sigmoid(logit) < min_opacity or whose
+ * beta < min_beta and copies the survivors, in their original order, from src[k] to
+ * dst[k] for k < nsets (src[0]: the parameters, which decide; src[1], src[2]: e.g. the two
+ * Adam moments, laid out like the parameters).  The opacity test is taken on the logit
+ * against ln(t / (1 - t)) and the beta test in binary64, so the decision is exact.  A NULL
+ * member of src[k] is skipped (dst[k]'s member must then be NULL too); dst must not
+ * overlap src.  *n_kept (host) receives the survivor count: the call waits for `stream`.
+ * scratch: device buffer of ges_prune_scratch_bytes(n) bytes.  Errors:
+ * GES_ERR_INVALID_ARGUMENT for n outside [0, 2^31), sh_degree outside 0..3, nsets outside
+ * 1..3, a NULL src[0].opacity_logits or src[0].beta (n > 0), a NULL dst member where the
+ * src member is set, min_opacity outside [0, 1] or a NaN min_beta; GES_ERR_CAPACITY for
+ * a small scratch.
+ *
+ * ges_shape_reset sets beta[0..n) to `value` (2: the Gaussian the splats start from) and
+ * clears the moments (either may be NULL). */
+typedef struct {
+  float* means;                  /* [n,3] */
+  float* log_scales;             /* [n,3] */
+  float* quats;                  /* [n,4] */
+  float* opacity_logits;         /* [n] */
+  float* sh;                     /* [n,(D+1)^2,3] */
+  float* beta;                   /* [n] */
+} ges_splat_set;
+size_t ges_prune_scratch_bytes(int64_t n);
+ges_status ges_prune_splats(int64_t n, int32_t sh_degree, const ges_splat_set* src, const ges_splat_set* dst,
+                            int32_t nsets, double min_opacity, double min_beta, void* scratch, size_t scratch_bytes,
+                            int64_t* n_kept, void* stream);
+ges_status ges_shape_reset(float* beta, float* exp_avg, float* exp_avg_sq, int64_t n, float value, void* stream);
+
 /* Learning rate at `step` of a log-linear decay from lr_init (step 0) to lr_final (step
  * max_steps, constant afterwards), times a delay factor that rises from delay_mult to 1
  * along a quarter sine over delay_steps (none when delay_steps <= 0).  The paper decays

@@ -405,6 +405,64 @@ ges_status ges_adam_step(const ges_adam_group* groups, int32_t ngroups, int64_t 
   return GES_OK;
 }
 
+size_t ges_prune_scratch_bytes(int64_t n) {
+  if (n < 0 || n >= (int64_t(1) << 31)) return 0;
+  return ges::prune_scratch_bytes(n);
+}
+
+ges_status ges_prune_splats(int64_t n, int32_t sh_degree, const ges_splat_set* src, const ges_splat_set* dst,
+                            int32_t nsets, double min_opacity, double min_beta, void* scratch, size_t scratch_bytes,
+                            int64_t* n_kept, void* stream) {
+  if (!src || !dst || !scratch || !n_kept) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(GES_ERR_INVALID_ARGUMENT, "n outside [0, 2^31)");
+  if (sh_degree < 0 || sh_degree > 3) return fail(GES_ERR_INVALID_ARGUMENT, "sh_degree outside 0..3");
+  if (nsets < 1 || nsets > 3) return fail(GES_ERR_INVALID_ARGUMENT, "nsets outside 1..3");
+  if (!(min_opacity >= 0.0 && min_opacity <= 1.0)) return fail(GES_ERR_INVALID_ARGUMENT, "min_opacity outside [0,1]");
+  if (std::isnan(min_beta)) return fail(GES_ERR_INVALID_ARGUMENT, "min_beta is NaN");
+  if (n > 0 && (!src[0].opacity_logits || !src[0].beta))
+    return fail(GES_ERR_INVALID_ARGUMENT, "src[0] needs opacity_logits and beta");
+  if (scratch_bytes < ges::prune_scratch_bytes(n)) return fail(GES_ERR_CAPACITY, "prune scratch too small");
+  const int K = (sh_degree + 1) * (sh_degree + 1);
+  const int32_t len[6] = {3, 3, 4, 1, 3 * K, 1};
+  const float* s[ges::kMaxPruneArrays] = {};
+  float* d[ges::kMaxPruneArrays] = {};
+  int32_t rl[ges::kMaxPruneArrays] = {};
+  for (int set = 0; set < nsets; ++set) {
+    const float* sp[6] = {src[set].means, src[set].log_scales, src[set].quats, src[set].opacity_logits, src[set].sh,
+                          src[set].beta};
+    float* dp[6] = {dst[set].means, dst[set].log_scales, dst[set].quats, dst[set].opacity_logits, dst[set].sh,
+                    dst[set].beta};
+    for (int k = 0; k < 6; ++k) {
+      if (!sp[k]) continue;
+      if (!dp[k]) return fail(GES_ERR_INVALID_ARGUMENT, "NULL destination for a source array");
+      s[6 * set + k] = sp[k];
+      d[6 * set + k] = dp[k];
+      rl[6 * set + k] = len[k];
+    }
+  }
+  const double bound = min_opacity <= 0.0 ? -HUGE_VAL
+                       : min_opacity >= 1.0 ? HUGE_VAL
+                                            : std::log(min_opacity / (1.0 - min_opacity));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int64_t* total_dev = reinterpret_cast<int64_t*>(scratch);
+  GES_CHECK_HIP(ges::launch_prune(s, d, rl, src[0].opacity_logits, src[0].beta, n, bound, min_beta, scratch, total_dev,
+                                  st), "prune");
+  int64_t kept = 0;
+  GES_CHECK_HIP(hipMemcpyAsync(&kept, total_dev, sizeof(kept), hipMemcpyDeviceToHost, st), "read kept count");
+  GES_CHECK_HIP(hipStreamSynchronize(st), "sync");
+  *n_kept = kept;
+  return GES_OK;
+}
+
+ges_status ges_shape_reset(float* beta, float* exp_avg, float* exp_avg_sq, int64_t n, float value, void* stream) {
+  if (n < 0) return fail(GES_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n > 0 && !beta) return fail(GES_ERR_INVALID_ARGUMENT, "NULL beta");
+  if (!std::isfinite(value)) return fail(GES_ERR_INVALID_ARGUMENT, "non-finite value");
+  GES_CHECK_HIP(ges::launch_shape_reset(beta, exp_avg, exp_avg_sq, n, value, reinterpret_cast<hipStream_t>(stream)),
+                "shape_reset");
+  return GES_OK;
+}
+
 double ges_expon_lr(int64_t step, double lr_init, double lr_final, int64_t max_steps, int64_t delay_steps,
                     double delay_mult) {
   if (!(lr_init > 0.0) || !(lr_final > 0.0) || max_steps < 1) return std::nan("");

@@ -152,6 +152,12 @@ hipError_t launch_ssim_loss(const float* img, const float* target, int w, int h,
                             float* loss, float* dL, hipStream_t stream);
 
 
+constexpr int kMaxPruneArrays = 18;   // parameters and two moment sets, six arrays each
+size_t prune_scratch_bytes(int64_t n);
+hipError_t launch_prune(const float* const* src, float* const* dst, const int32_t* rowlen, const float* opacity_logits,
+                        const float* beta, int64_t n, double logit_bound, double min_beta, void* scratch,
+                        int64_t* total_dev, hipStream_t stream);
+hipError_t launch_shape_reset(float* beta, float* m, float* v, int64_t n, float value, hipStream_t stream);
 hipError_t launch_adam(const ges_adam_group* groups, int ngroups, int64_t step, float b1, float b2, float eps,
                        hipStream_t stream);
 

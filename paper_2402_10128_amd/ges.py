@@ -71,6 +71,11 @@ class ges_adam_splats(C.Structure):
                 ("step", C.c_int64), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
+class ges_splat_set(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity_logits", C.c_void_p), ("sh", C.c_void_p), ("beta", C.c_void_p)]
+
+
 class ges_request_info(C.Structure):
     _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("t_submit_ns", C.c_uint64), ("t_start_ns", C.c_uint64),
                 ("t_done_ns", C.c_uint64), ("num_keys", C.c_uint64), ("batch_size", C.c_int32)]
@@ -106,6 +111,10 @@ _SIGS = {
     "ges_render_backward_adam": (C.c_int, [C.POINTER(ges_splats), C.POINTER(ges_camera), C.POINTER(ges_raster_params),
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.POINTER(ges_splat_grads), C.POINTER(ges_adam_splats), C.c_void_p]),
+    "ges_prune_scratch_bytes": (C.c_size_t, [C.c_int64]),
+    "ges_prune_splats": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(ges_splat_set), C.POINTER(ges_splat_set), C.c_int32,
+                                   C.c_double, C.c_double, C.c_void_p, C.c_size_t, C.POINTER(C.c_int64), C.c_void_p]),
+    "ges_shape_reset": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p]),
     "ges_adam_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "ges_expon_lr": (C.c_double, [C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_double]),
     "ges_serve_create": (C.c_int, [C.POINTER(ges_serve_config), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
@@ -317,6 +326,35 @@ def ges_render_backward_adam(splats, cam, params, splat_ws, key_ws, pixel_ws, dL
     _check(lib().ges_render_backward_adam(C.byref(splats), C.byref(cam), C.byref(params), _ptr(splat_ws),
                                           _ptr(key_ws), _ptr(pixel_ws), _ptr(dL_drgb), C.byref(g), C.byref(opt),
                                           _stream(stream)))
+
+
+def _splat_set(d: dict | None) -> ges_splat_set:
+    st = ges_splat_set()
+    for name in SPLAT_PARAMS:
+        t = None if d is None else d.get(name)
+        setattr(st, name, None if t is None else t.data_ptr())
+    return st
+
+
+def ges_prune_splats(src_sets: list, dst_sets: list, sh_degree: int, min_opacity: float, min_beta: float,
+                     scratch=None, stream=None) -> int:
+    """Compact the survivors of every set in src_sets into dst_sets (dicts of float32 CUDA tensors; set 0
+    holds the parameters); returns the survivor count (waits for the stream)."""
+    n = int(src_sets[0]["beta"].shape[0])
+    k = len(src_sets)
+    src = (ges_splat_set * k)(*[_splat_set(d) for d in src_sets])
+    dst = (ges_splat_set * k)(*[_splat_set(d) for d in dst_sets])
+    if scratch is None:
+        scratch = torch.empty(lib().ges_prune_scratch_bytes(n), dtype=torch.uint8, device=src_sets[0]["beta"].device)
+    kept = C.c_int64(0)
+    _check(lib().ges_prune_splats(n, int(sh_degree), src, dst, k, float(min_opacity), float(min_beta), _ptr(scratch),
+                                  scratch.numel(), C.byref(kept), _stream(stream)))
+    return kept.value
+
+
+def ges_shape_reset(beta, exp_avg=None, exp_avg_sq=None, value=2.0, stream=None):
+    _check(lib().ges_shape_reset(_ptr(beta), _ptr(exp_avg), _ptr(exp_avg_sq), int(beta.numel()), float(value),
+                                 _stream(stream)))
 
 
 def ges_expon_lr(step, lr_init, lr_final, max_steps, delay_steps=0, delay_mult=1.0) -> float:

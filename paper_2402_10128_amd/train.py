@@ -10,7 +10,11 @@ The step follows the paper's training recipe:
 Every stage runs in the library's kernels; this module only owns buffers and orders the calls on one stream.
 By default the Adam update runs inside the backward pass (ges_render_backward_adam), so the parameter
 gradients never go through memory.
-Densification, pruning and the opacity/shape resets of the full training loop are not part of the step.
+After the update, every shape_prune_interval iterations the splats whose opacity is below min_opacity or
+whose beta is below min_beta are removed with their moments, and every shape_reset_interval iterations every
+beta goes back to 2 (Sec. 4.4; Sec. 5.2; App. B.2: intervals 100 and 1,000).  When both fall on one
+iteration, pruning comes first, so it sees the learned shapes.  Densification and the opacity reset of the
+full training loop are not part of the step.
 """
 from __future__ import annotations
 
@@ -40,6 +44,11 @@ class TrainConfig:
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-15
+    shape_prune_interval: int = 100        # 0 switches pruning off
+    shape_reset_interval: int = 1000       # 0 switches the reset off
+    min_opacity: float = 0.005
+    min_beta: float = 0.5                  # Sec. 5.2 (App. B.2 gives 0.005)
+    beta_init: float = 2.0
     falloff: int = G.FALLOFF_PHI
     tile_cull: int = G.TILES_ELLIPSE
     rho: float = 0.1
@@ -58,12 +67,10 @@ class TrainStep:
         self.cam = cam
         self.target = target.contiguous()
         dev = target.device
-        self.s = G.splats_struct(*(scene[k] for k in ("means", "log_scales", "quats", "opacity_logits", "sh",
-                                                      "beta")))
         self.c = G.camera_struct(cam)
         self.p = G.params_struct(self.cfg.falloff, self.cfg.tile_cull, self.cfg.rho, self.cfg.bg)
         H, W = cam.height, cam.width
-        self.frame = G.Frame.create(self.s.n, W, H, dev)
+        self._bind_scene()
         self.image = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
         self.dL = torch.empty_like(self.image)
         self.loss = torch.empty((), dtype=torch.float32, device=dev)
@@ -74,6 +81,33 @@ class TrainStep:
         self.grads = None        # parameter gradients, allocated by the first unfused step
         self.exp_avg = {k: torch.zeros_like(v) for k, v in scene.items()}
         self.exp_avg_sq = {k: torch.zeros_like(v) for k, v in scene.items()}
+
+    def _bind_scene(self):
+        """Point the splat descriptor and the frame at the current scene tensors (after creation or pruning)."""
+        self.s = G.splats_struct(*(self.scene[k] for k in G.SPLAT_PARAMS))
+        self.frame = G.Frame.create(self.s.n, self.cam.width, self.cam.height, self.target.device)
+        self.grads = None
+
+    @property
+    def n(self) -> int:
+        return int(self.s.n)
+
+    def prune(self) -> int:
+        """Remove the splats below the opacity or shape bound, with their moments; returns the new count.
+        The scene, moment and frame tensors are replaced (read ``self.scene`` afterwards)."""
+        c = self.cfg
+        src = [self.scene, self.exp_avg, self.exp_avg_sq]
+        dst = [{k: torch.empty_like(v) for k, v in d.items()} for d in src]
+        sh_degree = int(self.s.sh_degree)
+        kept = G.ges_prune_splats(src, dst, sh_degree, c.min_opacity, c.min_beta)
+        if kept == self.n:
+            return kept
+        self.scene, self.exp_avg, self.exp_avg_sq = ({k: v[:kept] for k, v in d.items()} for d in dst)
+        self._bind_scene()
+        return kept
+
+    def shape_reset(self):
+        G.ges_shape_reset(self.scene["beta"], self.exp_avg["beta"], self.exp_avg_sq["beta"], self.cfg.beta_init)
 
     def omega(self, it: int) -> float:
         return min(max(it / self.cfg.total_iterations, 0.0), 1.0)
@@ -121,4 +155,8 @@ class TrainStep:
             groups = [(self.scene[k], self.grads[k], self.exp_avg[k], self.exp_avg_sq[k], lrs[k])
                       for k in GROUP_ORDER]
             G.ges_adam_step(groups, it, c.beta1, c.beta2, c.eps)
+        if c.shape_prune_interval and it % c.shape_prune_interval == 0:
+            self.prune()
+        if c.shape_reset_interval and it % c.shape_reset_interval == 0:
+            self.shape_reset()
         return self.loss

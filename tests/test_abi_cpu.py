@@ -154,3 +154,24 @@ def test_render_backward_adam_validates_before_any_device_work():
     opt.exp_avg_sq[4] = None
     assert lib.ges_render_backward_adam(*args(C.byref(opt))) == 1
     del sc
+
+
+def test_prune_and_reset_validate_before_any_device_work():
+    lib = G.lib()
+    assert lib.ges_prune_scratch_bytes(-1) == 0
+    assert lib.ges_prune_scratch_bytes(3_000_000) >= 8 * (3_000_000 // 256)
+    src = (G.ges_splat_set * 1)()
+    dst = (G.ges_splat_set * 1)()
+    kept = C.c_int64()
+    p = C.c_void_p(1 << 20)
+    assert lib.ges_prune_splats(10, 0, src, dst, 1, 0.005, 0.5, p, 1 << 20, C.byref(kept), None) == 1  # no logits
+    src[0].opacity_logits, src[0].beta = 1 << 21, 1 << 22
+    assert lib.ges_prune_splats(10, 0, src, dst, 1, 0.005, 0.5, p, 1 << 20, C.byref(kept), None) == 1  # NULL dst
+    dst[0].opacity_logits, dst[0].beta = 1 << 23, 1 << 24
+    assert lib.ges_prune_splats(10, 4, src, dst, 1, 0.005, 0.5, p, 1 << 20, C.byref(kept), None) == 1  # degree
+    assert lib.ges_prune_splats(10, 0, src, dst, 4, 0.005, 0.5, p, 1 << 20, C.byref(kept), None) == 1  # nsets
+    assert lib.ges_prune_splats(10, 0, src, dst, 1, 1.5, 0.5, p, 1 << 20, C.byref(kept), None) == 1    # opacity
+    assert lib.ges_prune_splats(10, 0, src, dst, 1, 0.005, float("nan"), p, 1 << 20, C.byref(kept), None) == 1
+    assert lib.ges_prune_splats(10, 0, src, dst, 1, 0.005, 0.5, p, 8, C.byref(kept), None) == 2        # scratch
+    assert lib.ges_shape_reset(None, None, None, 5, 2.0, None) == 1
+    assert lib.ges_shape_reset(p, None, None, 5, float("inf"), None) == 1

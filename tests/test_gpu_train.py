@@ -115,3 +115,34 @@ def test_fused_backward_adam_equals_two_calls(workload, n):
     for k in GROUP_ORDER:
         for a, b in zip(runs[0], runs[1]):
             assert torch.equal(a[k], b[k]), k
+
+
+def test_prune_and_shape_reset_hooks():
+    """The step's hooks on the 1,000-splat workload with betas spread over [0.2, 3]: pruning at iteration 2
+    keeps exactly the splats at or above both bounds (checked on the state just before it), in order and with
+    their moments; the shape reset at iteration 3 sets every beta to 2 and clears its moments; training then
+    goes on with finite losses."""
+    import math
+    cfg_w = synth.make_config(0)
+    sc, cam = cfg_w["scene"], cfg_w["camera"]
+    arrays = {k: np.array(v, np.float32) for k, v in sc.arrays().items()}
+    arrays["beta"] = np.random.default_rng(3).uniform(0.2, 3.0, arrays["beta"].shape).astype(np.float32)
+    cfg = TrainConfig(shape_prune_interval=0, shape_reset_interval=0, min_beta=0.5)
+    ts = TrainStep(to_device(arrays), cam, torch.as_tensor(np.asarray(cfg_w["target"], np.float32)).cuda(), cfg)
+    ts.step(1)
+    ts.step(2)
+    before = {k: v.cpu().numpy().copy() for k, v in ts.scene.items()}
+    m_before = {k: v.cpu().numpy().copy() for k, v in ts.exp_avg.items()}
+    kept = ts.prune()
+    bound = math.log(cfg.min_opacity / (1 - cfg.min_opacity))
+    keep = ~(before["opacity_logits"].astype(np.float64) < bound) & ~(before["beta"].astype(np.float64) < 0.5)
+    assert kept == int(keep.sum()) == ts.n and 0 < kept < len(keep)
+    for k in G.SPLAT_PARAMS:
+        assert np.array_equal(ts.scene[k].cpu().numpy(), before[k][keep]), k
+        assert np.array_equal(ts.exp_avg[k].cpu().numpy(), m_before[k][keep]), k
+    ts.cfg.shape_reset_interval = 3
+    loss = float(ts.step(3).cpu())
+    torch.cuda.synchronize()
+    assert torch.all(ts.scene["beta"] == 2.0) and not ts.exp_avg["beta"].any() and not ts.exp_avg_sq["beta"].any()
+    losses = [loss] + [float(ts.step(it).cpu()) for it in (4, 5)]
+    assert all(np.isfinite(losses))
