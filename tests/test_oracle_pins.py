@@ -676,3 +676,55 @@ def test_shape_reset_restores_gaussian_and_clears_moments():
     from oracle import prune as OPR
     b, m, v = OPR.shape_reset(np.array([0.3, 5.0], np.float32), np.ones(2, np.float32), np.ones(2, np.float32))
     assert list(b) == [2.0, 2.0] and not m.any() and not v.any()
+
+
+# ---- 1-D mixture simulation (Sec. 3.2; App. A.3)
+@pytest.mark.parametrize("kind", ["gmm", "dog", "log", "gef"])
+@pytest.mark.parametrize("positive", [True, False], ids=["pos", "free"])
+def test_mixture_gradient_matches_central_differences(kind, positive):
+    from oracle import mixture1d as MX
+    rng = np.random.default_rng(hash((kind, positive)) % 2 ** 32)
+    x = np.linspace(-3.0, 3.0, 41) + 0.0123           # no grid point on a mean
+    y = np.sin(x)
+    theta = np.stack([rng.normal(0, 1, 5), rng.uniform(-2, 2, 5), rng.uniform(0.4, 1.5, 5),
+                      rng.uniform(1.2, 3.0, 5)], axis=1)
+    _, g = MX.loss_and_grad(kind, x, y, theta, positive)
+    h = 1e-6
+    for i in range(5):
+        for k in range(4):
+            tp, tm = theta.copy(), theta.copy()
+            tp[i, k] += h
+            tm[i, k] -= h
+            fd = (MX.loss_and_grad(kind, x, y, tp, positive)[0] - MX.loss_and_grad(kind, x, y, tm, positive)[0]) / (2 * h)
+            assert abs(fd - g[i, k]) <= 1e-7 * max(1.0, abs(fd)), (kind, i, k, fd, g[i, k])
+
+
+def test_mixture_closed_forms():
+    """GEF at beta = 2 is the GMM (values and gradients, App. A.3); the LoG equals its weight at its mean;
+    the DoG's integral is w (sqrt(pi S1) - sqrt(pi S2)) with S1 = 2 s^2 + eps, S2 = 2 s^2 / 4 + eps."""
+    from oracle import mixture1d as MX
+    rng = np.random.default_rng(9)
+    x = np.linspace(-4, 4, 101) + 0.01
+    theta = np.stack([rng.normal(size=4), rng.uniform(-1, 1, 4), rng.uniform(0.5, 1, 4), np.full(4, 2.0)], 1)
+    cg, gg = MX.components("gmm", x, theta, False)
+    ce, ge = MX.components("gef", x, theta, False)
+    assert np.allclose(cg, ce, rtol=1e-14, atol=0) and np.allclose(gg[..., :3], ge[..., :3], rtol=1e-12, atol=1e-15)
+    c, _ = MX.components("log", np.array([0.3]), np.array([[1.7, 0.3, 0.8, 2.0]]), False)
+    assert c[0, 0] == 1.7
+    xs = np.linspace(-40, 40, 400001)
+    c, _ = MX.components("dog", xs, np.array([[1.3, 0.2, 0.9, 2.0]]), False)
+    S1, S2 = 2 * 0.81 + 1e-8, 2 * 0.81 / 4 + 1e-8
+    integral = float(np.sum((c[1:, 0] + c[:-1, 0]) * 0.5 * np.diff(xs)))
+    assert abs(integral - 1.3 * (np.sqrt(np.pi * S1) - np.sqrt(np.pi * S2))) < 1e-9
+
+
+def test_mixture_fit_recovers_a_gaussian():
+    """One GMM component fitted to the Gaussian signal exp(-x^2 / (2 width^2)) (App. A.3) from a nearby start
+    converges to it: weight 1, mean 0, s = width."""
+    from oracle import gef1d
+    from oracle import mixture1d as MX
+    x = np.linspace(-5, 5, 200)
+    y = gef1d.signal("gaussian", x, 1.0)
+    theta, losses, final = MX.fit("gmm", x, y, np.array([[0.7, 0.3, 1.4, 2.0]]), False, 3000, 0.01)
+    assert final < 1e-8 and losses[0] > 1e-2
+    assert np.allclose(theta[0, :3], [1.0, 0.0, 1.0], atol=1e-3)
