@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--falloff", choices=["phi", "gef"], default="phi")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
+    ap.add_argument("--no-mixture", action="store_true", help="skip the 1-D mixture-simulation sweep")
+    ap.add_argument("--mixture-epochs", type=int, default=1000)
     ap.add_argument("--no-train-step", action="store_true",
                     help="skip the full optimisation-step measurement (adds SSIM, per-step mask and Adam)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
@@ -283,6 +285,68 @@ def train_step_bench(dev, cfg, falloff, tile_cull, nsteps, warmup):
     return out
 
 
+def mixture_bench(dev, epochs, log_fn):
+    """The paper's 1-D mixture sweep (4 models x 6 signals x 8 N x 20 runs x 2 weight modes on 1,000
+    points) in one launch; reports problem-epochs/s, NaN runs and mean final losses per model, and the oracle's
+    rate on a bounded sample."""
+    import torch
+    from paper_2402_10128_amd import ges as G
+    from paper_2402_10128_amd import synth
+    W = synth.mixture_workload(seed=0)
+    P = len(W["problems"])
+    probs = torch.from_numpy(W["problems"]).to(dev)
+    tg = torch.from_numpy(W["targets"]).to(dev)
+    par0 = torch.from_numpy(W["params"]).to(dev)
+    par = par0.clone()
+    G.ges_mix_fit(probs, tg, W["x0"], W["dx"], par, 10, 0.01)      # warm-up (short)
+    par.copy_(par0)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    loss = G.ges_mix_fit(probs, tg, W["x0"], W["dx"], par, epochs, 0.01)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    loss = loss.cpu().numpy()
+    pr = W["problems"]
+    names = ["gmm", "dog", "log", "gef"]
+    per_model = {}
+    for k, name in enumerate(names):
+        sel = pr[:, 0] == k
+        fin = np.isfinite(loss[sel])
+        per_model[name] = {"nan_runs": int((~fin).sum()), "runs": int(sel.sum()),
+                           "mean_final_mse": float(np.mean(loss[sel][fin])) if fin.any() else None}
+    # square signal (target 0), positive weights: mean final MSE per N, the paper's headline comparison
+    square = {}
+    for k, name in enumerate(names):
+        row = {}
+        for n in synth.MIX_NS:
+            sel = (pr[:, 0] == k) & (pr[:, 1] == n) & (pr[:, 3] == 0) & (pr[:, 2] == 1)
+            v = loss[sel]
+            v = v[np.isfinite(v)]
+            row[str(n)] = float(np.mean(v)) if len(v) else None
+        square[name] = row
+    # oracle on this host: a sample of problems for a few epochs, scaled to problem-epochs/s
+    from oracle import mixture1d as MX
+    x = W["x0"] + W["dx"] * np.arange(W["m"], dtype=np.float64)
+    rng = np.random.default_rng(0)
+    sample = rng.choice(P, 24, replace=False)
+    t0 = time.perf_counter()
+    pe = 0
+    for p in sample:
+        model, n, pos, tgt = (int(v) for v in pr[p])
+        MX.fit(names[model], x, W["targets"][tgt].astype(np.float64), W["params"][p, :n].astype(np.float64),
+               bool(pos), 20, 0.01)
+        pe += 20
+    cpu_rate = pe / (time.perf_counter() - t0)
+    log_fn(f"mixture sweep: {P} problems x {epochs} epochs in {ms:.1f} ms")
+    return {"problems": P, "epochs": epochs, "points": W["m"], "ms": round(ms, 3),
+            "problem_epochs_per_s": round(P * epochs / (ms / 1e3), 1), "per_model": per_model,
+            "square_positive_mean_final_mse_by_n": square,
+            "cpu_baseline": {"value": round(cpu_rate, 2), "unit": "problem-epochs/s", "kind": "oracle",
+                             "sample": "24 random problems of the sweep, 20 epochs each, binary64 numpy"}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -415,6 +479,10 @@ def main():
         log("optimisation step (mask + render + L1/SSIM/frequency loss + adjoint + Adam)")
         train = train_step_bench(dev, cfg, falloff, tile_cull, args.steps, args.warmup)
         log(f"optimisation step {train['ms_per_step']:.3f} ms: " + json.dumps(train["stage_ms_per_launch"]))
+    mixture = None
+    if not args.no_mixture:
+        log("1-D mixture sweep")
+        mixture = mixture_bench(dev, args.mixture_epochs, log)
     serving = None
     if not args.no_serving:
         log("serving (workload 4)")
@@ -451,6 +519,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "train_step": train,
+        "mixture_sweep": mixture,
         "serving": serving,
     }
     print(json.dumps(res), flush=True)

@@ -189,7 +189,7 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
  * costs two event records per launch. */
 enum { GES_STAGE_PREPROCESS = 0, GES_STAGE_BIN_COUNT, GES_STAGE_BIN_SCAN, GES_STAGE_BIN_SCATTER, GES_STAGE_TILE_SORT,
        GES_STAGE_RASTER_FORWARD, GES_STAGE_RASTER_BACKWARD, GES_STAGE_PREPROCESS_BACKWARD, GES_STAGE_ZERO,
-       GES_STAGE_LOSS, GES_STAGE_ADAM, GES_STAGE_SSIM, GES_NUM_STAGES };
+       GES_STAGE_LOSS, GES_STAGE_ADAM, GES_STAGE_SSIM, GES_STAGE_MIX_FIT, GES_NUM_STAGES };
 ges_status ges_profile_enable(int32_t on);
 /* Time only the stages whose bit (1 << GES_STAGE_*) is set; 0 switches timing off. */
 ges_status ges_profile_select(uint32_t stage_mask);
@@ -307,6 +307,37 @@ ges_status ges_prune_splats(int64_t n, int32_t sh_degree, const ges_splat_set* s
                             int32_t nsets, double min_opacity, double min_beta, void* scratch, size_t scratch_bytes,
                             int64_t* n_kept, void* stream);
 ges_status ges_shape_reset(float* beta, float* exp_avg, float* exp_avg_sq, int64_t n, float value, void* stream);
+
+/* ---- the 1-D mixture simulation (Sec. 3.2; App. A.3) ---------------------------------
+ * Fits mixtures of n components to 1-D signals by Adam on the mean squared error over a
+ * linspace x_j = x0 + j dx, j < m, one problem per workgroup, all problems in one launch:
+ *   GMM  sum_i w_i exp(-(x-mu_i)^2 / (2 s_i^2 + 1e-8))                     (Eq. gaussianmixture)
+ *   DoG  sum_i w_i [exp(-(x-mu_i)^2 / (2 s_i^2 + 1e-8)) - exp(-(x-mu_i)^2 / (2 s_i^2/4 + 1e-8))]
+ *   LoG  sum_i w_i (1 - (x-mu_i)^2 / s_i^2) exp(-(x-mu_i)^2 / (2 s_i^2 + 1e-8))
+ *   GEF  sum_i w_i exp(-|x-mu_i|^beta_i / (2 s_i^2 + 1e-8))                 (Eq. genmixture)
+ * Component i's parameters are params[p][i][0..3] = (w_raw, mu, s, beta), w = w_raw or, with
+ * `positive`, softplus(w_raw); beta is used by GEF only (its gradient is 0 for the others).
+ * At x = mu the GEF derivatives w.r.t. mu and beta are taken as 0.  Computed in binary32.
+ * `problems` is a DEVICE array; a problem with n outside 1..GES_MIX_MAX_COMPONENTS, an unknown
+ * model or a target row outside 0..ntargets-1 is not run and gets a NaN loss.  params
+ * [nproblems][GES_MIX_MAX_COMPONENTS][4]: the initial values in, the values after `epochs`
+ * Adam steps out (rows i >= n untouched).  grad_out (same shape, may be NULL) receives the
+ * gradient at the initial values; final_loss[p] the MSE after the last step (NaN: the run
+ * diverged).  targets: device [ntargets][m].  Errors: GES_ERR_INVALID_ARGUMENT for NULL
+ * problems/targets/params/final_loss with nproblems > 0, m outside 1..GES_MIX_MAX_POINTS,
+ * epochs < 0, non-finite x0/dx/lr/eps, lr or eps < 0, or b1/b2 outside [0,1). */
+#define GES_MIX_MAX_COMPONENTS 128
+#define GES_MIX_MAX_POINTS 4096
+enum { GES_MIX_GMM = 0, GES_MIX_DOG = 1, GES_MIX_LOG = 2, GES_MIX_GEF = 3 };
+typedef struct {
+  int32_t model;                 /* GES_MIX_* */
+  int32_t n;                     /* components */
+  int32_t positive;              /* 1: weights through softplus */
+  int32_t target;                /* row of `targets` to fit */
+} ges_mix_problem;
+ges_status ges_mix_fit(const ges_mix_problem* problems, int32_t nproblems, const float* targets, int32_t ntargets,
+                       int32_t m, float x0, float dx, float* params, float* grad_out, float* final_loss,
+                       int32_t epochs, float lr, float beta1, float beta2, float eps, void* stream);
 
 /* Learning rate at `step` of a log-linear decay from lr_init (step 0) to lr_final (step
  * max_steps, constant afterwards), times a delay factor that rises from delay_mult to 1

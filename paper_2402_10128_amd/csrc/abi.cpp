@@ -463,6 +463,27 @@ ges_status ges_shape_reset(float* beta, float* exp_avg, float* exp_avg_sq, int64
   return GES_OK;
 }
 
+ges_status ges_mix_fit(const ges_mix_problem* problems, int32_t nproblems, const float* targets, int32_t ntargets,
+                       int32_t m, float x0, float dx, float* params, float* grad_out, float* final_loss,
+                       int32_t epochs, float lr, float beta1, float beta2, float eps, void* stream) {
+  if (nproblems < 0) return fail(GES_ERR_INVALID_ARGUMENT, "nproblems < 0");
+  if (nproblems > 0 && (!problems || !targets || !params || !final_loss))
+    return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (m < 1 || m > GES_MIX_MAX_POINTS) return fail(GES_ERR_INVALID_ARGUMENT, "m outside 1..4096");
+  if (ntargets < 1) return fail(GES_ERR_INVALID_ARGUMENT, "ntargets < 1");
+  if (epochs < 0) return fail(GES_ERR_INVALID_ARGUMENT, "epochs < 0");
+  if (!std::isfinite(x0) || !std::isfinite(dx) || !std::isfinite(lr) || !std::isfinite(eps) || lr < 0.f || eps < 0.f)
+    return fail(GES_ERR_INVALID_ARGUMENT, "bad x0/dx/lr/eps");
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+    return fail(GES_ERR_INVALID_ARGUMENT, "beta outside [0,1)");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  GES_CHECK_HIP(timed(GES_STAGE_MIX_FIT, st, [&] {
+                  return ges::launch_mix_fit(problems, nproblems, targets, ntargets, m, x0, dx, params, grad_out,
+                                             final_loss, epochs, lr, beta1, beta2, eps, st);
+                }), "mix_fit");
+  return GES_OK;
+}
+
 double ges_expon_lr(int64_t step, double lr_init, double lr_final, int64_t max_steps, int64_t delay_steps,
                     double delay_mult) {
   if (!(lr_init > 0.0) || !(lr_final > 0.0) || max_steps < 1) return std::nan("");

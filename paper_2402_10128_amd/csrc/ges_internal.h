@@ -158,6 +158,9 @@ hipError_t launch_prune(const float* const* src, float* const* dst, const int32_
                         const float* beta, int64_t n, double logit_bound, double min_beta, void* scratch,
                         int64_t* total_dev, hipStream_t stream);
 hipError_t launch_shape_reset(float* beta, float* m, float* v, int64_t n, float value, hipStream_t stream);
+hipError_t launch_mix_fit(const ges_mix_problem* problems, int nproblems, const float* targets, int ntargets, int m,
+                          float x0, float dx, float* params, float* grad_out, float* final_loss, int epochs, float lr,
+                          float b1, float b2, float eps, hipStream_t stream);
 hipError_t launch_adam(const ges_adam_group* groups, int ngroups, int64_t step, float b1, float b2, float eps,
                        hipStream_t stream);
 

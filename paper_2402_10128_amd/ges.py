@@ -76,6 +76,10 @@ class ges_splat_set(C.Structure):
                 ("opacity_logits", C.c_void_p), ("sh", C.c_void_p), ("beta", C.c_void_p)]
 
 
+class ges_mix_problem(C.Structure):
+    _fields_ = [("model", C.c_int32), ("n", C.c_int32), ("positive", C.c_int32), ("target", C.c_int32)]
+
+
 class ges_request_info(C.Structure):
     _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("t_submit_ns", C.c_uint64), ("t_start_ns", C.c_uint64),
                 ("t_done_ns", C.c_uint64), ("num_keys", C.c_uint64), ("batch_size", C.c_int32)]
@@ -115,6 +119,9 @@ _SIGS = {
     "ges_prune_splats": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(ges_splat_set), C.POINTER(ges_splat_set), C.c_int32,
                                    C.c_double, C.c_double, C.c_void_p, C.c_size_t, C.POINTER(C.c_int64), C.c_void_p]),
     "ges_shape_reset": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p]),
+    "ges_mix_fit": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_float,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_float, C.c_float,
+                              C.c_float, C.c_void_p]),
     "ges_adam_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "ges_expon_lr": (C.c_double, [C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_double]),
     "ges_serve_create": (C.c_int, [C.POINTER(ges_serve_config), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
@@ -237,7 +244,7 @@ def ges_frame_view_get(n, width, height, splat_ws, key_ws, num_keys, pixel_ws) -
 
 
 STAGES = ["preprocess", "bin_count", "bin_scan", "bin_scatter", "tile_sort", "raster_forward", "raster_backward",
-          "preprocess_backward", "zero", "loss", "adam", "ssim"]
+          "preprocess_backward", "zero", "loss", "adam", "ssim", "mix_fit"]
 
 
 def ges_profile_enable(on: bool):
@@ -355,6 +362,27 @@ def ges_prune_splats(src_sets: list, dst_sets: list, sh_degree: int, min_opacity
 def ges_shape_reset(beta, exp_avg=None, exp_avg_sq=None, value=2.0, stream=None):
     _check(lib().ges_shape_reset(_ptr(beta), _ptr(exp_avg), _ptr(exp_avg_sq), int(beta.numel()), float(value),
                                  _stream(stream)))
+
+
+MIX_MODELS = {"gmm": 0, "dog": 1, "log": 2, "gef": 3}
+MIX_MAX_COMPONENTS = 128
+
+
+def ges_mix_fit(problems, targets, x0, dx, params, epochs, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_out=None,
+                final_loss=None, stream=None):
+    """problems: int32 CUDA tensor [P, 4] (model, n, positive, target); targets [T, m]; params [P, 128, 4]
+    updated in place.  Returns final_loss [P]."""
+    P = int(problems.shape[0])
+    if problems.dtype != torch.int32 or problems.dim() != 2 or problems.shape[1] != 4 or not problems.is_contiguous():
+        raise ValueError("problems must be a contiguous int32 [P, 4] tensor")
+    if params.shape != (P, MIX_MAX_COMPONENTS, 4) or params.dtype != torch.float32 or not params.is_contiguous():
+        raise ValueError("params must be a contiguous float32 [P, 128, 4] tensor")
+    if final_loss is None:
+        final_loss = torch.empty(P, dtype=torch.float32, device=params.device)
+    _check(lib().ges_mix_fit(_ptr(problems), P, _ptr(targets), int(targets.shape[0]), int(targets.shape[1]),
+                             float(x0), float(dx), _ptr(params), _ptr(grad_out), _ptr(final_loss), int(epochs),
+                             float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+    return final_loss
 
 
 def ges_expon_lr(step, lr_init, lr_final, max_steps, delay_steps=0, delay_mult=1.0) -> float:

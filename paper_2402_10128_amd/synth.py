@@ -257,3 +257,55 @@ def serving_requests(n_req: int, n_scenes: int, resolutions, seed: int = 2000):
         w, h = resolutions[int(rng.integers(0, len(resolutions)))]
         out.append((s, orbit_camera(np.random.default_rng(seed + 1 + i), w, h)))
     return out
+
+
+# ---- the 1-D mixture simulation (Sec. 3.2; App. A.3) ------------------------------------------------
+MIX_SIGNALS = ("square", "triangle", "parabolic", "half_sinusoid", "gaussian", "exponential")
+MIX_MODEL_IDS = {"gmm": 0, "dog": 1, "log": 2, "gef": 3}
+MIX_NS = (2, 5, 8, 10, 15, 20, 50, 100)
+
+
+def mixture_signals(x: np.ndarray, width: float) -> np.ndarray:
+    """The six ground-truth signals of App. A.3 on the grid x, [6, len(x)] binary32: square, triangle and
+    parabola of support (-width/2, width/2), a half period of a sine over that support, a Gaussian of standard
+    deviation `width` and exp(-|x|) over the support."""
+    x = np.asarray(x, np.float64)
+    half = width / 2.0
+    inside = (x > -half) & (x < half)
+    rows = [inside.astype(np.float64),
+            np.where(inside, half - np.abs(x), 0.0),
+            np.where(inside, half * half - x * x, 0.0),
+            np.where(inside, np.sin((x + half) * math.pi / width), 0.0),
+            np.exp(-(x * x) / (2.0 * width * width)),
+            np.where(inside, np.exp(-np.abs(x)), 0.0)]
+    return np.stack(rows).astype(np.float32)
+
+
+def mixture_workload(seed: int = 0, models=("gmm", "dog", "log", "gef"), ns=MIX_NS, runs: int = 20,
+                     weights=("positive", "free"), m: int = 1000, x_range=(-5.0, 5.0), width: float = 2.0):
+    """Problems of the 1-D simulation: every model x signal x N x run x weight mode.
+
+    Returns dict(problems [P, 4] int32 (model, n, positive, target), targets [6, m], params [P, 128, 4]
+    binary32 initial values, x0, dx, and the recipe).  Initial values per component: w_raw ~ N(0, 0.5),
+    mu ~ U(-2, 2), s ~ U(0.2, 1.0), beta = 2 (every GEF starts Gaussian); one seeded draw per run."""
+    rng = np.random.default_rng(seed)
+    x0, x1 = x_range
+    dx = (x1 - x0) / (m - 1) if m > 1 else 0.0
+    x = x0 + dx * np.arange(m, dtype=np.float64)
+    targets = mixture_signals(x, width)
+    probs, params = [], []
+    for model in models:
+        for sig in range(len(MIX_SIGNALS)):
+            for n in ns:
+                for run in range(runs):
+                    for mode in weights:
+                        th = np.zeros((128, 4), np.float32)
+                        th[:n, 0] = rng.normal(0.0, 0.5, n)
+                        th[:n, 1] = rng.uniform(-2.0, 2.0, n)
+                        th[:n, 2] = rng.uniform(0.2, 1.0, n)
+                        th[:n, 3] = 2.0
+                        probs.append((MIX_MODEL_IDS[model], n, 1 if mode == "positive" else 0, sig))
+                        params.append(th)
+    return dict(problems=np.array(probs, np.int32).reshape(-1, 4), targets=targets,
+                params=np.array(params, np.float32).reshape(-1, 128, 4), x0=float(x0), dx=float(dx), m=m,
+                x=x, width=width)

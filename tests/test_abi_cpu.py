@@ -175,3 +175,14 @@ def test_prune_and_reset_validate_before_any_device_work():
     assert lib.ges_prune_splats(10, 0, src, dst, 1, 0.005, 0.5, p, 8, C.byref(kept), None) == 2        # scratch
     assert lib.ges_shape_reset(None, None, None, 5, 2.0, None) == 1
     assert lib.ges_shape_reset(p, None, None, 5, float("inf"), None) == 1
+
+
+def test_mix_fit_validates_before_any_device_work():
+    lib = G.lib()
+    p = C.c_void_p(1 << 20)
+    ok = (p, 1, p, 1, 100, -5.0, 0.1, p, None, p, 10, 0.01, 0.9, 0.999, 1e-8, None)
+    for pos, bad in [(0, None), (1, -1), (4, 0), (4, 5000), (3, 0), (10, -1), (11, float("nan")), (12, 1.0),
+                     (14, -1.0), (6, float("inf"))]:
+        args = list(ok)
+        args[pos] = bad
+        assert lib.ges_mix_fit(*args) == 1, (pos, bad)

@@ -1,0 +1,77 @@
+"""The batched 1-D mixture fit (Sec. 3.2; App. A.3) against the binary64 oracle.
+
+Tolerances (binary32 kernel): the gradient at the initial values sums m terms of rounding ~1e-7 relative,
+so it is compared to 1e-4 of the problem's largest gradient; over the first 5 Adam epochs every step moves a
+parameter by at most lr and its direction is settled where the gradient is, so parameters agree to 1e-4 and
+losses to 1e-4 relative.  Longer fits are not compared step for step: Adam's sign-like first steps make
+trajectories whose gradients pass through zero drift apart (about 1e-3 relative in loss by 100 epochs)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mixture1d as MX
+from paper_2402_10128_amd import ges as G
+from paper_2402_10128_amd import synth
+
+pytestmark = pytest.mark.gpu
+NAMES = ["gmm", "dog", "log", "gef"]
+LR = 0.01
+B1, B2, EPS = (float(np.float32(v)) for v in (0.9, 0.999, 1e-8))
+
+
+def _run(W, epochs, problems=None):
+    dev = torch.device("cuda:0")
+    probs = torch.from_numpy(W["problems"] if problems is None else problems).to(dev)
+    tg = torch.from_numpy(W["targets"]).to(dev)
+    par = torch.from_numpy(W["params"]).to(dev)
+    grad = torch.full_like(par, float("nan"))
+    loss = G.ges_mix_fit(probs, tg, W["x0"], W["dx"], par, epochs, LR, 0.9, 0.999, 1e-8, grad_out=grad)
+    torch.cuda.synchronize()
+    return par.cpu().numpy(), grad.cpu().numpy(), loss.cpu().numpy()
+
+
+def _compare(W, idx, par, grad, loss, epochs):
+    x = W["x0"] + W["dx"] * np.arange(W["m"], dtype=np.float64)
+    for p in idx:
+        model, n, pos, tgt = (int(v) for v in W["problems"][p])
+        th0 = W["params"][p, :n].astype(np.float64)
+        y = W["targets"][tgt].astype(np.float64)
+        _, g = MX.loss_and_grad(NAMES[model], x, y, th0, bool(pos))
+        assert np.abs(grad[p, :n] - g).max() <= 1e-4 * np.abs(g).max(), (p, NAMES[model], n)
+        th, _, final = MX.fit(NAMES[model], x, y, th0, bool(pos), epochs, float(np.float32(LR)), B1, B2, EPS)
+        assert np.abs(par[p, :n] - th).max() <= 1e-4, (p, NAMES[model], n)
+        assert abs(loss[p] - final) <= 1e-4 * final + 1e-9, (p, NAMES[model], n, loss[p], final)
+        assert np.array_equal(par[p, n:], W["params"][p, n:])   # rows past n untouched
+
+
+def test_mixture_small_batch_all_models():
+    W = synth.mixture_workload(seed=1, ns=(2, 5, 20), runs=1, m=200)
+    par, grad, loss = _run(W, 5)
+    _compare(W, range(len(W["problems"])), par, grad, loss, 5)
+
+
+def test_mixture_full_sweep_sampled():
+    """The paper's whole sweep (4 models x 6 signals x 8 N x 20 runs x 2 weight modes = 7,680 problems on
+    1,000 points) in one launch, 5 epochs, 48 sampled problems against the oracle."""
+    W = synth.mixture_workload(seed=0)
+    assert len(W["problems"]) == 7680
+    par, grad, loss = _run(W, 5)
+    idx = np.random.default_rng(5).choice(len(W["problems"]), 48, replace=False)
+    _compare(W, idx, par, grad, loss, 5)
+
+
+def test_mixture_edges_and_invalid_rows():
+    """One point; 128 components; rows with n = 0, n = 129, an unknown model or target get a NaN loss and
+    leave their parameters alone; the run is deterministic."""
+    W = synth.mixture_workload(seed=2, ns=(128,), runs=1, models=("gef", "gmm"), m=64)
+    par, grad, loss = _run(W, 3)
+    _compare(W, range(0, len(W["problems"]), 7), par, grad, loss, 3)
+    par2, _, loss2 = _run(W, 3)
+    assert np.array_equal(par, par2) and np.array_equal(loss, loss2)
+    W1 = synth.mixture_workload(seed=3, ns=(2,), runs=1, models=("log",), m=1)
+    par, grad, loss = _run(W1, 4)
+    _compare(W1, range(len(W1["problems"])), par, grad, loss, 4)
+    bad = W["problems"][:4].copy()
+    bad[0, 1], bad[1, 1], bad[2, 0], bad[3, 3] = 0, 129, 7, 9
+    par, _, loss = _run({**W, "params": W["params"][:4]}, 3, problems=bad)
+    assert np.isnan(loss).all() and np.array_equal(par, W["params"][:4])
