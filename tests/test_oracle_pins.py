@@ -728,3 +728,54 @@ def test_mixture_fit_recovers_a_gaussian():
     theta, losses, final = MX.fit("gmm", x, y, np.array([[0.7, 0.3, 1.4, 2.0]]), False, 3000, 0.01)
     assert final < 1e-8 and losses[0] > 1e-2
     assert np.allclose(theta[0, :3], [1.0, 0.0, 1.0], atol=1e-3)
+
+
+# ---- densification kept from Gaussian splatting (Sec. 5.2; App. B.2)
+def test_densify_hand_example():
+    """Four splats, threshold 0.0003, scale bound 0.05: splat 0 never visible (kept), 1 below the threshold
+    (kept), 2 small and above it (cloned), 3 large and above it (split into two children at mu + R(s z)
+    with log-scales reduced by ln 1.6).  Order: 0, 1, 2, clone of 2, children of 3; new moments are zero."""
+    from oracle import densify as OD
+    ls = np.log(np.array([[0.1, 0.1, 0.1], [0.02, 0.02, 0.02], [0.03, 0.01, 0.02], [0.2, 0.05, 0.05]]))
+    q = np.array([[1, 0, 0, 0], [1, 0, 0, 0], [1, 0, 0, 0], [0.7071067811865476, 0, 0, 0.7071067811865476]])
+    arrays = {"means": np.arange(12, dtype=np.float64).reshape(4, 3), "log_scales": ls, "quats": q,
+              "opacity_logits": np.array([0.1, 0.2, 0.3, 0.4]), "beta": np.array([2.0, 1.5, 1.0, 3.0])}
+    mom = {k: np.ones_like(v) for k, v in arrays.items()}
+    accum = np.array([0.0, 0.0002 * 4, 0.0003 * 3, 0.001 * 5])
+    count = np.array([0.0, 4.0, 3.0, 5.0])
+    z = np.zeros((4, 2, 3))
+    z[3, 0] = [1.0, 0.0, 0.0]
+    z[3, 1] = [0.0, -2.0, 0.0]
+    out, (om,), kind = OD.densify(arrays, [mom], accum, count, z, 0.0003, 0.05)
+    assert list(kind) == [0, 0, 1, 2]
+    assert np.array_equal(out["opacity_logits"], [0.1, 0.2, 0.3, 0.3, 0.4, 0.4])
+    # a quarter turn about z maps the x-axis offset 0.2 to +y and the y-axis offset -2 * 0.05 to +x
+    assert np.allclose(out["means"][4], [9.0, 10.2, 11.0]) and np.allclose(out["means"][5], [9.1, 10.0, 11.0])
+    assert np.allclose(out["log_scales"][4], ls[3] - np.log(1.6))
+    assert np.array_equal(om["beta"], [1, 1, 1, 0, 0, 0])
+
+
+def test_densify_split_children_sample_the_splat():
+    """Children drawn with many normal samples have the splat's covariance R S^2 R^T around its mean."""
+    from oracle import densify as OD
+    rng = np.random.default_rng(7)
+    n = 20000
+    q = np.array([0.9, 0.3, -0.2, 0.25])
+    ls = np.log([0.3, 0.1, 0.05])
+    arrays = {"means": np.tile([1.0, 2.0, 3.0], (n, 1)), "log_scales": np.tile(ls, (n, 1)), "quats": np.tile(q, (n, 1))}
+    out, _, kind = OD.densify(arrays, [], np.ones(n), np.ones(n), rng.standard_normal((n, 2, 3)), 0.5, 0.01)
+    assert (kind == 2).all() and len(out["means"]) == 2 * n
+    R = OD._rotation(q)
+    want = R @ np.diag(np.exp(2 * ls)) @ R.T
+    d = out["means"] - [1.0, 2.0, 3.0]
+    assert np.allclose(np.cov(d.T), want, atol=2e-3) and np.allclose(d.mean(0), 0.0, atol=3e-3)
+
+
+def test_ndc_statistic_and_opacity_reset():
+    from oracle import densify as OD
+    assert np.isclose(OD.ndc_grad_norm(np.array([3e-4]), np.array([4e-4]), 2, 2)[0], 5e-4)
+    acc, cnt = OD.accumulate(np.zeros(3), np.zeros(3), np.array([1.0, 1.0, 1.0]), np.zeros(3),
+                             np.array([True, False, True]), 100, 50)
+    assert list(acc) == [50.0, 0.0, 50.0] and list(cnt) == [1.0, 0.0, 1.0]
+    op, m, v = OD.opacity_reset(np.array([-6.0, 0.0, 3.0]), np.ones(3), np.ones(3))
+    assert np.allclose(1 / (1 + np.exp(-op)), [1 / (1 + np.exp(6.0)), 0.01, 0.01]) and not m.any() and not v.any()
