@@ -269,6 +269,9 @@ typedef struct {
   float lr[6];                   /* learning rate of each parameter array */
   int64_t step;                  /* Adam step t >= 1 */
   float beta1, beta2, eps;
+  float* grad_accum;             /* [n] densification statistic, or NULL: every visible splat adds the norm of its
+                                    mean-2D gradient in NDC units, ||(dL/du W/2, dL/dv H/2)|| ... */
+  float* grad_count;             /* [n] ... and 1 here (both NULL or both set) */
 } ges_adam_splats;
 ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
                                     void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
@@ -338,6 +341,30 @@ typedef struct {
 ges_status ges_mix_fit(const ges_mix_problem* problems, int32_t nproblems, const float* targets, int32_t ntargets,
                        int32_t m, float x0, float dx, float* params, float* grad_out, float* final_loss,
                        int32_t epochs, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* ---- densification kept from Gaussian splatting (Sec. 5.2; App. B.2) ---------------
+ * ges_densify classifies each splat from its statistic (ges_adam_splats.grad_accum /
+ * grad_count): selected when accum/count (0 if never visible) >= grad_threshold (0.0003),
+ * then cloned when its largest log-scale <= ln(scale_threshold) (percent_dense 0.01 times
+ * the scene extent) and split otherwise (tests in binary64).  dst[k] receives, for every
+ * set k < nsets, the unsplit splats in order, then one clone per cloned splat, then two
+ * children per split splat: means mu + R(q)(s * z_c) with z = normals[i][c][0..2] (given
+ * standard normal draws, [n][2][3]), log-scales reduced by ln 1.6, the other parameters
+ * copied.  Set 0 is the parameters (all six arrays required); sets 1, 2 are moments, copied
+ * for the unsplit splats and zero for clones and children.  *n_out (host) receives the new
+ * count (the call waits for `stream` after counting); when it exceeds dst_capacity nothing
+ * is written and GES_ERR_CAPACITY is returned (n_out still set).  scratch:
+ * ges_densify_scratch_bytes(n) bytes.  dst must not overlap src.
+ *
+ * ges_opacity_reset lowers every opacity above max_opacity (0.01) to it, on the logit
+ * (compared in binary64), and clears the moments (either may be NULL). */
+size_t ges_densify_scratch_bytes(int64_t n);
+ges_status ges_densify(int64_t n, int32_t sh_degree, const ges_splat_set* src, const ges_splat_set* dst,
+                       int32_t nsets, int64_t dst_capacity, const float* grad_accum, const float* grad_count,
+                       const float* normals, double grad_threshold, double scale_threshold, void* scratch,
+                       size_t scratch_bytes, int64_t* n_out, void* stream);
+ges_status ges_opacity_reset(float* opacity_logits, float* exp_avg, float* exp_avg_sq, int64_t n, double max_opacity,
+                             void* stream);
 
 /* Learning rate at `step` of a log-linear decay from lr_init (step 0) to lr_final (step
  * max_steps, constant afterwards), times a delay factor that rises from delay_mult to 1

@@ -272,6 +272,12 @@ ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* 
   a.b2 = opt->beta2;
   a.eps = opt->eps;
   a.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(bc2));
+  if ((opt->grad_accum == nullptr) != (opt->grad_count == nullptr))
+    return fail(GES_ERR_INVALID_ARGUMENT, "grad_accum and grad_count go together");
+  a.stat_accum = opt->grad_accum;
+  a.stat_count = opt->grad_count;
+  a.half_w = cam ? 0.5 * (double)cam->width : 0.0;
+  a.half_h = cam ? 0.5 * (double)cam->height : 0.0;
   return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, &a, stream);
 }
 
@@ -481,6 +487,70 @@ ges_status ges_mix_fit(const ges_mix_problem* problems, int32_t nproblems, const
                   return ges::launch_mix_fit(problems, nproblems, targets, ntargets, m, x0, dx, params, grad_out,
                                              final_loss, epochs, lr, beta1, beta2, eps, st);
                 }), "mix_fit");
+  return GES_OK;
+}
+
+size_t ges_densify_scratch_bytes(int64_t n) {
+  if (n < 0 || n >= (int64_t(1) << 31)) return 0;
+  return ges::densify_scratch_bytes(n);
+}
+
+ges_status ges_densify(int64_t n, int32_t sh_degree, const ges_splat_set* src, const ges_splat_set* dst,
+                       int32_t nsets, int64_t dst_capacity, const float* grad_accum, const float* grad_count,
+                       const float* normals, double grad_threshold, double scale_threshold, void* scratch,
+                       size_t scratch_bytes, int64_t* n_out, void* stream) {
+  if (!src || !dst || !scratch || !n_out) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(GES_ERR_INVALID_ARGUMENT, "n outside [0, 2^31)");
+  if (sh_degree < 0 || sh_degree > 3) return fail(GES_ERR_INVALID_ARGUMENT, "sh_degree outside 0..3");
+  if (nsets < 1 || nsets > 3) return fail(GES_ERR_INVALID_ARGUMENT, "nsets outside 1..3");
+  if (!std::isfinite(grad_threshold) || !(scale_threshold > 0.0) || !std::isfinite(scale_threshold))
+    return fail(GES_ERR_INVALID_ARGUMENT, "bad thresholds");
+  if (n > 0 && (!grad_accum || !grad_count || !normals)) return fail(GES_ERR_INVALID_ARGUMENT, "NULL statistics");
+  if (scratch_bytes < ges::densify_scratch_bytes(n)) return fail(GES_ERR_CAPACITY, "densify scratch too small");
+  const int K = (sh_degree + 1) * (sh_degree + 1);
+  const int32_t len[6] = {3, 3, 4, 1, 3 * K, 1};
+  const float* s[ges::kMaxPruneArrays] = {};
+  float* d[ges::kMaxPruneArrays] = {};
+  int32_t rl[ges::kMaxPruneArrays] = {};
+  for (int set = 0; set < nsets; ++set) {
+    const float* sp[6] = {src[set].means, src[set].log_scales, src[set].quats, src[set].opacity_logits, src[set].sh,
+                          src[set].beta};
+    float* dp[6] = {dst[set].means, dst[set].log_scales, dst[set].quats, dst[set].opacity_logits, dst[set].sh,
+                    dst[set].beta};
+    for (int k = 0; k < 6; ++k) {
+      if (!sp[k]) {
+        if (set == 0 && n > 0) return fail(GES_ERR_INVALID_ARGUMENT, "set 0 needs all six parameter arrays");
+        continue;
+      }
+      if (!dp[k]) return fail(GES_ERR_INVALID_ARGUMENT, "NULL destination for a source array");
+      s[6 * set + k] = sp[k];
+      d[6 * set + k] = dp[k];
+      rl[6 * set + k] = len[k];
+    }
+  }
+  const double lbound = std::log(scale_threshold);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  GES_CHECK_HIP(ges::launch_densify_count(grad_accum, grad_count, src[0].log_scales, n, grad_threshold, lbound, scratch,
+                                          st), "densify count");
+  int64_t tot[3] = {0, 0, 0};
+  GES_CHECK_HIP(hipMemcpyAsync(tot, scratch, sizeof(tot), hipMemcpyDeviceToHost, st), "read densify counts");
+  GES_CHECK_HIP(hipStreamSynchronize(st), "sync");
+  *n_out = tot[0] + tot[1] + 2 * tot[2];
+  if (*n_out > dst_capacity) return fail(GES_ERR_CAPACITY, "densified set exceeds dst_capacity");
+  if (*n_out >= (int64_t(1) << 31)) return fail(GES_ERR_CAPACITY, "densified set exceeds 2^31 splats");
+  GES_CHECK_HIP(ges::launch_densify_scatter(s, d, rl, nsets, grad_accum, grad_count, normals, n, grad_threshold, lbound,
+                                            std::log(1.6), tot[0], tot[1], scratch, st), "densify scatter");
+  return GES_OK;
+}
+
+ges_status ges_opacity_reset(float* opacity_logits, float* exp_avg, float* exp_avg_sq, int64_t n, double max_opacity,
+                             void* stream) {
+  if (n < 0) return fail(GES_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n > 0 && !opacity_logits) return fail(GES_ERR_INVALID_ARGUMENT, "NULL opacity_logits");
+  if (!(max_opacity > 0.0 && max_opacity < 1.0)) return fail(GES_ERR_INVALID_ARGUMENT, "max_opacity outside (0,1)");
+  GES_CHECK_HIP(ges::launch_opacity_reset(opacity_logits, exp_avg, exp_avg_sq, n,
+                                          std::log(max_opacity / (1.0 - max_opacity)),
+                                          reinterpret_cast<hipStream_t>(stream)), "opacity_reset");
   return GES_OK;
 }
 

@@ -125,6 +125,9 @@ struct AdamSplats {
   float* v[kNumPar];
   float step_size[kNumPar];
   float b1, b2, eps, inv_sqrt_bc2;
+  float* stat_accum;        // densification statistics (NULL: off): NDC mean-2D gradient norm ...
+  float* stat_count;        // ... and the number of iterations the splat was visible
+  double half_w, half_h;    // pixels per NDC unit
 };
 
 // --------------------------------------------------------------------------------------------
@@ -158,6 +161,17 @@ hipError_t launch_prune(const float* const* src, float* const* dst, const int32_
                         const float* beta, int64_t n, double logit_bound, double min_beta, void* scratch,
                         int64_t* total_dev, hipStream_t stream);
 hipError_t launch_shape_reset(float* beta, float* m, float* v, int64_t n, float value, hipStream_t stream);
+// exclusive offsets of nb block counts and their total (one block)
+hipError_t launch_block_scan(const uint32_t* counts, int64_t nb, uint32_t* offsets, int64_t* total,
+                             hipStream_t stream);
+size_t densify_scratch_bytes(int64_t n);
+hipError_t launch_densify_count(const float* accum, const float* count, const float* log_scales, int64_t n,
+                                double grad_threshold, double log_scale_bound, void* scratch, hipStream_t stream);
+hipError_t launch_densify_scatter(const float* const* src, float* const* dst, const int32_t* rowlen, int nsets,
+                                  const float* accum, const float* count, const float* normals, int64_t n,
+                                  double grad_threshold, double log_scale_bound, double log_split_div, int64_t unsplit,
+                                  int64_t clones, void* scratch, hipStream_t stream);
+hipError_t launch_opacity_reset(float* logits, float* m, float* v, int64_t n, double bound, hipStream_t stream);
 hipError_t launch_mix_fit(const ges_mix_problem* problems, int nproblems, const float* targets, int ntargets, int m,
                           float x0, float dx, float* params, float* grad_out, float* final_loss, int epochs, float lr,
                           float b1, float b2, float eps, hipStream_t stream);

@@ -107,6 +107,13 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
   const uint32_t flags = vis & 0xffu;
   const double2* gp = reinterpret_cast<const double2*>(V.grad2d + (int64_t)kGradStride * i);
   const double2 g01 = gp[0], g23 = gp[1], g45 = gp[2], g67 = gp[3], g89 = gp[4];
+  if constexpr (kAdam) {
+    if (A.stat_accum) {   // densification statistic: the mean-2D gradient in NDC units
+      const double su = g01.x * A.half_w, sv = g01.y * A.half_h;
+      A.stat_accum[i] += (float)sqrt(su * su + sv * sv);
+      A.stat_count[i] += 1.f;
+    }
+  }
   const double grgb[3] = {g67.x, g67.y, g89.x};
   const double gu = g01.x, gv = g01.y, ga = g23.x, gb = g23.y, gc = g45.x, gop = g45.y;
   const double gbeta2 = g89.y;

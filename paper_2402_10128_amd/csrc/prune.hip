@@ -141,6 +141,12 @@ hipError_t launch_prune(const float* const* src, float* const* dst, const int32_
   return hipGetLastError();
 }
 
+hipError_t launch_block_scan(const uint32_t* counts, int64_t nb, uint32_t* offsets, int64_t* total,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(prune_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, counts, nb, offsets, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_shape_reset(float* beta, float* m, float* v, int64_t n, float value, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>(4096, (n + 255) / 256);

@@ -68,7 +68,8 @@ class ges_adam_group(C.Structure):
 
 class ges_adam_splats(C.Structure):
     _fields_ = [("exp_avg", C.c_void_p * 6), ("exp_avg_sq", C.c_void_p * 6), ("lr", C.c_float * 6),
-                ("step", C.c_int64), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+                ("step", C.c_int64), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("grad_accum", C.c_void_p), ("grad_count", C.c_void_p)]
 
 
 class ges_splat_set(C.Structure):
@@ -122,6 +123,11 @@ _SIGS = {
     "ges_mix_fit": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_float,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_float, C.c_float,
                               C.c_float, C.c_void_p]),
+    "ges_densify_scratch_bytes": (C.c_size_t, [C.c_int64]),
+    "ges_densify": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(ges_splat_set), C.POINTER(ges_splat_set), C.c_int32,
+                              C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                              C.c_size_t, C.POINTER(C.c_int64), C.c_void_p]),
+    "ges_opacity_reset": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p]),
     "ges_adam_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "ges_expon_lr": (C.c_double, [C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_double]),
     "ges_serve_create": (C.c_int, [C.POINTER(ges_serve_config), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
@@ -317,9 +323,12 @@ SPLAT_PARAMS = ("means", "log_scales", "quats", "opacity_logits", "sh", "beta")
 
 def ges_render_backward_adam(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, exp_avg: dict,
                              exp_avg_sq: dict, lrs: dict, step, beta1=0.9, beta2=0.999, eps=1e-15, grads=None,
-                             stream=None):
-    """Backward pass with Adam fused in: updates the tensors behind ``splats`` and the moments in place."""
+                             grad_accum=None, grad_count=None, stream=None):
+    """Backward pass with Adam fused in: updates the tensors behind ``splats`` and the moments in place; with
+    grad_accum/grad_count also accumulates the densification statistic."""
     opt = ges_adam_splats()
+    opt.grad_accum = None if grad_accum is None else grad_accum.data_ptr()
+    opt.grad_count = None if grad_count is None else grad_count.data_ptr()
     for k, name in enumerate(SPLAT_PARAMS):
         opt.exp_avg[k] = exp_avg[name].data_ptr()
         opt.exp_avg_sq[k] = exp_avg_sq[name].data_ptr()
@@ -357,6 +366,29 @@ def ges_prune_splats(src_sets: list, dst_sets: list, sh_degree: int, min_opacity
     _check(lib().ges_prune_splats(n, int(sh_degree), src, dst, k, float(min_opacity), float(min_beta), _ptr(scratch),
                                   scratch.numel(), C.byref(kept), _stream(stream)))
     return kept.value
+
+
+def ges_densify(src_sets: list, dst_sets: list, sh_degree: int, grad_accum, grad_count, normals,
+                grad_threshold: float, scale_threshold: float, scratch=None, stream=None) -> int:
+    """Clone/split into dst_sets (dicts of float32 CUDA tensors with room for the result); returns the new
+    count (waits for the stream).  Raises GESError (capacity) when dst is too small."""
+    n = int(src_sets[0]["beta"].shape[0])
+    cap = int(dst_sets[0]["beta"].shape[0])
+    k = len(src_sets)
+    src = (ges_splat_set * k)(*[_splat_set(d) for d in src_sets])
+    dst = (ges_splat_set * k)(*[_splat_set(d) for d in dst_sets])
+    if scratch is None:
+        scratch = torch.empty(lib().ges_densify_scratch_bytes(n), dtype=torch.uint8, device=src_sets[0]["beta"].device)
+    out = C.c_int64(0)
+    _check(lib().ges_densify(n, int(sh_degree), src, dst, k, cap, _ptr(grad_accum), _ptr(grad_count), _ptr(normals),
+                             float(grad_threshold), float(scale_threshold), _ptr(scratch), scratch.numel(),
+                             C.byref(out), _stream(stream)))
+    return out.value
+
+
+def ges_opacity_reset(opacity_logits, exp_avg=None, exp_avg_sq=None, max_opacity=0.01, stream=None):
+    _check(lib().ges_opacity_reset(_ptr(opacity_logits), _ptr(exp_avg), _ptr(exp_avg_sq), int(opacity_logits.numel()),
+                                   float(max_opacity), _stream(stream)))
 
 
 def ges_shape_reset(beta, exp_avg=None, exp_avg_sq=None, value=2.0, stream=None):

@@ -13,8 +13,12 @@ gradients never go through memory.
 After the update, every shape_prune_interval iterations the splats whose opacity is below min_opacity or
 whose beta is below min_beta are removed with their moments, and every shape_reset_interval iterations every
 beta goes back to 2 (Sec. 4.4; Sec. 5.2; App. B.2: intervals 100 and 1,000).  When both fall on one
-iteration, pruning comes first, so it sees the learned shapes.  Densification and the opacity reset of the
-full training loop are not part of the step.
+iteration, pruning comes first, so it sees the learned shapes.
+Densification kept from Gaussian splatting (Sec. 5.2; App. B.2): until densify_until the backward pass
+accumulates each visible splat's NDC mean-2D gradient norm; after densify_from, every densify_interval
+iterations splats whose mean statistic reaches grad_threshold are cloned (small) or split in two (large,
+relative to percent_dense * scene_extent), with normal draws from a seeded device generator, before the
+pruning; every opacity_reset_interval iterations every opacity is capped at 0.01.
 """
 from __future__ import annotations
 
@@ -49,6 +53,14 @@ class TrainConfig:
     min_opacity: float = 0.005
     min_beta: float = 0.5                  # Sec. 5.2 (App. B.2 gives 0.005)
     beta_init: float = 2.0
+    densify_from: int = 500
+    densify_until: int = 15000
+    densify_interval: int = 100            # 0 switches densification off
+    grad_threshold: float = 0.0003
+    percent_dense: float = 0.01
+    scene_extent: float = 1.0
+    opacity_reset_interval: int = 3000     # 0 switches the reset off
+    seed: int = 0
     falloff: int = G.FALLOFF_PHI
     tile_cull: int = G.TILES_ELLIPSE
     rho: float = 0.1
@@ -81,12 +93,38 @@ class TrainStep:
         self.grads = None        # parameter gradients, allocated by the first unfused step
         self.exp_avg = {k: torch.zeros_like(v) for k, v in scene.items()}
         self.exp_avg_sq = {k: torch.zeros_like(v) for k, v in scene.items()}
+        self.gen = torch.Generator(device=dev).manual_seed(self.cfg.seed)
+        self._reset_stats()
 
     def _bind_scene(self):
         """Point the splat descriptor and the frame at the current scene tensors (after creation or pruning)."""
         self.s = G.splats_struct(*(self.scene[k] for k in G.SPLAT_PARAMS))
         self.frame = G.Frame.create(self.s.n, self.cam.width, self.cam.height, self.target.device)
         self.grads = None
+
+    def _reset_stats(self):
+        self.grad_accum = torch.zeros(self.n, dtype=torch.float32, device=self.target.device)
+        self.grad_count = torch.zeros(self.n, dtype=torch.float32, device=self.target.device)
+
+    def densify(self) -> int:
+        """Clone or split the splats whose mean statistic reaches the threshold; returns the new count.  The
+        scene, moments, statistics and frame are replaced (read ``self.scene`` afterwards)."""
+        c = self.cfg
+        n = self.n
+        normals = torch.randn((n, 2, 3), generator=self.gen, device=self.target.device)
+        src = [self.scene, self.exp_avg, self.exp_avg_sq]
+        dst = [{k: torch.empty((2 * n,) + tuple(v.shape[1:]), dtype=v.dtype, device=v.device) for k, v in d.items()}
+               for d in src]
+        out = G.ges_densify(src, dst, int(self.s.sh_degree), self.grad_accum, self.grad_count, normals,
+                            c.grad_threshold, c.percent_dense * c.scene_extent)
+        self.scene, self.exp_avg, self.exp_avg_sq = ({k: v[:out] for k, v in d.items()} for d in dst)
+        self._bind_scene()
+        self._reset_stats()
+        return out
+
+    def opacity_reset(self):
+        G.ges_opacity_reset(self.scene["opacity_logits"], self.exp_avg["opacity_logits"],
+                            self.exp_avg_sq["opacity_logits"], 0.01)
 
     @property
     def n(self) -> int:
@@ -102,8 +140,15 @@ class TrainStep:
         kept = G.ges_prune_splats(src, dst, sh_degree, c.min_opacity, c.min_beta)
         if kept == self.n:
             return kept
+        # the statistics follow the survivors: a pruning between densifications keeps them aligned
+        keep_stats = [{"opacity_logits": self.scene["opacity_logits"], "beta": self.scene["beta"]},
+                      {"opacity_logits": self.grad_accum, "beta": self.grad_count}]
+        new_stats = [{k: torch.empty_like(v) for k, v in d.items()} for d in keep_stats]
+        G.ges_prune_splats(keep_stats, new_stats, sh_degree, c.min_opacity, c.min_beta)
         self.scene, self.exp_avg, self.exp_avg_sq = ({k: v[:kept] for k, v in d.items()} for d in dst)
         self._bind_scene()
+        self.grad_accum = new_stats[1]["opacity_logits"][:kept].contiguous()
+        self.grad_count = new_stats[1]["beta"][:kept].contiguous()
         return kept
 
     def shape_reset(self):
@@ -143,10 +188,13 @@ class TrainStep:
         G.ges_loss(self.image, self.target, self.mask, lam_l1, c.lam_omega, self.dL, self.loss, self.loss_scratch)
         G.ges_ssim_loss(self.image, self.target, c.lam_ssim, self.loss, self.dL, self.ssim_scratch)
         lrs = self.learning_rates(it)
+        stats = c.densify_interval > 0 and it < c.densify_until
         if fused:
             G.ges_render_backward_adam(self.s, self.c, self.p, self.frame.splat_ws, self.frame.key_ws,
                                        self.frame.pixel_ws, self.dL, self.exp_avg, self.exp_avg_sq, lrs, it,
-                                       c.beta1, c.beta2, c.eps)
+                                       c.beta1, c.beta2, c.eps,
+                                       grad_accum=self.grad_accum if stats else None,
+                                       grad_count=self.grad_count if stats else None)
         else:
             if self.grads is None:
                 self.grads = {k: torch.empty_like(v) for k, v in self.scene.items()}
@@ -155,8 +203,12 @@ class TrainStep:
             groups = [(self.scene[k], self.grads[k], self.exp_avg[k], self.exp_avg_sq[k], lrs[k])
                       for k in GROUP_ORDER]
             G.ges_adam_step(groups, it, c.beta1, c.beta2, c.eps)
+        if stats and it > c.densify_from and it % c.densify_interval == 0:
+            self.densify()
         if c.shape_prune_interval and it % c.shape_prune_interval == 0:
             self.prune()
         if c.shape_reset_interval and it % c.shape_reset_interval == 0:
             self.shape_reset()
+        if c.opacity_reset_interval and it % c.opacity_reset_interval == 0:
+            self.opacity_reset()
         return self.loss
