@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
     ap.add_argument("--no-mixture", action="store_true", help="skip the 1-D mixture-simulation sweep")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the shape-strength sweep and the approximate/exact falloff comparison")
     ap.add_argument("--mixture-epochs", type=int, default=1000)
     ap.add_argument("--no-train-step", action="store_true",
                     help="skip the full optimisation-step measurement (adds SSIM, per-step mask and Adam)")
@@ -347,6 +349,48 @@ def mixture_bench(dev, epochs, log_fn):
                              "sample": "24 random problems of the sweep, 20 epochs each, binary64 numpy"}}
 
 
+def variants_bench(dev, cfg, tile_cull, steps, log_fn):
+    """The paper's shape-strength sweep (rho in 0.01..0.15, Table 'shape strength') and the approximate
+    (PHI) against the exact (GEF) falloff on the same scene: keys, pairs and forward+backward step time."""
+    import torch
+    from paper_2402_10128_amd import ges as G
+    sc, cam = cfg["scene"], cfg["camera"]
+    t = {k: torch.as_tensor(v).to(dev) for k, v in sc.arrays().items()}
+    s = G.splats_struct(t["means"], t["log_scales"], t["quats"], t["opacity_logits"], t["sh"], t["beta"])
+    c = G.camera_struct(cam)
+    W, H = cam.width, cam.height
+    frame = G.Frame.create(s.n, W, H, dev)
+    out = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    dL = torch.full_like(out, 1e-6)
+    grads = {k: torch.empty_like(v) for k, v in t.items()}
+    res = []
+    for falloff, rho in [(0, 0.01), (0, 0.05), (0, 0.1), (0, 0.15), (1, 0.1)]:
+        p = G.params_struct(falloff, tile_cull, rho, (0.0, 0.0, 0.0))
+
+        def step():
+            k = G.ges_preprocess(s, c, p, frame.splat_ws, True)
+            frame.ensure_keys(k)
+            G.ges_render_forward(s, c, p, frame.splat_ws, frame.key_ws, k, frame.pixel_ws, out)
+            G.ges_render_backward(s, c, p, frame.splat_ws, frame.key_ws, frame.pixel_ws, dL, grads)
+            return k
+
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            k = step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        st = G.frame_arrays(frame, s.n)["stats"]
+        res.append({"falloff": "phi" if falloff == 0 else "gef", "rho": rho, "num_keys": int(k),
+                    "pairs_composited": int(st[3]), "ms_per_step_with_key_readback": round(ms, 4)})
+        log_fn(f"variant falloff={res[-1]['falloff']} rho={rho}: {ms:.3f} ms, {k} keys")
+    del frame, t, grads, out, dL
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -479,6 +523,10 @@ def main():
         log("optimisation step (mask + render + L1/SSIM/frequency loss + adjoint + Adam)")
         train = train_step_bench(dev, cfg, falloff, tile_cull, args.steps, args.warmup)
         log(f"optimisation step {train['ms_per_step']:.3f} ms: " + json.dumps(train["stage_ms_per_launch"]))
+    variants = None
+    if not args.no_variants:
+        log("shape-strength sweep and falloff comparison")
+        variants = variants_bench(dev, cfg, tile_cull, min(args.steps, 5), log)
     mixture = None
     if not args.no_mixture:
         log("1-D mixture sweep")
@@ -519,6 +567,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "train_step": train,
+        "variants": variants,
         "mixture_sweep": mixture,
         "serving": serving,
     }
