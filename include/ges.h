@@ -326,7 +326,11 @@ ges_status ges_shape_reset(float* beta, float* exp_avg, float* exp_avg_sq, int64
  * [nproblems][GES_MIX_MAX_COMPONENTS][4]: the initial values in, the values after `epochs`
  * Adam steps out (rows i >= n untouched).  grad_out (same shape, may be NULL) receives the
  * gradient at the initial values; final_loss[p] the MSE after the last step (NaN: the run
- * diverged).  targets: device [ntargets][m].  Errors: GES_ERR_INVALID_ARGUMENT for NULL
+ * diverged).  targets: device [ntargets][m].  order (device [nproblems], may be NULL): the
+ * order in which workgroups take the problems, a permutation of 0..nproblems-1 (largest n
+ * first keeps the longest fits from starting last); results always go to each problem's own
+ * rows.  A workgroup whose entry lies outside 0..nproblems-1 does nothing (a problem left
+ * out of the permutation is then not run).  Errors: GES_ERR_INVALID_ARGUMENT for NULL
  * problems/targets/params/final_loss with nproblems > 0, m outside 1..GES_MIX_MAX_POINTS,
  * epochs < 0, non-finite x0/dx/lr/eps, lr or eps < 0, or b1/b2 outside [0,1). */
 #define GES_MIX_MAX_COMPONENTS 128
@@ -340,7 +344,8 @@ typedef struct {
 } ges_mix_problem;
 ges_status ges_mix_fit(const ges_mix_problem* problems, int32_t nproblems, const float* targets, int32_t ntargets,
                        int32_t m, float x0, float dx, float* params, float* grad_out, float* final_loss,
-                       int32_t epochs, float lr, float beta1, float beta2, float eps, void* stream);
+                       const int32_t* order, int32_t epochs, float lr, float beta1, float beta2, float eps,
+                       void* stream);
 
 /* ---- densification kept from Gaussian splatting (Sec. 5.2; App. B.2) ---------------
  * ges_densify classifies each splat from its statistic (ges_adam_splats.grad_accum /

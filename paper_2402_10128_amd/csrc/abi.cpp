@@ -471,7 +471,8 @@ ges_status ges_shape_reset(float* beta, float* exp_avg, float* exp_avg_sq, int64
 
 ges_status ges_mix_fit(const ges_mix_problem* problems, int32_t nproblems, const float* targets, int32_t ntargets,
                        int32_t m, float x0, float dx, float* params, float* grad_out, float* final_loss,
-                       int32_t epochs, float lr, float beta1, float beta2, float eps, void* stream) {
+                       const int32_t* order, int32_t epochs, float lr, float beta1, float beta2, float eps,
+                       void* stream) {
   if (nproblems < 0) return fail(GES_ERR_INVALID_ARGUMENT, "nproblems < 0");
   if (nproblems > 0 && (!problems || !targets || !params || !final_loss))
     return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
@@ -485,7 +486,7 @@ ges_status ges_mix_fit(const ges_mix_problem* problems, int32_t nproblems, const
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   GES_CHECK_HIP(timed(GES_STAGE_MIX_FIT, st, [&] {
                   return ges::launch_mix_fit(problems, nproblems, targets, ntargets, m, x0, dx, params, grad_out,
-                                             final_loss, epochs, lr, beta1, beta2, eps, st);
+                                             final_loss, order, epochs, lr, beta1, beta2, eps, st);
                 }), "mix_fit");
   return GES_OK;
 }

@@ -173,8 +173,8 @@ hipError_t launch_densify_scatter(const float* const* src, float* const* dst, co
                                   int64_t clones, void* scratch, hipStream_t stream);
 hipError_t launch_opacity_reset(float* logits, float* m, float* v, int64_t n, double bound, hipStream_t stream);
 hipError_t launch_mix_fit(const ges_mix_problem* problems, int nproblems, const float* targets, int ntargets, int m,
-                          float x0, float dx, float* params, float* grad_out, float* final_loss, int epochs, float lr,
-                          float b1, float b2, float eps, hipStream_t stream);
+                          float x0, float dx, float* params, float* grad_out, float* final_loss, const int32_t* order,
+                          int epochs, float lr, float b1, float b2, float eps, hipStream_t stream);
 hipError_t launch_adam(const ges_adam_group* groups, int ngroups, int64_t step, float b1, float b2, float eps,
                        hipStream_t stream);
 

@@ -34,6 +34,8 @@ struct MixArgs {
   float* params;          // [P][kMixMaxN][4]
   float* grad_out;        // [P][kMixMaxN][4] gradient at the initial parameters, or NULL
   float* final_loss;      // [P]
+  const int32_t* order;   // [P] problem index per block (a permutation), or NULL for the identity
+  int32_t nproblems;
   int32_t epochs;
   float lr, b1, b2, eps;
 };
@@ -123,7 +125,11 @@ __global__ void __launch_bounds__(kMixThreads) mix_fit_kernel(const MixArgs a) {
   __shared__ float gr[kMixMaxN][4];
   __shared__ MixComp comp[kMixMaxN];
   __shared__ float lsum[kMixThreads / 64];
-  const int p = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // blocks take problems from the largest n down (a problem's time grows with n), so the longest ones do
+  // not start last; results go to the problem's own rows
+  const int p = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
+  if (p < 0 || p >= a.nproblems) return;   // not a problem of this batch: nothing to do
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const ges_mix_problem pr = a.problems[p];
   const int n = pr.n, model = pr.model, positive = pr.positive;
   const int M = a.m;
@@ -206,10 +212,11 @@ __global__ void __launch_bounds__(kMixThreads) mix_fit_kernel(const MixArgs a) {
 }
 
 hipError_t launch_mix_fit(const ges_mix_problem* problems, int nproblems, const float* targets, int ntargets, int m,
-                          float x0, float dx, float* params, float* grad_out, float* final_loss, int epochs, float lr,
-                          float b1, float b2, float eps, hipStream_t stream) {
+                          float x0, float dx, float* params, float* grad_out, float* final_loss, const int32_t* order,
+                          int epochs, float lr, float b1, float b2, float eps, hipStream_t stream) {
   if (nproblems == 0) return hipSuccess;
-  MixArgs a{problems, targets, ntargets, m, x0, dx, params, grad_out, final_loss, epochs, lr, b1, b2, eps};
+  MixArgs a{problems, targets, ntargets, m, x0, dx, params, grad_out, final_loss, order, nproblems, epochs, lr, b1,
+            b2, eps};
   hipLaunchKernelGGL(mix_fit_kernel, dim3((unsigned)nproblems), dim3(kMixThreads), 0, stream, a);
   return hipGetLastError();
 }

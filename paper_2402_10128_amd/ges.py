@@ -121,8 +121,8 @@ _SIGS = {
                                    C.c_double, C.c_double, C.c_void_p, C.c_size_t, C.POINTER(C.c_int64), C.c_void_p]),
     "ges_shape_reset": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p]),
     "ges_mix_fit": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_float,
-                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_float, C.c_float,
-                              C.c_float, C.c_void_p]),
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_float,
+                              C.c_float, C.c_float, C.c_void_p]),
     "ges_densify_scratch_bytes": (C.c_size_t, [C.c_int64]),
     "ges_densify": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(ges_splat_set), C.POINTER(ges_splat_set), C.c_int32,
                               C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
@@ -401,9 +401,10 @@ MIX_MAX_COMPONENTS = 128
 
 
 def ges_mix_fit(problems, targets, x0, dx, params, epochs, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_out=None,
-                final_loss=None, stream=None):
+                final_loss=None, order="largest_first", stream=None):
     """problems: int32 CUDA tensor [P, 4] (model, n, positive, target); targets [T, m]; params [P, 128, 4]
-    updated in place.  Returns final_loss [P]."""
+    updated in place.  order: "largest_first" (workgroups take the problems by decreasing n), None (in
+    order) or an int32 CUDA permutation.  Returns final_loss [P]."""
     P = int(problems.shape[0])
     if problems.dtype != torch.int32 or problems.dim() != 2 or problems.shape[1] != 4 or not problems.is_contiguous():
         raise ValueError("problems must be a contiguous int32 [P, 4] tensor")
@@ -411,8 +412,12 @@ def ges_mix_fit(problems, targets, x0, dx, params, epochs, lr, beta1=0.9, beta2=
         raise ValueError("params must be a contiguous float32 [P, 128, 4] tensor")
     if final_loss is None:
         final_loss = torch.empty(P, dtype=torch.float32, device=params.device)
+    if isinstance(order, str):
+        # a stable sort on the device: the table is an input, the order only schedules it
+        order = torch.argsort(-problems[:, 1].to(torch.int64), stable=True).to(torch.int32)
     _check(lib().ges_mix_fit(_ptr(problems), P, _ptr(targets), int(targets.shape[0]), int(targets.shape[1]),
-                             float(x0), float(dx), _ptr(params), _ptr(grad_out), _ptr(final_loss), int(epochs),
+                             float(x0), float(dx), _ptr(params), _ptr(grad_out), _ptr(final_loss), _ptr(order),
+                             int(epochs),
                              float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
     return final_loss
 

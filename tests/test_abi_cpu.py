@@ -180,9 +180,9 @@ def test_prune_and_reset_validate_before_any_device_work():
 def test_mix_fit_validates_before_any_device_work():
     lib = G.lib()
     p = C.c_void_p(1 << 20)
-    ok = (p, 1, p, 1, 100, -5.0, 0.1, p, None, p, 10, 0.01, 0.9, 0.999, 1e-8, None)
-    for pos, bad in [(0, None), (1, -1), (4, 0), (4, 5000), (3, 0), (10, -1), (11, float("nan")), (12, 1.0),
-                     (14, -1.0), (6, float("inf"))]:
+    ok = (p, 1, p, 1, 100, -5.0, 0.1, p, None, p, None, 10, 0.01, 0.9, 0.999, 1e-8, None)
+    for pos, bad in [(0, None), (1, -1), (4, 0), (4, 5000), (3, 0), (11, -1), (12, float("nan")), (13, 1.0),
+                     (15, -1.0), (6, float("inf"))]:
         args = list(ok)
         args[pos] = bad
         assert lib.ges_mix_fit(*args) == 1, (pos, bad)

@@ -19,13 +19,13 @@ LR = 0.01
 B1, B2, EPS = (float(np.float32(v)) for v in (0.9, 0.999, 1e-8))
 
 
-def _run(W, epochs, problems=None):
+def _run(W, epochs, problems=None, order="largest_first"):
     dev = torch.device("cuda:0")
     probs = torch.from_numpy(W["problems"] if problems is None else problems).to(dev)
     tg = torch.from_numpy(W["targets"]).to(dev)
     par = torch.from_numpy(W["params"]).to(dev)
     grad = torch.full_like(par, float("nan"))
-    loss = G.ges_mix_fit(probs, tg, W["x0"], W["dx"], par, epochs, LR, 0.9, 0.999, 1e-8, grad_out=grad)
+    loss = G.ges_mix_fit(probs, tg, W["x0"], W["dx"], par, epochs, LR, 0.9, 0.999, 1e-8, grad_out=grad, order=order)
     torch.cuda.synchronize()
     return par.cpu().numpy(), grad.cpu().numpy(), loss.cpu().numpy()
 
@@ -48,6 +48,9 @@ def test_mixture_small_batch_all_models():
     W = synth.mixture_workload(seed=1, ns=(2, 5, 20), runs=1, m=200)
     par, grad, loss = _run(W, 5)
     _compare(W, range(len(W["problems"])), par, grad, loss, 5)
+    # the issue order only schedules the problems: in order and largest-first give the same bits
+    par2, grad2, loss2 = _run(W, 5, order=None)
+    assert np.array_equal(par, par2) and np.array_equal(grad, grad2) and np.array_equal(loss, loss2)
 
 
 def test_mixture_full_sweep_sampled():
