@@ -115,15 +115,42 @@ float log_c(float x) {
   return hi + lo;
 }
 
+// ln Gamma(x), x > 0, in binary32 for the exact shape modification (Sec. 4.2, Eq. probablity): the
+// recurrence Gamma(x) = Gamma(x + 1) / x lifts x to at least 8 (the factors multiplied into one product),
+// then Stirling's series with the terms 1/(12x), -1/(360x^3), 1/(1260x^5); finally minus ln of the product.
+float lgamma_c(float x) {
+  float prod = 1.0f;
+  while (x < 8.0f) {
+    prod = prod * x;
+    x = x + 1.0f;
+  }
+  const float lz = log_c(x);
+  float t = x - 0.5f;
+  t = t * lz;
+  t = t - x;
+  t = t + 0.918938533204672742f;                // ln(2 pi) / 2
+  const float iz = 1.0f / x;
+  const float iz2 = iz * iz;
+  float c = iz2 * (float)(1.0 / 1260.0);
+  c = (float)(1.0 / 360.0) - c;
+  c = c * iz2;
+  c = (float)(1.0 / 12.0) - c;
+  c = c * iz;
+  t = t + c;
+  return t - log_c(prod);
+}
+
 // Scalar policy: F32 mode uses the canonical functions, F64 mode libm.
 template <class S> struct M;
 template <> struct M<float> {
   static float ex(float x) { return exp_c(x); }
   static float lg(float x) { return log_c(x); }
+  static float lgam(float x) { return lgamma_c(x); }
 };
 template <> struct M<double> {
   static double ex(double x) { return std::exp(x); }
   static double lg(double x) { return std::log(x); }
+  static double lgam(double x) { return std::lgamma(x); }
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -316,6 +343,14 @@ void preprocess_one(int64_t i, const oc_splats* sp, const oc_camera* cam, const 
     S e = M<S>::ex(-t);
     S d = (S)1 + e;
     phi = (S)2 / d;
+  } else if (prm->falloff == OC_FALLOFF_PHI_EXACT) {
+    // exact modification 2 Gamma(3/beta) / Gamma(1/beta), normalised to 1 at beta = 2 (Eq. probablity)
+    if (!(beta > (S)0)) { cull(o, i); return; }
+    const S a3 = (S)3 / beta, a1 = (S)1 / beta;
+    S dl = M<S>::lgam(a3);
+    dl = dl - M<S>::lgam(a1);
+    phi = (S)2 * M<S>::ex(dl);
+    if (!std::isfinite(phi) || !(phi > (S)0)) { cull(o, i); return; }
   } else {
     if (!(beta > (S)0)) { cull(o, i); return; }
     phi = (S)1;
@@ -391,7 +426,7 @@ void preprocess_one(int64_t i, const oc_splats* sp, const oc_camera* cam, const 
   S L2 = M<S>::lg(o255);
   L2 = (S)2 * L2;
   S qm;
-  if (prm->falloff == OC_FALLOFF_PHI) {
+  if (prm->falloff != OC_FALLOFF_GEF) {   // Gaussian falloff (PHI and PHI_EXACT)
     qm = L2;
   } else {
     S e = (S)2 / beta;
@@ -549,7 +584,7 @@ inline bool pair_q(int mode, const Splat2D& s, int px, int py, double& q, double
 
 inline double falloff(int falloff_mode, double q, double beta) {
   if (q < 0.0) q = 0.0;
-  if (falloff_mode == OC_FALLOFF_PHI) return std::exp(-0.5 * q);
+  if (falloff_mode != OC_FALLOFF_GEF) return std::exp(-0.5 * q);
   return std::exp(-0.5 * std::pow(q, 0.5 * beta));
 }
 
@@ -709,7 +744,7 @@ void pixel_grads(const oc_params* p, const Splat2D* L, const std::vector<Contrib
     if (!c.clamped) { dG = s.o * dalpha; dop = c.G * dalpha; }
     double q = c.q < 0.0 ? 0.0 : c.q;
     double dq = 0.0, dbeta = 0.0;
-    if (p->falloff == OC_FALLOFF_PHI) {
+    if (p->falloff != OC_FALLOFF_GEF) {
       dq = c.q < 0.0 ? 0.0 : -0.5 * c.G * dG;
     } else {
       double qf = std::max(q, 1e-12);
@@ -798,6 +833,9 @@ extern "C" {
 
 void oc_exp_c(const float* x, float* y, int64_t n) {
   for (int64_t i = 0; i < n; ++i) y[i] = exp_c(x[i]);
+}
+void oc_lgamma_c(const float* x, float* y, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) y[i] = lgamma_c(x[i]);
 }
 void oc_log_c(const float* x, float* y, int64_t n) {
   for (int64_t i = 0; i < n; ++i) y[i] = log_c(x[i]);

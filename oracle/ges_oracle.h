@@ -37,7 +37,7 @@ extern "C" {
 #endif
 
 enum { OC_MODE_F32 = 0, OC_MODE_F64 = 1 };
-enum { OC_FALLOFF_PHI = 0, OC_FALLOFF_GEF = 1 };
+enum { OC_FALLOFF_PHI = 0, OC_FALLOFF_GEF = 1, OC_FALLOFF_PHI_EXACT = 2 };
 enum { OC_TILES_SQUARE = 0, OC_TILES_ELLIPSE = 1 };
 enum { OC_TILE = 16 };
 
@@ -87,6 +87,7 @@ typedef struct {
 /* Canonical binary32 exp / log (used by the F32 mode), exposed for tests. */
 void oc_exp_c(const float* x, float* y, int64_t n);
 void oc_log_c(const float* x, float* y, int64_t n);
+void oc_lgamma_c(const float* x, float* y, int64_t n);
 
 int oc_preprocess(int mode, const oc_splats* s, const oc_camera* cam, const oc_params* p, oc_record* out);
 

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 MODE_F32, MODE_F64 = 0, 1
-FALLOFF_PHI, FALLOFF_GEF = 0, 1
+FALLOFF_PHI, FALLOFF_GEF, FALLOFF_PHI_EXACT = 0, 1, 2
 TILES_SQUARE, TILES_ELLIPSE = 0, 1
 TILE = 16
 
@@ -259,6 +259,13 @@ def log_c(x):
     x = _f32(x).ravel()
     y = np.empty_like(x)
     lib().oc_log_c(_p(x), _p(y), C.c_int64(x.size))
+    return y
+
+
+def lgamma_c(x):
+    x = _f32(x).ravel()
+    y = np.empty_like(x)
+    lib().oc_lgamma_c(_p(x), _p(y), C.c_int64(x.size))
     return y
 
 

@@ -5,8 +5,9 @@ preprocess of the C++ oracle's F64 mode (GES, arXiv 2402.10128):
 
 * scale s = exp(log-scale); opacity o = sigmoid(logit);
 * unit quaternion -> rotation R; Sigma = (R S)(R S)^T with S = diag(phi * s) where
-  phi = 2 / (1 + exp(-(rho beta - 2 rho))) in the PHI falloff (Sec. 4.2, Eq. approx)
-  and phi = 1 in the GEF falloff (Eq. ges);
+  phi = 2 / (1 + exp(-(rho beta - 2 rho))) in the PHI falloff (Sec. 4.2, Eq. approx),
+  phi = 2 Gamma(3/beta) / Gamma(1/beta) in the PHI_EXACT variant (Eq. probablity, normalised to 1 at
+  beta = 2; Gaussian falloff) and phi = 1 in the GEF falloff (Eq. ges);
 * EWA (Sec. 4.1): Sigma' = J W Sigma W^T J^T + 0.3 I with W the camera rotation and
   J the perspective Jacobian at the camera-space mean (guard-clamped x/z, y/z);
 * conic = inverse of Sigma'; mean2D = (fx x/z + cx, fy y/z + cy);
@@ -79,6 +80,9 @@ def preprocess(params: dict, sh_degree: int, cam, falloff: int = 0, rho: float =
     rho = float(np.float32(rho))          # the renderer receives rho as binary32
     if falloff == 0:
         phi = 2.0 / (1.0 + torch.exp(-(rho * beta - 2.0 * rho)))
+    elif falloff == 2:
+        # exact modification 2 Gamma(3/beta) / Gamma(1/beta) (Eq. probablity, normalised to 1 at beta = 2)
+        phi = 2.0 * torch.exp(torch.lgamma(3.0 / beta) - torch.lgamma(1.0 / beta))
     else:
         phi = torch.ones_like(beta)
     Rq = quat_to_rot(params["quats"])
@@ -108,7 +112,7 @@ def preprocess(params: dict, sh_degree: int, cam, falloff: int = 0, rho: float =
     u = fx * p[:, 0] / z + cx
     v = fy * p[:, 1] / z + cy
     L2 = 2.0 * torch.log(255.0 * o)
-    qmax = L2 if falloff == 0 else torch.exp((2.0 / beta) * torch.log(L2))
+    qmax = L2 if falloff != 1 else torch.exp((2.0 / beta) * torch.log(L2))
     # colour
     Rnp = np.asarray(cam.R, np.float32).astype(np.float64).reshape(3, 3)
     campos = torch.as_tensor(-Rnp.T @ np.asarray(cam.t, np.float32).astype(np.float64))

@@ -394,7 +394,7 @@ def _render_f64(arrays, sc, cam, falloff, base_rec, g):
     return float((res["img"] * g).sum()), res["stats"]["decision_hash"]
 
 
-@pytest.mark.parametrize("falloff", [O.FALLOFF_PHI, O.FALLOFF_GEF])
+@pytest.mark.parametrize("falloff", [O.FALLOFF_PHI, O.FALLOFF_GEF, O.FALLOFF_PHI_EXACT])
 def test_oracle_gradient_matches_central_fd(oracle_mod, falloff):
     """Analytic binary64 gradient (reverse pass + autograd chain) vs central finite differences."""
     sc, cam, arrays = _fd_setup(falloff, n=300)
@@ -779,3 +779,52 @@ def test_ndc_statistic_and_opacity_reset():
     assert list(acc) == [50.0, 0.0, 50.0] and list(cnt) == [1.0, 0.0, 1.0]
     op, m, v = OD.opacity_reset(np.array([-6.0, 0.0, 3.0]), np.ones(3), np.ones(3))
     assert np.allclose(1 / (1 + np.exp(-op)), [1 / (1 + np.exp(6.0)), 0.01, 0.01]) and not m.any() and not v.any()
+
+
+
+# ---- exact shape modification 2 Gamma(3/beta) / Gamma(1/beta) (Sec. 4.2, Eq. probablity)
+def test_canonical_lgamma_against_libm(oracle_mod):
+    """The binary32 ln Gamma of the exact modification against the C library's binary64 lgamma: within
+    2e-5 absolute (a few binary32 ulps of the Stirling terms, which reach about 20 before they cancel) and
+    2e-6 relative for large arguments."""
+    x = np.concatenate([np.geomspace(0.03, 100.0, 400), [0.5, 1.0, 1.5, 2.0, 3.0, 7.999, 8.0]]).astype(np.float32)
+    got = O.lgamma_c(x).astype(np.float64)
+    want = np.array([math.lgamma(float(v)) for v in x])
+    assert np.all(np.abs(got - want) <= 2e-5 + 2e-6 * np.abs(want)), float(np.abs(got - want).max())
+
+
+@pytest.mark.parametrize("beta", [1.0, 1.5, 2.0, 3.0, 4.0])
+def test_exact_modification_single_splat(oracle_mod, beta):
+    """Isotropic splat on the optical axis in the exact mode: Sigma' = (f phi s / z0)^2 I + 0.3 I with
+    phi = 2 Gamma(3/beta) / Gamma(1/beta) from math.gamma (1 at beta = 2, 4 at beta = 1), in both oracle
+    precisions; the binary32 record uses the canonical ln Gamma and agrees to binary32 rounding."""
+    z0, s, f, logit = 3.0, 0.04, 40.0, 0.7
+    cam = _axis_camera(f=f)
+    arr = _one_splat_scene(z0, s, beta, logit)
+    orc = O.Oracle(arr, 0, cam, falloff=O.FALLOFF_PHI_EXACT)
+    b = float(np.float32(beta))
+    phi = 2 * math.gamma(3 / b) / math.gamma(1 / b)
+    if beta == 2.0:
+        assert abs(phi - 1.0) < 1e-15
+    if beta == 1.0:
+        assert abs(phi - 4.0) < 1e-14
+    s = math.exp(float(np.float32(math.log(s))))
+    var = (f * phi * s / z0) ** 2 + 0.3
+    r64 = orc.preprocess(O.MODE_F64)
+    np.testing.assert_allclose(r64.conic[0], [1 / var, 0.0, 1 / var], rtol=1e-12, atol=1e-15)
+    r32 = orc.preprocess(O.MODE_F32)
+    np.testing.assert_allclose(r32.conic[0], [1 / var, 0.0, 1 / var], rtol=1e-4, atol=1e-9)
+
+
+def test_exact_mode_f32_record_close_to_f64(oracle_mod):
+    cfg = synth.make_config(0)
+    sc, cam = cfg["scene"], cfg["camera"]
+    orc = O.Oracle(sc.arrays(), 0, cam, falloff=O.FALLOFF_PHI_EXACT)
+    r32, r64 = orc.preprocess(O.MODE_F32), orc.preprocess(O.MODE_F64)
+    both = (r32.tiles_touched > 0) & (r64.tiles_touched > 0)
+    assert both.sum() > 0.9 * max((r64.tiles_touched > 0).sum(), 1)
+    np.testing.assert_allclose(r32.conic[both], r64.conic[both], rtol=2e-4, atol=1e-7)
+    P = PF.to_params(sc.arrays())
+    out = PF.preprocess(P, 0, cam, O.FALLOFF_PHI_EXACT, 0.1, r64.clamp_bits)
+    vis = r64.tiles_touched > 0
+    np.testing.assert_allclose(out["a"].numpy()[vis], r64.conic[vis, 0], rtol=1e-9)
