@@ -364,7 +364,12 @@ def variants_bench(dev, cfg, tile_cull, steps, log_fn):
     dL = torch.full_like(out, 1e-6)
     grads = {k: torch.empty_like(v) for k, v in t.items()}
     res = []
-    for falloff, rho in [(0, 0.01), (0, 0.05), (0, 0.1), (0, 0.15), (1, 0.1)]:
+    beta_orig = t["beta"].clone()
+    # the exact modification 2 Gamma(3/b)/Gamma(1/b) is 240 at b = 0.5 (the scene's betas reach 0.5): it is
+    # compared with the approximation on a copy whose betas are clipped to [1, 4] (phi_exact <= 4)
+    for falloff, rho, clip in [(0, 0.01, False), (0, 0.05, False), (0, 0.1, False), (0, 0.15, False),
+                               (1, 0.1, False), (0, 0.1, True), (2, 0.1, True)]:
+        t["beta"].copy_(beta_orig.clamp(1.0, 4.0) if clip else beta_orig)
         p = G.params_struct(falloff, tile_cull, rho, (0.0, 0.0, 0.0))
 
         def step():
@@ -383,9 +388,10 @@ def variants_bench(dev, cfg, tile_cull, steps, log_fn):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / steps * 1e3
         st = G.frame_arrays(frame, s.n)["stats"]
-        res.append({"falloff": "phi" if falloff == 0 else "gef", "rho": rho, "num_keys": int(k),
+        res.append({"falloff": ("phi", "gef", "phi_exact")[falloff], "rho": rho, "beta_clipped_1_4": clip,
+                    "num_keys": int(k),
                     "pairs_composited": int(st[3]), "ms_per_step_with_key_readback": round(ms, 4)})
-        log_fn(f"variant falloff={res[-1]['falloff']} rho={rho}: {ms:.3f} ms, {k} keys")
+        log_fn(f"variant falloff={res[-1]['falloff']} rho={rho} clip={clip}: {ms:.3f} ms, {k} keys")
     del frame, t, grads, out, dL
     torch.cuda.empty_cache()
     return res

@@ -55,8 +55,12 @@ typedef enum {
  *      falloff is the Gaussian exp(-q/2).
  * GEF: the exact GES kernel of Eq. ges projected to the image: exp(-q^(beta/2) / 2)
  *      on the unmodified covariance.
+ * PHI_EXACT: the exact conversion the paper derives first (Sec. 4.2, Eq. probablity),
+ *      normalised to 1 at beta = 2: scales multiplied by 2 Gamma(3/beta) / Gamma(1/beta),
+ *      Gaussian falloff exp(-q/2); beta <= 0 culls.  (A variant: it grows without bound as
+ *      beta falls, which is why the paper approximates it.)
  * q is the quadratic form of the (0.3-dilated) projected covariance. */
-typedef enum { GES_FALLOFF_PHI = 0, GES_FALLOFF_GEF = 1 } ges_falloff;
+typedef enum { GES_FALLOFF_PHI = 0, GES_FALLOFF_GEF = 1, GES_FALLOFF_PHI_EXACT = 2 } ges_falloff;
 
 /* Which tiles list a splat: every tile of its bounding square (SQUARE) or only the
  * tiles whose pixel-centre box meets its alpha-floor ellipse (ELLIPSE).  Both give

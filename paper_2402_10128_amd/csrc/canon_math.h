@@ -78,4 +78,30 @@ __device__ __forceinline__ float canon_log(float x) {
   return hi + lo;
 }
 
+// Canonical binary32 ln Gamma(x) for x > 0, for the exact shape modification 2 Gamma(3/b) / Gamma(1/b):
+//   while x < 8: prod = prod * x; x = x + 1   (Gamma(x) = Gamma(x + k) / (x (x+1) ... (x+k-1)));
+//   Stirling: (x - 1/2) ln x - x + ln(2 pi)/2 + (1/x) (1/12 - (1/x^2)(1/360 - (1/x^2)/1260));
+//   minus ln prod.  Binary32 operations in the order written; constants the nearest binary32 values.
+__device__ __forceinline__ float canon_lgamma(float x) {
+  float prod = 1.0f;
+  while (x < 8.0f) {
+    prod = prod * x;
+    x = x + 1.0f;
+  }
+  const float lz = canon_log(x);
+  float t = x - 0.5f;
+  t = t * lz;
+  t = t - x;
+  t = t + 0x1.d67f1cp-1f;                       // ln(2 pi) / 2
+  const float iz = 1.0f / x;
+  const float iz2 = iz * iz;
+  float c = iz2 * 0x1.a01a02p-11f;              // 1/1260
+  c = 0x1.6c16c2p-9f - c;                       // 1/360
+  c = c * iz2;
+  c = 0x1.555556p-4f - c;                       // 1/12
+  c = c * iz;
+  t = t + c;
+  return t - canon_log(prod);
+}
+
 }  // namespace ges

@@ -109,7 +109,8 @@ inline std::string check_splats(const ges_splats* s) {
 
 inline std::string check_params(const ges_raster_params* p) {
   if (!p) return "params is NULL";
-  if (p->falloff != GES_FALLOFF_PHI && p->falloff != GES_FALLOFF_GEF) return "unknown falloff";
+  if (p->falloff != GES_FALLOFF_PHI && p->falloff != GES_FALLOFF_GEF && p->falloff != GES_FALLOFF_PHI_EXACT)
+    return "unknown falloff";
   if (p->tile_cull != GES_TILES_SQUARE && p->tile_cull != GES_TILES_ELLIPSE) return "unknown tile_cull";
   if (!std::isfinite(p->rho) || !std::isfinite(p->bg[0]) || !std::isfinite(p->bg[1]) || !std::isfinite(p->bg[2]))
     return "non-finite raster parameter";

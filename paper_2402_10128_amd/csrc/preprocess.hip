@@ -102,6 +102,13 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
     float e = canon_exp(-t);
     float d = 1.0f + e;
     phi = 2.0f / d;
+  } else if (V.falloff == GES_FALLOFF_PHI_EXACT) {
+    if (!(beta > 0.0f)) { write_culled(V, i); return; }
+    const float a3 = 3.0f / beta, a1 = 1.0f / beta;
+    float dl = canon_lgamma(a3);
+    dl = dl - canon_lgamma(a1);
+    phi = 2.0f * canon_exp(dl);
+    if (!__builtin_isfinite(phi) || !(phi > 0.0f)) { write_culled(V, i); return; }
   } else {
     if (!(beta > 0.0f)) { write_culled(V, i); return; }
     phi = 1.0f;
@@ -178,7 +185,7 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
   float L2 = canon_log(o255);
   L2 = 2.0f * L2;
   float qm;
-  if (V.falloff == GES_FALLOFF_PHI) {
+  if (V.falloff != GES_FALLOFF_GEF) {   // Gaussian falloff (PHI, PHI_EXACT)
     qm = L2;
   } else {
     float e = 2.0f / beta;

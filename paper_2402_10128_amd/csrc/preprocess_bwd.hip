@@ -77,6 +77,19 @@ __device__ __forceinline__ void emit4(float* g, const AdamSplats& A, int64_t idx
   }
 }
 
+// Digamma psi(x) for x > 0 in binary64: psi(x) = psi(x + k) - sum 1/(x + j) up to x + k >= 6, then the
+// asymptotic series ln x - 1/(2x) - 1/(12x^2) + 1/(120x^4) - 1/(252x^6) + 1/(240x^8) - 1/(132x^10).
+__device__ __forceinline__ double digamma(double x) {
+  double acc = 0.0;
+  while (x < 6.0) {
+    acc -= 1.0 / x;
+    x += 1.0;
+  }
+  const double i = 1.0 / x, i2 = i * i;
+  const double series = i2 * (1.0 / 12 - i2 * (1.0 / 120 - i2 * (1.0 / 252 - i2 * (1.0 / 240 - i2 / 132))));
+  return acc + log(x) - 0.5 * i - series;
+}
+
 constexpr int kRowPad = 13;   // float4 slots per staged SH-gradient row (12 used at degree 3; 13 spreads LDS banks)
 
 // Chain rule of splat i.  SH-gradient rows of degrees 1 and 3 (whole float4s) go to `row` in LDS; other
@@ -142,6 +155,7 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
   double phi = 1.0;
   const double rho = V.rho;
   if (V.falloff == GES_FALLOFF_PHI) phi = 2.0 / (1.0 + exp(-(rho * beta - 2.0 * rho)));
+  else if (V.falloff == GES_FALLOFF_PHI_EXACT) phi = 2.0 * exp(lgamma(3.0 / beta) - lgamma(1.0 / beta));
   const double S[3] = {phi * s[0], phi * s[1], phi * s[2]};
   double Mm[9];
   for (int r = 0; r < 3; ++r)
@@ -223,6 +237,8 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
   {
     double gb_ = 0.0;
     if (V.falloff == GES_FALLOFF_PHI) gb_ = gphi * rho * phi * (1.0 - 0.5 * phi);
+    else if (V.falloff == GES_FALLOFF_PHI_EXACT)   // d phi / d beta = phi (psi(1/b) - 3 psi(3/b)) / b^2
+      gb_ = gphi * phi * (digamma(1.0 / beta) - 3.0 * digamma(3.0 / beta)) / (beta * beta);
     else gb_ = gbeta2;
     emit<kAdam, kParBeta>(G.beta, A, i, (float)gb_);
   }

@@ -388,7 +388,7 @@ hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipS
   const int64_t span = 8 * kXcdGroup;   // the grid covers whole rounds of groups
   const dim3 grid((unsigned)((b.total_tiles + span - 1) / span * span));
   // every view of a batch shares the falloff (the server fixes it per instance)
-  if (b.falloff == GES_FALLOFF_PHI)
+  if (b.falloff != GES_FALLOFF_GEF)   // Gaussian falloff (PHI, PHI_EXACT)
     hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_PHI>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
                        b.total_tiles, b.key_capacity);
   else
@@ -404,7 +404,7 @@ hipError_t launch_raster_backward(const DeviceBatch* dbatch, const Batch& b, hip
   if (b.total_tiles == 0) return hipSuccess;
   const int64_t span = 8 * kXcdGroup;   // the grid covers whole rounds of groups
   const dim3 grid((unsigned)((b.total_tiles + span - 1) / span * span));
-  if (b.falloff == GES_FALLOFF_PHI)
+  if (b.falloff != GES_FALLOFF_GEF)
     hipLaunchKernelGGL(raster_backward_kernel<GES_FALLOFF_PHI>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
                        b.total_tiles);
   else
