@@ -21,7 +21,7 @@ GES_OK = 0
 GRAD2D_STRIDE = 12   # GES_GRAD2D_STRIDE: binary64 slots per splat in the 2-D gradient rows
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "CAPACITY", 3: "OUT_OF_MEMORY", 4: "DEVICE", 5: "BUSY",
                 6: "NOT_FOUND", 7: "INTERNAL"}
-FALLOFF_PHI, FALLOFF_GEF = 0, 1
+FALLOFF_PHI, FALLOFF_GEF, FALLOFF_PHI_EXACT = 0, 1, 2
 TILES_SQUARE, TILES_ELLIPSE = 0, 1
 TILE = 16
 
