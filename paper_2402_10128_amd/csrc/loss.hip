@@ -79,7 +79,9 @@ __global__ void blur_h_kernel(const MaskWeights mw, const float* __restrict__ lo
   if (x >= wl) return;
   const float* row = low + (size_t)y * wl;
   float a1 = 0.f, a2 = 0.f;
+#pragma unroll 8
   for (int k = -mw.r1; k <= mw.r1; ++k) a1 += mw.w1[k + mw.r1] * row[min(max(x + k, 0), wl - 1)];
+#pragma unroll 8
   for (int k = -mw.r2; k <= mw.r2; ++k) a2 += mw.w2[k + mw.r2] * row[min(max(x + k, 0), wl - 1)];
   h1[(size_t)y * wl + x] = a1;
   h2[(size_t)y * wl + x] = a2;
@@ -94,8 +96,10 @@ __global__ void __launch_bounds__(128) blur_v_dog_kernel(MaskScratch* __restrict
   const int y = blockIdx.y;
   float d = 0.f;
   if (x < wl) {
-    float a1 = 0.f, a2 = 0.f;
+    float a1 = 0.f, a2 = 0.f;   // unrolled so that several rows' loads are in flight at once
+#pragma unroll 8
     for (int k = -mw.r1; k <= mw.r1; ++k) a1 += mw.w1[k + mw.r1] * h1[(size_t)min(max(y + k, 0), hl - 1) * wl + x];
+#pragma unroll 8
     for (int k = -mw.r2; k <= mw.r2; ++k) a2 += mw.w2[k + mw.r2] * h2[(size_t)min(max(y + k, 0), hl - 1) * wl + x];
     d = fabsf(a1 - a2);
     dog[(size_t)y * wl + x] = d;

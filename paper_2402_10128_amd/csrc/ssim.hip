@@ -31,6 +31,7 @@ constexpr int kSsimIn = kSsimT + 2 * kSsimR;     // staged edge (42)
 constexpr int kSsimPitch = kSsimIn + 1;
 constexpr int kSsimThreads = 256;
 constexpr int kSsimStage = (3 * kSsimIn * kSsimIn + kSsimThreads - 1) / kSsimThreads;   // staged values per thread
+constexpr int kSsimStage1 = (kSsimIn * kSsimIn + kSsimThreads - 1) / kSsimThreads;     // one channel
 constexpr int kSsimGroups = kSsimT / 4;          // 4 neighbouring outputs per thread and pass
 constexpr int kSsimSpan = 4 + 2 * kSsimR;         // staged values those 4 outputs read (14)
 static_assert(kSsimT * kSsimGroups == kSsimThreads, "one 4-output strip per thread in the pass down");
@@ -55,48 +56,47 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_fwd_kernel(const float* __r
                                                                 const SsimWeights wt, float* __restrict__ maps,
                                                                 double* __restrict__ partial, int tiles_x,
                                                                 int ntiles) {
-  __shared__ float sx[3][kSsimIn][kSsimPitch];
-  __shared__ float sy[3][kSsimIn][kSsimPitch];
+  __shared__ float sx[kSsimIn][kSsimPitch];
+  __shared__ float sy[kSsimIn][kSsimPitch];
   __shared__ __align__(16) float hs[5][kSsimIn][kSsimT];
   __shared__ double red[kSsimThreads / 64];
   const int tile = ssim_tile(blockIdx.x, ntiles);
   if (tile < 0) return;
   const int t = threadIdx.x;
   const int x0 = (tile % tiles_x) * kSsimT - kSsimR, y0 = (tile / tiles_x) * kSsimT - kSsimR;
-  // stage both images (all three channels, rows of 42 interleaved pixels = 126 contiguous floats); every
-  // load of a thread is issued before the first LDS store, so their latencies overlap
-  float ra[kSsimStage], rb[kSsimStage];
-#pragma unroll
-  for (int j = 0; j < kSsimStage; ++j) {
-    const int e = t + j * kSsimThreads;
-    ra[j] = 0.f;
-    rb[j] = 0.f;
-    if (e < kSsimIn * kSsimIn * 3) {
-      const int r = e / (kSsimIn * 3), q = e - r * (kSsimIn * 3);
-      const int col = q / 3, c = q - col * 3;
-      const int gx = x0 + col, gy = y0 + r;
-      if (gx >= 0 && gx < w && gy >= 0 && gy < h) {
-        const size_t o = 3 * ((size_t)gy * w + gx) + c;
-        ra[j] = img[o];
-        rb[j] = tgt[o];
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kSsimStage; ++j) {
-    const int e = t + j * kSsimThreads;
-    if (e < kSsimIn * kSsimIn * 3) {
-      const int r = e / (kSsimIn * 3), q = e - r * (kSsimIn * 3);
-      const int col = q / 3, c = q - col * 3;
-      const int gx = x0 + col, gy = y0 + r;
-      const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;   // padding is 0, i.e. -1/2 after the shift
-      sx[c][r][col] = (in ? ra[j] : 0.f) - kSsimShift;
-      sy[c][r][col] = (in ? rb[j] : 0.f) - kSsimShift;
-    }
-  }
   const size_t plane = (size_t)w * h;
   float ssum = 0.f;
   for (int c = 0; c < 3; ++c) {
+    // stage channel c of both images (one channel at a time keeps the block's LDS at 41 KB, three blocks
+    // per CU; the other channels' bytes of each line come again from L2); loads first, then the stores
+    float ra[kSsimStage1], rb[kSsimStage1];
+#pragma unroll
+    for (int j = 0; j < kSsimStage1; ++j) {
+      const int e = t + j * kSsimThreads;
+      ra[j] = 0.f;
+      rb[j] = 0.f;
+      if (e < kSsimIn * kSsimIn) {
+        const int r = e / kSsimIn, col = e - r * kSsimIn;
+        const int gx = x0 + col, gy = y0 + r;
+        if (gx >= 0 && gx < w && gy >= 0 && gy < h) {
+          const size_t o = 3 * ((size_t)gy * w + gx) + c;
+          ra[j] = img[o];
+          rb[j] = tgt[o];
+        }
+      }
+    }
+    __syncthreads();   // the previous channel's horizontal pass has read sx, sy
+#pragma unroll
+    for (int j = 0; j < kSsimStage1; ++j) {
+      const int e = t + j * kSsimThreads;
+      if (e < kSsimIn * kSsimIn) {
+        const int r = e / kSsimIn, col = e - r * kSsimIn;
+        const int gx = x0 + col, gy = y0 + r;
+        const bool in = gx >= 0 && gx < w && gy >= 0 && gy < h;   // padding is 0, i.e. -1/2 after the shift
+        sx[r][col] = (in ? ra[j] : 0.f) - kSsimShift;
+        sy[r][col] = (in ? rb[j] : 0.f) - kSsimShift;
+      }
+    }
     __syncthreads();
     // across: row r, columns 4g..4g+3 from the 14 staged values they span
     for (int i = t; i < kSsimIn * kSsimGroups; i += kSsimThreads) {
@@ -104,8 +104,8 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_fwd_kernel(const float* __r
       float a[kSsimSpan], b[kSsimSpan];
 #pragma unroll
       for (int k = 0; k < kSsimSpan; ++k) {
-        a[k] = sx[c][r][col0 + k];
-        b[k] = sy[c][r][col0 + k];
+        a[k] = sx[r][col0 + k];
+        b[k] = sy[r][col0 + k];
       }
       float m[5][4];
 #pragma unroll
