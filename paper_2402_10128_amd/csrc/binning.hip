@@ -210,35 +210,67 @@ __global__ void __launch_bounds__(kBinBlockThreads) bin_count_kernel(const Devic
 }
 
 // One thread per (view, tile): exclusive prefix over the chunk rows, 16 rows per batch of loads.
+// Column scans: a block takes 64 consecutive tiles; its four waves take a quarter of every column each (the
+// lanes of a wave read 64 consecutive counts per row, one coalesced 256-byte load), the quarters' sums meet
+// in LDS, and each wave writes its quarter's exclusive prefix.  (One lane per whole column left it as one
+// chain of 256 dependent loads.)
+constexpr int kColSplit = 4;
 __global__ void __launch_bounds__(256) bin_colscan_kernel(const DeviceBatch* __restrict__ db, int64_t total_tiles) {
-  const int64_t gt = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (gt >= total_tiles) return;
-  const int v = view_of_block(db->tile_prefix, db->nviews, gt);
-  const ViewDesc& V = db->views[v];
-  const int T = V.tiles_x * V.tiles_y;
-  const int t = (int)(gt - db->tile_prefix[v]);
-  uint32_t* col = V.bin_counts + t;
-  uint32_t acc = 0;
-  const int G = V.bin_blocks;
-  int g = 0;
-  for (; g + 16 <= G; g += 16) {
+  __shared__ uint32_t psum[kColSplit][64];
+  const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+  const int64_t gt = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = gt < total_tiles;
+  int v = 0, T = 1, G = 0, t = 0;
+  uint32_t* col = nullptr;
+  if (live) {
+    v = view_of_block(db->tile_prefix, db->nviews, gt);
+    const ViewDesc& V = db->views[v];
+    T = V.tiles_x * V.tiles_y;
+    t = (int)(gt - db->tile_prefix[v]);
+    col = V.bin_counts + t;
+    G = V.bin_blocks;
+  }
+  const int per = (G + kColSplit - 1) / kColSplit;
+  const int g0 = min(G, part * per), g1 = min(G, g0 + per);
+  uint32_t sum = 0;
+  int g = g0;
+  for (; g + 16 <= g1; g += 16) {   // 16 loads in flight, then their sum
+    uint32_t c[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c[k] = col[(int64_t)(g + k) * T];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sum += c[k];
+  }
+  for (; g < g1; ++g) sum += col[(int64_t)g * T];
+  psum[part][lane] = sum;
+  __syncthreads();
+  if (!live) return;
+  uint32_t acc = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < kColSplit; ++k) {
+    if (k < part) acc += psum[k][lane];
+    total += psum[k][lane];
+  }
+  g = g0;
+  for (; g + 16 <= g1; g += 16) {
     uint32_t c[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) c[k] = col[(int64_t)(g + k) * T];
 #pragma unroll
     for (int k = 0; k < 16; ++k) { col[(int64_t)(g + k) * T] = acc; acc += c[k]; }
   }
-  for (; g < G; ++g) {
+  for (; g < g1; ++g) {
     const uint32_t c = col[(int64_t)g * T];
     col[(int64_t)g * T] = acc;
     acc += c;
   }
-  V.tile_total[t] = acc;
+  if (part == kColSplit - 1) db->views[v].tile_total[t] = total;
 }
 
 // Single block: exclusive scan of every view's tile totals (views in order) into ranges; per-view
 // key counts into the view headers and the batch total into keys_total (saturating at 2^32-1).
 __global__ void __launch_bounds__(1024) bin_tilescan_kernel(const DeviceBatch* __restrict__ db, uint32_t* keys_total) {
+  constexpr int kPer = 8;   // consecutive tiles per thread: one pass covers 8,192 tiles
   __shared__ unsigned long long wsum[16];
   __shared__ unsigned long long carry;
   if (threadIdx.x == 0) carry = 0;
@@ -248,11 +280,17 @@ __global__ void __launch_bounds__(1024) bin_tilescan_kernel(const DeviceBatch* _
     const ViewDesc& V = db->views[v];
     const int T = V.tiles_x * V.tiles_y;
     const unsigned long long view_start = carry;
-    for (int base = 0; base < T; base += 1024) {
-      const int t = base + threadIdx.x;
-      const unsigned long long x = t < T ? V.tile_total[t] : 0ull;
-      // inclusive wave scan
-      unsigned long long s = x;
+    for (int base = 0; base < T; base += 1024 * kPer) {
+      const int t0 = base + threadIdx.x * kPer;
+      uint32_t x[kPer];
+      unsigned long long local = 0;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        x[k] = t0 + k < T ? V.tile_total[t0 + k] : 0u;
+        local += x[k];
+      }
+      // inclusive wave scan of the threads' sums, then the waves' sums in order
+      unsigned long long s = local;
 #pragma unroll
       for (int d = 1; d < 64; d <<= 1) {
         const unsigned long long y = __shfl_up(s, d, 64);
@@ -262,15 +300,20 @@ __global__ void __launch_bounds__(1024) bin_tilescan_kernel(const DeviceBatch* _
       __syncthreads();
       unsigned long long wpre = 0;
       for (int k = 0; k < wid; ++k) wpre += wsum[k];
-      const unsigned long long excl = carry + wpre + s - x;
-      if (t < T) {
-        const unsigned long long e = excl + x;
-        const uint32_t st = excl > 0xffffffffull ? 0xffffffffu : (uint32_t)excl;
-        const uint32_t en = e > 0xffffffffull ? 0xffffffffu : (uint32_t)e;
-        V.ranges[t] = x == 0 ? make_uint2(0u, 0u) : make_uint2(st, en);
+      unsigned long long run = carry + wpre + s - local;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int t = t0 + k;
+        const unsigned long long e = run + x[k];
+        if (t < T) {
+          const uint32_t st = run > 0xffffffffull ? 0xffffffffu : (uint32_t)run;
+          const uint32_t en = e > 0xffffffffull ? 0xffffffffu : (uint32_t)e;
+          V.ranges[t] = x[k] == 0 ? make_uint2(0u, 0u) : make_uint2(st, en);
+        }
+        run = e;
       }
       __syncthreads();
-      if (threadIdx.x == 1023) carry = excl + x;
+      if (threadIdx.x == 1023) carry = run;
       __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -318,7 +361,7 @@ hipError_t launch_bin_count(const DeviceBatch* dbatch, const Batch& b, hipStream
 hipError_t launch_bin_scan(const DeviceBatch* dbatch, const Batch& b, const int32_t* /*tiles_per_view*/,
                            hipStream_t stream) {
   if (b.total_tiles > 0) {
-    hipLaunchKernelGGL(bin_colscan_kernel, dim3((unsigned)((b.total_tiles + 255) / 256)), dim3(256), 0, stream, dbatch,
+    hipLaunchKernelGGL(bin_colscan_kernel, dim3((unsigned)((b.total_tiles + 63) / 64)), dim3(256), 0, stream, dbatch,
                        b.total_tiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
