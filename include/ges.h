@@ -256,6 +256,15 @@ typedef struct {
 ges_status ges_adam_step(const ges_adam_group* groups, int32_t ngroups, int64_t step, float beta1, float beta2,
                          float eps, void* stream);
 
+/* Backward pass of one more view of a multi-view step: like ges_render_backward, but this view's
+ * parameter gradients are ADDED to the buffers of `grads` (which hold the earlier views' sum; the first
+ * view uses ges_render_backward).  grad_accum / grad_count (both NULL or both set) accumulate the
+ * densification statistic as in ges_adam_splats.  Sums run in view order (deterministic). */
+ges_status ges_render_backward_accumulate(const ges_splats* splats, const ges_camera* cam,
+                                          const ges_raster_params* params, void* splat_ws, void* key_ws,
+                                          void* pixel_ws, const float* dL_drgb, const ges_splat_grads* grads,
+                                          float* grad_accum, float* grad_count, void* stream);
+
 /* Backward pass with the optimiser step fused in: the effect of ges_render_backward followed by
  * ges_adam_step over the six parameter arrays of `splats` (same arguments and rules as those two
  * calls), in one pass over the splats: each parameter gradient goes straight into its Adam update
@@ -276,6 +285,9 @@ typedef struct {
   float* grad_accum;             /* [n] densification statistic, or NULL: every visible splat adds the norm of its
                                     mean-2D gradient in NDC units, ||(dL/du W/2, dL/dv H/2)|| ... */
   float* grad_count;             /* [n] ... and 1 here (both NULL or both set) */
+  const float* grads_in[6];      /* per parameter array, or NULL: gradients of other views (e.g. summed by
+                                    ges_render_backward_accumulate) added to this view's before the update;
+                                    quats and, at SH degree 1 or 3, sh must be 16-byte aligned */
 } ges_adam_splats;
 ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
                                     void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,

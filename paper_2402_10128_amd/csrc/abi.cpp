@@ -205,10 +205,11 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
 
 static ges_status render_backward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
                                   void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
-                                  const ges_splat_grads* grads, const ges::AdamSplats* adam, void* stream_) {
+                                  const ges_splat_grads* grads, const ges::AdamSplats* adam, bool fused,
+                                  void* stream_) {
   const std::string e = check_all(splats, cam, params);
   if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
-  if (!splat_ws || !pixel_ws || !dL_drgb || (!grads && !adam)) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (!splat_ws || !pixel_ws || !dL_drgb || (!grads && !fused)) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
   const ges_splat_grads none{};
   if (!grads) grads = &none;
   if (grads->quats && (reinterpret_cast<uintptr_t>(grads->quats) & 15u))
@@ -228,7 +229,7 @@ static ges_status render_backward(const ges_splats* splats, const ges_camera* ca
                 }), "zero grad2d");
   GES_CHECK_HIP(timed(GES_STAGE_RASTER_BACKWARD, stream, [&] { return ges::launch_raster_backward(db, b, stream); }), "raster_backward");
   GES_CHECK_HIP(timed(GES_STAGE_PREPROCESS_BACKWARD, stream,
-                      [&] { return ges::launch_preprocess_backward(db, b, grads, stream, adam); }),
+                      [&] { return ges::launch_preprocess_backward(db, b, grads, stream, adam, fused); }),
                 "preprocess_backward");
   return GES_OK;
 }
@@ -237,7 +238,23 @@ ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, 
                                void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
                                const ges_splat_grads* grads, void* stream) {
   if (!grads) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
-  return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, nullptr, stream);
+  return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, nullptr, false, stream);
+}
+
+ges_status ges_render_backward_accumulate(const ges_splats* splats, const ges_camera* cam,
+                                          const ges_raster_params* params, void* splat_ws, void* key_ws,
+                                          void* pixel_ws, const float* dL_drgb, const ges_splat_grads* grads,
+                                          float* grad_accum, float* grad_count, void* stream) {
+  if (!grads || !cam) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if ((grad_accum == nullptr) != (grad_count == nullptr))
+    return fail(GES_ERR_INVALID_ARGUMENT, "grad_accum and grad_count go together");
+  ges::AdamSplats a{};
+  a.accumulate = 1;
+  a.stat_accum = grad_accum;
+  a.stat_count = grad_count;
+  a.half_w = 0.5 * (double)cam->width;
+  a.half_h = 0.5 * (double)cam->height;
+  return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, &a, false, stream);
 }
 
 ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
@@ -278,7 +295,12 @@ ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* 
   a.stat_count = opt->grad_count;
   a.half_w = cam ? 0.5 * (double)cam->width : 0.0;
   a.half_h = cam ? 0.5 * (double)cam->height : 0.0;
-  return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, &a, stream);
+  for (int k = 0; k < ges::kNumPar; ++k) a.gin[k] = opt->grads_in[k];
+  const bool sh_vec_in = splats->sh_degree == 1 || splats->sh_degree == 3;
+  if ((reinterpret_cast<uintptr_t>(a.gin[ges::kParQuats]) & 15u) ||
+      (sh_vec_in && (reinterpret_cast<uintptr_t>(a.gin[ges::kParSh]) & 15u)))
+    return fail(GES_ERR_INVALID_ARGUMENT, "grads_in quats/sh must be 16-byte aligned");
+  return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, &a, true, stream);
 }
 
 ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* splat_ws, void* key_ws, uint64_t num_keys,

@@ -128,6 +128,8 @@ struct AdamSplats {
   float* stat_accum;        // densification statistics (NULL: off): NDC mean-2D gradient norm ...
   float* stat_count;        // ... and the number of iterations the splat was visible
   double half_w, half_h;    // pixels per NDC unit
+  const float* gin[kNumPar];  // fused update: gradients of other views added first (NULL: none)
+  int32_t accumulate;       // stored gradients: add to the buffers instead of overwriting them
 };
 
 // --------------------------------------------------------------------------------------------
@@ -139,8 +141,10 @@ hipError_t launch_bin_scatter(const DeviceBatch* dbatch, const Batch& b, hipStre
 hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_raster_backward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+// args (may be NULL): the fused update's arguments when `fused`; otherwise only accumulate and the
+// densification statistic are read
 hipError_t launch_preprocess_backward(const DeviceBatch* dbatch, const Batch& b, const ges_splat_grads* grads,
-                                      hipStream_t stream, const AdamSplats* adam = nullptr);
+                                      hipStream_t stream, const AdamSplats* args = nullptr, bool fused = false);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
 
 hipError_t launch_freq_mask(const float* target, int w, int h, float omega, void* scratch, uint8_t* mask,

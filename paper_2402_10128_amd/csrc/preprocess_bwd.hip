@@ -50,7 +50,10 @@ __device__ __forceinline__ void sh_basis_f64(double x, double y, double z, int d
 // applied at once as an Adam update of the parameter (the gradient never goes through memory).
 template <bool kAdam, int P>
 __device__ __forceinline__ void emit(float* g, const AdamSplats& A, int64_t idx, float val) {
-  if (g) g[idx] = val;
+  if constexpr (kAdam) {
+    if (A.gin[P]) val = A.gin[P][idx] + val;      // the other views' gradients, then this view's
+  }
+  if (g) g[idx] = A.accumulate ? g[idx] + val : val;
   if constexpr (kAdam) {
     float p = A.p[P][idx], m = A.m[P][idx], v = A.v[P][idx];
     adam_update(p, val, m, v, A.b1, A.b2, A.eps, A.step_size[P], A.inv_sqrt_bc2);
@@ -62,7 +65,21 @@ __device__ __forceinline__ void emit(float* g, const AdamSplats& A, int64_t idx,
 
 template <bool kAdam, int P>
 __device__ __forceinline__ void emit4(float* g, const AdamSplats& A, int64_t idx4, float4 val) {
-  if (g) reinterpret_cast<float4*>(g)[idx4] = val;
+  if constexpr (kAdam) {
+    if (A.gin[P]) {
+      const float4 o = reinterpret_cast<const float4*>(A.gin[P])[idx4];
+      val = make_float4(o.x + val.x, o.y + val.y, o.z + val.z, o.w + val.w);
+    }
+  }
+  if (g) {
+    float4* d = reinterpret_cast<float4*>(g) + idx4;
+    if (A.accumulate) {
+      const float4 o = *d;
+      *d = make_float4(o.x + val.x, o.y + val.y, o.z + val.z, o.w + val.w);
+    } else {
+      *d = val;
+    }
+  }
   if constexpr (kAdam) {
     float4 p = reinterpret_cast<const float4*>(A.p[P])[idx4];
     float4 m = reinterpret_cast<const float4*>(A.m[P])[idx4];
@@ -120,12 +137,10 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
   const uint32_t flags = vis & 0xffu;
   const double2* gp = reinterpret_cast<const double2*>(V.grad2d + (int64_t)kGradStride * i);
   const double2 g01 = gp[0], g23 = gp[1], g45 = gp[2], g67 = gp[3], g89 = gp[4];
-  if constexpr (kAdam) {
-    if (A.stat_accum) {   // densification statistic: the mean-2D gradient in NDC units
-      const double su = g01.x * A.half_w, sv = g01.y * A.half_h;
-      A.stat_accum[i] += (float)sqrt(su * su + sv * sv);
-      A.stat_count[i] += 1.f;
-    }
+  if (A.stat_accum) {   // densification statistic: the mean-2D gradient in NDC units
+    const double su = g01.x * A.half_w, sv = g01.y * A.half_h;
+    A.stat_accum[i] += (float)sqrt(su * su + sv * sv);
+    A.stat_count[i] += 1.f;
   }
   const double grgb[3] = {g67.x, g67.y, g89.x};
   const double gu = g01.x, gv = g01.y, ga = g23.x, gb = g23.y, gc = g45.x, gop = g45.y;
@@ -377,16 +392,17 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(const DeviceBa
 }
 
 hipError_t launch_preprocess_backward(const DeviceBatch* dbatch, const Batch& b, const ges_splat_grads* grads,
-                                      hipStream_t stream, const AdamSplats* adam) {
+                                      hipStream_t stream, const AdamSplats* args, bool fused) {
   if (b.pre_blocks == 0) return hipSuccess;
   const ges_splat_grads none{};
   const ges_splat_grads& g = grads ? *grads : none;
-  if (adam)
+  const AdamSplats a = args ? *args : AdamSplats{};
+  if (fused)
     hipLaunchKernelGGL(preprocess_backward_kernel<true>, dim3((unsigned)b.pre_blocks), dim3(256), 0, stream, dbatch, g,
-                       *adam);
+                       a);
   else
     hipLaunchKernelGGL(preprocess_backward_kernel<false>, dim3((unsigned)b.pre_blocks), dim3(256), 0, stream, dbatch,
-                       g, AdamSplats{});
+                       g, a);
   return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ class ges_adam_group(C.Structure):
 class ges_adam_splats(C.Structure):
     _fields_ = [("exp_avg", C.c_void_p * 6), ("exp_avg_sq", C.c_void_p * 6), ("lr", C.c_float * 6),
                 ("step", C.c_int64), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
-                ("grad_accum", C.c_void_p), ("grad_count", C.c_void_p)]
+                ("grad_accum", C.c_void_p), ("grad_count", C.c_void_p), ("grads_in", C.c_void_p * 6)]
 
 
 class ges_splat_set(C.Structure):
@@ -123,6 +123,10 @@ _SIGS = {
     "ges_mix_fit": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_float,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_float,
                               C.c_float, C.c_float, C.c_void_p]),
+    "ges_render_backward_accumulate": (C.c_int, [C.POINTER(ges_splats), C.POINTER(ges_camera),
+                                                 C.POINTER(ges_raster_params), C.c_void_p, C.c_void_p, C.c_void_p,
+                                                 C.c_void_p, C.POINTER(ges_splat_grads), C.c_void_p, C.c_void_p,
+                                                 C.c_void_p]),
     "ges_densify_scratch_bytes": (C.c_size_t, [C.c_int64]),
     "ges_densify": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(ges_splat_set), C.POINTER(ges_splat_set), C.c_int32,
                               C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
@@ -323,10 +327,13 @@ SPLAT_PARAMS = ("means", "log_scales", "quats", "opacity_logits", "sh", "beta")
 
 def ges_render_backward_adam(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, exp_avg: dict,
                              exp_avg_sq: dict, lrs: dict, step, beta1=0.9, beta2=0.999, eps=1e-15, grads=None,
-                             grad_accum=None, grad_count=None, stream=None):
+                             grad_accum=None, grad_count=None, grads_in=None, stream=None):
     """Backward pass with Adam fused in: updates the tensors behind ``splats`` and the moments in place; with
-    grad_accum/grad_count also accumulates the densification statistic."""
+    grad_accum/grad_count also accumulates the densification statistic; grads_in (dict) holds other views'
+    gradients added to this view's before the update."""
     opt = ges_adam_splats()
+    for k, name in enumerate(SPLAT_PARAMS):
+        opt.grads_in[k] = None if grads_in is None else grads_in[name].data_ptr()
     opt.grad_accum = None if grad_accum is None else grad_accum.data_ptr()
     opt.grad_count = None if grad_count is None else grad_count.data_ptr()
     for k, name in enumerate(SPLAT_PARAMS):
@@ -420,6 +427,18 @@ def ges_mix_fit(problems, targets, x0, dx, params, epochs, lr, beta1=0.9, beta2=
                              int(epochs),
                              float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
     return final_loss
+
+
+def ges_render_backward_accumulate(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads: dict,
+                                   grad_accum=None, grad_count=None, stream=None):
+    """Backward pass of one more view: its parameter gradients are added to ``grads``."""
+    g = ges_splat_grads()
+    for k in SPLAT_PARAMS:
+        t = grads.get(k)
+        setattr(g, k, None if t is None else t.data_ptr())
+    _check(lib().ges_render_backward_accumulate(C.byref(splats), C.byref(cam), C.byref(params), _ptr(splat_ws),
+                                                _ptr(key_ws), _ptr(pixel_ws), _ptr(dL_drgb), C.byref(g),
+                                                _ptr(grad_accum), _ptr(grad_count), _stream(stream)))
 
 
 def ges_expon_lr(step, lr_init, lr_final, max_steps, delay_steps=0, delay_mult=1.0) -> float:

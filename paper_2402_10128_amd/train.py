@@ -73,19 +73,28 @@ class TrainStep:
     scene: dict of contiguous float32 CUDA tensors (means, log_scales, quats, opacity_logits, sh, beta).
     """
 
-    def __init__(self, scene: dict, cam, target: torch.Tensor, cfg: TrainConfig | None = None):
+    def __init__(self, scene: dict, cam, target, cfg: TrainConfig | None = None):
+        """cam, target: one view, or equal-sized lists of views of one resolution trained together: the loss is
+        the mean over the views, their gradients are summed (view order) before one update."""
         self.cfg = cfg or TrainConfig()
         self.scene = scene
-        self.cam = cam
-        self.target = target.contiguous()
-        dev = target.device
-        self.c = G.camera_struct(cam)
+        self.cams = list(cam) if isinstance(cam, (list, tuple)) else [cam]
+        self.targets = [t.contiguous() for t in (target if isinstance(target, (list, tuple)) else [target])]
+        if len(self.cams) != len(self.targets) or not self.cams:
+            raise ValueError("one target per camera")
+        if any((c.width, c.height) != (self.cams[0].width, self.cams[0].height) for c in self.cams):
+            raise ValueError("the views of one step share a resolution")
+        self.cam, self.target = self.cams[0], self.targets[0]
+        dev = self.target.device
+        self.cstructs = [G.camera_struct(c) for c in self.cams]
+        self.c = self.cstructs[0]
         self.p = G.params_struct(self.cfg.falloff, self.cfg.tile_cull, self.cfg.rho, self.cfg.bg)
-        H, W = cam.height, cam.width
+        H, W = self.cam.height, self.cam.width
         self._bind_scene()
         self.image = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
         self.dL = torch.empty_like(self.image)
-        self.loss = torch.empty((), dtype=torch.float32, device=dev)
+        self.view_loss = torch.empty(len(self.cams), dtype=torch.float32, device=dev)
+        self.loss = self.view_loss[0]
         self.mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
         self.mask_scratch = torch.empty(G.lib().ges_mask_scratch_bytes(W, H), dtype=torch.uint8, device=dev)
         self.loss_scratch = torch.empty(G.lib().ges_loss_scratch_bytes(), dtype=torch.uint8, device=dev)
@@ -173,36 +182,48 @@ class TrainStep:
         L = G.lib()
         stream = G._stream(None)
         H, W = self.cam.height, self.cam.width
-        _check(L.ges_freq_mask(G._ptr(self.target), W, H, float(self.omega(it)), G._ptr(self.mask_scratch),
-                               G._ptr(self.mask), stream))
-        if read_num_keys:
-            k = G.ges_preprocess(self.s, self.c, self.p, self.frame.splat_ws, True)
-            self.frame.ensure_keys(k)
-        else:
-            G.ges_preprocess(self.s, self.c, self.p, self.frame.splat_ws, False)
-            k = self.frame.key_capacity
-        self.frame.num_keys = k
-        G.ges_render_forward(self.s, self.c, self.p, self.frame.splat_ws, self.frame.key_ws, k, self.frame.pixel_ws,
-                             self.image)
-        lam_l1 = 1.0 - c.lam_ssim - c.lam_omega
-        G.ges_loss(self.image, self.target, self.mask, lam_l1, c.lam_omega, self.dL, self.loss, self.loss_scratch)
-        G.ges_ssim_loss(self.image, self.target, c.lam_ssim, self.loss, self.dL, self.ssim_scratch)
+        B = len(self.cams)
         lrs = self.learning_rates(it)
         stats = c.densify_interval > 0 and it < c.densify_until
-        if fused:
-            G.ges_render_backward_adam(self.s, self.c, self.p, self.frame.splat_ws, self.frame.key_ws,
-                                       self.frame.pixel_ws, self.dL, self.exp_avg, self.exp_avg_sq, lrs, it,
-                                       c.beta1, c.beta2, c.eps,
-                                       grad_accum=self.grad_accum if stats else None,
-                                       grad_count=self.grad_count if stats else None)
-        else:
-            if self.grads is None:
-                self.grads = {k: torch.empty_like(v) for k, v in self.scene.items()}
-            G.ges_render_backward(self.s, self.c, self.p, self.frame.splat_ws, self.frame.key_ws,
-                                  self.frame.pixel_ws, self.dL, self.grads)
+        acc = self.grad_accum if stats else None
+        cnt = self.grad_count if stats else None
+        if (B > 1 or not fused) and self.grads is None:
+            self.grads = {k: torch.empty_like(v) for k, v in self.scene.items()}
+        for v in range(B):
+            cs, target = self.cstructs[v], self.targets[v]
+            _check(L.ges_freq_mask(G._ptr(target), W, H, float(self.omega(it)), G._ptr(self.mask_scratch),
+                                   G._ptr(self.mask), stream))
+            if read_num_keys:
+                k = G.ges_preprocess(self.s, cs, self.p, self.frame.splat_ws, True)
+                self.frame.ensure_keys(k)
+            else:
+                G.ges_preprocess(self.s, cs, self.p, self.frame.splat_ws, False)
+                k = self.frame.key_capacity
+            self.frame.num_keys = k
+            G.ges_render_forward(self.s, cs, self.p, self.frame.splat_ws, self.frame.key_ws, k, self.frame.pixel_ws,
+                                 self.image)
+            # the step's loss is the mean over the views: each view's terms carry 1/B
+            lam_l1 = (1.0 - c.lam_ssim - c.lam_omega) / B
+            loss_v = self.view_loss[v]
+            G.ges_loss(self.image, target, self.mask, lam_l1, c.lam_omega / B, self.dL, loss_v, self.loss_scratch)
+            G.ges_ssim_loss(self.image, target, c.lam_ssim / B, loss_v, self.dL, self.ssim_scratch)
+            ws = (self.s, cs, self.p, self.frame.splat_ws, self.frame.key_ws, self.frame.pixel_ws, self.dL)
+            last = v == B - 1
+            if fused and last:   # the last view's backward updates from the sum of every view's gradients
+                G.ges_render_backward_adam(*ws, self.exp_avg, self.exp_avg_sq, lrs, it, c.beta1, c.beta2, c.eps,
+                                           grad_accum=acc, grad_count=cnt, grads_in=self.grads if B > 1 else None)
+            elif v == 0 and acc is None:
+                G.ges_render_backward(*ws, self.grads)
+            else:
+                if v == 0:
+                    for g in self.grads.values():
+                        g.zero_()
+                G.ges_render_backward_accumulate(*ws, self.grads, acc, cnt)
+        if not fused:
             groups = [(self.scene[k], self.grads[k], self.exp_avg[k], self.exp_avg_sq[k], lrs[k])
                       for k in GROUP_ORDER]
             G.ges_adam_step(groups, it, c.beta1, c.beta2, c.eps)
+        self.loss = self.view_loss.sum() if B > 1 else self.view_loss[0]
         if stats and it > c.densify_from and it % c.densify_interval == 0:
             self.densify()
         if c.shape_prune_interval and it % c.shape_prune_interval == 0:

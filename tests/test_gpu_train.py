@@ -146,3 +146,62 @@ def test_prune_and_shape_reset_hooks():
     assert torch.all(ts.scene["beta"] == 2.0) and not ts.exp_avg["beta"].any() and not ts.exp_avg_sq["beta"].any()
     losses = [loss] + [float(ts.step(it).cpu()) for it in (4, 5)]
     assert all(np.isfinite(losses))
+
+
+def test_accumulating_backward_matches_the_oracle_sum_over_views():
+    """Two views of the 1,000-splat workload: the first view's backward, then the second's added with
+    ges_render_backward_accumulate, against the sum of the oracle's gradients of both views (within the
+    parity bound beyond the summed allowances for floating-point-ambiguous decisions)."""
+    from .parity_helpers import grad3d_check
+    cfg_w = synth.make_config(0)
+    sc, cam0 = cfg_w["scene"], cfg_w["camera"]
+    cam1 = synth.pinhole(cam0.width, cam0.height, (0.6, -0.4, -3.8))
+    arrays = sc.arrays()
+    rng = np.random.default_rng(17)
+    dLs = [rng.standard_normal((cam0.height, cam0.width, 3)).astype(np.float32) for _ in range(2)]
+    refs = [oracle_full(arrays, sc.sh_degree, cam, 0, 1, dL=d.astype(np.float64)) for cam, d in zip((cam0, cam1), dLs)]
+    t = to_device(arrays)
+    s = G.splats_struct(*(t[k] for k in G.SPLAT_PARAMS))
+    p = G.params_struct(0, 1, 0.1, (0.0, 0.0, 0.0))
+    frame = G.Frame.create(s.n, cam0.width, cam0.height, "cuda")
+    grads = {k: torch.empty_like(v) for k, v in t.items()}
+    out = torch.empty((cam0.height, cam0.width, 3), device="cuda")
+    for v, cam in enumerate((cam0, cam1)):
+        c = G.camera_struct(cam)
+        k = G.ges_preprocess(s, c, p, frame.splat_ws, True)
+        frame.ensure_keys(k)
+        G.ges_render_forward(s, c, p, frame.splat_ws, frame.key_ws, k, frame.pixel_ws, out)
+        ws = (s, c, p, frame.splat_ws, frame.key_ws, frame.pixel_ws, torch.from_numpy(dLs[v]).cuda())
+        if v == 0:
+            G.ges_render_backward(*ws, grads)
+        else:
+            G.ges_render_backward_accumulate(*ws, grads)
+    torch.cuda.synchronize()
+    for k in G.SPLAT_PARAMS:
+        want = np.asarray(refs[0]["grads"][k]) + np.asarray(refs[1]["grads"][k])
+        allow = np.asarray(refs[0]["allow"][k]) + np.asarray(refs[1]["allow"][k])
+        e = grad3d_check(grads[k].cpu().numpy(), want, allow)
+        assert e["max"] <= GRAD_RTOL, (k, e)
+
+
+def test_multi_view_step_fused_equals_two_calls():
+    """A two-view training step: the fused update from the summed gradients (grads_in) and the stand-alone
+    Adam after both views' accumulated backward give the same bits over three steps."""
+    cfg_w = synth.make_config(0)
+    sc, cam0 = cfg_w["scene"], cfg_w["camera"]
+    cam1 = synth.pinhole(cam0.width, cam0.height, (0.6, -0.4, -3.8))
+    tg = torch.as_tensor(np.asarray(cfg_w["target"], np.float32)).cuda()
+    tg1 = torch.flip(tg, dims=[1]).contiguous()
+    runs = []
+    for fused in (True, False):
+        scene = to_device(sc.arrays())
+        ts = TrainStep(scene, [cam0, cam1], [tg, tg1], TrainConfig())
+        losses = [float(ts.step(it, fused=fused).cpu()) for it in range(1, 4)]
+        torch.cuda.synchronize()
+        runs.append((scene, ts.exp_avg, ts.exp_avg_sq, ts.grad_accum, ts.grad_count, losses))
+    for k in GROUP_ORDER:
+        for a, b in zip(runs[0][:3], runs[1][:3]):
+            assert torch.equal(a[k], b[k]), k
+    assert torch.equal(runs[0][3], runs[1][3]) and torch.equal(runs[0][4], runs[1][4])
+    assert runs[0][5] == runs[1][5] and all(np.isfinite(runs[0][5]))
+    assert 0 < float(runs[0][4].max().cpu()) <= 3 * 2          # at most one visit per view and step
