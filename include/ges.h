@@ -110,7 +110,9 @@ const char* ges_last_error(void);
  * splat_ws holds the per-splat projected records, the tile-binning tables, the
  * tile ranges and the per-splat 2-D gradient accumulators; pixel_ws holds the
  * per-pixel final transmittance and contributor count that the backward pass
- * re-uses (so no per-pixel lists are stored).  Either output pointer may be NULL. */
+ * re-uses (so no per-pixel lists are stored).  Either output pointer may be NULL.
+ * Both workspaces are caller-owned device memory and must be 256-byte aligned (device allocations
+ * are); the preprocess, forward and backward entry points reject others with INVALID_ARGUMENT. */
 ges_status ges_workspace_query(int64_t n, int32_t width, int32_t height, size_t* splat_ws_bytes,
                                size_t* pixel_ws_bytes);
 

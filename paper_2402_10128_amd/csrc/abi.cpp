@@ -156,6 +156,7 @@ ges_status ges_preprocess(const ges_splats* splats, const ges_camera* cam, const
   const std::string e = check_all(splats, cam, params);
   if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
   if (!splat_ws) return fail(GES_ERR_INVALID_ARGUMENT, "splat_ws is NULL");
+  if (reinterpret_cast<uintptr_t>(splat_ws) & 255u) return fail(GES_ERR_INVALID_ARGUMENT, "splat_ws must be 256-byte aligned");
   const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
   if (splat_ws_bytes < fp.splat_bytes) return fail(GES_ERR_CAPACITY, "splat workspace too small");
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
@@ -181,6 +182,8 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
   const std::string e = check_all(splats, cam, params);
   if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
   if (!splat_ws || !pixel_ws || !out_rgb) return fail(GES_ERR_INVALID_ARGUMENT, "NULL workspace or output");
+  if ((reinterpret_cast<uintptr_t>(splat_ws) | reinterpret_cast<uintptr_t>(pixel_ws)) & 255u)
+    return fail(GES_ERR_INVALID_ARGUMENT, "workspaces must be 256-byte aligned");
   if (num_keys >= 0xffffffffull) return fail(GES_ERR_CAPACITY, "more than 2^32-2 keys");
   const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
   const ges::KeyPlan kp = ges::plan_keys(num_keys, fp.tiles);
@@ -210,6 +213,8 @@ static ges_status render_backward(const ges_splats* splats, const ges_camera* ca
   const std::string e = check_all(splats, cam, params);
   if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
   if (!splat_ws || !pixel_ws || !dL_drgb || (!grads && !fused)) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(splat_ws) | reinterpret_cast<uintptr_t>(pixel_ws)) & 255u)
+    return fail(GES_ERR_INVALID_ARGUMENT, "workspaces must be 256-byte aligned");
   const ges_splat_grads none{};
   if (!grads) grads = &none;
   if (grads->quats && (reinterpret_cast<uintptr_t>(grads->quats) & 15u))

@@ -17,7 +17,7 @@ struct FramePlan {
   int bin_blocks = 1, bin_chunk = 0;
   // splat workspace
   size_t off_db = 0, off_hdr = 0, off_rec = 0, off_grad = 0, off_vis = 0, off_counts = 0, off_total = 0,
-         off_ranges = 0, off_tstats = 0;
+         off_ranges = 0, off_tstats = 0, off_twork = 0, off_gorder = 0;
   size_t splat_bytes = 0;
   // pixel workspace
   size_t off_final_T = 0, off_n_contrib = 0, pixel_bytes = 0;
@@ -43,6 +43,8 @@ inline FramePlan plan_frame(int64_t n, int w, int h) {
   p.off_total = o;   o += align256((size_t)p.tiles * 4);
   p.off_ranges = o;  o += align256((size_t)p.tiles * 8);
   p.off_tstats = o;  o += align256((size_t)p.tiles * 16);
+  p.off_twork = o;   o += align256((size_t)p.tiles * 4);
+  p.off_gorder = o;  o += align256((size_t)(p.tiles + 7) / 8 * 4);
   p.splat_bytes = o;
   size_t q = 0;
   const size_t px = (size_t)w * h;
@@ -156,6 +158,8 @@ inline void attach_splat_ws(ViewDesc& V, const FramePlan& fp, void* splat_ws) {
   V.tile_total = reinterpret_cast<uint32_t*>(b + fp.off_total);
   V.ranges = reinterpret_cast<uint2*>(b + fp.off_ranges);
   V.tile_stats = reinterpret_cast<unsigned long long*>(b + fp.off_tstats);
+  V.tile_work = reinterpret_cast<uint32_t*>(b + fp.off_twork);
+  V.group_order = reinterpret_cast<uint32_t*>(b + fp.off_gorder);
   V.header = reinterpret_cast<unsigned long long*>(b + fp.off_hdr);
   V.bin_blocks = fp.bin_blocks;
   V.bin_chunk = fp.bin_chunk;

@@ -61,6 +61,8 @@ struct ViewDesc {
   uint2* ranges;                 // [tiles] [start,end) into the key arrays (global positions)
   unsigned long long* header;    // [0] keys of this view, [1] error flags, [2] [3] pair statistics
   unsigned long long* tile_stats;  // [tiles][2] pairs examined and composited per tile (forward pass)
+  uint32_t* tile_work;           // [tiles] list position + 1 of the tile's last composited splat (forward pass)
+  uint32_t* group_order;         // [ceil(tiles / 8)] tile groups, heaviest backward walk first
   double* grad2d;                // [n][kGradStride] binary64 accumulators (cross-tile sums)
   uint32_t* vis;                 // [n] bit 31: the splat touches a tile; bits 0..4: its clamp flags
   float* final_T;                // [h*w]

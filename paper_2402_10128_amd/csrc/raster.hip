@@ -52,6 +52,20 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t blk) {
   return ((blk & 7) + 8 * (i / kXcdGroup)) * kXcdGroup + (i % kXcdGroup);
 }
 
+// The backward pass of a single view deals groups of kXcdGroup tiles in the order group_order gives (its
+// heaviest walks first, so that the longest waves start at once and the light ones fill in behind them),
+// group by group to the XCDs as xcd_tile does.  Returns -1 past the last tile.
+__device__ __forceinline__ int64_t ordered_tile(int64_t blk, const uint32_t* group_order, int64_t tiles) {
+  const int64_t i = blk >> 3;
+  const int64_t gi = (blk & 7) + 8 * (i / kXcdGroup);
+  const int64_t ngroups = (tiles + kXcdGroup - 1) / kXcdGroup;
+  if (gi >= ngroups) return -1;
+  const uint32_t g = group_order[gi];
+  if (g >= ngroups) return -1;
+  const int64_t t = (int64_t)g * kXcdGroup + (i % kXcdGroup);
+  return t < tiles ? t : -1;
+}
+
 template <int FALLOFF>
 __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* __restrict__ db,
                                                             const uint32_t* __restrict__ sorted_ids,
@@ -137,13 +151,17 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
     // every tile into one counter serialise across the XCDs: two per tile cost about 50 us per frame.)
     // pixels still alive examined the whole list (out-of-image pixels were never alive)
     unsigned long long e = (unsigned long long)n_exam + (unsigned long long)__popc(alive) * (uint32_t)n, b = n_blend;
+    // and the length of the backward walk over the tile: its last composited position
+    uint32_t m = max(max(last[0], last[1]), max(last[2], last[3]));
     for (int off = 32; off > 0; off >>= 1) {
       e += __shfl_xor(e, off, 64);
       b += __shfl_xor(b, off, 64);
+      m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
     }
     if (lane == 0) {
       V.tile_stats[2 * lt] = e;
       V.tile_stats[2 * lt + 1] = b;
+      V.tile_work[lt] = m;
     }
   }
 #pragma unroll
@@ -190,12 +208,12 @@ constexpr int kFlush = 32;   // splats whose row partials are parked in LDS befo
 template <int FALLOFF>
 __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* __restrict__ db,
                                                              const uint32_t* __restrict__ sorted_ids,
-                                                             int64_t total_tiles) {
+                                                             int64_t total_tiles, int ordered) {
   __shared__ float4 sA[64], sB[64], sC[64];
   __shared__ float sRed[kFlush][4][10];   // [splat slot][lane row][component]
   __shared__ uint32_t sId[kFlush];
-  const int64_t gt = xcd_tile(blockIdx.x);
-  if (gt >= total_tiles) return;
+  const int64_t gt = ordered ? ordered_tile(blockIdx.x, db->views[0].group_order, total_tiles) : xcd_tile(blockIdx.x);
+  if (gt < 0 || gt >= total_tiles) return;
   const int v = view_of_block(db->tile_prefix, db->nviews, gt);
   const ViewDesc& V = db->views[v];
   const int lt = (int)(gt - db->tile_prefix[v]);
@@ -282,7 +300,7 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         const bool clamped = oG > kAlphaMax;
         const float alpha = valid ? (clamped ? kAlphaMax : oG) : 0.f;
         const float inv = valid ? fast_rcp(1.f - alpha) : 1.f;
-        T[k] = valid ? T[k] * inv : T[k];  // transmittance before this splat
+        T[k] = T[k] * inv;                 // transmittance before this splat (unchanged: inv = 1 exactly)
         const float w = alpha * T[k];
         pr = __builtin_fmaf(w, g[k][0], pr);
         pg = __builtin_fmaf(w, g[k][1], pg);
@@ -294,20 +312,21 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         S[k][1] = __builtin_fmaf(alpha, d1, S[k][1]);
         S[k][2] = __builtin_fmaf(alpha, d2, S[k][2]);
         any = any || valid;
-        // below the clamp: dL/do = G dL/dalpha and G dL/dG = alpha dL/dalpha; above it both are 0
-        const bool grad = valid && !clamped;
-        po = __builtin_fmaf(grad ? G : 0.f, dalpha, po);
-        const float adal = grad ? alpha * dalpha : 0.f;
+        // below the clamp: dL/do = G dL/dalpha and G dL/dG = alpha dL/dalpha = o (G dL/dalpha); above it
+        // both are 0.  Per pixel only gd = G dL/dalpha is formed: the opacity o and the constant of dG/dq
+        // are common to the splat's terms and multiply its row sums once (dq below is dL/dq / (o k)).
+        const float gd = (valid && !clamped) ? G * dalpha : 0.f;
+        po += gd;
         float dq;
         if (FALLOFF == GES_FALLOFF_PHI) {
-          dq = q0 >= 0.f ? -0.5f * adal : 0.f;
+          dq = q0 >= 0.f ? gd : 0.f;   // dG/dq = -G/2: k = -1/2
         } else {
-          // dG/dq = -(beta/4) q^(beta/2 - 1) G  (q floored at 1e-12);  dG/dbeta = -(1/4) q^(beta/2) ln q G
+          // dG/dq = -(beta/4) q^(beta/2 - 1) G  (q floored at 1e-12): k = -beta/4;
+          // dG/dbeta = -(1/4) q^(beta/2) ln q G: the row sum of q^(beta/2) log2 q gd takes -(ln 2)/4 o
           const float qf = fmaxf(q, 1e-12f);
           const float qpow = fast_exp2((0.5f * B.w - 1.f) * fast_log2(qf));
-          dq = (grad && q0 >= 0.f) ? (-0.25f * B.w) * qpow * adal : 0.f;
-          const float cb = (grad && q > 0.f) ? -0.25f * qb * (lq * 0.69314718055994531f) : 0.f;
-          pbeta = __builtin_fmaf(cb, adal, pbeta);
+          dq = q0 >= 0.f ? qpow * gd : 0.f;
+          pbeta = __builtin_fmaf(q > 0.f ? qb * lq : 0.f, gd, pbeta);
         }
         const float dqdx = dq * dx, dqdy = dq * dy;
         su = __builtin_fmaf(dq, __builtin_fmaf(A.z, dx, A.w * dy), su);
@@ -322,9 +341,12 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         const float r5 = row_sum(po), r6 = row_sum(pr), r7 = row_sum(pg), r8 = row_sum(pbl);
         const float r9 = FALLOFF == GES_FALLOFF_GEF ? row_sum(pbeta) : 0.f;
         if ((lane & 15) == 15) {
+          // the splat's common factors: o k for the dq sums, o for dL/dbeta
+          const float kq = FALLOFF == GES_FALLOFF_PHI ? -0.5f * B.z : (-0.25f * B.w) * B.z;
           float* d = sRed[nslot][row];
-          d[0] = r0; d[1] = r1; d[2] = r2; d[3] = r3; d[4] = r4;
-          d[5] = r5; d[6] = r6; d[7] = r7; d[8] = r8; d[9] = r9;
+          d[0] = kq * r0; d[1] = kq * r1; d[2] = kq * r2; d[3] = kq * r3; d[4] = kq * r4;
+          d[5] = r5; d[6] = r6; d[7] = r7; d[8] = r8;
+          d[9] = FALLOFF == GES_FALLOFF_GEF ? (-0.25f * 0.69314718055994531f * B.z) * r9 : 0.f;
         }
         if (lane == 0) sId[nslot] = __float_as_uint(Cc.w);
         ++nslot;
@@ -355,9 +377,28 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   }
 }
 
-// One block: every view's per-tile pair statistics summed into its header ([2] examined, [3] composited).
+// Bucket of a tile group for the backward order: 0 holds the heaviest walks (1,023 positions or more).
+constexpr int kOrderBuckets = 1024;
+static_assert(kXcdGroup == 8, "a tile group's work words are read as two 16-byte loads");
+__device__ __forceinline__ int group_bucket(const uint32_t* work, int64_t g, int64_t tiles) {
+  uint32_t w = 0;
+  if ((g + 1) * kXcdGroup <= tiles) {   // a whole group (the work array is 256-byte aligned)
+    const uint4 a = reinterpret_cast<const uint4*>(work)[2 * g];
+    const uint4 b = reinterpret_cast<const uint4*>(work)[2 * g + 1];
+    w = max(max(max(a.x, a.y), max(a.z, a.w)), max(max(b.x, b.y), max(b.z, b.w)));
+  } else {
+    for (int64_t t = g * kXcdGroup; t < tiles; ++t) w = max(w, work[t]);
+  }
+  return kOrderBuckets - 1 - (int)min(w, (uint32_t)(kOrderBuckets - 1));
+}
+
+// One block: every view's per-tile pair statistics summed into its header ([2] examined, [3] composited);
+// for a single view, also the order of its tile groups for the backward pass: a counting sort on the
+// group's longest walk, heaviest first (the order within a bucket is immaterial).
 __global__ void __launch_bounds__(1024) raster_stats_kernel(const DeviceBatch* __restrict__ db) {
   __shared__ unsigned long long part[2][16];
+  __shared__ uint32_t cursor[kOrderBuckets];
+  __shared__ uint32_t wsum[16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int v = 0; v < db->nviews; ++v) {
     const ViewDesc& V = db->views[v];
@@ -381,6 +422,31 @@ __global__ void __launch_bounds__(1024) raster_stats_kernel(const DeviceBatch* _
     }
     __syncthreads();   // part[] is rewritten for the next view
   }
+  if (db->nviews != 1) return;
+  const ViewDesc& V = db->views[0];
+  const int64_t tiles = (int64_t)V.tiles_x * V.tiles_y;
+  const int64_t ngroups = (tiles + kXcdGroup - 1) / kXcdGroup;
+  const int tid = threadIdx.x;
+  cursor[tid] = 0u;   // one bucket per thread
+  __syncthreads();
+  for (int64_t g = tid; g < ngroups; g += 1024) atomicAdd(&cursor[group_bucket(V.tile_work, g, tiles)], 1u);
+  __syncthreads();
+  const uint32_t c = cursor[tid];   // exclusive scan of the bucket counts
+  uint32_t s = c;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)s, d, 64);
+    if (lane >= d) s += y;
+  }
+  if (lane == 63) wsum[w] = s;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int k = 0; k < w; ++k) pre += wsum[k];
+  cursor[tid] = pre + s - c;
+  __syncthreads();
+  for (int64_t g = tid; g < ngroups; g += 1024) {
+    const uint32_t pos = atomicAdd(&cursor[group_bucket(V.tile_work, g, tiles)], 1u);
+    V.group_order[pos] = (uint32_t)g;
+  }
 }
 
 hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {
@@ -402,14 +468,15 @@ hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipS
 
 hipError_t launch_raster_backward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {
   if (b.total_tiles == 0) return hipSuccess;
+  const int ordered = b.nviews == 1;   // the forward's statistics pass ordered the groups of a single view
   const int64_t span = 8 * kXcdGroup;   // the grid covers whole rounds of groups
   const dim3 grid((unsigned)((b.total_tiles + span - 1) / span * span));
   if (b.falloff != GES_FALLOFF_GEF)
     hipLaunchKernelGGL(raster_backward_kernel<GES_FALLOFF_PHI>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
-                       b.total_tiles);
+                       b.total_tiles, ordered);
   else
     hipLaunchKernelGGL(raster_backward_kernel<GES_FALLOFF_GEF>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
-                       b.total_tiles);
+                       b.total_tiles, ordered);
   return hipGetLastError();
 }
 

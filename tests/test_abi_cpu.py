@@ -186,3 +186,24 @@ def test_mix_fit_validates_before_any_device_work():
         args = list(ok)
         args[pos] = bad
         assert lib.ges_mix_fit(*args) == 1, (pos, bad)
+
+
+def test_workspaces_must_be_256_byte_aligned():
+    # the kernels move records and tile words as 16-byte vectors and accumulate binary64 atomics in place
+    lib = G.lib()
+    cam = G.camera_struct(synth.pinhole(64, 64, (0, 0, -4.0)))
+    p = G.params_struct()
+    s = G.ges_splats()
+    s.n = 0
+    k = C.c_uint64(0)
+    bad, ok = C.c_void_p((1 << 20) + 64), C.c_void_p(1 << 21)
+    assert lib.ges_preprocess(C.byref(s), C.byref(cam), C.byref(p), bad, 1 << 30, C.byref(k), None) == 1
+    assert b"aligned" in lib.ges_last_error()
+    assert lib.ges_render_forward(C.byref(s), C.byref(cam), C.byref(p), bad, None, 0, 0, ok,
+                                  C.c_void_p(1 << 23), None) == 1
+    assert lib.ges_render_forward(C.byref(s), C.byref(cam), C.byref(p), ok, None, 0, 0, bad,
+                                  C.c_void_p(1 << 23), None) == 1
+    g = G.ges_splat_grads()
+    assert lib.ges_render_backward(C.byref(s), C.byref(cam), C.byref(p), bad, None, ok, C.c_void_p(1 << 23),
+                                   C.byref(g), None) == 1
+    assert b"aligned" in lib.ges_last_error()
