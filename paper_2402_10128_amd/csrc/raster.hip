@@ -14,8 +14,8 @@
 // to the 8 XCDs in groups of 8 neighbours (see xcd_tile).
 // The backward pass walks each pixel's contributors back to front, recovering the transmittance
 // before splat j as T_j = T_(j+1) / (1 - alpha_j) from the stored final T, so no per-pixel lists are
-// kept.  Per splat, the 4 pixels of a lane are summed in registers and each row of 16 lanes by four
-// DPP steps; one lane per row parks the row sums in LDS, and every 32 splats each lane finishes one
+// kept.  Per splat, the 4 pixels of a lane are summed in registers and each row of 16 lanes by a DPP
+// reduce-scatter; the row's lanes park the row sums in LDS, and every 32 splats each lane finishes one
 // parked splat (4 row sums) and adds its components to binary64 accumulators with float64 atomics
 // (the cross-tile sums of a splat often cancel; binary32 accumulation would lose accuracy there).
 // Factors of 2 common to a splat's terms (the mean2D and b gradients) are applied once per (tile, splat).
@@ -203,6 +203,28 @@ __device__ __forceinline__ float wave_sum_to_63(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+// One exchange step of a reduce-scatter inside rows of 16 lanes: the lane pairs with the lane that the
+// involution CTRL maps it to (row_mirror: l^15, row_half_mirror: l^7, quad_perm [2,3,0,1]: l^2); the lane
+// with the bit set keeps the second operand's partial sum and sends the first, its partner the reverse.
+template <int CTRL>
+__device__ __forceinline__ float xstep(float lo, float hi, bool upper) {
+  const float keep = upper ? hi : lo;
+  const float send = upper ? lo : hi;
+  return keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), CTRL, 0xf, 0xf, false));
+}
+
+// Row sums of 8 values in 8 DPP adds and 14 selects instead of 32 DPP adds: the partner masks 15, 7, 2, 1
+// span the 16 lanes of a row, and lane l ends with the sum of value (l >> 1) & 7 over its row.
+__device__ __forceinline__ float row_scatter8(float a0, float a1, float a2, float a3, float a4, float a5, float a6,
+                                              float a7, int lane) {
+  const bool u3 = lane & 8, u2 = lane & 4, u1 = lane & 2;
+  const float b0 = xstep<0x140>(a0, a4, u3), b1 = xstep<0x140>(a1, a5, u3);   // row_mirror
+  const float b2 = xstep<0x140>(a2, a6, u3), b3 = xstep<0x140>(a3, a7, u3);
+  const float c0 = xstep<0x141>(b0, b2, u2), c1 = xstep<0x141>(b1, b3, u2);   // row_half_mirror
+  const float d0 = xstep<0x4E>(c0, c1, u1);                                    // quad_perm [2,3,0,1]
+  return dpp_add<0xB1, 0xf>(d0);                                               // quad_perm [1,0,3,2]
+}
+
 constexpr int kFlush = 32;   // splats whose row partials are parked in LDS before one atomic flush
 
 template <int FALLOFF>
@@ -336,16 +358,18 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         pc = __builtin_fmaf(dqdy, dy, pc);
       }
       if (__any(any)) {
-        // rows of 16 lanes reduce in registers; one lane per row parks the 10 row sums in LDS
-        const float r0 = row_sum(su), r1 = row_sum(sv), r2 = row_sum(pa), r3 = row_sum(pb), r4 = row_sum(pc);
-        const float r5 = row_sum(po), r6 = row_sum(pr), r7 = row_sum(pg), r8 = row_sum(pbl);
+        // rows of 16 lanes reduce in registers: the first 8 sums by a reduce-scatter (after it, lanes 2i and
+        // 2i+1 of a row hold row sum i), the blue and beta sums by a full row sum; the row's lanes then park
+        // the 10 sums in LDS, each scaled by the splat's common factor (o k for the dq sums, o for dL/dbeta)
+        const float e = row_scatter8(su, sv, pa, pb, pc, po, pr, pg, lane);
+        const float r8 = row_sum(pbl);
         const float r9 = FALLOFF == GES_FALLOFF_GEF ? row_sum(pbeta) : 0.f;
+        const float kq = FALLOFF == GES_FALLOFF_PHI ? -0.5f * B.z : (-0.25f * B.w) * B.z;
+        float* d = sRed[nslot][row];
+        const int idx = (lane >> 1) & 7;
+        if ((lane & 1) == 0) d[idx] = idx < 5 ? kq * e : e;
         if ((lane & 15) == 15) {
-          // the splat's common factors: o k for the dq sums, o for dL/dbeta
-          const float kq = FALLOFF == GES_FALLOFF_PHI ? -0.5f * B.z : (-0.25f * B.w) * B.z;
-          float* d = sRed[nslot][row];
-          d[0] = kq * r0; d[1] = kq * r1; d[2] = kq * r2; d[3] = kq * r3; d[4] = kq * r4;
-          d[5] = r5; d[6] = r6; d[7] = r7; d[8] = r8;
+          d[8] = r8;
           d[9] = FALLOFF == GES_FALLOFF_GEF ? (-0.25f * 0.69314718055994531f * B.z) * r9 : 0.f;
         }
         if (lane == 0) sId[nslot] = __float_as_uint(Cc.w);
