@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define GES_ABI_VERSION 1u
+#define GES_ABI_VERSION 2u
 #define GES_TILE 16
 #define GES_GRAD2D_STRIDE 12   /* binary64 slots per splat in the 2-D gradient rows */
 
@@ -178,6 +178,9 @@ typedef struct {
   const uint64_t* stats;         /* [4]: keys, error word (bit 0: key capacity too small), pairs examined,
                                     pairs composited (after ges_render_forward) */
   int32_t tiles_x, tiles_y;
+  const uint32_t* tile_work;     /* [tiles] per tile, the largest n_contrib of its pixels (after ges_render_forward) */
+  const uint32_t* group_order;   /* [ceil(tiles/8)] groups of 8 consecutive tiles in the order the backward pass
+                                    deals them, heaviest tile_work first (after ges_render_forward) */
 } ges_frame_view;
 /* Record layout, 16 x 32-bit words per splat:
  *   0 u, 1 v, 2 conic a, 3 conic b, 4 conic c, 5 q_max, 6 opacity, 7 beta,

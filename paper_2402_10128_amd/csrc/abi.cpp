@@ -333,6 +333,8 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
   }
   out->tiles_x = fp.tiles_x;
   out->tiles_y = fp.tiles_y;
+  out->tile_work = reinterpret_cast<const uint32_t*>(sw + fp.off_twork);
+  out->group_order = reinterpret_cast<const uint32_t*>(sw + fp.off_gorder);
   return GES_OK;
 }
 

@@ -53,7 +53,8 @@ class ges_splat_grads(C.Structure):
 class ges_frame_view(C.Structure):
     _fields_ = [("records", C.c_void_p), ("tile_ranges", C.c_void_p), ("sorted_ids", C.c_void_p),
                 ("bucket_pairs", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
-                ("grad2d", C.c_void_p), ("stats", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32)]
+                ("grad2d", C.c_void_p), ("stats", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
+                ("tile_work", C.c_void_p), ("group_order", C.c_void_p)]
 
 
 class ges_serve_config(C.Structure):
@@ -494,6 +495,8 @@ def frame_arrays(frame: Frame, n: int) -> dict:
     out["ranges"] = sl(v.tile_ranges, 8 * T, ws).view(torch.int32).reshape(T, 2).cpu().numpy().view(np.uint32)
     out["grad2d"] = sl(v.grad2d, 8 * GRAD2D_STRIDE * n, ws).view(torch.float64).reshape(n, GRAD2D_STRIDE).cpu().numpy()
     out["stats"] = sl(v.stats, 32, ws).view(torch.int64).cpu().numpy()
+    out["tile_work"] = sl(v.tile_work, 4 * T, ws).view(torch.int32).cpu().numpy().view(np.uint32)
+    out["group_order"] = sl(v.group_order, 4 * ((T + 7) // 8), ws).view(torch.int32).cpu().numpy().view(np.uint32)
     if frame.key_ws is not None and frame.num_keys > 0:
         K = frame.num_keys
         out["sorted_ids"] = sl(v.sorted_ids, 4 * K, frame.key_ws).view(torch.int32).cpu().numpy().view(np.uint32)

@@ -187,3 +187,26 @@ def test_parity_across_shape_strength(rho):
     for k in gpu["grads"]:
         e = grad3d_check(gpu["grads"][k], ref["grads"][k], ref["allow"][k])
         assert e["max"] <= GRAD_RTOL, (k, e)
+
+
+@pytest.mark.parametrize("size", [(200, 136), (71, 45), (1600, 1040)], ids=["117_tiles", "15_tiles", "6500_tiles"])
+def test_backward_tile_order_is_a_heaviest_first_permutation(size):
+    """The forward pass records each tile's backward walk (the largest n_contrib of its pixels) and orders the
+    groups of 8 tiles for the backward: a permutation of the groups whose longest walks never increase
+    (walks of 1,023 and beyond share the first bucket).  Checked against the frame's own n_contrib."""
+    w, h = size
+    sc, cam = _inputs(1, 20000 if w < 1000 else 200000, w, h)
+    print(f"[order] {w}x{h}", flush=True)
+    gpu = gpu_render(sc.arrays(), sc.sh_degree, cam, O.FALLOFF_PHI, O.TILES_ELLIPSE)
+    tx, ty = (w + 15) // 16, (h + 15) // 16
+    nc = np.zeros((ty * 16, tx * 16), np.uint32)
+    nc[:h, :w] = gpu["n_contrib"]
+    walk = nc.reshape(ty, 16, tx, 16).max(axis=(1, 3)).ravel()
+    np.testing.assert_array_equal(gpu["tile_work"], walk)
+    ngroups = (tx * ty + 7) // 8
+    pad = np.zeros(ngroups * 8, np.uint32)
+    pad[:tx * ty] = walk
+    key = np.minimum(pad.reshape(ngroups, 8).max(axis=1), 1023)
+    order = gpu["group_order"].astype(np.int64)
+    np.testing.assert_array_equal(np.sort(order), np.arange(ngroups))
+    assert np.all(np.diff(key[order].astype(np.int64)) <= 0)
