@@ -213,6 +213,22 @@ size_t ges_mask_scratch_bytes(int32_t width, int32_t height);
 ges_status ges_freq_mask(const float* target, int32_t width, int32_t height, float omega, void* scratch,
                          uint8_t* mask, void* stream);
 
+/* ---- the frequency mask without a scratch argument ----------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight training
+ * or serving loops, harnesses that forbid hipMalloc.  Same arguments, kernels and result bits as
+ * ges_freq_mask, but the scratch is a fixed array of GES_MASK_STATIC_SCRATCH_BYTES that the
+ * library holds on every device it runs on (from the first call on that device until the process
+ * ends); the call allocates nothing.  The array's address is looked up on the first call with a
+ * device current; `stream` must belong to the current device.  Every call on one device shares
+ * that device's array and leaves its contents behind (the mask's kernels clear what must start at
+ * zero), so calls whose work overlaps on one device (several streams or threads) race: order them
+ * on one stream.  Errors: those of ges_freq_mask; GES_ERR_CAPACITY when
+ * ges_mask_scratch_bytes(width,height) exceeds GES_MASK_STATIC_SCRATCH_BYTES (images up to about
+ * 13 Mpx fit, e.g. 3840x2160); GES_ERR_DEVICE if the array cannot be looked up. */
+#define GES_MASK_STATIC_SCRATCH_BYTES ((size_t)8 << 20)
+ges_status ges_freq_mask_static(const float* target, int32_t width, int32_t height, float omega, uint8_t* mask,
+                                void* stream);
+
 /* L = lam_l1 mean|I - T| + lam_w mean(|I - T| M) over height*width*3 values, and
  * dL/dI = (lam_l1 + lam_w M) sign(I - T) / (3 h w).  mask may be NULL (then lam_w is
  * ignored).  scratch: device buffer of ges_loss_scratch_bytes() bytes (per-block partial sums, added in

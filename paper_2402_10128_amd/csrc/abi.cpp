@@ -387,6 +387,18 @@ ges_status ges_freq_mask(const float* target, int32_t width, int32_t height, flo
   return GES_OK;
 }
 
+ges_status ges_freq_mask_static(const float* target, int32_t width, int32_t height, float omega, uint8_t* mask,
+                                void* stream) {
+  if (!target || !mask) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return fail(GES_ERR_INVALID_ARGUMENT, "bad sizes");
+  if (!(omega >= 0.f && omega <= 1.f)) return fail(GES_ERR_INVALID_ARGUMENT, "omega outside [0,1]");
+  if (ges::freq_mask_scratch_bytes(width, height) > ges::freq_mask_static_capacity())
+    return fail(GES_ERR_CAPACITY, "image too large for the library's mask scratch (GES_MASK_STATIC_SCRATCH_BYTES)");
+  GES_CHECK_HIP(ges::launch_freq_mask_static(target, width, height, omega, mask, reinterpret_cast<hipStream_t>(stream)),
+                "freq_mask_static");
+  return GES_OK;
+}
+
 size_t ges_loss_scratch_bytes(void) { return ges::loss_scratch_bytes(); }
 
 ges_status ges_loss(const float* img, const float* target, const uint8_t* mask, int32_t width, int32_t height,

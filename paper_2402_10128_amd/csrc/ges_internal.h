@@ -152,6 +152,10 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
 hipError_t launch_freq_mask(const float* target, int w, int h, float omega, void* scratch, uint8_t* mask,
                             hipStream_t stream);
 size_t freq_mask_scratch_bytes(int w, int h);
+// the mask with the library's per-device scratch array (GES_MASK_STATIC_SCRATCH_BYTES); allocates nothing
+size_t freq_mask_static_capacity();
+hipError_t launch_freq_mask_static(const float* target, int w, int h, float omega, uint8_t* mask,
+                                   hipStream_t stream);
 size_t loss_scratch_bytes();
 hipError_t launch_loss(const float* img, const float* target, const uint8_t* mask, int w, int h, float lam_l1,
                        float lam_w, void* scratch, float* loss_out, float* dL_dimg, hipStream_t stream);

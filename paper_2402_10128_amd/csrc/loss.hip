@@ -12,6 +12,7 @@
 // Memory: the loss reads I, T (12 B/px each) and M (1 B/px) and writes dL/dI (12 B/px): HBM-bound.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "ges_internal.h"
 
@@ -144,6 +145,44 @@ hipError_t launch_freq_mask(const float* target, int w, int h, float omega, void
   hipLaunchKernelGGL(mask_up_kernel, dim3((w + 255) / 256, h), dim3(256), 0, stream, ms, dog, wl, w, h,
                      invert ? 1 : 0, mask);
   return hipGetLastError();
+}
+
+// ---- the mask with library-held scratch (no scratch argument, no allocation) -------------------
+// One fixed array per device; its device address is looked up once per device, with that device
+// current, and kept.  Host code never passes the array's own name to a kernel (on the host that name is a
+// stand-in, not a device address): every use goes through the looked-up pointer.
+constexpr size_t kMaskStaticBytes = GES_MASK_STATIC_SCRATCH_BYTES;
+constexpr int kMaxStaticDevices = 64;
+static __device__ __align__(256) unsigned char mask_static_scratch[kMaskStaticBytes];
+
+namespace {
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxStaticDevices] = {};
+}  // namespace
+
+size_t freq_mask_static_capacity() { return kMaskStaticBytes; }
+
+hipError_t launch_freq_mask_static(const float* target, int w, int h, float omega, uint8_t* mask,
+                                   hipStream_t stream) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxStaticDevices) return hipErrorInvalidDevice;
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+      e = hipGetSymbolAddress(&g_static_ptr[dev], HIP_SYMBOL(mask_static_scratch));
+      if (e != hipSuccess) {
+        g_static_ptr[dev] = nullptr;
+        return e;
+      }
+    }
+    ptr = g_static_ptr[dev];
+  }
+  // the maximum word the scratch holds is cleared by the first kernel of the mask, so nothing else
+  // has to start at zero
+  return launch_freq_mask(target, w, h, omega, ptr, mask, stream);
 }
 
 constexpr int kLossThreads = 256;

@@ -286,6 +286,15 @@ def ges_freq_mask(target, omega, mask=None, stream=None):
     return mask
 
 
+def ges_freq_mask_static(target, omega, mask=None, stream=None):
+    """The frequency mask with the library's own scratch array (no scratch buffer is allocated)."""
+    H, W = int(target.shape[0]), int(target.shape[1])
+    if mask is None:
+        mask = torch.empty((H, W), dtype=torch.uint8, device=target.device)
+    _check(lib().ges_freq_mask_static(_ptr(target), W, H, float(omega), _ptr(mask), _stream(stream)))
+    return mask
+
+
 def ges_loss(img, target, mask, lam_l1, lam_w, dL_dimg=None, loss_out=None, scratch=None, stream=None):
     H, W = int(img.shape[0]), int(img.shape[1])
     if dL_dimg is None:

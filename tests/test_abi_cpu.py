@@ -207,3 +207,15 @@ def test_workspaces_must_be_256_byte_aligned():
     assert lib.ges_render_backward(C.byref(s), C.byref(cam), C.byref(p), bad, None, ok, C.c_void_p(1 << 23),
                                    C.byref(g), None) == 1
     assert b"aligned" in lib.ges_last_error()
+
+
+def test_static_scratch_mask_validates_before_any_device_work():
+    """The mask entry point without a scratch argument refuses images beyond its fixed scratch array
+    (CAPACITY) and bad arguments (INVALID_ARGUMENT) on the host."""
+    lib = G.lib()
+    fake = C.c_void_p(1 << 20)
+    assert lib.ges_freq_mask_static(fake, 16384, 16384, C.c_float(0.75), fake, None) == 2
+    assert b"GES_MASK_STATIC_SCRATCH_BYTES" in lib.ges_last_error()
+    assert lib.ges_freq_mask_static(None, 64, 64, C.c_float(0.75), fake, None) == 1
+    assert lib.ges_freq_mask_static(fake, 64, 64, C.c_float(1.5), fake, None) == 1
+    assert lib.ges_freq_mask_static(fake, 0, 64, C.c_float(0.5), fake, None) == 1
