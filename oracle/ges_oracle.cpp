@@ -768,8 +768,169 @@ void pixel_grads(const oc_params* p, const Splat2D* L, const std::vector<Contrib
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Rounding-error bound of one pixel's terms in a binary32 implementation.
+//
+// The GPU evaluates each composited pair's contributions (the ten terms of pixel_grads) in binary32,
+// with hardware exp2/log2/reciprocal, and recovers the transmittance back to front by division from
+// the stored binary32 final transmittance.  The amount by which such an evaluation may differ from the
+// binary64 terms above is bounded here by first-order running error analysis (Wilkinson; Higham,
+// "Accuracy and Stability of Numerical Algorithms", 2nd ed., Sec. 3.3): every computed quantity x
+// carries an absolute bound E(x), propagated by
+//     E(a +- b) = E(a) + E(b) + u|a +- b|,   E(a b) = |a| E(b) + |b| E(a) + u|a b|,
+//     E(f(x))   = |f'(x)| E(x) + e_f |f(x)|  for f in {exp2, log2, 1/x},
+// with u = 2^-24 (binary32 round to nearest) and e_f = 2u (one ulp).  The model of the implementation:
+//   * the record fields, dx, dy and q are binary32 values shared bit for bit with the oracle (exact);
+//   * G = exp2(x) with x a rounded product of q (PHI) or of q^(beta/2) = exp2((beta/2) log2 q) (GEF)
+//     by -log2(e)/2; log2 within one ulp of its result or 2u absolute where the result is below 1;
+//   * alpha = o G rounded, or the binary32 constant 0.99 when clamped (|0.99f - 0.99| absolute);
+//   * T: forward product T (1 - alpha) rounded per step, stored in binary32, then recovered back to
+//     front by T / (1 - alpha) through a reciprocal and a product (covers any forward recomputation too);
+//   * S (colour behind): S + alpha (c - S) or alpha c + (1 - alpha) S per step, each rounding at most
+//     4u (|c| + |S|);
+//   * each term is a product of those quantities with a few rounded operations, counted per term.
+// Decisions (alpha floor, clamp, termination) are the oracle's; their ambiguity is `delta`'s business.
+// The summation over a tile's pixels is not included: its bound depends on the summation order and is
+// gamma * sum |terms| (`mass`).
+// ------------------------------------------------------------------------------------------------
+constexpr double kU = 0x1p-24;
+constexpr double kUlp = 2.0 * kU;
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kLog2e = 1.44269504088896340736;
+
+inline double log2_abs_err(double l) { return kUlp * std::max(std::fabs(l), 1.0); }
+
+struct TermBound { int64_t j; double e[10]; };
+
+void pixel_error_bounds(const oc_params* p, const Splat2D* L, const std::vector<Contrib>& cs, double Tfin,
+                        const double g[3], std::vector<TermBound>& out) {
+  out.clear();
+  const size_t m = cs.size();
+  if (m == 0) return;
+  const bool gef = p->falloff == OC_FALLOFF_GEF;
+  const double clampErr = std::fabs(0.99 - (double)0.99f);
+  // per contribution: relative error of G, absolute error of alpha and of (1 - alpha)
+  std::vector<double> eG(m), Ea(m), Eom(m), Ef(m + 1), Eb(m + 1);
+  std::vector<double> eqb(m, 0.0), El(m, 0.0);
+  for (size_t k = 0; k < m; ++k) {
+    const Contrib& c = cs[k];
+    const Splat2D& s = L[c.j];
+    const double q = c.q < 0.0 ? 0.0 : c.q;
+    if (!gef) {
+      // x = (-log2e/2) q: the constant and the product round (2u |x|), exp2 adds one ulp
+      const double x = 0.5 * kLog2e * q;
+      eG[k] = kLn2 * 2.0 * kU * x + kUlp;
+    } else if (q > 0.0) {
+      const double l = std::log2(q);
+      El[k] = log2_abs_err(l);
+      const double arg = 0.5 * s.beta * l;
+      const double Earg = 0.5 * s.beta * El[k] + 2.0 * kU * std::fabs(arg);
+      eqb[k] = kLn2 * Earg + kUlp;
+      const double qb = std::exp2(arg);
+      const double x = 0.5 * kLog2e * qb;
+      eG[k] = kLn2 * x * (eqb[k] + 2.0 * kU) + kUlp;
+    } else {
+      eG[k] = 0.0;   // q = 0: G = exp2(0) = 1 exactly
+    }
+    Ea[k] = c.clamped ? clampErr : c.alpha * (eG[k] + kU);
+    Eom[k] = Ea[k] + kU * (1.0 - c.alpha);
+  }
+  // forward transmittance, then the stored value and its recovery back to front
+  Ef[0] = 0.0;
+  for (size_t k = 0; k < m; ++k) {
+    const double Tn = cs[k].T * (1.0 - cs[k].alpha);
+    Ef[k + 1] = Ef[k] * (1.0 - cs[k].alpha) + cs[k].T * Eom[k] + kU * Tn;
+  }
+  Eb[m] = Ef[m] + kU * Tfin;
+  for (size_t kk = m; kk-- > 0;) {
+    const double om = 1.0 - cs[kk].alpha;
+    const double Tn = cs[kk].T * om;
+    Eb[kk] = Eb[kk + 1] / om + Tn * Eom[kk] / (om * om) + 3.0 * kU * cs[kk].T;
+  }
+  const double bgg = p->bg[0] * g[0] + p->bg[1] * g[1] + p->bg[2] * g[2];
+  const double bgabs = std::fabs(p->bg[0] * g[0]) + std::fabs(p->bg[1] * g[1]) + std::fabs(p->bg[2] * g[2]);
+  double S[3] = {0.0, 0.0, 0.0}, ES[3] = {0.0, 0.0, 0.0};
+  for (size_t kk = m; kk-- > 0;) {
+    const Contrib& c = cs[kk];
+    const Splat2D& s = L[c.j];
+    const double col[3] = {s.r, s.g, s.bl};
+    const double om = 1.0 - c.alpha;
+    const double T = c.T, ET = Eb[kk];
+    TermBound tb;
+    tb.j = c.j;
+    for (int i = 0; i < 10; ++i) tb.e[i] = 0.0;
+    // dL/dalpha = sum_ch g T (c - S) - Tfin bgg / (1 - alpha)
+    double D = 0.0, ED = 0.0, absSum = 0.0;
+    for (int ch = 0; ch < 3; ++ch) {
+      D += g[ch] * T * (col[ch] - S[ch]);
+      ED += std::fabs(g[ch]) * (T * ES[ch] + std::fabs(col[ch] - S[ch]) * ET);
+      absSum += std::fabs(g[ch]) * (std::fabs(col[ch]) + std::fabs(S[ch]));
+    }
+    ED += 5.0 * kU * T * absSum;
+    const double bp = Tfin * bgg / om;
+    ED += bgabs * (Eb[m] / om + Tfin * Eom[kk] / (om * om) + 6.0 * kU * Tfin / om);
+    D -= bp;
+    ED += kU * std::fabs(D);
+    // colour: alpha T g
+    for (int ch = 0; ch < 3; ++ch) {
+      const double v = c.alpha * T * g[ch];
+      tb.e[6 + ch] = std::fabs(g[ch]) * (c.alpha * ET + T * Ea[kk]) + 2.0 * kU * std::fabs(v);
+    }
+    if (!c.clamped) {
+      const double G = c.G;
+      const double gd = G * D;
+      const double Egd = G * ED + std::fabs(D) * G * eG[kk] + kU * std::fabs(gd);
+      tb.e[5] = Egd;
+      const double q = c.q < 0.0 ? 0.0 : c.q;
+      double dq = 0.0, Edq = 0.0;
+      if (c.q < 0.0) {
+        // q rounded below 0 at the centre: no dL/dq term on either side
+      } else if (!gef) {
+        dq = -0.5 * s.o * gd;
+        Edq = 0.5 * s.o * Egd + 2.0 * kU * std::fabs(dq);
+      } else {
+        const double qf = std::max(q, 1e-12);
+        const double lf = std::log2(qf);
+        const double arg2 = (0.5 * s.beta - 1.0) * lf;
+        const double Earg2 = std::fabs(0.5 * s.beta - 1.0) * log2_abs_err(lf) + 2.0 * kU * std::fabs(arg2);
+        const double qpow = std::exp2(arg2);
+        const double eqpow = kLn2 * Earg2 + kUlp;
+        dq = -0.25 * s.beta * qpow * s.o * gd;
+        Edq = 0.25 * s.beta * s.o * (qpow * Egd + std::fabs(gd) * qpow * eqpow) + 3.0 * kU * std::fabs(dq);
+        if (q > 0.0) {
+          const double l = std::log2(q);
+          const double qb = std::exp2(0.5 * s.beta * l);
+          const double w = qb * l;
+          const double Ew = std::fabs(l) * qb * eqb[kk] + qb * El[kk] + kU * std::fabs(w);
+          const double v9 = 0.25 * kLn2 * s.o * w * gd;
+          tb.e[9] = 0.25 * kLn2 * s.o * (std::fabs(w) * Egd + std::fabs(gd) * Ew) + 3.0 * kU * std::fabs(v9);
+        }
+      }
+      (void)dq;
+      const double dx = c.dx, dy = c.dy;
+      const double hu = s.a * dx + s.b * dy, hv = s.b * dx + s.c * dy;
+      const double Ehu = 2.0 * kU * (std::fabs(s.a * dx) + std::fabs(s.b * dy));
+      const double Ehv = 2.0 * kU * (std::fabs(s.b * dx) + std::fabs(s.c * dy));
+      const double adq = std::fabs(dq);
+      tb.e[0] = 2.0 * (std::fabs(hu) * Edq + adq * Ehu) + kU * 2.0 * adq * std::fabs(hu);
+      tb.e[1] = 2.0 * (std::fabs(hv) * Edq + adq * Ehv) + kU * 2.0 * adq * std::fabs(hv);
+      tb.e[2] = dx * dx * Edq + 2.0 * kU * adq * dx * dx;
+      tb.e[3] = 2.0 * std::fabs(dx * dy) * Edq + 2.0 * kU * 2.0 * adq * std::fabs(dx * dy);
+      tb.e[4] = dy * dy * Edq + 2.0 * kU * adq * dy * dy;
+    }
+    out.push_back(tb);
+    // S <- alpha c + (1 - alpha) S
+    for (int ch = 0; ch < 3; ++ch) {
+      const double Sn = c.alpha * col[ch] + om * S[ch];
+      ES[ch] = om * ES[ch] + std::fabs(col[ch] - S[ch]) * Ea[kk] + 4.0 * kU * (std::fabs(col[ch]) + std::fabs(S[ch]));
+      S[ch] = Sn;
+    }
+  }
+}
+
 void pixel_backward(int mode, const oc_params* p, const Splat2D* L, const uint32_t* ids, int64_t len, int px,
-                    int py, const double g[3], double* g2d, double* delta, double* mass, int64_t* examined) {
+                    int py, const double g[3], double* g2d, double* delta, double* mass, double* ebound,
+                    int64_t* examined) {
   std::vector<Contrib> cs;
   std::vector<PixelGrad> prim, alt;
   double tm, cm;
@@ -788,6 +949,17 @@ void pixel_backward(int mode, const oc_params* p, const Splat2D* L, const uint32
         const double a = std::fabs(pg.v[k]);
 #pragma omp atomic
         ms[k] += a;
+      }
+    }
+  }
+  if (ebound) {
+    std::vector<TermBound> eb;
+    pixel_error_bounds(p, L, cs, Tfin, g, eb);
+    for (const TermBound& tb : eb) {
+      double* es = ebound + 10 * (int64_t)ids[tb.j];
+      for (int k = 0; k < 10; ++k) {
+#pragma omp atomic
+        es[k] += tb.e[k];
       }
     }
   }
@@ -1008,7 +1180,8 @@ int oc_render_untiled(int mode, const oc_record* r, int64_t n, const oc_camera* 
 }
 
 int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera* cam, const oc_params* p,
-                        const double* dL_dimg, double* g2d, double* delta, double* mass, oc_stats* stats) {
+                        const double* dL_dimg, double* g2d, double* delta, double* mass, double* ebound,
+                        oc_stats* stats) {
   std::vector<uint32_t> ids;
   for (int64_t i = 0; i < n; ++i)
     if (r->tiles_touched[i] > 0) ids.push_back((uint32_t)i);
@@ -1024,7 +1197,7 @@ int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera
     for (int px = 0; px < cam->width; ++px) {
       const int64_t pix = (int64_t)py * cam->width + px;
       pixel_backward(mode, p, L.data(), ids.data(), (int64_t)L.size(), px, py, dL_dimg + 3 * pix, g2d, delta, mass,
-                     &tot);
+                     ebound, &tot);
     }
   if (stats) { std::memset(stats, 0, sizeof(*stats)); stats->pairs_examined = tot; }
   return 0;
@@ -1032,7 +1205,7 @@ int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera
 
 int oc_backward(int mode, const oc_record* r, int64_t n, const oc_camera* cam, const oc_params* p,
                 const uint32_t* values, const int64_t* ranges, const int32_t* tiles, int64_t n_tiles,
-                const double* dL_dimg, double* g2d, double* delta, double* mass, oc_stats* stats) {
+                const double* dL_dimg, double* g2d, double* delta, double* mass, double* ebound, oc_stats* stats) {
   (void)n;
   const int TX = tiles_x(cam), TY = tiles_y(cam);
   const int64_t nt = tiles ? n_tiles : (int64_t)TX * TY;
@@ -1052,7 +1225,8 @@ int oc_backward(int mode, const oc_record* r, int64_t n, const oc_camera* cam, c
       for (int py = y0; py <= y1; ++py)
         for (int px = x0; px <= x1; ++px) {
           const int64_t pix = (int64_t)py * cam->width + px;
-          pixel_backward(mode, p, L.data(), values + s0, s1 - s0, px, py, dL_dimg + 3 * pix, g2d, delta, mass, &ex);
+          pixel_backward(mode, p, L.data(), values + s0, s1 - s0, px, py, dL_dimg + 3 * pix, g2d, delta, mass,
+                         ebound, &ex);
         }
     }
 #pragma omp critical

@@ -139,14 +139,19 @@ int oc_render_untiled(int mode, const oc_record* r, int64_t n, const oc_camera* 
  * 1e-4) or alpha clamp (o G within 1e-5 of 0.99) is ambiguous in floating point, the absolute
  * difference between the gradients of the two branches of that decision.
  * mass [n,10] (nullable) accumulates the sum of |per-pixel contribution|, the scale of the rounding
- * error of any implementation that forms each contribution with a relative error. */
+ * error of summing the contributions in binary32.
+ * ebound [n,10] (nullable) accumulates a first-order bound on the error of each per-pixel
+ * contribution when it is evaluated in binary32 with one-ulp exp2/log2/reciprocal and the
+ * transmittance recovered back to front by division (running error analysis; model in the source). */
 int oc_backward(int mode, const oc_record* r, int64_t n, const oc_camera* cam, const oc_params* p,
                 const uint32_t* values, const int64_t* ranges, const int32_t* tiles, int64_t n_tiles,
-                const double* dL_dimg, double* g2d, double* delta, double* mass, oc_stats* stats);
+                const double* dL_dimg, double* g2d, double* delta, double* mass, double* ebound,
+                oc_stats* stats);
 
 /* Untiled reverse pass: every pixel walks all visible splats in (depth, index) order. */
 int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera* cam, const oc_params* p,
-                        const double* dL_dimg, double* g2d, double* delta, double* mass, oc_stats* stats);
+                        const double* dL_dimg, double* g2d, double* delta, double* mass, double* ebound,
+                        oc_stats* stats);
 
 int oc_num_threads(void);
 

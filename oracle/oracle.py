@@ -219,27 +219,29 @@ class Oracle:
                    with_delta=False):
         """Per-splat gradient of <dL_dimg, image> w.r.t. (u,v,a,b,c,opacity,r,g,b,beta).
 
-        with_delta: also return the per-splat allowance from floating-point-ambiguous decisions and the
-        per-splat absolute mass of the summed contributions."""
+        with_delta: also return, per splat and component, the allowance from floating-point-ambiguous
+        decisions (delta), the sum of |per-pixel contribution| (mass) and the first-order bound on the
+        binary32 evaluation error of the contributions (ebound): (g2d, delta, mass, ebound, stats)."""
         g2d = np.zeros((rec.n, 10))
         delta = np.zeros((rec.n, 10)) if with_delta else None
         mass = np.zeros((rec.n, 10)) if with_delta else None
+        ebound = np.zeros((rec.n, 10)) if with_delta else None
         d = np.ascontiguousarray(dL_dimg, np.float64)
         st = _Stats()
         rc = rec.c()
         if values is None:
             rv = lib().oc_backward_untiled(mode, C.byref(rc), C.c_int64(rec.n), C.byref(self.cs), C.byref(self.ps),
-                                           _p(d), _p(g2d), _p(delta), _p(mass), C.byref(st))
+                                           _p(d), _p(g2d), _p(delta), _p(mass), _p(ebound), C.byref(st))
         else:
             tl = None if tiles is None else np.ascontiguousarray(tiles, np.int32)
             rv = lib().oc_backward(mode, C.byref(rc), C.c_int64(rec.n), C.byref(self.cs), C.byref(self.ps),
                                    _p(np.ascontiguousarray(values, np.uint32)),
                                    _p(np.ascontiguousarray(ranges, np.int64)), _p(tl),
                                    C.c_int64(0 if tl is None else len(tl)), _p(d), _p(g2d), _p(delta), _p(mass),
-                                   C.byref(st))
+                                   _p(ebound), C.byref(st))
         assert rv == 0, rv
         if with_delta:
-            return g2d, delta, mass, _stats_dict(st)
+            return g2d, delta, mass, ebound, _stats_dict(st)
         return g2d, _stats_dict(st)
 
 

@@ -4,7 +4,10 @@ Tolerances (stated per result):
   * per-splat records, keys, sort order, tile ranges: bit-exact (mismatch count must be 0);
   * image: <= 1e-5 absolute per FP32 channel on pixels whose termination decision is not within
     1e-3 (relative) of the 1e-4 threshold; flagged pixels must match one of the two branches;
-  * gradients: |g - r| / max(|r|, 1e-2 * rms(r)) <= 1e-3 per tensor.
+  * gradients: |g - r| / max(|r|, 1e-2 * rms(r)) <= 1e-3 per tensor, beyond a derived allowance for what
+    a binary32 implementation may legitimately differ by (allowance2d); entries whose allowance is
+    negligible are held to the plain bound, and the entries that pass only through the allowance are
+    counted and reported.
 """
 from __future__ import annotations
 
@@ -18,7 +21,14 @@ from paper_2402_10128_amd import ges as G
 IMG_ATOL = 1e-5
 GRAD_RTOL = 1e-3
 GRAD_FLOOR = 1e-2
-TERM_EPS = 1e-5   # rounding allowance per summed contribution (binary32 terms with hardware exp2/rcp)
+# Rounding of the GPU's sums of per-pixel terms.  A term reaches its (tile, splat) sum through at most 12
+# binary32 roundings: 4 pixels accumulated per lane, 16 lanes per row reduced in 4 levels, 4 rows in 2,
+# the splat's scale factor (o times the constant of dG/dq, or 2), and spares; the per-tile sums are
+# then added in binary64 (at most 8,160 tiles).  Hence |error| <= gamma_12 * sum|terms| (Higham, Sec. 4.2),
+# with sum|terms| the oracle's `mass`.
+U32 = 2.0 ** -24
+TILE_SUM_ROUNDINGS = 12
+GAMMA_SUM = TILE_SUM_ROUNDINGS * U32 / (1.0 - TILE_SUM_ROUNDINGS * U32) + 8160 * 2.0 ** -53
 
 
 def to_device(arrays: dict, device="cuda"):
@@ -102,29 +112,55 @@ def grad_rel_err(g, r):
                 norm=float(nrm))
 
 
-def allowance2d(r, delta, mass):
-    """Per 2-D component: the ambiguous-decision allowance plus the rounding of a sum whose terms each carry
-    a relative error of TERM_EPS (the sum of |terms| is `mass`)."""
-    return delta + TERM_EPS * mass + TERM_EPS * np.abs(r)
+def allowance2d(delta, ebound, mass):
+    """Per 2-D component: the other branch of ambiguous decisions (delta), the first-order binary32 error
+    bound of the per-pixel terms (ebound) and the rounding of their binary32 sums (GAMMA_SUM * mass)."""
+    return delta + ebound + GAMMA_SUM * mass
 
 
-def grad2d_check(g, r, delta, mass):
-    """2-D accumulators: error beyond the allowance, relative to max(|r|, floor)."""
+def _excess(g, r, allow, floor):
+    """Error beyond the allowance relative to max(|r|, floor); counts of entries that pass only through the
+    allowance, and the largest plain relative error over entries whose allowance is negligible
+    (below 1e-4 of max(|r|, floor)): those must meet the plain bound."""
+    scale = np.maximum(np.abs(r), floor)
+    err = np.abs(g - r)
+    excess = np.maximum(err - allow, 0.0) / scale
+    plain = err / scale
+    negligible = allow <= 1e-4 * scale
+    return dict(max=float(excess.max()) if excess.size else 0.0,
+                only_by_allowance=int(((plain > GRAD_RTOL) & (excess <= GRAD_RTOL)).sum()),
+                entries=int(excess.size),
+                plain_max_negligible_allowance=float(plain[negligible].max()) if negligible.any() else 0.0,
+                allowance_over_tol_median=float(np.median(allow / scale / GRAD_RTOL)) if excess.size else 0.0)
+
+
+def grad2d_check(g, r, delta, mass, ebound):
+    """2-D accumulators against the oracle (see _excess); ambiguous entries are those with delta > 0."""
     g = np.asarray(g, np.float64)
     r = np.asarray(r, np.float64)
     floor = np.maximum(GRAD_FLOOR * np.sqrt(np.mean(r * r, axis=0, keepdims=True)), 1e-30)
-    excess = np.maximum(np.abs(g - r) - allowance2d(r, delta, mass), 0.0) / np.maximum(np.abs(r), floor)
-    return dict(max=float(excess.max()) if excess.size else 0.0, ambiguous_entries=int((delta > 0).sum()))
+    out = _excess(g, r, allowance2d(delta, ebound, mass), floor)
+    out["ambiguous_entries"] = int((delta > 0).sum())
+    return out
 
 
 def grad3d_check(g, r, allow):
-    """Parameter gradients: error beyond the propagated allowance |J|^T a, relative to max(|r|, floor)."""
+    """Parameter gradients: error beyond the propagated allowance |J|^T a (see _excess)."""
     g = np.asarray(g, np.float64).ravel()
     r = np.asarray(r, np.float64).ravel()
     a = np.asarray(allow, np.float64).ravel()
     floor = max(GRAD_FLOOR * np.sqrt(np.mean(r * r)), 1e-30) if r.size else 1.0
-    excess = np.maximum(np.abs(g - r) - a, 0.0) / np.maximum(np.abs(r), floor)
-    return dict(max=float(excess.max()) if excess.size else 0.0)
+    return _excess(g, r, a, floor)
+
+
+def assert_grad_ok(name, res):
+    """The parity bound: nothing beyond the allowance, and the plain bound where the allowance is negligible."""
+    print(f"  {name}: beyond allowance {res['max']:.2e}, passing only by the allowance {res['only_by_allowance']} "
+          f"of {res['entries']}, plain max where the allowance is negligible "
+          f"{res['plain_max_negligible_allowance']:.2e}, median allowance / tolerance "
+          f"{res['allowance_over_tol_median']:.2e}", flush=True)
+    assert res["max"] <= GRAD_RTOL, (name, res)
+    assert res["plain_max_negligible_allowance"] <= GRAD_RTOL, (name, res)
 
 
 def ambiguous_splats(r2d, delta):
@@ -143,12 +179,13 @@ def oracle_full(arrays, sh_degree, cam, falloff=0, tile_cull=0, rho=0.1, bg=(0.0
     out = orc.render(rec, vals, ranges)
     res = dict(orc=orc, rec=rec, keys=keys, values=vals, ranges=ranges, out=out)
     if dL is not None:
-        g2d, delta, mass, _ = orc.backward2d(rec, dL, vals, ranges, with_delta=True)
+        g2d, delta, mass, ebound, _ = orc.backward2d(rec, dL, vals, ranges, with_delta=True)
         res["g2d"] = g2d
         res["delta"] = delta
         res["mass"] = mass
+        res["ebound"] = ebound
         vis = rec.tiles_touched > 0
         res["grads"] = PF.chain_to_params(arrays, sh_degree, cam, g2d, vis, rec.clamp_bits, falloff, rho)
-        res["allow"] = PF.abs_chain(arrays, sh_degree, cam, allowance2d(g2d, delta, mass), vis, rec.clamp_bits,
+        res["allow"] = PF.abs_chain(arrays, sh_degree, cam, allowance2d(delta, ebound, mass), vis, rec.clamp_bits,
                                     falloff, rho)
     return res

@@ -16,8 +16,8 @@ from oracle import oracle as O
 from oracle import preprocess_f64 as PF
 from paper_2402_10128_amd import synth
 
-from .parity_helpers import (GRAD_RTOL, IMG_ATOL, allowance2d, ambiguous_splats, gpu_render, grad2d_check,
-                             grad3d_check, image_compare, record_mismatches)
+from .parity_helpers import (GRAD_RTOL, IMG_ATOL, allowance2d, ambiguous_splats, assert_grad_ok, gpu_render,
+                             grad2d_check, grad3d_check, image_compare, record_mismatches)
 
 pytestmark = pytest.mark.gpu
 
@@ -92,11 +92,11 @@ def test_full_size_sampled_parity(case):
     unf = pix_mask & ~out["flags"].astype(bool)
     assert np.array_equal(gpu["n_contrib"][unf], out["n_contrib"][unf].astype(np.uint32))
 
-    g2d, delta, mass, _ = orc.backward2d(rec, dL.astype(np.float64), values, ranges, tiles=tiles, with_delta=True)
+    g2d, delta, mass, ebound, _ = orc.backward2d(rec, dL.astype(np.float64), values, ranges, tiles=tiles, with_delta=True)
     ncomp = 10 if falloff == O.FALLOFF_GEF else 9
-    chk = grad2d_check(gpu["grad2d"][:, :ncomp], g2d[:, :ncomp], delta[:, :ncomp], mass[:, :ncomp])
-    print("  grad2d", chk, flush=True)
-    assert chk["max"] <= GRAD_RTOL, chk
+    chk = grad2d_check(gpu["grad2d"][:, :ncomp], g2d[:, :ncomp], delta[:, :ncomp], mass[:, :ncomp],
+                       ebound[:, :ncomp])
+    assert_grad_ok("grad2d", chk)
 
     reach = np.abs(g2d).sum(axis=1) > 0
     idx = np.nonzero(reach)[0]
@@ -104,7 +104,7 @@ def test_full_size_sampled_parity(case):
     vis = rec.tiles_touched[idx] > 0
     clamp = rec.clamp_bits[idx]
     ref = PF.chain_to_params(sub, sc.sh_degree, cam, g2d[idx], vis, clamp, falloff, 0.1)
-    allow = PF.abs_chain(sub, sc.sh_degree, cam, allowance2d(g2d[idx], delta[idx], mass[idx]), vis, clamp,
+    allow = PF.abs_chain(sub, sc.sh_degree, cam, allowance2d(delta[idx], ebound[idx], mass[idx]), vis, clamp,
                          falloff, 0.1)
     amb = ambiguous_splats(g2d[idx, :ncomp], delta[idx, :ncomp])
     print(f"  {len(idx)} splats reached, {int(amb.sum())} with an ambiguous decision", flush=True)
@@ -113,6 +113,4 @@ def test_full_size_sampled_parity(case):
         rest = np.ones(g.shape[0], bool)
         rest[idx] = False
         assert not np.any(g[rest]), f"{k}: gradient of a splat outside the sampled tiles"
-        r = grad3d_check(g[idx], ref[k], allow[k])
-        print(f"  {k}: {r}", flush=True)
-        assert r["max"] <= GRAD_RTOL, (k, r)
+        assert_grad_ok(k, grad3d_check(g[idx], ref[k], allow[k]))
