@@ -152,8 +152,11 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
                               void* splat_ws, void* key_ws, size_t key_ws_bytes, uint64_t num_keys,
                               void* pixel_ws, float* out_rgb, void* stream);
 
-/* Backward pass: given dL/d(out_rgb) [height,width,3], walks every pixel's
- * contributors back to front recovering the transmittance by division, accumulates
+/* Backward pass (Sec. 4.4: the splats' position, opacity, covariance, SH colour and
+ * shape are optimised through the rasterizer's gradients; the derivative of the
+ * compositing of Sec. 4.2, Eq. transimttance): given dL/d(out_rgb) [height,width,3],
+ * walks every pixel's contributors back to front recovering the transmittance by
+ * division, accumulates
  * the gradient of each splat's 2-D quantities (mean2D, conic, opacity, colour and,
  * with the GEF falloff, beta), then maps them to the parameters through the
  * preprocess chain rule (evaluated in binary64).  Every gradient buffer of `grads`
@@ -416,7 +419,13 @@ ges_status ges_opacity_reset(float* opacity_logits, float* exp_avg, float* exp_a
 double ges_expon_lr(int64_t step, double lr_init, double lr_final, int64_t max_steps, int64_t delay_steps,
                     double delay_mult);
 
-/* ---- serving: continuous batching of render requests ----------------------------- */
+/* ---- serving: continuous batching of render requests -----------------------------
+ * Forward renders (Sec. 4.2, Eq. transimttance, the same kernels as ges_render_forward)
+ * of scenes resident in device memory, for many cameras and resolutions at once: the
+ * real-time rendering the method is built for (Sec. 1; Sec. 5.2 reports render speed).
+ * Requests arriving while a batch runs are admitted into the next batch as slots and
+ * pool memory free up; every batch runs one preprocess, one scatter/sort and one raster
+ * launch over all of its views, on one of two streams. */
 typedef struct ges_server ges_server;
 
 typedef struct {
@@ -458,6 +467,24 @@ ges_status ges_serve_add_scene(ges_server* s, const ges_splats* scene, int32_t* 
 ges_status ges_serve_submit(ges_server* s, int32_t scene_id, const ges_camera* cam, float* out_rgb_device,
                             uint64_t* request_id);
 ges_status ges_serve_poll(ges_server* s, uint64_t request_id, ges_request_info* info);
+/* As ges_serve_submit, and (tests) the finished request also leaves copies of its frame
+ * arrays in inspect_device, a 256-byte-aligned device buffer of inspect_bytes bytes laid
+ * out as (each part starting on a 256-byte boundary, in this order):
+ *   records   [n,16] FP32, the per-splat record of ges_frame_view (64 B per splat);
+ *   ranges    [tiles,2] u32, each tile's [start,end) in the batch's sorted ids;
+ *   n_contrib [height,width] u32 (written there by the raster itself);
+ *   header    4 x u64: this view's keys, error word, pairs examined, pairs composited
+ *             (the part is 256 bytes);
+ *   ids       [batch keys] u32, the batch's sorted splat ids (every view of the batch),
+ *             copied only if inspect_bytes >= ges_serve_inspect_bytes(n, w, h, batch keys);
+ *             ges_serve_poll's num_keys gives the batch's key count.
+ * inspect_bytes below ges_serve_inspect_bytes(n, w, h, 0): CAPACITY; a misaligned
+ * buffer: INVALID_ARGUMENT.  The buffer must stay alive until the request finishes. */
+ges_status ges_serve_submit_inspect(ges_server* s, int32_t scene_id, const ges_camera* cam, float* out_rgb_device,
+                                    void* inspect_device, size_t inspect_bytes, uint64_t* request_id);
+/* Size of that layout for a scene of n splats, a width x height view and a batch of
+ * batch_keys keys (0 for invalid sizes). */
+size_t ges_serve_inspect_bytes(int64_t n, int32_t width, int32_t height, uint64_t batch_keys);
 /* Block until every request submitted so far has finished (done, failed or rejected). */
 ges_status ges_serve_drain(ges_server* s);
 /* Stops the server; requests still queued are cancelled, running ones are completed. */

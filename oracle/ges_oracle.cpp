@@ -1021,6 +1021,14 @@ int oc_num_threads(void) {
 #endif
 }
 
+void oc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int oc_preprocess(int mode, const oc_splats* s, const oc_camera* cam, const oc_params* p, oc_record* out) {
   if (!s || !cam || !p || !out || s->n < 0 || s->sh_degree < 0 || s->sh_degree > 3) return -1;
   if (mode == OC_MODE_F32) preprocess_all<float>(s, cam, p, out);

@@ -154,6 +154,8 @@ int oc_backward_untiled(int mode, const oc_record* r, int64_t n, const oc_camera
                         oc_stats* stats);
 
 int oc_num_threads(void);
+/* Threads of the following OpenMP loops (n > 0). */
+void oc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -273,3 +273,7 @@ def lgamma_c(x):
 
 def num_threads():
     return lib().oc_num_threads()
+
+
+def set_num_threads(n: int):
+    lib().oc_set_num_threads(int(n))

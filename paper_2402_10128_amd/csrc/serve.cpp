@@ -99,6 +99,8 @@ struct Request {
   uint64_t t_submit = 0, t_start = 0, t_done = 0, num_keys = 0;
   int32_t batch_size = 0;
   size_t ws_off = 0, ws_bytes = 0;
+  char* inspect = nullptr;        // device buffer receiving copies of the view's frame arrays (tests)
+  size_t inspect_bytes = 0;
 };
 
 struct BatchWork {
@@ -111,6 +113,7 @@ struct BatchWork {
   int stream = 0;
   hipEvent_t done = nullptr;
   std::unique_ptr<DeviceBatch> host;         // kept alive until the batch retires
+  std::vector<std::pair<char*, size_t>> inspect;   // per view: inspection buffer (may be null) and its size
   uint64_t sim_done_ns = 0;
 };
 
@@ -156,6 +159,21 @@ namespace {
 
 bool finished_state(int32_t s) {
   return s == GES_REQ_DONE || s == GES_REQ_FAILED || s == GES_REQ_REJECTED || s == GES_REQ_CANCELLED;
+}
+
+// Inspection buffer of a served request: the view's records, tile ranges (positions in the batch's sorted
+// ids), n_contrib and header, then the batch's sorted ids; every part 256-byte aligned.
+struct ServeInspectLayout { size_t off_records, off_ranges, off_n_contrib, off_header, off_ids, bytes; };
+ServeInspectLayout serve_inspect_layout(int64_t n, int32_t w, int32_t h, uint64_t batch_keys) {
+  ServeInspectLayout L{};
+  const size_t tiles = (size_t)((w + kTile - 1) / kTile) * (size_t)((h + kTile - 1) / kTile);
+  L.off_records = 0;
+  L.off_ranges = align256(64 * (size_t)n);
+  L.off_n_contrib = L.off_ranges + align256(8 * tiles);
+  L.off_header = L.off_n_contrib + align256(4 * (size_t)w * (size_t)h);
+  L.off_ids = L.off_header + 256;
+  L.bytes = L.off_ids + align256(4 * (size_t)batch_keys);
+  return L;
 }
 
 size_t request_bytes(const ges_splats& sc, const ges_camera& c) {
@@ -206,6 +224,18 @@ class GpuExecutor : public Executor {
     hipError_t e = launch_bin_scatter(db, bt, st);
     if (e == hipSuccess) e = launch_tile_sort(db, bt, st);
     if (e == hipSuccess) e = launch_raster_forward(db, bt, st);
+    for (int v = 0; v < bt.nviews && e == hipSuccess; ++v) {
+      if (!b.inspect[(size_t)v].first) continue;
+      const ViewDesc& V = b.host->views[v];
+      const ServeInspectLayout L = serve_inspect_layout(V.n, V.width, V.height, b.keys);
+      char* dst = b.inspect[(size_t)v].first;
+      const int64_t tiles = (int64_t)V.tiles_x * V.tiles_y;
+      if (V.n > 0) e = hipMemcpyAsync(dst + L.off_records, V.rec, 64 * (size_t)V.n, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(dst + L.off_ranges, V.ranges, 8 * (size_t)tiles, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(dst + L.off_header, V.header, 32, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess && b.keys > 0 && L.bytes <= b.inspect[(size_t)v].second)
+        e = hipMemcpyAsync(dst + L.off_ids, bt.sorted_ids, 4 * (size_t)b.keys, hipMemcpyDeviceToDevice, st);
+    }
     if (e == hipSuccess && !b.done) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(b.done, st);
     if (e != hipSuccess) { err = hipGetErrorString(e); return GES_ERR_DEVICE; }
@@ -317,6 +347,7 @@ void build_views(ges_server* s, BatchWork& b) {
   std::memset(&h, 0, offsetof(DeviceBatch, views));
   h.nviews = (int32_t)b.ids.size();
   b.plans.clear();
+  b.inspect.clear();
   int64_t pre = 0, bin = 0, tiles = 0;
   for (size_t v = 0; v < b.ids.size(); ++v) {
     const Request& r = s->reqs.at(b.ids[v]);
@@ -327,6 +358,11 @@ void build_views(ges_server* s, BatchWork& b) {
     fill_view(V, &sc, &r.cam, &s->params);
     attach_view(V, fp, s->pool + r.ws_off);
     V.out_rgb = r.out;
+    b.inspect.emplace_back(r.inspect, r.inspect_bytes);
+    // an inspected request's raster writes its n_contrib straight into the inspection buffer
+    if (r.inspect)
+      V.n_contrib = reinterpret_cast<uint32_t*>(
+          r.inspect + serve_inspect_layout(sc.n, r.cam.width, r.cam.height, 0).off_n_contrib);
     h.pre_prefix[v] = pre;
     h.bin_prefix[v] = bin;
     h.tile_prefix[v] = tiles;
@@ -520,7 +556,18 @@ ges_status ges_serve_add_scene(ges_server* s, const ges_splats* scene, int32_t* 
 
 ges_status ges_serve_submit(ges_server* s, int32_t scene_id, const ges_camera* cam, float* out_rgb_device,
                             uint64_t* request_id) {
+  return ges_serve_submit_inspect(s, scene_id, cam, out_rgb_device, nullptr, 0, request_id);
+}
+
+size_t ges_serve_inspect_bytes(int64_t n, int32_t width, int32_t height, uint64_t batch_keys) {
+  if (n < 0 || width < 1 || height < 1) return 0;
+  return ges::serve_inspect_layout(n, width, height, batch_keys).bytes;
+}
+
+ges_status ges_serve_submit_inspect(ges_server* s, int32_t scene_id, const ges_camera* cam, float* out_rgb_device,
+                                    void* inspect_device, size_t inspect_bytes, uint64_t* request_id) {
   if (!s || !cam || !out_rgb_device || !request_id) return GES_ERR_INVALID_ARGUMENT;
+  if (inspect_device && (reinterpret_cast<uintptr_t>(inspect_device) % 256 != 0)) return GES_ERR_INVALID_ARGUMENT;
   if (!ges::check_camera(cam).empty()) return GES_ERR_INVALID_ARGUMENT;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return GES_ERR_INVALID_ARGUMENT;
@@ -532,6 +579,13 @@ ges_status ges_serve_submit(ges_server* s, int32_t scene_id, const ges_camera* c
   r.cam = *cam;
   r.out = out_rgb_device;
   r.t_submit = ges::now_ns();
+  if (inspect_device) {
+    const ges_splats& sc = s->scenes[(size_t)scene_id];
+    if (inspect_bytes < ges::serve_inspect_layout(sc.n, cam->width, cam->height, 0).bytes)
+      return GES_ERR_CAPACITY;
+    r.inspect = reinterpret_cast<char*>(inspect_device);
+    r.inspect_bytes = inspect_bytes;
+  }
   const size_t need = ges::request_bytes(s->scenes[(size_t)scene_id], *cam) + ges::table_bytes();
   *request_id = r.id;
   if (need > s->alloc->size()) {

@@ -140,6 +140,9 @@ _SIGS = {
                                              C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
     "ges_serve_add_scene": (C.c_int, [C.c_void_p, C.POINTER(ges_splats), C.POINTER(C.c_int32)]),
     "ges_serve_submit": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(ges_camera), C.c_void_p, C.POINTER(C.c_uint64)]),
+    "ges_serve_submit_inspect": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(ges_camera), C.c_void_p, C.c_void_p,
+                                           C.c_size_t, C.POINTER(C.c_uint64)]),
+    "ges_serve_inspect_bytes": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32, C.c_uint64]),
     "ges_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ges_request_info)]),
     "ges_serve_drain": (C.c_int, [C.c_void_p]),
     "ges_serve_destroy": (C.c_int, [C.c_void_p]),

@@ -61,12 +61,18 @@ class Server:
         G._check(G.lib().ges_serve_add_scene(self._h, C.byref(s), C.byref(sid)))
         return sid.value
 
-    def submit(self, scene_id: int, cam, out_ptr) -> int:
-        """out_ptr: a CUDA float32 tensor [h,w,3] or (simulated) any non-zero integer."""
+    def submit(self, scene_id: int, cam, out_ptr, inspect=None) -> int:
+        """out_ptr: a CUDA float32 tensor [h,w,3] or (simulated) any non-zero integer.  inspect: optional
+        256-byte-aligned CUDA uint8 tensor receiving the request's frame arrays (see inspect_arrays)."""
         ptr = out_ptr.data_ptr() if hasattr(out_ptr, "data_ptr") else int(out_ptr)
         rid = C.c_uint64(0)
-        G._check(G.lib().ges_serve_submit(self._h, int(scene_id), C.byref(G.camera_struct(cam)), C.c_void_p(ptr),
-                                          C.byref(rid)))
+        if inspect is None:
+            G._check(G.lib().ges_serve_submit(self._h, int(scene_id), C.byref(G.camera_struct(cam)), C.c_void_p(ptr),
+                                              C.byref(rid)))
+        else:
+            G._check(G.lib().ges_serve_submit_inspect(self._h, int(scene_id), C.byref(G.camera_struct(cam)),
+                                                      C.c_void_p(ptr), C.c_void_p(inspect.data_ptr()),
+                                                      inspect.numel(), C.byref(rid)))
         return rid.value
 
     def poll(self, rid: int) -> dict:
@@ -124,3 +130,25 @@ def run_stream(server: Server, requests, outs, rate_hz: float | None, seed: int 
     return dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                 mean_ms=float(lat.mean()), mpix_s=px / ((t_last - t_first) / 1e9) / 1e6, all_done=ok,
                 mean_batch=float(np.mean([x["batch_size"] for x in infos])), infos=infos)
+
+
+def _align256(x: int) -> int:
+    return (x + 255) // 256 * 256
+
+
+def inspect_arrays(buf, n: int, width: int, height: int, batch_keys: int) -> dict:
+    """numpy copies of a served request's inspection buffer, laid out as ges_serve_submit_inspect documents."""
+    tiles = ((width + 15) // 16) * ((height + 15) // 16)
+    px = width * height
+    off_ranges = _align256(64 * n)
+    off_nc = off_ranges + _align256(8 * tiles)
+    off_hdr = off_nc + _align256(4 * px)
+    off_ids = off_hdr + 256
+    b = buf.cpu().numpy()
+    out = dict(records=b[:64 * n].view(np.float32).reshape(n, 16),
+               ranges=b[off_ranges:off_ranges + 8 * tiles].view(np.uint32).reshape(tiles, 2),
+               n_contrib=b[off_nc:off_nc + 4 * px].view(np.uint32).reshape(height, width),
+               header=b[off_hdr:off_hdr + 32].view(np.uint64))
+    if b.size >= off_ids + 4 * batch_keys:
+        out["ids"] = b[off_ids:off_ids + 4 * batch_keys].view(np.uint32)
+    return out

@@ -1,14 +1,17 @@
-"""Serving on the GPU: a request's image is bit-identical alone, in a mixed batch and through the plain
-render path; batched serving beats one-request-at-a-time serving in throughput and p99 latency."""
+"""Serving on the GPU: every request of a mixed batch against the oracle (records, per-tile lists and
+ranges bit-exact, image within 1e-5 under the flag protocol); a request's image is bit-identical alone, in
+a mixed batch and through the plain render path; batched serving beats one-request-at-a-time serving in
+throughput and p99 latency."""
 import numpy as np
 import pytest
 import torch
 
+from oracle import oracle as O
 from paper_2402_10128_amd import ges as G
 from paper_2402_10128_amd import synth
-from paper_2402_10128_amd.serve import Server, run_stream
+from paper_2402_10128_amd.serve import Server, inspect_arrays, run_stream
 
-from .parity_helpers import to_device
+from .parity_helpers import IMG_ATOL, image_compare, record_mismatches, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -21,6 +24,67 @@ def _scenes(sizes, seed=500):
 
 def _requests(n_req, n_scenes, seed=2000):
     return synth.serving_requests(n_req, n_scenes, RES, seed=seed)
+
+
+def test_served_requests_match_the_oracle():
+    """One mixed batch of 8 requests over 3 resident scenes and 4 resolutions (one ragged: 200x136 is 12.5 x
+    8.5 tiles): per request, every record bit-exact, the view's key count, every tile's list (its range in
+    the batch's sorted ids) equal to the oracle's, and the image within 1e-5 per channel with n_contrib
+    equal on unflagged pixels -- every tile of the small views, 48 sampled tiles (random, a 2x2 block and
+    the longest lists) of the 1280x720 ones."""
+    sizes = [20_000, 50_000, 80_000]
+    host = [synth.scene_clusters(n, 500 + i) for i, n in enumerate(sizes)]
+    scenes = [to_device(h.arrays()) for h in host]
+    plan = [(0, (256, 256)), (1, (200, 136)), (2, (1280, 720)), (0, (512, 512)), (1, (1280, 720)), (2, (200, 136)),
+            (1, (256, 256)), (2, (512, 512))]
+    reqs = [(k, synth.orbit_camera(np.random.default_rng(3000 + i), w, h)) for i, (k, (w, h)) in enumerate(plan)]
+    outs = [torch.zeros((c.height, c.width, 3), device="cuda") for _, c in reqs]
+    bufs = [torch.zeros(64 << 20, dtype=torch.uint8, device="cuda") for _ in reqs]
+    with Server(4 << 30, max_slots=8) as srv:
+        ids = [srv.add_scene(sc) for sc in scenes]
+        rids = [srv.submit(ids[k], cam, out, inspect=b) for (k, cam), out, b in zip(reqs, outs, bufs)]
+        srv.drain()
+        infos = [srv.poll(r) for r in rids]
+    assert all(i["state"] == "DONE" for i in infos)
+    print("batch sizes:", [i["batch_size"] for i in infos], flush=True)
+    assert max(i["batch_size"] for i in infos) > 1
+    rng = np.random.default_rng(4)
+    for i, ((k, cam), out, buf, info) in enumerate(zip(reqs, outs, bufs, infos)):
+        n = sizes[k]
+        a = inspect_arrays(buf, n, cam.width, cam.height, info["num_keys"])
+        assert "ids" in a, "inspection buffer too small for the batch's sorted ids"
+        orc = O.Oracle(host[k].arrays(), host[k].sh_degree, cam, falloff=O.FALLOFF_PHI, tile_cull=O.TILES_ELLIPSE)
+        rec = orc.preprocess(O.MODE_F32)
+        keys, vals, ranges = orc.build_keys(rec)
+        mm = record_mismatches(a["records"], rec)
+        assert all(v == 0 for v in mm.values()), (i, mm)
+        assert int(a["header"][0]) == len(keys), (i, int(a["header"][0]), len(keys))
+        assert int(a["header"][1]) == 0, "error word set"
+        g_len = a["ranges"][:, 1].astype(np.int64) - a["ranges"][:, 0]
+        o_len = ranges[:, 1] - ranges[:, 0]
+        assert np.array_equal(g_len, o_len), i
+        assert np.all(a["ranges"][o_len == 0] == 0), "empty tiles must have the range (0, 0)"
+        for t in np.nonzero(o_len)[0]:
+            g0, g1 = a["ranges"][t]
+            assert np.array_equal(a["ids"][g0:g1], vals[ranges[t, 0]:ranges[t, 1]]), (i, t)
+        T = orc.TX * orc.TY
+        if cam.width * cam.height > 512 * 512:
+            block = [ty * orc.TX + tx for ty in (20, 21) for tx in (38, 39)]
+            longest = list(np.argsort(o_len)[-4:])
+            tiles = np.unique(np.concatenate([rng.choice(T, 40, replace=False), block, longest])).astype(np.int32)
+        else:
+            tiles = None
+        ref = orc.render(rec, vals, ranges, tiles=tiles)
+        mask = np.zeros((cam.height, cam.width), bool)
+        for t in (range(T) if tiles is None else tiles):
+            ty, tx = divmod(int(t), orc.TX)
+            mask[16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16] = True
+        cmp = image_compare(out.cpu().numpy(), ref, pixels_mask=mask)
+        print(f"  request {i}: scene {k} {cam.width}x{cam.height} K={len(keys)} batch {info['batch_size']} "
+              f"tiles {'all' if tiles is None else len(tiles)} image {cmp}", flush=True)
+        assert cmp["max_err"] <= IMG_ATOL and cmp["flagged_max_err"] <= IMG_ATOL, (i, cmp)
+        unf = mask & ~ref["flags"].astype(bool)
+        assert np.array_equal(a["n_contrib"][unf], ref["n_contrib"][unf].astype(np.uint32)), i
 
 
 def test_alone_equals_mixed_equals_plain_render():

@@ -136,3 +136,36 @@ def test_continuous_batching_admits_arrivals_while_busy():
         later = [s.poll(i)["batch_size"] for i in rest]
     assert b0 == 1
     assert max(later) >= 4
+
+
+def test_inspection_submit_validates_its_buffer():
+    """ges_serve_submit_inspect: the layout size of ges_serve_inspect_bytes (records, ranges, n_contrib,
+    header, batch ids, each 256-byte aligned), a misaligned buffer and one too small for the view refused
+    before the request is queued."""
+    n, w, h = 10_000, 256, 256
+    a = lambda x: (x + 255) // 256 * 256
+    want = a(64 * n) + a(8 * 256) + a(4 * w * h) + 256 + a(4 * 1000)
+    assert G.lib().ges_serve_inspect_bytes(n, w, h, 1000) == want
+    assert G.lib().ges_serve_inspect_bytes(n, 0, h, 0) == 0
+
+    class Buf:   # a stand-in device buffer: never dereferenced by the simulated executor
+        def __init__(self, ptr, size):
+            self.ptr, self.size = ptr, size
+
+        def data_ptr(self):
+            return self.ptr
+
+        def numel(self):
+            return self.size
+
+    with Server(1 << 30, max_slots=4, simulated=dict(batch_ns=100_000)) as s:
+        sid = s.add_scene(dict(n=n))
+        with pytest.raises(G.GESError) as e:
+            s.submit(sid, CAM, 1, inspect=Buf((1 << 30) + 8, want))
+        assert e.value.status == 1
+        with pytest.raises(G.GESError) as e:
+            s.submit(sid, CAM, 1, inspect=Buf(1 << 30, G.lib().ges_serve_inspect_bytes(n, w, h, 0) - 1))
+        assert e.value.status == 2
+        rid = s.submit(sid, CAM, 1)
+        s.drain()
+        assert s.poll(rid)["state"] == "DONE"
