@@ -31,12 +31,20 @@ sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector peak (packed FMA)
+VALU_PEAK_TOPS = 39.32         # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: non-packed lane operations (T/s)
 
-# Floating-point operations per pair of the raster (FMA = 2), see DESIGN.md "Rooflines":
+# Raster work per pair in VALU lane-slots (a transcendental counts as 4): the forward examines a pair in
+# 8 slots and composites it in 22 (PHI; GEF adds log2 and exp2: 30); the backward walks a pair in 8 and
+# differentiates a composited one in 55 (GEF: 67).  Beside them, FLOPs (FMA = 2) for the FP32 peak.
+FWD_SLOTS_EXAMINED = 8
+FWD_SLOTS_BLENDED = {0: 22, 1: 30}
+BWD_SLOTS_WALKED = 8
+BWD_SLOTS_BLENDED = {0: 55, 1: 67}
 FWD_FLOP_EXAMINED = 9          # dx, dy, quadratic form
 FWD_FLOP_BLENDED = {0: 12, 1: 15}   # falloff, alpha, transmittance, colour (PHI, GEF)
 BWD_FLOP_EXAMINED = 9
 BWD_FLOP_BLENDED = {0: 51, 1: 60}
+RASTER_STAGES = ("raster_forward", "raster_backward")
 
 
 def parse():
@@ -48,6 +56,8 @@ def parse():
     ap.add_argument("--tile-cull", choices=["square", "ellipse"], default="ellipse")
     ap.add_argument("--falloff", choices=["phi", "gef"], default="phi")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the forward+backward measurements of the 1M-splat and 5M-splat workloads")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
     ap.add_argument("--no-mixture", action="store_true", help="skip the 1-D mixture-simulation sweep")
     ap.add_argument("--no-variants", action="store_true",
@@ -65,17 +75,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(stage, n, sh_coeffs, K, tiles, bin_blocks, px, ellipse):
-    """Minimum HBM bytes of one launch of an HBM-bound stage (rooflines)."""
+def algorithmic_bytes(stage, n, sh_coeffs, K, C, L, px):
+    """Minimum HBM bytes of one launch of an HBM-bound stage: n splats, K keys, C candidate slots, L listed
+    splats, px pixels (the per-unit figures are listed in the design doc)."""
     splat_in = 12 + 12 + 16 + 4 + 4 + 12 * sh_coeffs
-    rec_tile_read = 48 if ellipse else 16
-    table = 4 * bin_blocks * tiles
     return {
-        "preprocess": n * (splat_in + 64),
-        "bin_count": n * rec_tile_read + table,
-        "bin_scan": 2 * table + 12 * tiles,
-        "bin_scatter": n * (rec_tile_read + 16) + table + 8 * K,
-        "tile_sort": 12 * K,
+        # parameters in; record, visibility word, depth key and candidate count out
+        "preprocess": n * (splat_in + 64 + 4 + 8),
+        # the item keys in, the listed (key, item) pairs out
+        "depth_sort": 4 * n + 8 * L,
+        # the depth order and the candidate counts in, chunk offsets out
+        "key_scan": 8 * L + L // 16,
+        # per listed splat its order entry, record and count in, tile count and visibility out; 8 B per slot
+        "duplicate": L * (4 + 64 + 4 + 8) + 8 * C,
+        # the slots in, the sorted (tile, splat) pairs out
+        "tile_sort": 8 * C + 8 * K,
         "preprocess_backward": n * (16 + 12 + 16 + 4 + 12 * sh_coeffs + 48 + 80 + 4 * (3 + 3 + 4 + 1 + 1 + 3 * sh_coeffs)),
         "zero": 96 * n,
         "loss": 37 * px,
@@ -91,16 +105,61 @@ def algorithmic_bytes(stage, n, sh_coeffs, K, tiles, bin_blocks, px, ellipse):
     }.get(stage)
 
 
+def raster_work(stage, falloff, pairs_exam, pairs_blend, bwd_walk):
+    """(VALU lane-slots, FLOPs) of one launch of a raster stage from its exact pair counts."""
+    f = 1 if falloff == 1 else 0
+    if stage == "raster_forward":
+        slots = FWD_SLOTS_EXAMINED * (pairs_exam - pairs_blend) + FWD_SLOTS_BLENDED[f] * pairs_blend
+        flop = FWD_FLOP_EXAMINED * pairs_exam + FWD_FLOP_BLENDED[f] * pairs_blend
+    else:
+        slots = BWD_SLOTS_WALKED * (bwd_walk - pairs_blend) + BWD_SLOTS_BLENDED[f] * pairs_blend
+        flop = BWD_FLOP_EXAMINED * bwd_walk + BWD_FLOP_BLENDED[f] * pairs_blend
+    return slots, flop
+
+
+def stage_rooflines(per_stage, m, falloff, workload):
+    """Each stage's fraction of its roofline: VALU lane-slots against 39.3 T/s for the raster (with the FLOP
+    figure beside it and, from the committed counters, the issued-over-algorithmic lane-slot ratio), HBM
+    bytes against 8 TB/s for the rest (with the counters' measured-over-algorithmic byte ratio)."""
+    out = {}
+    for stage, ms in per_stage.items():
+        if ms <= 0:
+            continue
+        if stage in RASTER_STAGES:
+            slots, flop = raster_work(stage, falloff, m["pairs_exam"], m["pairs_blend"], m["bwd_walk"])
+            tops = slots / (ms / 1e3) / 1e12
+            row = {"bound": "alu", "achieved": round(tops, 3), "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s",
+                   "frac": round(tops / VALU_PEAK_TOPS, 4), "algorithmic_lane_ops": slots,
+                   "flop_tflops": round(flop / (ms / 1e3) / 1e12, 3),
+                   "flop_frac_of_157.3": round(flop / (ms / 1e3) / 1e12 / FP32_PEAK_TFLOPS, 4)}
+            issued = read_counter(stage, workload, "valu_insts_per_launch")
+            if issued is not None:
+                row["issued_over_algorithmic"] = round(issued * 64 / slots, 3)
+        else:
+            nbytes = algorithmic_bytes(stage, m["n"], m["sh_k"], m["K"], m["C"], m["L"], m["px"])
+            if nbytes is None:
+                continue
+            gbs = nbytes / (ms / 1e3) / 1e9
+            row = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": nbytes}
+            measured = read_counter(stage, workload, "hbm_bytes_per_launch")
+            if measured is not None:
+                row["measured_over_algorithmic"] = round(measured / nbytes, 3)
+        out[stage] = row
+    return out
+
+
 def kernel_source_hash(stage):
     src = {"raster_forward": "raster.hip", "raster_backward": "raster.hip", "preprocess": "preprocess.hip",
-           "preprocess_backward": "preprocess.hip", "tile_sort": "tile_sort.hip", "bin_count": "binning.hip",
-           "bin_scatter": "binning.hip", "bin_scan": "binning.hip", "loss": "loss.hip", "zero": "loss.hip"}[stage]
+           "preprocess_backward": "preprocess_bwd.hip", "tile_sort": "radix.hip", "depth_sort": "radix.hip",
+           "duplicate": "binning.hip", "key_scan": "binning.hip", "loss": "loss.hip", "zero": "loss.hip"}[stage]
     with open(os.path.join(HERE, "paper_2402_10128_amd", "csrc", src), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(stage, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches this source."""
+def read_counter(stage, workload, field):
+    """A per-launch counter figure of a stage from the committed rocprofv3 summary
+    profiles/<stage>_counters_workload<k>.md, if that summary was taken from the current source."""
     path = os.path.join(HERE, "profiles", f"{stage}_counters_workload{workload}.md")
     if not os.path.exists(path):
         return None
@@ -113,58 +172,141 @@ def read_traffic(stage, workload):
     if fields.get("source_sha256_16") != kernel_source_hash(stage):
         return None
     try:
-        return float(fields["hbm_bytes_per_launch"])
+        return float(fields[field])
     except (KeyError, ValueError):
         return None
 
 
-def cpu_baseline(cfg, falloff, tile_cull, budget_tiles=160):
-    """The oracle on this host: full per-splat preprocess, forward+backward of a sample of tiles,
-    binary64 chain rule on a splat subset; extrapolated to one full frame."""
-    import torch
+def _oracle_frame(cfg, falloff, tile_cull, backward=True):
+    """One whole frame on the oracle (test infrastructure): preprocess, keys and their sort, the per-pixel
+    render and, with backward, the reverse pass and the binary64 chain rule.  Seconds per part."""
     from oracle import oracle as O
     from oracle import preprocess_f64 as PF
     sc, cam = cfg["scene"], cfg["camera"]
-    arr = sc.arrays()
-    n = sc.n
-    orc = O.Oracle(arr, sc.sh_degree, cam, falloff=falloff, tile_cull=tile_cull)
+    orc = O.Oracle(sc.arrays(), sc.sh_degree, cam, falloff=falloff, tile_cull=tile_cull)
+    t = {}
     t0 = time.perf_counter()
     rec = orc.preprocess(O.MODE_F32)
-    t_pre = time.perf_counter() - t0
-    rng = np.random.default_rng(0)
-    T = orc.TX * orc.TY
-    tiles = np.sort(rng.choice(T, size=min(budget_tiles, T), replace=False)).astype(np.int32)
+    t["preprocess"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    vals, ranges = [], np.zeros((T, 2), np.int64)
-    pos = 0
-    for t in tiles:
-        lst = orc.tile_list(rec, int(t))
-        ranges[t] = (pos, pos + len(lst))
+    _, vals, ranges = orc.build_keys(rec)
+    t["keys"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orc.render(rec, vals, ranges)
+    t["render"] = time.perf_counter() - t0
+    if backward:
+        dL = np.random.default_rng(1).standard_normal((cam.height, cam.width, 3))
+        t0 = time.perf_counter()
+        g2d, _ = orc.backward2d(rec, dL, vals, ranges)
+        t["backward"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        PF.chain_to_params(sc.arrays(), sc.sh_degree, cam, g2d, rec.tiles_touched > 0, rec.clamp_bits, falloff, 0.1)
+        t["chain_rule"] = time.perf_counter() - t0
+    return t
+
+
+def _oracle_tiles(cfg, falloff, tile_cull, tiles, backward=True):
+    """The oracle on a sample of tiles: full preprocess, those tiles' sorted lists, their per-pixel render
+    (and reverse pass).  Seconds per part."""
+    from oracle import oracle as O
+    sc, cam = cfg["scene"], cfg["camera"]
+    orc = O.Oracle(sc.arrays(), sc.sh_degree, cam, falloff=falloff, tile_cull=tile_cull)
+    t = {}
+    t0 = time.perf_counter()
+    rec = orc.preprocess(O.MODE_F32)
+    t["preprocess"] = time.perf_counter() - t0
+    T = orc.TX * orc.TY
+    t0 = time.perf_counter()
+    vals, ranges, pos = [], np.zeros((T, 2), np.int64), 0
+    for tt in tiles:
+        lst = orc.tile_list(rec, int(tt))
+        ranges[tt] = (pos, pos + len(lst))
         pos += len(lst)
         vals.append(lst)
     values = np.concatenate(vals) if vals else np.zeros(0, np.uint32)
-    t_lists = time.perf_counter() - t0
-    dL = np.random.default_rng(1).standard_normal((cam.height, cam.width, 3))
+    t["lists"] = time.perf_counter() - t0
+    tl = np.asarray(tiles, np.int32)
     t0 = time.perf_counter()
-    orc.render(rec, values, ranges, tiles=tiles)
-    orc.backward2d(rec, dL, values, ranges, tiles=tiles)
-    t_tiles = time.perf_counter() - t0
-    sub = min(n, 200_000)
-    sub_arr = {k: v[:sub] for k, v in arr.items()}
-    g2d = np.random.default_rng(2).standard_normal((sub, 10))
-    torch.set_num_threads(O.num_threads())
-    t0 = time.perf_counter()
-    PF.chain_to_params(sub_arr, sc.sh_degree, cam, g2d, rec.tiles_touched[:sub] > 0, rec.clamp_bits[:sub],
-                       falloff, 0.1)
-    t_chain = (time.perf_counter() - t0) * (n / sub)
-    frac = len(tiles) / T
-    t_full = t_pre + (t_lists + t_tiles) / frac + t_chain
-    px = cam.width * cam.height
-    return {"value": round(px / t_full / 1e6, 5), "unit": "Mpix/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": (f"full per-splat preprocess of {n} splats ({t_pre:.1f}s); per-pixel forward+backward and "
-                       f"list building on {len(tiles)} random tiles of {T} ({t_lists + t_tiles:.1f}s, scaled by "
-                       f"{T}/{len(tiles)}); binary64 chain rule on {sub} splats ({t_chain * sub / n:.1f}s, scaled by "
-                       f"{n}/{sub}); estimated full frame {t_full:.1f}s")}
+    orc.render(rec, values, ranges, tiles=tl)
+    if backward:
+        dL = np.random.default_rng(1).standard_normal((cam.height, cam.width, 3))
+        orc.backward2d(rec, dL, values, ranges, tiles=tl)
+    t["tiles"] = time.perf_counter() - t0
+    return t
+
+
+def cpu_baseline(cfgs, falloff, tile_cull, log_fn):
+    """The oracle as it stands, on this host's cores, on each workload (a baseline, not the target):
+    workload 0 whole frame at 1 thread and at all threads, workload 1 whole forward, workload 2 whole
+    forward+backward (the headline figure), workload 3 on 80 sampled tiles, workload 4 on 64 whole
+    requests."""
+    import platform
+
+    import torch
+    from oracle import oracle as O
+    from paper_2402_10128_amd import synth
+    cores = O.num_threads()
+    cpu_model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    legs = {}
+
+    def px(cfg):
+        return cfg["camera"].width * cfg["camera"].height
+
+    for th in sorted({1, cores}):
+        O.set_num_threads(th)
+        torch.set_num_threads(th)
+        t = _oracle_frame(cfgs[0], falloff, tile_cull)
+        legs[f"workload0_fwd_bwd_{th}_threads"] = {"mpix_s": round(px(cfgs[0]) / sum(t.values()) / 1e6, 5),
+                                                    "s": round(sum(t.values()), 3), "threads": th}
+    O.set_num_threads(cores)
+    torch.set_num_threads(cores)
+    log_fn(f"cpu: workload 0 {legs}")
+    t = _oracle_frame(cfgs[1], falloff, tile_cull, backward=False)
+    legs["workload1_forward"] = {"mpix_s": round(px(cfgs[1]) / sum(t.values()) / 1e6, 5), "s": round(sum(t.values()), 2),
+                                 "parts_s": {k: round(v, 2) for k, v in t.items()}}
+    log_fn(f"cpu: workload 1 forward {legs['workload1_forward']}")
+    t = _oracle_frame(cfgs[2], falloff, tile_cull, backward=True)
+    head_s = sum(t.values())
+    legs["workload2_fwd_bwd"] = {"mpix_s": round(px(cfgs[2]) / head_s / 1e6, 5), "s": round(head_s, 2),
+                                 "parts_s": {k: round(v, 2) for k, v in t.items()}}
+    log_fn(f"cpu: workload 2 forward+backward {legs['workload2_fwd_bwd']}")
+    cam3 = cfgs[3]["camera"]
+    TX, TY = (cam3.width + 15) // 16, (cam3.height + 15) // 16
+    rng = np.random.default_rng(3)
+    block = [ty * TX + tx for ty in range(TY // 2 - 2, TY // 2 + 2) for tx in range(TX // 2 - 2, TX // 2 + 2)]
+    tiles = np.unique(np.concatenate([rng.choice(TX * TY, 64, replace=False), block]))
+    t = _oracle_tiles(cfgs[3], falloff, tile_cull, tiles)
+    legs["workload3_sampled_tiles"] = {"mpix_s": round(256 * len(tiles) / (t["lists"] + t["tiles"]) / 1e6, 5),
+                                       "tiles": int(len(tiles)), "parts_s": {k: round(v, 2) for k, v in t.items()},
+                                       "note": "forward+backward of 64 random tiles and a central 4x4 block; "
+                                               "the rate excludes the whole-scene preprocess"}
+    log_fn(f"cpu: workload 3 sampled {legs['workload3_sampled_tiles']}")
+    scenes = [synth.scene_clusters(n, 1004 + 10 * i) for i, n in enumerate(synth.SERVING_SIZES)]
+    reqs = synth.serving_requests(64, len(scenes), list(synth.SERVING_RESOLUTIONS), seed=2000)
+    per_req, tot_px = [], 0
+    for k, cam in reqs:
+        t = _oracle_frame(dict(scene=scenes[k], camera=cam), falloff, tile_cull, backward=False)
+        per_req.append(sum(t.values()))
+        tot_px += cam.width * cam.height
+    legs["workload4_requests"] = {"mpix_s": round(tot_px / sum(per_req) / 1e6, 5),
+                                  "mean_ms_per_request": round(1e3 * float(np.mean(per_req)), 1),
+                                  "p99_ms_per_request": round(1e3 * float(np.percentile(per_req, 99)), 1),
+                                  "requests": len(reqs),
+                                  "note": "64 whole requests of the serving recipe (scenes drawn on the host), "
+                                          "rendered one after another"}
+    log_fn(f"cpu: workload 4 requests {legs['workload4_requests']}")
+    return {"value": legs["workload2_fwd_bwd"]["mpix_s"], "unit": "Mpix/s", "cores": cores, "kind": "oracle",
+            "sample": "one whole 3M-splat 1920x1080 forward+backward frame on the oracle (preprocess, keys, "
+                      f"per-pixel render and reverse pass, binary64 chain rule): {head_s:.1f} s",
+            "cpu_model": cpu_model, "legs": legs}
 
 
 def serving_bench(dev, n_req, log_fn):
@@ -278,7 +420,7 @@ def train_step_bench(dev, cfg, falloff, tile_cull, nsteps, warmup):
     for stage in ("adam", "ssim", "preprocess_backward"):
         if stage in per_stage:
             key = "preprocess_backward_adam" if stage == "preprocess_backward" else stage
-            nbytes = algorithmic_bytes(key, sc.n, sh_k, 0, 0, 1, W * H, True)
+            nbytes = algorithmic_bytes(key, sc.n, sh_k, 0, 0, 0, W * H)
             gbs = nbytes / (per_stage[stage] / 1e3) / 1e9
             out[key] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": nbytes}
@@ -397,24 +539,13 @@ def variants_bench(dev, cfg, tile_cull, steps, log_fn):
     return res
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
-        sys.exit(2)
+def fwd_bwd(dev, cfg, falloff, tile_cull, steps, warmup, log_fn):
+    """Forward + loss + backward steps of one workload: the timed steps (no host synchronisation: the kernels
+    take the key count from the device against the frame's capacity, checked afterwards), per-stage device
+    times from a separate profiled pass, the dominant kernel's launch time over the timed steps, the pair
+    counts and the same step with the key-count read-back."""
     import torch
     from paper_2402_10128_amd import ges as G
-    from paper_2402_10128_amd import synth
-    if not torch.cuda.is_available():
-        print(json.dumps({"error": "no GPU visible"}))
-        sys.exit(2)
-    G.lib()
-    dev = torch.device("cuda:0")
-    falloff = 0 if args.falloff == "phi" else 1
-    tile_cull = 0 if args.tile_cull == "square" else 1
-    log(f"generating workload {args.workload}")
-    cfg = synth.make_config(args.workload)
     sc, cam = cfg["scene"], cfg["camera"]
     t = {k: torch.as_tensor(v).to(dev) for k, v in sc.arrays().items()}
     target = torch.as_tensor(cfg["target"]).to(dev)
@@ -433,10 +564,9 @@ def main():
     grads = {k: torch.empty_like(v) for k, v in t.items()}
 
     def step(readback):
-        """One training step.  readback=True reads the key count back after the preprocess (a host sync
-        in mid-step) and renders with exactly that capacity; readback=False renders with the frame's key
-        capacity and lets the kernels take the count from the device (an overflow would be flagged in
-        the frame's error word, checked below)."""
+        """One step.  readback=True reads the slot count back after the preprocess (a host sync in mid-step)
+        and renders with exactly that capacity; readback=False renders with the frame's capacity and lets the
+        kernels take the count from the device (an overflow would be flagged in the error word)."""
         if readback:
             k = G.ges_preprocess(s, c, p, frame.splat_ws, True)
             frame.ensure_keys(k)
@@ -458,60 +588,78 @@ def main():
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / nsteps
 
-    log("warmup")
-    for _ in range(args.warmup):
+    for _ in range(max(1, warmup)):
         step(True)
     torch.cuda.synchronize()
-    K = G.frame_arrays(frame, s.n)["stats"][0]
-    # 1. per-stage device times: every launch bracketed by events (a few steps, not the timed ones)
+    C = int(frame.num_keys)
     G.ges_profile_enable(True)
     G.ges_profile_read(reset=True)
-    timed(min(args.steps, 5), False)
+    timed(min(steps, 5), False)
     stages = G.ges_profile_read(reset=True)
     per_stage = {name: round(ms / nl, 4) for name, (ms, nl) in stages.items() if nl}
     dominant = max(per_stage, key=per_stage.get)
-    # 2. the timed steps: only the dominant kernel is bracketed by events (for its roofline)
     G.ges_profile_select([dominant])
-    log(f"timing {args.steps} steps")
     t_host0 = time.perf_counter()
-    ms_step = timed(args.steps, False)
+    ms_step = timed(steps, False)
     t_host = time.perf_counter() - t_host0
     dom = G.ges_profile_read(reset=True)[dominant]
     G.ges_profile_enable(False)
-    avg_ms = dom[0] / dom[1]
-    st = G.frame_arrays(frame, s.n)["stats"]
-    if int(st[1]) != 0 or int(st[0]) != int(K):
-        raise RuntimeError(f"key capacity overflow or key count change during timing: {st[:2]}, expected {K}")
-    # 3. for reference: the same step with the key-count read-back inside it
-    ms_step_readback = timed(min(args.steps, 5), True)
-    K = int(K)
-    mpix = W * H / (ms_step / 1e3) / 1e6
     fa = G.frame_arrays(frame, s.n)
-    pairs_exam, pairs_blend = int(fa["stats"][2]), int(fa["stats"][3])
-    bwd_walk = int(fa["n_contrib"].astype(np.int64).sum())
-    log(f"{ms_step:.3f} ms/step  {mpix:.1f} Mpix/s  K={K}  host {t_host / args.steps * 1e3:.2f} ms/step  "
-        f"(with key read-back {ms_step_readback:.3f} ms/step)")
+    st = fa["stats"]
+    if int(st[1]) != 0:
+        raise RuntimeError(f"key capacity overflow during timing: error word {int(st[1])}")
+    ms_step_readback = timed(min(steps, 5), True)
+    vis = int((fa["records"][:, 15].view(np.uint32) > 0).sum())
+    m = dict(ms_step=ms_step, ms_step_readback=ms_step_readback, host_ms=t_host / steps * 1e3, per_stage=per_stage,
+             dominant=dominant, dominant_ms=dom[0] / dom[1], n=s.n, sh_k=(sc.sh_degree + 1) ** 2, K=int(st[0]),
+             C=C, L=vis, px=W * H, pairs_exam=int(st[2]), pairs_blend=int(st[3]),
+             bwd_walk=int(fa["n_contrib"].astype(np.int64).sum()),
+             max_list=int((fa["ranges"][:, 1].astype(np.int64) - fa["ranges"][:, 0]).max(initial=0)))
+    log_fn(f"{W}x{H} n={s.n}: {ms_step:.3f} ms/step, {W * H / ms_step / 1e3:.1f} Mpix/s, K={m['K']} slots={C}, "
+           f"stages {json.dumps(per_stage)}")
+    del frame, t, grads, out, dL
+    torch.cuda.empty_cache()
+    return m
 
-    log("stage ms/launch (profiled pass): " + json.dumps(per_stage) + f"; {dominant} in the timed steps {avg_ms:.4f}")
-    n, sh_k = s.n, (sc.sh_degree + 1) ** 2
-    fp = frame
-    T = ((W + 15) // 16) * ((H + 15) // 16)
-    bin_blocks = max(1, min(256, (n + 8191) // 8192))
-    if dominant in ("raster_forward", "raster_backward"):
-        if dominant == "raster_forward":
-            flop = FWD_FLOP_EXAMINED * pairs_exam + FWD_FLOP_BLENDED[falloff] * pairs_blend
-        else:
-            flop = BWD_FLOP_EXAMINED * bwd_walk + BWD_FLOP_BLENDED[falloff] * pairs_blend
-        achieved = flop / (avg_ms / 1e3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "kernel": dominant,
-                "algorithmic_flop_per_launch": flop}
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import torch
+    from paper_2402_10128_amd import ges as G
+    from paper_2402_10128_amd import synth
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    G.lib()
+    dev = torch.device("cuda:0")
+    falloff = 0 if args.falloff == "phi" else 1
+    tile_cull = 0 if args.tile_cull == "square" else 1
+    log(f"generating workload {args.workload}")
+    cfg = synth.make_config(args.workload)
+    sc, cam = cfg["scene"], cfg["camera"]
+    W, H = cam.width, cam.height
+    log(f"timing {args.steps} steps")
+    m = fwd_bwd(dev, cfg, falloff, tile_cull, args.steps, args.warmup, log)
+    ms_step, per_stage, dominant, avg_ms = m["ms_step"], m["per_stage"], m["dominant"], m["dominant_ms"]
+    mpix = W * H / (ms_step / 1e3) / 1e6
+    rooflines = stage_rooflines(per_stage, m, falloff, args.workload)
+    dom = dict(rooflines[dominant])
+    if dominant in RASTER_STAGES:
+        roof = {"bound": "alu", "achieved": dom["achieved"], "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s",
+                "frac": round(dom["achieved"] / VALU_PEAK_TOPS, 5), "kernel": dominant,
+                "algorithmic_lane_ops_per_launch": dom["algorithmic_lane_ops"],
+                "flop": {"achieved": dom["flop_tflops"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": dom["flop_frac_of_157.3"]}}
+        if "issued_over_algorithmic" in dom:
+            roof["issued_over_algorithmic"] = dom["issued_over_algorithmic"]
     else:
-        nbytes = algorithmic_bytes(dominant, n, sh_k, K, T, bin_blocks, W * H, tile_cull == 1)
-        achieved = nbytes / (avg_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": dominant, "algorithmic_bytes_per_launch": nbytes}
-    roof["traffic"] = read_traffic(dominant, args.workload)
+        roof = {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom["frac"], "kernel": dominant, "algorithmic_bytes_per_launch": dom["algorithmic_bytes"]}
+    roof["traffic"] = read_counter(dominant, args.workload, "hbm_bytes_per_launch")
     roof["avg_launch_ms"] = avg_ms
 
     if args.copy_calibration:
@@ -522,8 +670,21 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    del frame, t, grads, out, dL
-    torch.cuda.empty_cache()
+    others, cfgs = {}, {args.workload: cfg}
+    if not args.no_other_workloads:
+        for wl in (1, 3):
+            if wl == args.workload:
+                continue
+            log(f"workload {wl} forward+backward")
+            cfgs[wl] = synth.make_config(wl)
+            mw = fwd_bwd(dev, cfgs[wl], falloff, tile_cull, min(args.steps, 10), min(args.warmup, 2), log)
+            cw = cfgs[wl]["camera"]
+            others[str(wl)] = {"workload": {1: "1M splats 1600x1040", 3: "5M splats 1920x1080 heavy overlap"}[wl],
+                               "ms_per_step": round(mw["ms_step"], 4),
+                               "mpix_s": round(cw.width * cw.height / (mw["ms_step"] / 1e3) / 1e6, 3),
+                               "num_keys": mw["K"], "candidate_slots": mw["C"], "max_list": mw["max_list"],
+                               "stage_ms_per_launch": mw["per_stage"],
+                               "stage_roofline": stage_rooflines(mw["per_stage"], mw, falloff, wl)}
     train = None
     if not args.no_train_step:
         log("optimisation step (mask + render + L1/SSIM/frequency loss + adjoint + Adam)")
@@ -546,7 +707,10 @@ def main():
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
         try:
-            cpu = cpu_baseline(cfg, falloff, tile_cull)
+            for wl in (0, 1, 2, 3):
+                if wl not in cfgs:
+                    cfgs[wl] = synth.make_config(wl)
+            cpu = cpu_baseline(cfgs, falloff, tile_cull, log)
         except Exception as e:  # reported, never silently replaced
             cpu = {"error": repr(e)}
 
@@ -560,18 +724,21 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
-        "ms_per_step_with_key_readback": round(ms_step_readback, 4),
+        "ms_per_step_with_key_readback": round(m["ms_step_readback"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": names[args.workload], "splats": n, "width": W, "height": H,
+        "config": {"workload": names[args.workload], "splats": m["n"], "width": W, "height": H,
                    "sh_degree": sc.sh_degree, "falloff": args.falloff, "tile_cull": args.tile_cull,
-                   "loss": cfg.get("loss"), "num_keys": K, "pairs_examined_fwd": pairs_exam,
-                   "pairs_composited": pairs_blend, "stage_ms_per_launch": per_stage},
+                   "loss": cfg.get("loss"), "num_keys": m["K"], "candidate_slots": m["C"],
+                   "pairs_examined_fwd": m["pairs_exam"], "pairs_composited": m["pairs_blend"],
+                   "pairs_walked_bwd": m["bwd_walk"], "stage_ms_per_launch": per_stage,
+                   "stage_roofline": rooflines},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "other_workloads": others,
         "train_step": train,
         "variants": variants,
         "mixture_sweep": mixture,

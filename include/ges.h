@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define GES_ABI_VERSION 2u
+#define GES_ABI_VERSION 3u
 #define GES_TILE 16
 #define GES_GRAD2D_STRIDE 12   /* binary64 slots per splat in the 2-D gradient rows */
 
@@ -107,8 +107,9 @@ uint32_t ges_abi_version(void);
 const char* ges_last_error(void);
 
 /* Sizes of the per-frame workspaces for n splats at width x height.
- * splat_ws holds the per-splat projected records, the tile-binning tables, the
- * tile ranges and the per-splat 2-D gradient accumulators; pixel_ws holds the
+ * splat_ws holds the per-splat projected records, the depth order of the splats and
+ * the candidate offsets along it, the tile ranges and the per-splat 2-D gradient
+ * accumulators; pixel_ws holds the
  * per-pixel final transmittance and contributor count that the backward pass
  * re-uses (so no per-pixel lists are stored).  Either output pointer may be NULL.
  * Both workspaces are caller-owned device memory and must be 256-byte aligned (device allocations
@@ -116,36 +117,39 @@ const char* ges_last_error(void);
 ges_status ges_workspace_query(int64_t n, int32_t width, int32_t height, size_t* splat_ws_bytes,
                                size_t* pixel_ws_bytes);
 
-/* Size of the key workspace for num_keys (tile, splat) pairs of a width x height frame with n splats:
- * sorted splat ids (4 B per pair), bucketed pairs (8 B), a second pair buffer for lists beyond the
- * LDS sort (8 B) and the list of long-list tiles (4 B per tile).  Width/height outside [1,16384]:
- * GES_ERR_INVALID_ARGUMENT; num_keys >= 2^32-1: GES_ERR_CAPACITY. */
+/* Size of the key workspace for num_keys candidate (tile, splat) slots of a width x height
+ * frame with n splats: two buffers of (tile, splat index) pairs (16 B per slot, the sorted
+ * splat ids first) and the digit table of the tile sort (1 B per 4 slots).  Width/height
+ * outside [1,16384]: GES_ERR_INVALID_ARGUMENT; num_keys >= 2^32-1: GES_ERR_CAPACITY. */
 ges_status ges_key_workspace_query(uint64_t num_keys, int64_t n, int32_t width, int32_t height,
                                    size_t* key_ws_bytes);
 
 /* Preprocess (Sec. 4.1-4.2): per splat, view transform, 3-D covariance from scale and
  * rotation with the shape modification, EWA projection J W Sigma W^T J^T, conic,
  * mean2D, alpha-floor threshold, beta-dependent screen radius, tile rectangle and
- * SH colour; then counts the (tile, splat) pairs per tile and fixes every tile's
- * [start,end) range in the sorted key order.
+ * SH colour; then sorts the listed splats by depth (ties by index) and lays out one
+ * slot per candidate tile of each splat along that order.
  * num_keys_host: if not NULL, the call waits for the stream and stores the number
- * of keys of this frame there (the only host synchronisation of a frame).
+ * of candidate slots of this frame there -- the key capacity the frame needs, an upper
+ * bound of its (tile, splat) keys (equal to it for GES_TILES_SQUARE) -- the only host
+ * synchronisation of a frame.
  * Errors: INVALID_ARGUMENT (see conventions), CAPACITY if splat_ws_bytes is too small. */
 ges_status ges_preprocess(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
                           void* splat_ws, size_t splat_ws_bytes, uint64_t* num_keys_host, void* stream);
 
-/* Forward render (Sec. 4.2, Eq. transimttance discretised): scatters the pairs into
- * their tiles, sorts every tile's list by (depth, splat index) in LDS, and
- * composites front to back per pixel with alpha = min(0.99, opacity * falloff),
- * skipping pairs below the 1/255 alpha floor and stopping a pixel before the splat
- * that would take its transmittance below 1e-4.
- * out_rgb: [height,width,3] FP32, overwritten.  num_keys is the key capacity of key_ws
- * (key_ws_bytes >= ges_key_workspace_query(num_keys, ...)) and must be at least the key
+/* Forward render (Sec. 4.2, Eq. transimttance discretised): fills the candidate slots
+ * with the (tile, splat) pairs whose tile the splat meets, sorts them stably by tile
+ * (every tile's list is then in (depth, splat index) order), fixes every tile's
+ * [start,end) range, and composites front to back per pixel with
+ * alpha = min(0.99, opacity * falloff), skipping pairs below the 1/255 alpha floor and
+ * stopping a pixel before the splat that would take its transmittance below 1e-4.
+ * out_rgb: [height,width,3] FP32, overwritten.  num_keys is the slot capacity of key_ws
+ * (key_ws_bytes >= ges_key_workspace_query(num_keys, ...)) and must be at least the slot
  * count of the frame: either the value ges_preprocess returned, or any larger capacity,
  * in which case no read-back is needed (the kernels take the count from the device).  If
- * the frame's count exceeds num_keys, tiles beyond the capacity render as background and
- * bit 0 of the frame's error word (ges_frame_view stats[1]) is set.  The same num_keys
- * must be passed to ges_frame_view_get.
+ * the frame's count exceeds num_keys, the pairs of the slots beyond the capacity are
+ * dropped and bit 0 of the frame's error word (ges_frame_view stats[1]) is set.  The
+ * same num_keys must be passed to ges_frame_view_get.
  * The splat, pixel and key workspaces must stay untouched until the matching
  * ges_render_backward (if any) has been enqueued. */
 ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
@@ -171,9 +175,9 @@ ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, 
  * Device views into a frame's workspaces, valid after the call that fills them. */
 typedef struct {
   const float* records;          /* [n,16] per-splat record, see below (after ges_preprocess) */
-  const uint32_t* tile_ranges;   /* [tiles,2] [start,end) into the sorted lists (after ges_preprocess) */
-  const uint32_t* sorted_ids;    /* [num_keys] splat index per sorted entry (after ges_render_forward) */
-  const uint32_t* bucket_pairs;  /* [num_keys,2] (depth bits, splat index) in tile order, unsorted within a tile */
+  const uint32_t* tile_ranges;   /* [tiles,2] [start,end) into the sorted lists (after ges_render_forward) */
+  const uint32_t* sorted_ids;    /* [keys] splat index per sorted entry (after ges_render_forward) */
+  const uint32_t* sorted_tiles;  /* [keys] tile per sorted entry (after ges_render_forward) */
   const float* final_T;          /* [height,width] (after ges_render_forward) */
   const uint32_t* n_contrib;     /* [height,width] list position + 1 of the last composited splat */
   const double* grad2d;          /* [n,GES_GRAD2D_STRIDE] dL/d(u,v,a,b,c,opacity,r,g,b,beta) in slots 0..9, binary64
@@ -199,7 +203,7 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
  * and returns the accumulated device milliseconds and launch counts per stage
  * (indices GES_STAGE_*), then optionally clears them.  Off by default; enabling it
  * costs two event records per launch. */
-enum { GES_STAGE_PREPROCESS = 0, GES_STAGE_BIN_COUNT, GES_STAGE_BIN_SCAN, GES_STAGE_BIN_SCATTER, GES_STAGE_TILE_SORT,
+enum { GES_STAGE_PREPROCESS = 0, GES_STAGE_DEPTH_SORT, GES_STAGE_KEY_SCAN, GES_STAGE_DUPLICATE, GES_STAGE_TILE_SORT,
        GES_STAGE_RASTER_FORWARD, GES_STAGE_RASTER_BACKWARD, GES_STAGE_PREPROCESS_BACKWARD, GES_STAGE_ZERO,
        GES_STAGE_LOSS, GES_STAGE_ADAM, GES_STAGE_SSIM, GES_STAGE_MIX_FIT, GES_NUM_STAGES };
 ges_status ges_profile_enable(int32_t on);

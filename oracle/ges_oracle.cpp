@@ -212,8 +212,10 @@ void sh_basis(S x, S y, S z, int degree, S* Y) {
 
 // ------------------------------------------------------------------------------------------------
 // Ellipse-tile test (ELLIPSE tile culling).  A tile is kept when the minimum of the splat's quadratic
-// form over the tile's box of pixel centres, less a rounding allowance of 1e-3 times the magnitude of
-// its terms, does not exceed q_max.  The minimum over a box lies at an interior point only if the
+// form over the tile's box of pixel centres, less a rounding allowance of 1e-5 times the magnitude of
+// its terms, does not exceed q_max.  The allowance covers the binary32 rounding of this minimum and of a
+// pixel's own q (a few units in the last place of the terms, below 1e-6 of their magnitude), so every
+// pixel that passes the alpha floor lies in a kept tile.  The minimum over a box lies at an interior point only if the
 // centre is inside; otherwise on one of the four edges, where it is a 1-D quadratic minimised at the
 // clamped stationary point -b e / c (resp. -b e / a), evaluated with the reciprocals 1/c and 1/a
 // formed once per splat.
@@ -231,7 +233,7 @@ S edge_min(S a, S b, S c, S inv_c, S e, S lo, S hi) {
   S q = A + C;
   S mag = q + std::fabs(B);
   q = q + B;
-  S slack = (S)1e-3 * mag;
+  S slack = (S)1e-5 * mag;
   return q - slack;
 }
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libges.so")
-SOURCES = ["preprocess.hip", "preprocess_bwd.hip", "binning.hip", "tile_sort.hip", "raster.hip", "loss.hip", "optim.hip", "ssim.hip", "prune.hip", "mixture.hip", "densify.hip", "abi.cpp",
+SOURCES = ["preprocess.hip", "preprocess_bwd.hip", "binning.hip", "radix.hip", "raster.hip", "loss.hip", "optim.hip", "ssim.hip", "prune.hip", "mixture.hip", "densify.hip", "abi.cpp",
            "serve.cpp"]
 ARCH = os.environ.get("GES_OFFLOAD_ARCH", "gfx950")
 

@@ -81,13 +81,16 @@ hipError_t upload_single_view(const ges_splats* s, const ges_camera* c, const ge
   hb.nviews = 1;
   hb.pre_prefix[0] = 0;
   hb.pre_prefix[1] = (s->n + 255) / 256;
-  hb.bin_prefix[0] = 0;
-  hb.bin_prefix[1] = fp.bin_blocks;
+  hb.item_prefix[0] = 0;
+  hb.item_prefix[1] = s->n;
   hb.tile_prefix[0] = 0;
   hb.tile_prefix[1] = fp.tiles;
   ges::ViewDesc& V = hb.views[0];
   ges::fill_view(V, s, c, p);
   ges::attach_splat_ws(V, fp, splat_ws);
+  const ges::SortWs sw = ges::attach_sort_ws(ges::plan_sort(s->n), reinterpret_cast<char*>(splat_ws) + fp.off_sort);
+  V.item_key = sw.item_key;
+  V.item_cand = sw.item_cand;
   if (pixel_ws) {
     char* pw = reinterpret_cast<char*>(pixel_ws);
     V.final_T = reinterpret_cast<float*>(pw + fp.off_final_T);
@@ -104,10 +107,13 @@ ges::Batch single_batch(const ges_splats* s, const ges_raster_params* p, const g
   b.nviews = 1;
   b.falloff = p->falloff;
   b.total_tiles = fp.tiles;
+  b.tile_cull = p->tile_cull;
   b.pre_blocks = (s->n + 255) / 256;
-  b.bin_blocks = fp.bin_blocks;
-  b.keys_total = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(splat_ws) + fp.off_hdr + 128);
-  b.sort_queue = b.keys_total + 1;
+  b.items = s->n;
+  b.sw = ges::attach_sort_ws(ges::plan_sort(s->n), reinterpret_cast<char*>(splat_ws) + fp.off_sort);
+  b.keys_total = &b.sw.cells[1];
+  b.tile_passes = ges::tile_passes(fp.tiles);
+  b.dup_buffer = b.tile_passes & 1;
   return b;
 }
 
@@ -161,16 +167,16 @@ ges_status ges_preprocess(const ges_splats* splats, const ges_camera* cam, const
   if (splat_ws_bytes < fp.splat_bytes) return fail(GES_ERR_CAPACITY, "splat workspace too small");
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
   GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, nullptr, nullptr, nullptr, stream), "upload");
-  const ges::Batch b = single_batch(splats, params, fp, splat_ws);
+  ges::Batch b = single_batch(splats, params, fp, splat_ws);
   const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
   GES_CHECK_HIP(timed(GES_STAGE_PREPROCESS, stream, [&] { return ges::launch_preprocess(db, b, stream); }), "preprocess");
-  GES_CHECK_HIP(timed(GES_STAGE_BIN_COUNT, stream, [&] { return ges::launch_bin_count(db, b, stream); }), "bin_count");
-  GES_CHECK_HIP(timed(GES_STAGE_BIN_SCAN, stream, [&] { return ges::launch_bin_scan(db, b, nullptr, stream); }), "bin_scan");
+  GES_CHECK_HIP(timed(GES_STAGE_DEPTH_SORT, stream, [&] { return ges::launch_depth_sort(db, b, stream); }), "depth_sort");
+  GES_CHECK_HIP(timed(GES_STAGE_KEY_SCAN, stream, [&] { return ges::launch_key_scan(db, b, stream); }), "key_scan");
   if (num_keys_host) {
     uint32_t k = 0;
     GES_CHECK_HIP(hipMemcpyAsync(&k, b.keys_total, 4, hipMemcpyDeviceToHost, stream), "read num_keys");
     GES_CHECK_HIP(hipStreamSynchronize(stream), "sync");
-    if (k == 0xffffffffu) return fail(GES_ERR_CAPACITY, "more than 2^32-2 (tile, splat) keys in one frame");
+    if (k == 0xffffffffu) return fail(GES_ERR_CAPACITY, "more than 2^32-2 candidate (tile, splat) pairs in one frame");
     *num_keys_host = k;
   }
   return GES_OK;
@@ -191,16 +197,14 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
   GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, out_rgb, nullptr, stream), "upload");
   ges::Batch b = single_batch(splats, params, fp, splat_ws);
-  char* kw = reinterpret_cast<char*>(key_ws);
   b.key_capacity = num_keys;
   if (num_keys > 0) {
-    b.pairs = reinterpret_cast<uint2*>(kw + kp.off_pairs);
-    b.pairs_tmp = reinterpret_cast<uint2*>(kw + kp.off_tmp);
-    b.sorted_ids = reinterpret_cast<uint32_t*>(kw + kp.off_sorted);
-    b.long_list = reinterpret_cast<uint32_t*>(kw + kp.off_list);
+    b.kw = ges::attach_key_ws(kp, key_ws);
+    b.sorted_ids = b.kw.val[0];
+    b.sorted_tiles = b.kw.key[0];
   }
   const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
-  GES_CHECK_HIP(timed(GES_STAGE_BIN_SCATTER, stream, [&] { return ges::launch_bin_scatter(db, b, stream); }), "bin_scatter");
+  GES_CHECK_HIP(timed(GES_STAGE_DUPLICATE, stream, [&] { return ges::launch_duplicate(db, b, stream); }), "duplicate");
   GES_CHECK_HIP(timed(GES_STAGE_TILE_SORT, stream, [&] { return ges::launch_tile_sort(db, b, stream); }), "tile_sort");
   GES_CHECK_HIP(timed(GES_STAGE_RASTER_FORWARD, stream, [&] { return ges::launch_raster_forward(db, b, stream); }), "raster_forward");
   return GES_OK;
@@ -226,7 +230,7 @@ static ges_status render_backward(const ges_splats* splats, const ges_camera* ca
   GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, nullptr, dL_drgb, stream), "upload");
   ges::Batch b = single_batch(splats, params, fp, splat_ws);
   // the sorted ids of the forward pass; ranges bound every access, so the capacity is not needed here
-  if (key_ws) b.sorted_ids = reinterpret_cast<uint32_t*>(key_ws);   // KeyPlan::off_sorted == 0
+  if (key_ws) b.sorted_ids = reinterpret_cast<uint32_t*>(key_ws);   // KeyPlan::off_val0 == 0
   const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
   GES_CHECK_HIP(timed(GES_STAGE_ZERO, stream, [&] {
                   return ges::launch_zero(reinterpret_cast<char*>(splat_ws) + fp.off_grad,
@@ -323,8 +327,8 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
   if (key_ws) {
     const ges::KeyPlan kp = ges::plan_keys(num_keys, fp.tiles);
     char* kw = reinterpret_cast<char*>(key_ws);
-    out->sorted_ids = reinterpret_cast<const uint32_t*>(kw + kp.off_sorted);
-    out->bucket_pairs = reinterpret_cast<const uint32_t*>(kw + kp.off_pairs);
+    out->sorted_ids = reinterpret_cast<const uint32_t*>(kw + kp.off_val0);
+    out->sorted_tiles = reinterpret_cast<const uint32_t*>(kw + kp.off_key0);
   }
   if (pixel_ws) {
     char* pw = reinterpret_cast<char*>(pixel_ws);

@@ -11,14 +11,55 @@ namespace ges {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Depth-first binning buffers of a batch of `items` splats (SortWs).
+struct SortPlan {
+  size_t off_key = 0, off_cand = 0, off_dk0 = 0, off_dv0 = 0, off_dk1 = 0, off_dv1 = 0, off_table = 0,
+         off_totals = 0, off_chunks = 0, off_cells = 0, bytes = 0;
+};
+
+inline SortPlan plan_sort(int64_t items) {
+  SortPlan p;
+  const size_t n = (size_t)items;
+  size_t o = 0;
+  p.off_key = o;    o += align256(n * 4);
+  p.off_cand = o;   o += align256(n * 4);
+  p.off_dk0 = o;    o += align256(n * 4);
+  p.off_dv0 = o;    o += align256(n * 4);
+  p.off_dk1 = o;    o += align256(n * 4);
+  p.off_dv1 = o;    o += align256(n * 4);
+  p.off_table = o;  o += align256((size_t)256 * radix_blocks((uint64_t)n, kRadixItemsSmall) * 4);
+  p.off_totals = o; o += 1024;
+  p.off_chunks = o; o += align256(((n + 255) / 256 + 1) * 4);
+  p.off_cells = o;  o += 256;
+  p.bytes = o;
+  return p;
+}
+
+inline SortWs attach_sort_ws(const SortPlan& p, void* base) {
+  char* b = reinterpret_cast<char*>(base);
+  SortWs w{};
+  w.item_key = reinterpret_cast<uint32_t*>(b + p.off_key);
+  w.item_cand = reinterpret_cast<uint32_t*>(b + p.off_cand);
+  w.dk[0] = reinterpret_cast<uint32_t*>(b + p.off_dk0);
+  w.dv[0] = reinterpret_cast<uint32_t*>(b + p.off_dv0);
+  w.dk[1] = reinterpret_cast<uint32_t*>(b + p.off_dk1);
+  w.dv[1] = reinterpret_cast<uint32_t*>(b + p.off_dv1);
+  w.table = reinterpret_cast<uint32_t*>(b + p.off_table);
+  w.totals = reinterpret_cast<uint32_t*>(b + p.off_totals);
+  w.chunk_off = reinterpret_cast<uint32_t*>(b + p.off_chunks);
+  w.cells = reinterpret_cast<uint32_t*>(b + p.off_cells);
+  w.depth_final = 1;   // four passes: 0 -> 1 -> 0 -> 1 from the item keys (set again by launch_depth_sort)
+  return w;
+}
+
 struct FramePlan {
   int tiles_x = 0, tiles_y = 0;
   int64_t tiles = 0;
-  int bin_blocks = 1, bin_chunk = 0;
-  // splat workspace
-  size_t off_db = 0, off_hdr = 0, off_rec = 0, off_grad = 0, off_vis = 0, off_counts = 0, off_total = 0,
-         off_ranges = 0, off_tstats = 0, off_twork = 0, off_gorder = 0;
-  size_t splat_bytes = 0;
+  // splat workspace; the binning buffers of the frame's own batch come last (a server gives a batch of
+  // views one such region and its views only the part before it)
+  size_t off_db = 0, off_hdr = 0, off_rec = 0, off_grad = 0, off_vis = 0, off_ranges = 0, off_tstats = 0,
+         off_twork = 0, off_gorder = 0, off_sort = 0;
+  size_t view_bytes = 0, splat_bytes = 0;
   // pixel workspace
   size_t off_final_T = 0, off_n_contrib = 0, pixel_bytes = 0;
 };
@@ -28,23 +69,18 @@ inline FramePlan plan_frame(int64_t n, int w, int h) {
   p.tiles_x = (w + kTile - 1) / kTile;
   p.tiles_y = (h + kTile - 1) / kTile;
   p.tiles = (int64_t)p.tiles_x * p.tiles_y;
-  int64_t g = (n + 8191) / 8192;
-  if (g < 1) g = 1;
-  if (g > kMaxBinBlocks) g = kMaxBinBlocks;
-  p.bin_blocks = (int)g;
-  p.bin_chunk = (int)((n + g - 1) / g);
   size_t o = 0;
   p.off_db = o;      o += align256(sizeof(DeviceBatch));
   p.off_hdr = o;     o += 256;
   p.off_rec = o;     o += align256((size_t)n * kRecWords * 4);
   p.off_grad = o;    o += align256((size_t)n * kGradStride * 8);
   p.off_vis = o;     o += align256((size_t)n * 4);
-  p.off_counts = o;  o += align256((size_t)p.bin_blocks * (size_t)p.tiles * 4);
-  p.off_total = o;   o += align256((size_t)p.tiles * 4);
   p.off_ranges = o;  o += align256((size_t)p.tiles * 8);
   p.off_tstats = o;  o += align256((size_t)p.tiles * 16);
   p.off_twork = o;   o += align256((size_t)p.tiles * 4);
   p.off_gorder = o;  o += align256((size_t)(p.tiles + 7) / 8 * 4);
+  p.view_bytes = o;
+  p.off_sort = o;    o += plan_sort(n).bytes;
   p.splat_bytes = o;
   size_t q = 0;
   const size_t px = (size_t)w * h;
@@ -54,21 +90,44 @@ inline FramePlan plan_frame(int64_t n, int w, int h) {
   return p;
 }
 
-// The sorted ids come first so that the backward pass can find them without the key count; the
-// last region lists the tiles whose lists go to the long-list sort (one u32 per tile of the batch).
+// Tile passes of a batch: 8-bit digits covering the largest batch tile id.
+inline int tile_passes(int64_t total_tiles) {
+  int bits = 1;
+  while (bits < 63 && ((int64_t)1 << bits) < total_tiles) ++bits;
+  return (bits + 7) / 8;
+}
+
+// Key workspace: two buffers of `slots` (tile, splat) pairs, the splat ids of buffer 0 first so that the
+// backward pass finds the sorted ids at the start of the workspace without the slot count; then the table
+// of the tile passes.
 struct KeyPlan {
-  size_t off_sorted = 0, off_pairs = 0, off_tmp = 0, off_list = 0, bytes = 0;
+  size_t off_val0 = 0, off_key0 = 0, off_val1 = 0, off_key1 = 0, off_table = 0, off_totals = 0, bytes = 0;
 };
 
-inline KeyPlan plan_keys(uint64_t k, int64_t tiles) {
+inline KeyPlan plan_keys(uint64_t slots, int64_t /*tiles*/) {
   KeyPlan p;
+  const size_t k = (size_t)slots;
   size_t o = 0;
-  p.off_sorted = o; o += align256((size_t)k * 4);
-  p.off_pairs = o;  o += align256((size_t)k * 8);
-  p.off_tmp = o;    o += align256((size_t)k * 8);
-  p.off_list = o;   o += align256((size_t)tiles * 4);
+  p.off_val0 = o;   o += align256(k * 4);
+  p.off_key0 = o;   o += align256(k * 4);
+  p.off_val1 = o;   o += align256(k * 4);
+  p.off_key1 = o;   o += align256(k * 4);
+  p.off_table = o;  o += align256((size_t)256 * radix_blocks(slots, kRadixItemsLarge) * 4);
+  p.off_totals = o; o += 1024;
   p.bytes = o;
   return p;
+}
+
+inline KeyWs attach_key_ws(const KeyPlan& p, void* base) {
+  char* b = reinterpret_cast<char*>(base);
+  KeyWs w{};
+  w.val[0] = reinterpret_cast<uint32_t*>(b + p.off_val0);
+  w.key[0] = reinterpret_cast<uint32_t*>(b + p.off_key0);
+  w.val[1] = reinterpret_cast<uint32_t*>(b + p.off_val1);
+  w.key[1] = reinterpret_cast<uint32_t*>(b + p.off_key1);
+  w.table = reinterpret_cast<uint32_t*>(b + p.off_table);
+  w.totals = reinterpret_cast<uint32_t*>(b + p.off_totals);
+  return w;
 }
 
 // Validation of the public structs; returns an empty string when valid.
@@ -149,20 +208,17 @@ inline void fill_view(ViewDesc& V, const ges_splats* s, const ges_camera* c, con
   for (int k = 0; k < 3; ++k) V.bg[k] = p->bg[k];
 }
 
+// The per-view part of a splat workspace (the item arrays are attached with the batch's SortWs).
 inline void attach_splat_ws(ViewDesc& V, const FramePlan& fp, void* splat_ws) {
   char* b = reinterpret_cast<char*>(splat_ws);
   V.rec = reinterpret_cast<float4*>(b + fp.off_rec);
   V.grad2d = reinterpret_cast<double*>(b + fp.off_grad);
   V.vis = reinterpret_cast<uint32_t*>(b + fp.off_vis);
-  V.bin_counts = reinterpret_cast<uint32_t*>(b + fp.off_counts);
-  V.tile_total = reinterpret_cast<uint32_t*>(b + fp.off_total);
   V.ranges = reinterpret_cast<uint2*>(b + fp.off_ranges);
   V.tile_stats = reinterpret_cast<unsigned long long*>(b + fp.off_tstats);
   V.tile_work = reinterpret_cast<uint32_t*>(b + fp.off_twork);
   V.group_order = reinterpret_cast<uint32_t*>(b + fp.off_gorder);
   V.header = reinterpret_cast<unsigned long long*>(b + fp.off_hdr);
-  V.bin_blocks = fp.bin_blocks;
-  V.bin_chunk = fp.bin_chunk;
 }
 
 }  // namespace ges

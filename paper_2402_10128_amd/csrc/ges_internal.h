@@ -17,11 +17,10 @@ constexpr int kTilePx = kTile * kTile;   // 256 pixels, 4 per lane of one wave64
 constexpr int kRecWords = 16;            // 64-byte per-splat record
 constexpr int kGradStride = GES_GRAD2D_STRIDE;   // doubles per splat in the 2-D gradient accumulator
 constexpr int kMaxViews = 64;
-constexpr int kBinBlockThreads = 1024;
-constexpr int kMaxBinBlocks = 256;       // splat chunks per view for the tile histogram
-constexpr int kBinLdsTiles = 12288;      // tiles per LDS window of the histogram (48 KB)
-constexpr int kSortCap = 4096;           // per-tile lists up to this length: one 256-thread block per tile
-constexpr int kLongSortBlocks = 256;     // persistent blocks of the long-list sort (one per CU)
+constexpr int kRadixThreads = 256;       // radix passes: blocks of 256 threads ...
+constexpr int kRadixItemsLarge = 16;     // ... holding 16 items each (the pair sort) ...
+constexpr int kRadixItemsSmall = 4;      // ... or 4 (the depth sort of the splats: more blocks to hide latency)
+constexpr uint32_t kNoKey = 0xffffffffu; // radix key of an item that a filtering pass drops
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 
@@ -56,8 +55,8 @@ struct ViewDesc {
   float bg[3];
   // workspaces (device)
   float4* rec;                   // [n] x 4 float4
-  uint32_t* bin_counts;          // [bin_blocks][tiles] per-chunk tile counts, then exclusive column prefix
-  uint32_t* tile_total;          // [tiles] entries per tile
+  uint32_t* item_key;            // [n] depth bits of a listed splat, kNoKey otherwise (this view's part of the
+  uint32_t* item_cand;           // [n]   batch's depth-sort items), and its number of candidate tiles
   uint2* ranges;                 // [tiles] [start,end) into the key arrays (global positions)
   unsigned long long* header;    // [0] keys of this view, [1] error flags, [2] [3] pair statistics
   unsigned long long* tile_stats;  // [tiles][2] pairs examined and composited per tile (forward pass)
@@ -69,25 +68,48 @@ struct ViewDesc {
   uint32_t* n_contrib;           // [h*w]
   float* out_rgb;                // [h*w*3]
   const float* dL_drgb;          // [h*w*3] (backward only)
-  int32_t bin_blocks;            // number of splat chunks (histogram rows)
-  int32_t bin_chunk;             // splats per chunk
-  int64_t tile_base;             // first tile of this view in the batch's global tile numbering
-  int64_t pre_block_base;        // first block of this view in the preprocess grid
-  int64_t bin_block_base;        // first block of this view in the binning grids
+};
+
+// Depth-first binning of a batch.  Items are the splats of every view, view after view (item j of view v
+// is splat j - item_prefix[v]).  The preprocess writes each item's depth key and candidate-tile count;
+// the listed items are sorted by depth (stable: equal depths keep index order), their candidate tiles are
+// laid out in that order, each candidate becomes a (tile, splat) pair or a dropped slot, and a stable sort
+// by tile gives every tile's list in depth order.
+struct SortWs {
+  uint32_t* item_key;            // [items]
+  uint32_t* item_cand;           // [items]
+  uint32_t* dk[2];               // [items] depth-sort keys, ping-pong
+  uint32_t* dv[2];               // [items] depth-sort values (item index), ping-pong
+  uint32_t* table;               // [256][items_blocks] per-block digit counts of a pass, then their prefix
+  uint32_t* totals;              // [256] per-digit totals of a pass
+  uint32_t* chunk_off;           // [items / 256 + 1] candidate slots before each 256-item chunk of the depth order
+  uint32_t* cells;               // [0] listed items, [1] candidate slots (saturating), [2] keys, [3] spare
+  int depth_final;               // dv[depth_final] holds the depth order after the last pass
+};
+
+// Key workspace of a batch: [capacity] slots of (tile, splat) pairs, two buffers; the final order lands in
+// buffer 0 (val[0] first in the workspace: the backward finds the sorted splat ids there).
+struct KeyWs {
+  uint32_t* val[2];
+  uint32_t* key[2];
+  uint32_t* table;               // [256][key_blocks]
+  uint32_t* totals;              // [256]
 };
 
 struct Batch {
   int32_t nviews;
   int32_t falloff;               // shared by every view of a batch
+  int32_t tile_cull;             // shared by every view of a batch
+  int32_t tile_passes;           // 8-bit digit passes of the tile sort (tile ids of the batch)
   int64_t total_tiles;
   int64_t pre_blocks;
-  int64_t bin_blocks;
-  uint32_t* keys_total;          // device: total keys of the batch (u32 saturating counter)
-  uint32_t* sort_queue;          // device: [0] long lists found, [1] long lists claimed (keys_total + 1)
-  uint32_t* long_list;           // [total tiles] tiles whose lists exceed kSortCap (key workspace)
-  uint2* pairs;                  // [key capacity] (depth bits, splat index) bucketed by tile
-  uint2* pairs_tmp;              // [key capacity] second buffer for large-list sorts
-  uint32_t* sorted_ids;          // [key capacity]
+  int64_t items;                 // splats of all views
+  SortWs sw;
+  KeyWs kw;
+  uint32_t* keys_total;          // device: candidate slots of the batch (sw.cells + 1)
+  uint32_t* sorted_ids;          // [key capacity] splat index per sorted pair (kw.val[0])
+  uint32_t* sorted_tiles;        // [key capacity] batch tile per sorted pair (kw.key[0])
+  int dup_buffer;                // buffer the duplication writes (so that the last tile pass ends in 0)
   uint64_t key_capacity;
 };
 
@@ -95,7 +117,7 @@ struct Batch {
 // The prefix tables come first so that only the views in use need to be copied.
 struct DeviceBatch {
   int64_t pre_prefix[kMaxViews + 1];
-  int64_t bin_prefix[kMaxViews + 1];
+  int64_t item_prefix[kMaxViews + 1];
   int64_t tile_prefix[kMaxViews + 1];
   int32_t nviews;
   int32_t pad_;
@@ -137,10 +159,35 @@ struct AdamSplats {
 // --------------------------------------------------------------------------------------------
 // launchers (implemented in the .hip files); all enqueue on `stream` and return hipError_t
 hipError_t launch_preprocess(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
-hipError_t launch_bin_count(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
-hipError_t launch_bin_scan(const DeviceBatch* dbatch, const Batch& b, const int32_t* tiles_per_view, hipStream_t stream);
-hipError_t launch_bin_scatter(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+// depth-first binning (binning.hip): depth order of the listed splats, candidate slots along it (with the
+// batch's slot count in keys_total), then in the render: (tile, splat) pairs, the stable sort by tile and
+// the tile ranges
+hipError_t launch_depth_sort(const DeviceBatch* dbatch, Batch& b, hipStream_t stream);
+hipError_t launch_key_scan(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+hipError_t launch_duplicate(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+// one stable LSD radix pass over (u32 key, u32 value) items with 8-bit digits (radix.hip)
+struct RadixPass {
+  int32_t items;                 // per thread: kRadixItemsLarge or kRadixItemsSmall
+  int32_t bits;                  // digit width (1..8)
+  const uint32_t* keys_in;
+  const uint32_t* vals_in;       // NULL: an item's value is its index
+  uint32_t* keys_out;
+  uint32_t* vals_out;
+  const uint32_t* count_dev;     // number of items (device), or NULL: count_host
+  uint32_t count_host;
+  uint32_t nblocks;              // table width: blocks of 256 x items items covering the largest count
+  int32_t shift;                 // digit = (key >> shift) & ((1 << bits) - 1)
+  int32_t filter;                // drop items whose key is kNoKey; the kept count goes to count_out
+  uint32_t* table;               // [256][nblocks]
+  uint32_t* totals;              // [256]
+  uint32_t* count_out;
+};
+hipError_t launch_radix_pass(const RadixPass& p, hipStream_t stream);
+inline uint32_t radix_blocks(uint64_t n, int items) {
+  const uint64_t tile = (uint64_t)kRadixThreads * items;
+  return (uint32_t)((n + tile - 1) / tile);
+}
 hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_raster_backward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 // args (may be NULL): the fused update's arguments when `fused`; otherwise only accumulate and the

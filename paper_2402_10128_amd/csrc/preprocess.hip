@@ -24,6 +24,8 @@ __device__ __forceinline__ float min_c(float a, float b) { return geom_min(a, b)
 __device__ __forceinline__ void write_culled(const ViewDesc& V, int64_t i) {
   float4* rec = V.rec;
   V.vis[i] = 0u;
+  V.item_key[i] = kNoKey;
+  V.item_cand[i] = 0u;
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   rec[4 * i + 0] = z;
   rec[4 * i + 1] = z;
@@ -217,8 +219,8 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
   if (!(xl <= xh) || !(yl <= yh)) { write_culled(V, i); return; }
   const int tx0 = (int)xl / kTile, tx1 = (int)xh / kTile;
   const int ty0 = (int)yl / kTile, ty1 = (int)yh / kTile;
-  // SQUARE: every tile of the rectangle.  ELLIPSE: the rectangle's area here; the tile histogram
-  // pass replaces it by the exact number of tiles the ellipse meets (possibly 0).
+  // SQUARE: every tile of the rectangle.  ELLIPSE: the rectangle's area here; the duplication
+  // replaces it by the exact number of tiles the ellipse meets (possibly 0).
   const uint32_t touched = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
 
   float shv[3 * K];
@@ -257,9 +259,15 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
     rgb[ch] = acc;
   }
 
-  // visibility and clamp flags for the backward pass (ELLIPSE: the histogram pass clears the bit of a
-  // splat whose ellipse meets no tile)
+  // visibility and clamp flags for the backward pass (ELLIPSE: the duplication clears the bit of a
+  // splat whose ellipse meets no tile); the splat's depth-sort key and its number of candidate tiles
   V.vis[i] = (touched ? kVisBit : 0u) | bits;
+  {
+    SplatTiles st;
+    candidate_tiles(u, vv, ca, cb, cc, qm, tx0, ty0, tx1, ty1, V.tile_cull == GES_TILES_ELLIPSE, st);
+    V.item_key[i] = __float_as_uint(z);
+    V.item_cand[i] = candidate_count(st, V.height);
+  }
   rec[4 * i + 0] = make_float4(u, vv, ca, cb);
   rec[4 * i + 1] = make_float4(cc, qm, op, beta);
   rec[4 * i + 2] = make_float4(rgb[0], rgb[1], rgb[2], z);

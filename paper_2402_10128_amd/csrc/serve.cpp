@@ -106,7 +106,8 @@ struct Request {
 struct BatchWork {
   std::vector<uint64_t> ids;
   std::vector<FramePlan> plans;
-  size_t table_off = 0, table_bytes = 0;     // device view table
+  size_t table_off = 0, table_bytes = 0;     // device view table, then the batch's binning buffers
+  int64_t items = 0;                         // splats of the batch's views
   size_t key_off = 0, key_bytes = 0;
   bool has_keys = false;
   uint64_t keys = 0;
@@ -178,8 +179,15 @@ ServeInspectLayout serve_inspect_layout(int64_t n, int32_t w, int32_t h, uint64_
 
 size_t request_bytes(const ges_splats& sc, const ges_camera& c) {
   FramePlan fp = plan_frame(sc.n, c.width, c.height);
-  // the view table lives in the batch; the per-view device batch slot is not needed
-  return fp.splat_bytes - align256(sizeof(DeviceBatch));
+  // the view table and the binning buffers live in the batch; the per-view device batch slot is not needed
+  return fp.view_bytes - align256(sizeof(DeviceBatch));
+}
+
+size_t table_bytes() { return align256(device_batch_bytes(kMaxViews)); }
+
+// The batch's binning buffers follow its view table.
+SortWs batch_sort_ws(char* pool, const BatchWork& b) {
+  return attach_sort_ws(plan_sort(b.items), pool + b.table_off + table_bytes());
 }
 
 // Per-view splat workspace: the plan's layout minus the leading view-table slot.
@@ -206,13 +214,13 @@ class GpuExecutor : public Executor {
     Batch bt = make_batch(b, pool);
     hipError_t e = hipMemcpyAsync(db, b.host.get(), device_batch_bytes(bt.nviews), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_preprocess(db, bt, st);
-    if (e == hipSuccess) e = launch_bin_count(db, bt, st);
-    if (e == hipSuccess) e = launch_bin_scan(db, bt, nullptr, st);
+    if (e == hipSuccess) e = launch_depth_sort(db, bt, st);
+    if (e == hipSuccess) e = launch_key_scan(db, bt, st);
     uint32_t k = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&k, bt.keys_total, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { err = hipGetErrorString(e); return GES_ERR_DEVICE; }
-    if (k == 0xffffffffu) { err = "more than 2^32-2 keys in one batch"; return GES_ERR_CAPACITY; }
+    if (k == 0xffffffffu) { err = "more than 2^32-2 candidate pairs in one batch"; return GES_ERR_CAPACITY; }
     b.keys = k;
     return GES_OK;
   }
@@ -221,7 +229,7 @@ class GpuExecutor : public Executor {
     hipStream_t st = streams_[b.stream];
     const DeviceBatch* db = reinterpret_cast<const DeviceBatch*>(pool + b.table_off);
     Batch bt = make_batch(b, pool);
-    hipError_t e = launch_bin_scatter(db, bt, st);
+    hipError_t e = launch_duplicate(db, bt, st);
     if (e == hipSuccess) e = launch_tile_sort(db, bt, st);
     if (e == hipSuccess) e = launch_raster_forward(db, bt, st);
     for (int v = 0; v < bt.nviews && e == hipSuccess; ++v) {
@@ -257,18 +265,18 @@ class GpuExecutor : public Executor {
     const DeviceBatch& h = *b.host;
     bt.nviews = h.nviews;
     bt.falloff = h.views[0].falloff;
+    bt.tile_cull = h.views[0].tile_cull;
     bt.total_tiles = h.tile_prefix[h.nviews];
     bt.pre_blocks = h.pre_prefix[h.nviews];
-    bt.bin_blocks = h.bin_prefix[h.nviews];
-    bt.keys_total = reinterpret_cast<uint32_t*>(pool + b.table_off + align256(device_batch_bytes(kMaxViews)));
-    bt.sort_queue = bt.keys_total + 1;
+    bt.items = h.item_prefix[h.nviews];
+    bt.sw = batch_sort_ws(pool, b);
+    bt.keys_total = &bt.sw.cells[1];
+    bt.tile_passes = tile_passes(bt.total_tiles);
+    bt.dup_buffer = bt.tile_passes & 1;
     if (b.has_keys && b.keys > 0) {
-      const KeyPlan kp = plan_keys(b.keys, bt.total_tiles);
-      char* kw = pool + b.key_off;
-      bt.sorted_ids = reinterpret_cast<uint32_t*>(kw + kp.off_sorted);
-      bt.pairs = reinterpret_cast<uint2*>(kw + kp.off_pairs);
-      bt.pairs_tmp = reinterpret_cast<uint2*>(kw + kp.off_tmp);
-      bt.long_list = reinterpret_cast<uint32_t*>(kw + kp.off_list);
+      bt.kw = attach_key_ws(plan_keys(b.keys, bt.total_tiles), pool + b.key_off);
+      bt.sorted_ids = bt.kw.val[0];
+      bt.sorted_tiles = bt.kw.key[0];
       bt.key_capacity = b.keys;
     }
     return bt;
@@ -339,8 +347,6 @@ void retire(ges_server* s, std::unique_lock<std::mutex>& lk, bool wait_oldest) {
   if (any) s->cv_done.notify_all();
 }
 
-size_t table_bytes() { return align256(device_batch_bytes(kMaxViews)) + 256; }
-
 void build_views(ges_server* s, BatchWork& b) {
   b.host.reset(new DeviceBatch());
   DeviceBatch& h = *b.host;
@@ -348,7 +354,10 @@ void build_views(ges_server* s, BatchWork& b) {
   h.nviews = (int32_t)b.ids.size();
   b.plans.clear();
   b.inspect.clear();
-  int64_t pre = 0, bin = 0, tiles = 0;
+  int64_t pre = 0, items = 0, tiles = 0;
+  b.items = 0;
+  for (uint64_t id : b.ids) b.items += s->scenes[(size_t)s->reqs.at(id).scene].n;
+  const SortWs sw = batch_sort_ws(s->pool, b);
   for (size_t v = 0; v < b.ids.size(); ++v) {
     const Request& r = s->reqs.at(b.ids[v]);
     const ges_splats& sc = s->scenes[(size_t)r.scene];
@@ -363,15 +372,17 @@ void build_views(ges_server* s, BatchWork& b) {
     if (r.inspect)
       V.n_contrib = reinterpret_cast<uint32_t*>(
           r.inspect + serve_inspect_layout(sc.n, r.cam.width, r.cam.height, 0).off_n_contrib);
+    V.item_key = sw.item_key + items;
+    V.item_cand = sw.item_cand + items;
     h.pre_prefix[v] = pre;
-    h.bin_prefix[v] = bin;
+    h.item_prefix[v] = items;
     h.tile_prefix[v] = tiles;
     pre += (sc.n + 255) / 256;
-    bin += fp.bin_blocks;
+    items += sc.n;
     tiles += fp.tiles;
   }
   h.pre_prefix[b.ids.size()] = pre;
-  h.bin_prefix[b.ids.size()] = bin;
+  h.item_prefix[b.ids.size()] = items;
   h.tile_prefix[b.ids.size()] = tiles;
 }
 
@@ -394,16 +405,7 @@ void worker_loop(ges_server* s) {
     // ---- 1. admission under the pool budget
     BatchWork b;
     const int slots = s->cfg.sequential ? 1 : std::max(1, std::min(s->cfg.max_slots, (int32_t)kMaxViews));
-    if (!s->alloc->alloc(table_bytes(), &b.table_off)) {
-      if (!s->inflight.empty()) { retire(s, lk, true); continue; }
-      // nothing in flight and no room for even the table: fail the head request
-      Request& r = s->reqs.at(s->queue.front());
-      s->queue.pop_front();
-      finish_request(s, r, GES_REQ_FAILED, GES_ERR_OUT_OF_MEMORY);
-      s->cv_done.notify_all();
-      continue;
-    }
-    b.table_bytes = table_bytes();
+    int64_t items = 0;
     while (!s->queue.empty() && (int)b.ids.size() < slots) {
       Request& r = s->reqs.at(s->queue.front());
       const size_t need = request_bytes(s->scenes[(size_t)r.scene], r.cam);
@@ -414,10 +416,23 @@ void worker_loop(ges_server* s) {
       r.state = GES_REQ_RUNNING;
       r.t_start = now_ns();
       b.ids.push_back(r.id);
+      items += s->scenes[(size_t)r.scene].n;
       s->queue.pop_front();
     }
+    // the view table and the binning buffers of the batch; without room, give back the newest views
+    while (!b.ids.empty()) {
+      const size_t tb = table_bytes() + plan_sort(items).bytes;
+      if (s->alloc->alloc(tb, &b.table_off)) { b.table_bytes = tb; break; }
+      const uint64_t id = b.ids.back();
+      b.ids.pop_back();
+      Request& r = s->reqs.at(id);
+      s->alloc->release(r.ws_off, r.ws_bytes);
+      r.ws_bytes = 0;
+      r.state = GES_REQ_QUEUED;
+      items -= s->scenes[(size_t)r.scene].n;
+      s->queue.push_front(id);
+    }
     if (b.ids.empty()) {
-      s->alloc->release(b.table_off, b.table_bytes);
       if (!s->inflight.empty()) retire(s, lk, true);
       else {   // the head request cannot fit even in an idle pool
         Request& r = s->reqs.at(s->queue.front());
@@ -586,7 +601,8 @@ ges_status ges_serve_submit_inspect(ges_server* s, int32_t scene_id, const ges_c
     r.inspect = reinterpret_cast<char*>(inspect_device);
     r.inspect_bytes = inspect_bytes;
   }
-  const size_t need = ges::request_bytes(s->scenes[(size_t)scene_id], *cam) + ges::table_bytes();
+  const size_t need = ges::request_bytes(s->scenes[(size_t)scene_id], *cam) + ges::table_bytes() +
+                      ges::plan_sort(s->scenes[(size_t)scene_id].n).bytes;
   *request_id = r.id;
   if (need > s->alloc->size()) {
     // can never be admitted: reject at once

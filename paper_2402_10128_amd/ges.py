@@ -52,7 +52,7 @@ class ges_splat_grads(C.Structure):
 
 class ges_frame_view(C.Structure):
     _fields_ = [("records", C.c_void_p), ("tile_ranges", C.c_void_p), ("sorted_ids", C.c_void_p),
-                ("bucket_pairs", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
+                ("sorted_tiles", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
                 ("grad2d", C.c_void_p), ("stats", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
                 ("tile_work", C.c_void_p), ("group_order", C.c_void_p)]
 
@@ -257,7 +257,7 @@ def ges_frame_view_get(n, width, height, splat_ws, key_ws, num_keys, pixel_ws) -
     return v
 
 
-STAGES = ["preprocess", "bin_count", "bin_scan", "bin_scatter", "tile_sort", "raster_forward", "raster_backward",
+STAGES = ["preprocess", "depth_sort", "key_scan", "duplicate", "tile_sort", "raster_forward", "raster_backward",
           "preprocess_backward", "zero", "loss", "adam", "ssim", "mix_fit"]
 
 
@@ -469,8 +469,8 @@ class Frame:
     splat_ws: torch.Tensor
     pixel_ws: torch.Tensor
     key_ws: torch.Tensor | None = None
-    num_keys: int = 0        # the key count (or capacity) the frame was rendered with
-    key_capacity: int = 0    # keys the current key workspace holds
+    num_keys: int = 0        # the slot count (or capacity) the frame was rendered with
+    key_capacity: int = 0    # slots the current key workspace holds
 
     @staticmethod
     def create(n, width, height, device="cuda"):
@@ -507,13 +507,13 @@ def frame_arrays(frame: Frame, n: int) -> dict:
     out["ranges"] = sl(v.tile_ranges, 8 * T, ws).view(torch.int32).reshape(T, 2).cpu().numpy().view(np.uint32)
     out["grad2d"] = sl(v.grad2d, 8 * GRAD2D_STRIDE * n, ws).view(torch.float64).reshape(n, GRAD2D_STRIDE).cpu().numpy()
     out["stats"] = sl(v.stats, 32, ws).view(torch.int64).cpu().numpy()
+    out["keys"] = int(out["stats"][0])
     out["tile_work"] = sl(v.tile_work, 4 * T, ws).view(torch.int32).cpu().numpy().view(np.uint32)
     out["group_order"] = sl(v.group_order, 4 * ((T + 7) // 8), ws).view(torch.int32).cpu().numpy().view(np.uint32)
     if frame.key_ws is not None and frame.num_keys > 0:
-        K = frame.num_keys
+        K = min(out["keys"], frame.num_keys)
         out["sorted_ids"] = sl(v.sorted_ids, 4 * K, frame.key_ws).view(torch.int32).cpu().numpy().view(np.uint32)
-        out["bucket_pairs"] = sl(v.bucket_pairs, 8 * K, frame.key_ws).view(torch.int32).reshape(K, 2).cpu().numpy().view(
-            np.uint32)
+        out["sorted_tiles"] = sl(v.sorted_tiles, 4 * K, frame.key_ws).view(torch.int32).cpu().numpy().view(np.uint32)
     px = frame.width * frame.height
     out["final_T"] = sl(v.final_T, 4 * px, frame.pixel_ws).view(torch.float32).reshape(frame.height, frame.width).cpu().numpy()
     out["n_contrib"] = sl(v.n_contrib, 4 * px, frame.pixel_ws).view(torch.int32).reshape(

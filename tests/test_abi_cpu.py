@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_queries():
-    assert G.ges_abi_version() == 2
+    assert G.ges_abi_version() == 3
     sb, pb = G.ges_workspace_query(1000, 64, 64)
     assert sb > 1000 * 64 and pb >= 64 * 64 * 8
     assert G.ges_key_workspace_query(100, 1000, 64, 64) >= 100 * 20

@@ -68,7 +68,8 @@ def test_full_size_sampled_parity(case):
     print("  record mismatches", mm, flush=True)
     assert all(v == 0 for v in mm.values()), mm
     K = int(counts.sum())
-    assert gpu["num_keys"] == K, (gpu["num_keys"], K)
+    assert gpu["keys"] == K and gpu["num_keys"] >= K, (gpu["keys"], gpu["num_keys"], K)
+    assert np.array_equal(gpu["sorted_tiles"], np.repeat(np.arange(TX * TY), counts)), "sorted tile ids differ"
     ends = np.cumsum(counts)
     ref_ranges = np.stack([ends - counts, ends], 1)
     ref_ranges[counts == 0] = 0
