@@ -75,9 +75,9 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(stage, n, sh_coeffs, K, C, L, px):
+def algorithmic_bytes(stage, n, sh_coeffs, K, C, L, px, R=0):
     """Minimum HBM bytes of one launch of an HBM-bound stage: n splats, K keys, C candidate slots, L listed
-    splats, px pixels (the per-unit figures are listed in the design doc)."""
+    splats, px pixels, R rows stored by the backward raster (the per-unit figures are listed in the design doc)."""
     splat_in = 12 + 12 + 16 + 4 + 4 + 12 * sh_coeffs
     return {
         # parameters in; record, visibility word, depth key and candidate count out
@@ -90,8 +90,12 @@ def algorithmic_bytes(stage, n, sh_coeffs, K, C, L, px):
         "duplicate": L * (4 + 64 + 4 + 8) + 8 * C,
         # the slots in, the sorted (tile, splat) pairs out
         "tile_sort": 8 * C + 8 * K,
+        # per listed splat its order entry, count and first slot in and its 2-D gradient out (80 B); the slot
+        # marks (1 bit per slot); the 10 sums of every stored row
+        "row_reduce": L * (4 + 4 + 4 + 80) + C // 8 + 40 * R,
         "preprocess_backward": n * (16 + 12 + 16 + 4 + 12 * sh_coeffs + 48 + 80 + 4 * (3 + 3 + 4 + 1 + 1 + 3 * sh_coeffs)),
-        "zero": 96 * n,
+        # the row marks cleared before the backward raster
+        "zero": C // 8,
         "loss": 37 * px,
         # the preprocess backward with Adam fused in: its inputs as above, no gradient stores, and per
         # parameter the two moments read (8 B) and the parameter and both moments written (12 B)
@@ -136,7 +140,7 @@ def stage_rooflines(per_stage, m, falloff, workload):
             if issued is not None:
                 row["issued_over_algorithmic"] = round(issued * 64 / slots, 3)
         else:
-            nbytes = algorithmic_bytes(stage, m["n"], m["sh_k"], m["K"], m["C"], m["L"], m["px"])
+            nbytes = algorithmic_bytes(stage, m["n"], m["sh_k"], m["K"], m["C"], m["L"], m["px"], m.get("R", 0))
             if nbytes is None:
                 continue
             gbs = nbytes / (ms / 1e3) / 1e9
@@ -152,7 +156,8 @@ def stage_rooflines(per_stage, m, falloff, workload):
 def kernel_source_hash(stage):
     src = {"raster_forward": "raster.hip", "raster_backward": "raster.hip", "preprocess": "preprocess.hip",
            "preprocess_backward": "preprocess_bwd.hip", "tile_sort": "radix.hip", "depth_sort": "radix.hip",
-           "duplicate": "binning.hip", "key_scan": "binning.hip", "loss": "loss.hip", "zero": "loss.hip"}[stage]
+           "duplicate": "binning.hip", "key_scan": "binning.hip", "row_reduce": "binning.hip", "loss": "loss.hip",
+           "zero": "loss.hip"}[stage]
     with open(os.path.join(HERE, "paper_2402_10128_amd", "csrc", src), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
@@ -612,7 +617,7 @@ def fwd_bwd(dev, cfg, falloff, tile_cull, steps, warmup, log_fn):
     vis = int((fa["records"][:, 15].view(np.uint32) > 0).sum())
     m = dict(ms_step=ms_step, ms_step_readback=ms_step_readback, host_ms=t_host / steps * 1e3, per_stage=per_stage,
              dominant=dominant, dominant_ms=dom[0] / dom[1], n=s.n, sh_k=(sc.sh_degree + 1) ** 2, K=int(st[0]),
-             C=C, L=vis, px=W * H, pairs_exam=int(st[2]), pairs_blend=int(st[3]),
+             C=C, L=vis, px=W * H, R=fa.get("rows_stored", 0), pairs_exam=int(st[2]), pairs_blend=int(st[3]),
              bwd_walk=int(fa["n_contrib"].astype(np.int64).sum()),
              max_list=int((fa["ranges"][:, 1].astype(np.int64) - fa["ranges"][:, 0]).max(initial=0)))
     log_fn(f"{W}x{H} n={s.n}: {ms_step:.3f} ms/step, {W * H / ms_step / 1e3:.1f} Mpix/s, K={m['K']} slots={C}, "

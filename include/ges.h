@@ -92,7 +92,11 @@ typedef struct {
   int32_t tile_cull;             /* ges_tile_cull */
   float rho;                     /* shape strength of phi_rho (the paper uses 0.1) */
   float bg[3];                   /* background colour composited behind the splats */
+  uint32_t flags;                /* GES_RASTER_* bits (0: none) */
 } ges_raster_params;
+/* ges_render_backward also stores each splat's summed 2-D gradient in the frame's grad2d
+ * rows (ges_frame_view; inspection and tests), 96 bytes per listed splat. */
+#define GES_RASTER_KEEP_GRAD2D 1u
 
 typedef struct {                 /* device pointers, same shapes as ges_splats; overwritten (not accumulated) */
   float* means;
@@ -176,18 +180,21 @@ ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, 
 typedef struct {
   const float* records;          /* [n,16] per-splat record, see below (after ges_preprocess) */
   const uint32_t* tile_ranges;   /* [tiles,2] [start,end) into the sorted lists (after ges_render_forward) */
-  const uint32_t* sorted_ids;    /* [keys] splat index per sorted entry (after ges_render_forward) */
+  const uint32_t* sorted_pairs;  /* [keys,2] (splat index, candidate slot) per sorted entry (after ges_render_forward) */
   const uint32_t* sorted_tiles;  /* [keys] tile per sorted entry (after ges_render_forward) */
   const float* final_T;          /* [height,width] (after ges_render_forward) */
   const uint32_t* n_contrib;     /* [height,width] list position + 1 of the last composited splat */
   const double* grad2d;          /* [n,GES_GRAD2D_STRIDE] dL/d(u,v,a,b,c,opacity,r,g,b,beta) in slots 0..9, binary64
-                                    (after ges_render_backward) */
+                                    (after ges_render_backward: the rows of listed splats; with
+                                    GES_RASTER_KEEP_GRAD2D every row, those of unlisted splats zero) */
   const uint64_t* stats;         /* [4]: keys, error word (bit 0: key capacity too small), pairs examined,
                                     pairs composited (after ges_render_forward) */
   int32_t tiles_x, tiles_y;
   const uint32_t* tile_work;     /* [tiles] per tile, the largest n_contrib of its pixels (after ges_render_forward) */
   const uint32_t* group_order;   /* [ceil(tiles/8)] groups of 8 consecutive tiles in the order the backward pass
                                     deals them, heaviest tile_work first (after ges_render_forward) */
+  const uint32_t* row_marks;     /* [ceil(num_keys/32)] bit s: the backward stored a row of per-(tile, splat)
+                                    sums at candidate slot s (after ges_render_backward; NULL without key_ws) */
 } ges_frame_view;
 /* Record layout, 16 x 32-bit words per splat:
  *   0 u, 1 v, 2 conic a, 3 conic b, 4 conic c, 5 q_max, 6 opacity, 7 beta,
@@ -205,7 +212,7 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
  * costs two event records per launch. */
 enum { GES_STAGE_PREPROCESS = 0, GES_STAGE_DEPTH_SORT, GES_STAGE_KEY_SCAN, GES_STAGE_DUPLICATE, GES_STAGE_TILE_SORT,
        GES_STAGE_RASTER_FORWARD, GES_STAGE_RASTER_BACKWARD, GES_STAGE_PREPROCESS_BACKWARD, GES_STAGE_ZERO,
-       GES_STAGE_LOSS, GES_STAGE_ADAM, GES_STAGE_SSIM, GES_STAGE_MIX_FIT, GES_NUM_STAGES };
+       GES_STAGE_LOSS, GES_STAGE_ADAM, GES_STAGE_SSIM, GES_STAGE_MIX_FIT, GES_STAGE_ROW_REDUCE, GES_NUM_STAGES };
 ges_status ges_profile_enable(int32_t on);
 /* Time only the stages whose bit (1 << GES_STAGE_*) is set; 0 switches timing off. */
 ges_status ges_profile_select(uint32_t stage_mask);
@@ -479,7 +486,7 @@ ges_status ges_serve_poll(ges_server* s, uint64_t request_id, ges_request_info* 
  *   n_contrib [height,width] u32 (written there by the raster itself);
  *   header    4 x u64: this view's keys, error word, pairs examined, pairs composited
  *             (the part is 256 bytes);
- *   ids       [batch keys] u32, the batch's sorted splat ids (every view of the batch),
+ *   ids       [batch keys,2] u32, the batch's sorted (splat index, slot) pairs (every view),
  *             copied only if inspect_bytes >= ges_serve_inspect_bytes(n, w, h, batch keys);
  *             ges_serve_poll's num_keys gives the batch's key count.
  * inspect_bytes below ges_serve_inspect_bytes(n, w, h, 0): CAPACITY; a misaligned

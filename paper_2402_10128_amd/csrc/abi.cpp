@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "frame.h"
@@ -17,6 +18,11 @@ namespace {
 
 thread_local std::string g_last_error;
 thread_local ges::DeviceBatch g_host_batch;   // staging copy of the view table (pageable; copied per call)
+
+// The key workspace and slot capacity each splat workspace was last rendered with: the backward pass reads
+// the sorted pairs and writes its rows there (its signature carries no slot count).
+std::mutex g_keys_mu;
+std::unordered_map<const void*, std::pair<void*, uint64_t>> g_keys_of_frame;
 
 ges_status fail(ges_status s, const std::string& msg) {
   g_last_error = msg;
@@ -76,7 +82,8 @@ hipError_t timed(int stage, hipStream_t stream, F&& launch) {
 // Build the single-view batch of a frame and copy it into the splat workspace.
 hipError_t upload_single_view(const ges_splats* s, const ges_camera* c, const ges_raster_params* p,
                               const ges::FramePlan& fp, void* splat_ws, void* pixel_ws, float* out_rgb,
-                              const float* dL_drgb, hipStream_t stream) {
+                              const float* dL_drgb, hipStream_t stream, void* key_ws = nullptr,
+                              uint64_t key_slots = 0) {
   ges::DeviceBatch& hb = g_host_batch;
   hb.nviews = 1;
   hb.pre_prefix[0] = 0;
@@ -98,6 +105,15 @@ hipError_t upload_single_view(const ges_splats* s, const ges_camera* c, const ge
   }
   V.out_rgb = out_rgb;
   V.dL_drgb = dL_drgb;
+  if (key_ws && key_slots) {   // the backward's rows of per-(tile, splat) sums
+    const ges::KeyPlan kp = ges::plan_keys(key_slots, true);
+    char* kw = reinterpret_cast<char*>(key_ws);
+    V.sorted_pairs = reinterpret_cast<const uint2*>(kw + kp.off_pv0);
+    V.grad_rows = reinterpret_cast<float*>(kw + kp.off_rows);
+    V.grad_bits = reinterpret_cast<uint32_t*>(kw + kp.off_bits);
+    V.grad_slots = key_slots;
+  }
+  V.keep_grad2d = (p->flags & GES_RASTER_KEEP_GRAD2D) ? 1 : 0;
   void* dst = reinterpret_cast<char*>(splat_ws) + fp.off_db;
   return hipMemcpyAsync(dst, &hb, ges::device_batch_bytes(1), hipMemcpyHostToDevice, stream);
 }
@@ -153,7 +169,7 @@ ges_status ges_key_workspace_query(uint64_t num_keys, int64_t n, int32_t width, 
   if (width < 1 || height < 1 || width > 16384 || height > 16384)
     return fail(GES_ERR_INVALID_ARGUMENT, "width/height outside [1,16384]");
   if (num_keys >= 0xffffffffull) return fail(GES_ERR_CAPACITY, "more than 2^32-2 keys");
-  *key_ws_bytes = ges::plan_keys(num_keys, ges::plan_frame(0, width, height).tiles).bytes;
+  *key_ws_bytes = ges::plan_keys(num_keys, true).bytes;
   return GES_OK;
 }
 
@@ -192,15 +208,21 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
     return fail(GES_ERR_INVALID_ARGUMENT, "workspaces must be 256-byte aligned");
   if (num_keys >= 0xffffffffull) return fail(GES_ERR_CAPACITY, "more than 2^32-2 keys");
   const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
-  const ges::KeyPlan kp = ges::plan_keys(num_keys, fp.tiles);
+  const ges::KeyPlan kp = ges::plan_keys(num_keys, true);
   if (num_keys > 0 && (!key_ws || key_ws_bytes < kp.bytes)) return fail(GES_ERR_CAPACITY, "key workspace too small");
+  if (num_keys > 0 && (reinterpret_cast<uintptr_t>(key_ws) & 255u))
+    return fail(GES_ERR_INVALID_ARGUMENT, "key_ws must be 256-byte aligned");
+  {
+    std::lock_guard<std::mutex> lk(g_keys_mu);
+    g_keys_of_frame[splat_ws] = {num_keys > 0 ? key_ws : nullptr, num_keys};
+  }
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
   GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, out_rgb, nullptr, stream), "upload");
   ges::Batch b = single_batch(splats, params, fp, splat_ws);
   b.key_capacity = num_keys;
   if (num_keys > 0) {
     b.kw = ges::attach_key_ws(kp, key_ws);
-    b.sorted_ids = b.kw.val[0];
+    b.sorted_pairs = b.kw.pv[0];
     b.sorted_tiles = b.kw.key[0];
   }
   const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
@@ -227,16 +249,34 @@ static ges_status render_backward(const ges_splats* splats, const ges_camera* ca
     return fail(GES_ERR_INVALID_ARGUMENT, "grads->sh must be 16-byte aligned");
   const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-  GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, nullptr, dL_drgb, stream), "upload");
+  uint64_t slots = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_keys_mu);
+    auto it = g_keys_of_frame.find(splat_ws);
+    if (it == g_keys_of_frame.end()) return fail(GES_ERR_INVALID_ARGUMENT, "no forward pass of this splat workspace");
+    if (it->second.first != (it->second.second ? key_ws : nullptr))
+      return fail(GES_ERR_INVALID_ARGUMENT, "key_ws differs from the forward pass of this splat workspace");
+    slots = it->second.second;
+  }
+  GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, nullptr, dL_drgb, stream, key_ws,
+                                   slots), "upload");
   ges::Batch b = single_batch(splats, params, fp, splat_ws);
-  // the sorted ids of the forward pass; ranges bound every access, so the capacity is not needed here
-  if (key_ws) b.sorted_ids = reinterpret_cast<uint32_t*>(key_ws);   // KeyPlan::off_val0 == 0
+  const ges::KeyPlan kp = ges::plan_keys(slots, true);
+  if (slots) b.sorted_pairs = reinterpret_cast<const uint2*>(reinterpret_cast<char*>(key_ws) + kp.off_pv0);
   const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
-  GES_CHECK_HIP(timed(GES_STAGE_ZERO, stream, [&] {
-                  return ges::launch_zero(reinterpret_cast<char*>(splat_ws) + fp.off_grad,
-                                          (size_t)splats->n * ges::kGradStride * 8, stream);
-                }), "zero grad2d");
+  if (slots)
+    GES_CHECK_HIP(timed(GES_STAGE_ZERO, stream, [&] {
+                    return ges::launch_zero(reinterpret_cast<char*>(key_ws) + kp.off_bits, (slots + 31) / 32 * 4,
+                                            stream);
+                  }), "clear row marks");
   GES_CHECK_HIP(timed(GES_STAGE_RASTER_BACKWARD, stream, [&] { return ges::launch_raster_backward(db, b, stream); }), "raster_backward");
+  // every listed splat's row of grad2d (zero when its slots lie beyond the key capacity)
+  char* kwb = reinterpret_cast<char*>(key_ws);
+  GES_CHECK_HIP(timed(GES_STAGE_ROW_REDUCE, stream, [&] {
+                  return ges::launch_row_reduce(db, b, slots ? reinterpret_cast<const float*>(kwb + kp.off_rows) : nullptr,
+                                                slots ? reinterpret_cast<const uint32_t*>(kwb + kp.off_bits) : nullptr,
+                                                slots, stream);
+                }), "row_reduce");
   GES_CHECK_HIP(timed(GES_STAGE_PREPROCESS_BACKWARD, stream,
                       [&] { return ges::launch_preprocess_backward(db, b, grads, stream, adam, fused); }),
                 "preprocess_backward");
@@ -325,10 +365,11 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
   out->grad2d = reinterpret_cast<const double*>(sw + fp.off_grad);
   out->stats = reinterpret_cast<const uint64_t*>(sw + fp.off_hdr);
   if (key_ws) {
-    const ges::KeyPlan kp = ges::plan_keys(num_keys, fp.tiles);
+    const ges::KeyPlan kp = ges::plan_keys(num_keys, true);
     char* kw = reinterpret_cast<char*>(key_ws);
-    out->sorted_ids = reinterpret_cast<const uint32_t*>(kw + kp.off_val0);
+    out->sorted_pairs = reinterpret_cast<const uint32_t*>(kw + kp.off_pv0);
     out->sorted_tiles = reinterpret_cast<const uint32_t*>(kw + kp.off_key0);
+    out->row_marks = reinterpret_cast<const uint32_t*>(kw + kp.off_bits);
   }
   if (pixel_ws) {
     char* pw = reinterpret_cast<char*>(pixel_ws);

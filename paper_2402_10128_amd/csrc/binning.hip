@@ -32,7 +32,7 @@ __global__ void clear_cells_kernel(uint32_t* cells) {
 
 hipError_t launch_depth_sort(const DeviceBatch* /*dbatch*/, Batch& b, hipStream_t stream) {
   SortWs& w = b.sw;
-  const uint32_t nb = radix_blocks((uint64_t)b.items, kRadixItemsSmall);
+  const uint32_t nb = radix_blocks((uint64_t)b.items, kRadixItemsDepth);
   if (nb == 0) {   // no splat: no pass runs, so nothing else would write the listed count
     hipLaunchKernelGGL(clear_cells_kernel, dim3(1), dim3(64), 0, stream, w.cells);
     w.depth_final = 1;
@@ -43,7 +43,7 @@ hipError_t launch_depth_sort(const DeviceBatch* /*dbatch*/, Batch& b, hipStream_
   int cur = 0;
   for (int pass = 0; pass < kDepthPasses; ++pass) {
     RadixPass p{};
-    p.items = kRadixItemsSmall;
+    p.items = kRadixItemsDepth;
     p.bits = 8;
     p.keys_in = kin;
     p.vals_in = vin;
@@ -334,6 +334,8 @@ __global__ void __launch_bounds__(256) duplicate_kernel(const DeviceBatch* __res
       const uint32_t h = W.hits[lane];
       reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = h;
       V.vis[i] = (h ? kVisBit : 0u) | flags;
+      const uint64_t first = slot0 + (sincl - nslots);   // the splat's first slot (its rows in the backward)
+      V.slot_off[i] = first > 0xffffffffull ? 0xffffffffu : (uint32_t)first;
       if (h) atomicAdd(&view_keys[v], h);
     }
   }
@@ -348,8 +350,152 @@ hipError_t launch_duplicate(const DeviceBatch* dbatch, const Batch& b, hipStream
   if (chunks == 0 || b.key_capacity == 0) return hipSuccess;
   const int X = b.dup_buffer;
   hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)chunks), dim3(256), 0, stream, dbatch,
-                     w.dv[w.depth_final], w.item_cand, w.chunk_off, w.cells, b.kw.key[X], b.kw.val[X],
+                     w.dv[w.depth_final], w.item_cand, w.chunk_off, w.cells, b.kw.key[X],
+                     reinterpret_cast<uint32_t*>(b.kw.pv[X]),
                      b.key_capacity, b.tile_cull == GES_TILES_ELLIPSE ? 1 : 0);
+  return hipGetLastError();
+}
+
+// After the backward raster: each listed splat's 2-D gradient, the sum of the rows the raster stored at its
+// slots (one per tile whose pixels it reached), added in binary64 in an order fixed by the slot layout alone,
+// so the backward is deterministic.  One lane per splat, in depth order (a wave's rows lie in one stretch of
+// the row buffer).  A splat with at most kSmallSlots slots is summed by its own lane in slot order, the
+// marked rows of a 32-slot word fetched kRowBatch at a time (their loads issued together).  Larger splats
+// (a lane would walk them alone, and their rows would be fetched one lane at a time) are summed after that
+// by groups of 16 lanes, four splats of the wave at a time: lane q of a group adds the slots q, q + 16, ...
+// in order, and the group's sums are added by a fixed butterfly.
+constexpr int kRowBatch = 4;
+constexpr uint32_t kSmallSlots = 32;
+
+__device__ __forceinline__ void add_row(double* g, const Vec4* r) {
+  g[0] += r[0][0]; g[1] += r[0][1]; g[2] += r[0][2]; g[3] += r[0][3];
+  g[4] += r[1][0]; g[5] += r[1][1]; g[6] += r[1][2]; g[7] += r[1][3];
+  g[8] += r[2][0]; g[9] += r[2][1];
+}
+
+__device__ __forceinline__ void store_grad2d(double* dst, const double* g) {
+  double2* gs = reinterpret_cast<double2*>(dst);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) gs[c] = make_double2(g[2 * c], g[2 * c + 1]);
+}
+
+// ONE: the batch holds a single view (its descriptor then reads through scalar loads).
+template <bool ONE>
+__global__ void __launch_bounds__(256) row_reduce_kernel(const DeviceBatch* __restrict__ db,
+                                                         const uint32_t* __restrict__ order,
+                                                         const uint32_t* __restrict__ item_cand,
+                                                         const uint32_t* __restrict__ cells,
+                                                         const float* __restrict__ rows_,
+                                                         const uint32_t* __restrict__ bits_, uint64_t nslots) {
+  const int lane = threadIdx.x & 63;
+  const int64_t listed = (int64_t)cells[0];
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k - lane >= listed) return;   // the whole wave lies past the listed splats
+  const bool valid = k < listed;
+  uint32_t j = 0, cand = 0;
+  if (valid) {
+    j = order[k];
+    cand = item_cand[j];
+  }
+  int v = 0;
+  int64_t i = j;
+  if (!ONE && valid) {
+    v = view_of_item(db, j);
+    i = (int64_t)j - db->item_prefix[v];
+  }
+  const ViewDesc& V = db->views[ONE ? 0 : v];
+  uint64_t off = 0, end = 0;
+  if (valid) {
+    off = min<uint64_t>(V.slot_off[i], nslots);
+    end = min<uint64_t>(off + cand, nslots);
+  }
+  const bool big = cand > kSmallSlots;   // cand is 0 on lanes past the listed splats
+  const GlobalU32* bits = (const GlobalU32*)bits_;
+  const GlobalVec4* rows = (const GlobalVec4*)rows_;
+  if (valid && !big) {
+    double g[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (uint64_t lo = off & ~(uint64_t)31; lo < end; lo += 32) {
+      uint32_t m = bits[lo >> 5];
+      if (lo < off) m &= ~0u << (uint32_t)(off - lo);
+      if (end - lo < 32) m &= (1u << (uint32_t)(end - lo)) - 1u;
+      while (m) {
+        Vec4 r[kRowBatch][3];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+          if (m) {
+            const GlobalVec4* q = rows + (lo + (uint32_t)__builtin_ctz(m)) * (kRowFloats / 4);
+            r[u][0] = q[0];
+            r[u][1] = q[1];
+            r[u][2] = q[2];
+          } else {
+            r[u][0] = Vec4{0.f, 0.f, 0.f, 0.f};
+            r[u][1] = r[u][0];
+            r[u][2] = r[u][0];
+          }
+          m &= m - 1u;
+        }
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) add_row(g, r[u]);   // in slot order; a missing row adds zeros
+      }
+    }
+    store_grad2d(V.grad2d + (int64_t)kGradStride * i, g);
+  }
+  // the wave's large splats, four at a time (group grp of 16 lanes takes the grp-th one left)
+  uint64_t pending = __ballot(big);
+  const int grp = lane >> 4, q = lane & 15;
+  while (pending) {
+    uint64_t m = pending;
+    for (int r = 0; r < grp; ++r) m &= m - 1;
+    const bool has = m != 0;
+    const int src = has ? (int)__builtin_ctzll(m) : lane;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pending &= pending - 1;
+    const unsigned long long so = __shfl((unsigned long long)off, src, 64);
+    unsigned long long se = __shfl((unsigned long long)end, src, 64);
+    const long long si = __shfl((long long)i, src, 64);
+    const int sv = ONE ? 0 : __shfl(v, src, 64);
+    if (!has) se = so;
+    double h[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (uint64_t base = so; base < se; base += 16 * kRowBatch) {
+      Vec4 r[kRowBatch][3];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const uint64_t s = base + (uint64_t)(q + 16 * u);
+        if (s < se && ((bits[s >> 5] >> (uint32_t)(s & 31u)) & 1u)) {
+          const GlobalVec4* p = rows + s * (kRowFloats / 4);
+          r[u][0] = p[0];
+          r[u][1] = p[1];
+          r[u][2] = p[2];
+        } else {
+          r[u][0] = Vec4{0.f, 0.f, 0.f, 0.f};
+          r[u][1] = r[u][0];
+          r[u][2] = r[u][0];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) add_row(h, r[u]);
+    }
+    // every lane of the group ends with the same sums (each step adds the same two values on both sides)
+#pragma unroll
+    for (int d = 8; d >= 1; d >>= 1) {
+#pragma unroll
+      for (int c = 0; c < 10; ++c) h[c] += __shfl_xor(h[c], d, 16);
+    }
+    if (has && q == 0) store_grad2d(db->views[sv].grad2d + (int64_t)kGradStride * si, h);
+  }
+}
+
+hipError_t launch_row_reduce(const DeviceBatch* dbatch, const Batch& b, const float* rows, const uint32_t* bits,
+                             uint64_t nslots, hipStream_t stream) {
+  if (b.items == 0) return hipSuccess;
+  const SortWs& w = b.sw;
+  const dim3 grid((unsigned)((b.items + 255) / 256));
+  if (b.nviews == 1)
+    hipLaunchKernelGGL(row_reduce_kernel<true>, grid, dim3(256), 0, stream, dbatch, w.dv[w.depth_final], w.item_cand,
+                       w.cells, rows, bits, nslots);
+  else
+    hipLaunchKernelGGL(row_reduce_kernel<false>, grid, dim3(256), 0, stream, dbatch, w.dv[w.depth_final],
+                       w.item_cand, w.cells, rows, bits, nslots);
   return hipGetLastError();
 }
 
@@ -374,7 +520,7 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const DeviceBatch* __r
 hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {
   if (b.key_capacity == 0) return hipSuccess;
   const SortWs& w = b.sw;
-  const uint32_t nb = radix_blocks(b.key_capacity, kRadixItemsLarge);
+  const uint32_t nb = radix_blocks(b.key_capacity, kRadixItemsPair);
   // the tile bits split evenly over the passes (13 bits: 7 + 6), so that no pass scatters to more digit
   // runs than it must
   int bits = 1;
@@ -384,12 +530,14 @@ hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream
     const int left = b.tile_passes - pass;
     const int pb = (bits - shift + left - 1) / left;
     RadixPass p{};
-    p.items = kRadixItemsLarge;
+    p.items = kRadixItemsPair;
     p.bits = pb;
+    p.pair = 1;   // the first pass pairs each splat index with its slot
     p.keys_in = b.kw.key[cur];
-    p.vals_in = b.kw.val[cur];
+    if (pass == 0) p.vals_in = reinterpret_cast<const uint32_t*>(b.kw.pv[cur]);
+    else p.pvals_in = b.kw.pv[cur];
     p.keys_out = b.kw.key[cur ^ 1];
-    p.vals_out = b.kw.val[cur ^ 1];
+    p.pvals_out = b.kw.pv[cur ^ 1];
     p.count_dev = pass == 0 ? &w.cells[3] : &w.cells[2];
     p.nblocks = nb;
     p.shift = shift;

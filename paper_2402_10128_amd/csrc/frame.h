@@ -27,7 +27,7 @@ inline SortPlan plan_sort(int64_t items) {
   p.off_dv0 = o;    o += align256(n * 4);
   p.off_dk1 = o;    o += align256(n * 4);
   p.off_dv1 = o;    o += align256(n * 4);
-  p.off_table = o;  o += align256((size_t)256 * radix_blocks((uint64_t)n, kRadixItemsSmall) * 4);
+  p.off_table = o;  o += align256((size_t)256 * radix_blocks((uint64_t)n, kRadixItemsDepth) * 4);
   p.off_totals = o; o += 1024;
   p.off_chunks = o; o += align256(((n + 255) / 256 + 1) * 4);
   p.off_cells = o;  o += 256;
@@ -57,8 +57,8 @@ struct FramePlan {
   int64_t tiles = 0;
   // splat workspace; the binning buffers of the frame's own batch come last (a server gives a batch of
   // views one such region and its views only the part before it)
-  size_t off_db = 0, off_hdr = 0, off_rec = 0, off_grad = 0, off_vis = 0, off_ranges = 0, off_tstats = 0,
-         off_twork = 0, off_gorder = 0, off_sort = 0;
+  size_t off_db = 0, off_hdr = 0, off_rec = 0, off_grad = 0, off_vis = 0, off_slotoff = 0, off_ranges = 0,
+         off_tstats = 0, off_twork = 0, off_gorder = 0, off_sort = 0;
   size_t view_bytes = 0, splat_bytes = 0;
   // pixel workspace
   size_t off_final_T = 0, off_n_contrib = 0, pixel_bytes = 0;
@@ -75,6 +75,7 @@ inline FramePlan plan_frame(int64_t n, int w, int h) {
   p.off_rec = o;     o += align256((size_t)n * kRecWords * 4);
   p.off_grad = o;    o += align256((size_t)n * kGradStride * 8);
   p.off_vis = o;     o += align256((size_t)n * 4);
+  p.off_slotoff = o; o += align256((size_t)n * 4);
   p.off_ranges = o;  o += align256((size_t)p.tiles * 8);
   p.off_tstats = o;  o += align256((size_t)p.tiles * 16);
   p.off_twork = o;   o += align256((size_t)p.tiles * 4);
@@ -97,23 +98,29 @@ inline int tile_passes(int64_t total_tiles) {
   return (bits + 7) / 8;
 }
 
-// Key workspace: two buffers of `slots` (tile, splat) pairs, the splat ids of buffer 0 first so that the
-// backward pass finds the sorted ids at the start of the workspace without the slot count; then the table
-// of the tile passes.
+// Key workspace of `slots` candidate slots: two buffers of (tile; splat index, slot) pairs, the values of
+// buffer 0 first (the sorted pairs the raster reads); the table of the tile passes; and, for frames that
+// run the backward pass, one 48-byte row per slot for the backward's per-(tile, splat) sums with a bit per
+// slot marking the written rows.
 struct KeyPlan {
-  size_t off_val0 = 0, off_key0 = 0, off_val1 = 0, off_key1 = 0, off_table = 0, off_totals = 0, bytes = 0;
+  size_t off_pv0 = 0, off_key0 = 0, off_pv1 = 0, off_key1 = 0, off_table = 0, off_totals = 0, off_rows = 0,
+         off_bits = 0, bytes = 0;
 };
 
-inline KeyPlan plan_keys(uint64_t slots, int64_t /*tiles*/) {
+inline KeyPlan plan_keys(uint64_t slots, bool backward_rows) {
   KeyPlan p;
   const size_t k = (size_t)slots;
   size_t o = 0;
-  p.off_val0 = o;   o += align256(k * 4);
+  p.off_pv0 = o;    o += align256(k * 8);
   p.off_key0 = o;   o += align256(k * 4);
-  p.off_val1 = o;   o += align256(k * 4);
+  p.off_pv1 = o;    o += align256(k * 8);
   p.off_key1 = o;   o += align256(k * 4);
-  p.off_table = o;  o += align256((size_t)256 * radix_blocks(slots, kRadixItemsLarge) * 4);
+  p.off_table = o;  o += align256((size_t)256 * radix_blocks(slots, kRadixItemsPair) * 4);
   p.off_totals = o; o += 1024;
+  if (backward_rows) {
+    p.off_rows = o; o += align256(k * kRowFloats * 4);
+    p.off_bits = o; o += align256((k + 31) / 32 * 4);
+  }
   p.bytes = o;
   return p;
 }
@@ -121,9 +128,9 @@ inline KeyPlan plan_keys(uint64_t slots, int64_t /*tiles*/) {
 inline KeyWs attach_key_ws(const KeyPlan& p, void* base) {
   char* b = reinterpret_cast<char*>(base);
   KeyWs w{};
-  w.val[0] = reinterpret_cast<uint32_t*>(b + p.off_val0);
+  w.pv[0] = reinterpret_cast<uint2*>(b + p.off_pv0);
   w.key[0] = reinterpret_cast<uint32_t*>(b + p.off_key0);
-  w.val[1] = reinterpret_cast<uint32_t*>(b + p.off_val1);
+  w.pv[1] = reinterpret_cast<uint2*>(b + p.off_pv1);
   w.key[1] = reinterpret_cast<uint32_t*>(b + p.off_key1);
   w.table = reinterpret_cast<uint32_t*>(b + p.off_table);
   w.totals = reinterpret_cast<uint32_t*>(b + p.off_totals);
@@ -214,6 +221,7 @@ inline void attach_splat_ws(ViewDesc& V, const FramePlan& fp, void* splat_ws) {
   V.rec = reinterpret_cast<float4*>(b + fp.off_rec);
   V.grad2d = reinterpret_cast<double*>(b + fp.off_grad);
   V.vis = reinterpret_cast<uint32_t*>(b + fp.off_vis);
+  V.slot_off = reinterpret_cast<uint32_t*>(b + fp.off_slotoff);
   V.ranges = reinterpret_cast<uint2*>(b + fp.off_ranges);
   V.tile_stats = reinterpret_cast<unsigned long long*>(b + fp.off_tstats);
   V.tile_work = reinterpret_cast<uint32_t*>(b + fp.off_twork);

@@ -18,8 +18,8 @@ constexpr int kRecWords = 16;            // 64-byte per-splat record
 constexpr int kGradStride = GES_GRAD2D_STRIDE;   // doubles per splat in the 2-D gradient accumulator
 constexpr int kMaxViews = 64;
 constexpr int kRadixThreads = 256;       // radix passes: blocks of 256 threads ...
-constexpr int kRadixItemsLarge = 16;     // ... holding 16 items each (the pair sort) ...
-constexpr int kRadixItemsSmall = 4;      // ... or 4 (the depth sort of the splats: more blocks to hide latency)
+constexpr int kRadixItemsDepth = 16;     // ... holding 16 items each (the depth sort of the splats) ...
+constexpr int kRadixItemsPair = 8;       // ... or 8 (the pair sort: its 12-byte items need twice the LDS)
 constexpr uint32_t kNoKey = 0xffffffffu; // radix key of an item that a filtering pass drops
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
@@ -62,7 +62,13 @@ struct ViewDesc {
   unsigned long long* tile_stats;  // [tiles][2] pairs examined and composited per tile (forward pass)
   uint32_t* tile_work;           // [tiles] list position + 1 of the tile's last composited splat (forward pass)
   uint32_t* group_order;         // [ceil(tiles / 8)] tile groups, heaviest backward walk first
-  double* grad2d;                // [n][kGradStride] binary64 accumulators (cross-tile sums)
+  double* grad2d;                // [n][kGradStride] binary64 2-D gradients (stored with keep_grad2d only)
+  uint32_t* slot_off;            // [n] first candidate slot of a listed splat (the duplication writes it)
+  const uint2* sorted_pairs;     // [keys] (splat index, slot) per sorted pair (backward)
+  float* grad_rows;              // [slots][kRowFloats] per-(tile, splat) sums of the backward, at the pair's slot
+  uint32_t* grad_bits;           // [slots / 32] slots whose row the backward wrote
+  uint64_t grad_slots;           // slots the rows cover (the key capacity of the forward pass)
+  int32_t keep_grad2d;           // store the summed 2-D gradients in grad2d
   uint32_t* vis;                 // [n] bit 31: the splat touches a tile; bits 0..4: its clamp flags
   float* final_T;                // [h*w]
   uint32_t* n_contrib;           // [h*w]
@@ -90,11 +96,13 @@ struct SortWs {
 // Key workspace of a batch: [capacity] slots of (tile, splat) pairs, two buffers; the final order lands in
 // buffer 0 (val[0] first in the workspace: the backward finds the sorted splat ids there).
 struct KeyWs {
-  uint32_t* val[2];
+  uint2* pv[2];                  // (splat index, slot) values of the tile passes; the duplication writes the
+                                 // splat indices as u32 into the first half of pv[dup_buffer]
   uint32_t* key[2];
   uint32_t* table;               // [256][key_blocks]
   uint32_t* totals;              // [256]
 };
+constexpr int kRowFloats = 12;   // floats per backward row (10 used; 48 bytes keep rows 16-byte aligned)
 
 struct Batch {
   int32_t nviews;
@@ -107,7 +115,7 @@ struct Batch {
   SortWs sw;
   KeyWs kw;
   uint32_t* keys_total;          // device: candidate slots of the batch (sw.cells + 1)
-  uint32_t* sorted_ids;          // [key capacity] splat index per sorted pair (kw.val[0])
+  const uint2* sorted_pairs;     // [key capacity] (splat index, slot) per sorted pair (kw.pv[0])
   uint32_t* sorted_tiles;        // [key capacity] batch tile per sorted pair (kw.key[0])
   int dup_buffer;                // buffer the duplication writes (so that the last tile pass ends in 0)
   uint64_t key_capacity;
@@ -166,14 +174,22 @@ hipError_t launch_depth_sort(const DeviceBatch* dbatch, Batch& b, hipStream_t st
 hipError_t launch_key_scan(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_duplicate(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
+// after the backward raster: every listed splat's 2-D gradient from its rows (nslots of kRowFloats floats,
+// marked in bits), in slot order (binary64); zero for a splat whose slots lie beyond nslots
+hipError_t launch_row_reduce(const DeviceBatch* dbatch, const Batch& b, const float* rows, const uint32_t* bits,
+                             uint64_t nslots, hipStream_t stream);
 // one stable LSD radix pass over (u32 key, u32 value) items with 8-bit digits (radix.hip)
 struct RadixPass {
-  int32_t items;                 // per thread: kRadixItemsLarge or kRadixItemsSmall
+  int32_t items;                 // per thread: kRadixItemsDepth (pair == 0) or kRadixItemsPair (pair == 1)
   int32_t bits;                  // digit width (1..8)
+  int32_t pair;                  // values are (u32, slot) pairs: read from pvals_in, or made from vals_in and
+                                 // the item index; written to pvals_out
   const uint32_t* keys_in;
   const uint32_t* vals_in;       // NULL: an item's value is its index
+  const uint2* pvals_in;
   uint32_t* keys_out;
   uint32_t* vals_out;
+  uint2* pvals_out;
   const uint32_t* count_dev;     // number of items (device), or NULL: count_host
   uint32_t count_host;
   uint32_t nblocks;              // table width: blocks of 256 x items items covering the largest count
@@ -242,6 +258,7 @@ hipError_t launch_adam(const ges_adam_group* groups, int ngroups, int64_t step, 
 typedef float Vec4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const Vec4 GlobalRec;
 typedef __attribute__((address_space(1))) double GlobalF64;
+typedef __attribute__((address_space(1))) Vec4 GlobalVec4;
 typedef __attribute__((address_space(1))) uint32_t GlobalU32;
 
 __device__ __forceinline__ float4 rec_load(const GlobalRec* rec, size_t i) {

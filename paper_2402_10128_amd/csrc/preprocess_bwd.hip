@@ -118,6 +118,11 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
   const uint32_t vis = V.vis[i];
   const int64_t sh0 = (int64_t)3 * K * i;
   if (!(vis & kVisBit)) {
+    if (V.keep_grad2d) {   // inspection: the rows of unlisted splats read as zero
+      double2* gz = reinterpret_cast<double2*>(V.grad2d + (int64_t)kGradStride * i);
+#pragma unroll
+      for (int k = 0; k < kGradStride / 2; ++k) gz[k] = make_double2(0.0, 0.0);
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       emit<kAdam, kParMeans>(G.means, A, 3 * i + c, 0.f);
@@ -135,6 +140,7 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
     return;
   }
   const uint32_t flags = vis & 0xffu;
+  // the splat's 2-D gradient, summed from its rows by the reduction that follows the backward raster
   const double2* gp = reinterpret_cast<const double2*>(V.grad2d + (int64_t)kGradStride * i);
   const double2 g01 = gp[0], g23 = gp[1], g45 = gp[2], g67 = gp[3], g89 = gp[4];
   if (A.stat_accum) {   // densification statistic: the mean-2D gradient in NDC units

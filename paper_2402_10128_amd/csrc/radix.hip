@@ -10,9 +10,11 @@
 //              digit) against wave-private digit counters -- places them in LDS in digit order, and writes
 //              each digit's run to its global position (exclusive digit total prefix + the block's offset),
 //              so that consecutive threads write consecutive addresses.
-// A block holds 256 x ITEMS items: 16 per thread for the pair sort, 4 for the depth sort of the splats
-// (four times the blocks, to hide the latency of short passes).  A filtering pass drops items whose key
-// is kNoKey (compaction) and stores the kept count.
+// A block holds 256 x ITEMS items: 16 per thread for the depth sort of the splats, 8 for the pair sort
+// (whose 12-byte items would otherwise leave room for two blocks per compute unit in LDS).  A filtering pass drops items whose key
+// is kNoKey (compaction) and stores the kept count.  With PAIR, a value is a (u32, slot) pair whose slot is
+// the item's index in the pass that makes the pairs: the pair sort carries each pair's slot in the
+// candidate layout to the backward pass.
 #include "ges_internal.h"
 
 namespace ges {
@@ -116,13 +118,19 @@ __global__ void __launch_bounds__(kRadixThreads) radix_scan_kernel(RadixPass p) 
   if (threadIdx.x == 0) p.totals[blockIdx.x] = carry;
 }
 
-template <int ITEMS>
+template <bool PAIR>
+struct RadixVal { typedef uint32_t T; };
+template <>
+struct RadixVal<true> { typedef uint2 T; };
+
+template <int ITEMS, bool PAIR>
 __global__ void __launch_bounds__(kRadixThreads) radix_downsweep_kernel(RadixPass p) {
+  typedef typename RadixVal<PAIR>::T Val;
   constexpr int kWaves = kRadixThreads / 64;
   constexpr int kTile = kRadixThreads * ITEMS;
   constexpr int kPerWave = kTile / kWaves;   // contiguous items of one wave
   __shared__ uint32_t sk[kTile];
-  __shared__ uint32_t sv[kTile];
+  __shared__ Val sv[kTile];
   __shared__ uint32_t cnt[kWaves][256];   // per-wave digit counts, then each wave's base within its digit
   __shared__ uint32_t dstart[256];        // block-local start of each digit
   __shared__ uint32_t gstart[256];        // global position of the block's first item of each digit
@@ -139,7 +147,8 @@ __global__ void __launch_bounds__(kRadixThreads) radix_downsweep_kernel(RadixPas
   if (base >= n) return;   // whole block
   for (int d = lane; d < 256; d += 64) cnt[w][d] = 0u;
   radix_wave_fence();
-  uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+  uint32_t key[ITEMS], rank[ITEMS];
+  Val val[ITEMS];
   uint32_t validmask = 0;
   const uint64_t wbase = base + (uint64_t)w * kPerWave;
 #pragma unroll
@@ -147,7 +156,12 @@ __global__ void __launch_bounds__(kRadixThreads) radix_downsweep_kernel(RadixPas
     const uint64_t i = wbase + (uint64_t)r * 64 + lane;
     const bool in = i < n;
     key[r] = in ? p.keys_in[i] : kNoKey;
-    val[r] = in ? (p.vals_in ? p.vals_in[i] : (uint32_t)i) : 0u;
+    if constexpr (PAIR) {
+      val[r] = !in ? make_uint2(0u, 0u)
+                   : (p.pvals_in ? p.pvals_in[i] : make_uint2(p.vals_in ? p.vals_in[i] : (uint32_t)i, (uint32_t)i));
+    } else {
+      val[r] = in ? (p.vals_in ? p.vals_in[i] : (uint32_t)i) : 0u;
+    }
     validmask |= (in && !(p.filter && key[r] == kNoKey)) ? (1u << r) : 0u;
   }
 #pragma unroll
@@ -207,11 +221,12 @@ __global__ void __launch_bounds__(kRadixThreads) radix_downsweep_kernel(RadixPas
     const uint32_t dg = radix_digit(p, k);
     const uint32_t dst = gstart[dg] + (j - dstart[dg]);
     p.keys_out[dst] = k;
-    p.vals_out[dst] = sv[j];
+    if constexpr (PAIR) p.pvals_out[dst] = sv[j];
+    else p.vals_out[dst] = sv[j];
   }
 }
 
-template <int ITEMS>
+template <int ITEMS, bool PAIR>
 hipError_t launch_radix_pass_t(const RadixPass& p, hipStream_t stream) {
   hipLaunchKernelGGL(radix_upsweep_kernel<ITEMS>, dim3(p.nblocks), dim3(kRadixThreads), 0, stream, p);
   hipError_t e = hipGetLastError();
@@ -219,15 +234,15 @@ hipError_t launch_radix_pass_t(const RadixPass& p, hipStream_t stream) {
   hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(kRadixThreads), 0, stream, p);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(radix_downsweep_kernel<ITEMS>, dim3(p.nblocks), dim3(kRadixThreads), 0, stream, p);
+  hipLaunchKernelGGL((radix_downsweep_kernel<ITEMS, PAIR>), dim3(p.nblocks), dim3(kRadixThreads), 0, stream, p);
   return hipGetLastError();
 }
 
 hipError_t launch_radix_pass(const RadixPass& p, hipStream_t stream) {
   if (p.nblocks == 0) return hipSuccess;
   if (p.bits < 1 || p.bits > 8) return hipErrorInvalidValue;
-  if (p.items == kRadixItemsLarge) return launch_radix_pass_t<kRadixItemsLarge>(p, stream);
-  if (p.items == kRadixItemsSmall) return launch_radix_pass_t<kRadixItemsSmall>(p, stream);
+  if (p.items == kRadixItemsPair && p.pair) return launch_radix_pass_t<kRadixItemsPair, true>(p, stream);
+  if (p.items == kRadixItemsDepth && !p.pair) return launch_radix_pass_t<kRadixItemsDepth, false>(p, stream);
   return hipErrorInvalidValue;
 }
 

@@ -68,7 +68,7 @@ __device__ __forceinline__ int64_t ordered_tile(int64_t blk, const uint32_t* gro
 
 template <int FALLOFF>
 __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* __restrict__ db,
-                                                            const uint32_t* __restrict__ sorted_ids,
+                                                            const uint2* __restrict__ sorted_pairs,
                                                             int64_t total_tiles,
                                                             uint64_t capacity) {
   __shared__ float4 sA[64], sB[64], sC[64];
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
     if (!__any(alive != 0)) break;
     const int cnt = min(64, n - base);
     if (lane < cnt) {
-      const uint32_t id = sorted_ids[rg.x + base + lane];
+      const uint32_t id = sorted_pairs[rg.x + base + lane].x;
       const float4 a = rec_load(rec, 4 * (size_t)id);
       const float4 b = rec_load(rec, 4 * (size_t)id + 1);
       const float4 c = rec_load(rec, 4 * (size_t)id + 2);
@@ -229,11 +229,11 @@ constexpr int kFlush = 32;   // splats whose row partials are parked in LDS befo
 
 template <int FALLOFF>
 __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* __restrict__ db,
-                                                             const uint32_t* __restrict__ sorted_ids,
+                                                             const uint2* __restrict__ sorted_pairs,
                                                              int64_t total_tiles, int ordered) {
   __shared__ float4 sA[64], sB[64], sC[64];
-  __shared__ float sRed[kFlush][4][10];   // [splat slot][lane row][component]
-  __shared__ uint32_t sId[kFlush];
+  __shared__ float sRed[kFlush][4][10];   // [parked splat][lane row][component]
+  __shared__ uint32_t sSlot[kFlush];      // the parked splat's slot: its row of this tile's sums
   const int64_t gt = ordered ? ordered_tile(blockIdx.x, db->views[0].group_order, total_tiles) : xcd_tile(blockIdx.x);
   if (gt < 0 || gt >= total_tiles) return;
   const int v = view_of_block(db->tile_prefix, db->nviews, gt);
@@ -273,21 +273,22 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, off, 64));
   const uint2 rg = V.ranges[lt];
   const GlobalRec* rec = (const GlobalRec*)(V.rec);
-  // global address space: the accumulation atomics then count only against vmcnt, and the LDS waits of the
-  // following splats do not wait for them (flat atomics count against lgkmcnt too)
-  GlobalF64* grad2d = (GlobalF64*)(V.grad2d);
+  // global address space: the row stores then count only against vmcnt, and the LDS waits of the following
+  // splats do not wait for them (flat stores count against lgkmcnt too)
+  GlobalVec4* rows = (GlobalVec4*)(V.grad_rows);
+  GlobalU32* bits = (GlobalU32*)(V.grad_bits);
   int nslot = 0;
   for (int hi = (int)maxlast; hi > 0; hi -= 64) {
     const int lo = max(0, hi - 64);
     const int cnt = hi - lo;
     if (lane < cnt) {
-      const uint32_t id = sorted_ids[rg.x + lo + lane];
-      const float4 a = rec_load(rec, 4 * (size_t)id);
-      const float4 b = rec_load(rec, 4 * (size_t)id + 1);
-      const float4 c = rec_load(rec, 4 * (size_t)id + 2);
+      const uint2 pr = sorted_pairs[rg.x + lo + lane];   // (splat index, slot)
+      const float4 a = rec_load(rec, 4 * (size_t)pr.x);
+      const float4 b = rec_load(rec, 4 * (size_t)pr.x + 1);
+      const float4 c = rec_load(rec, 4 * (size_t)pr.x + 2);
       sA[lane] = make_float4(a.x, a.y, a.z, a.w);
       sB[lane] = b;
-      sC[lane] = make_float4(c.x, c.y, c.z, __uint_as_float(id));
+      sC[lane] = make_float4(c.x, c.y, c.z, __uint_as_float(pr.y));
     }
     __syncthreads();
     for (int j = cnt - 1; j >= 0; --j) {
@@ -372,14 +373,15 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
           d[8] = r8;
           d[9] = FALLOFF == GES_FALLOFF_GEF ? (-0.25f * 0.69314718055994531f * B.z) * r9 : 0.f;
         }
-        if (lane == 0) sId[nslot] = __float_as_uint(Cc.w);
+        if (lane == 0) sSlot[nslot] = __float_as_uint(Cc.w);
         ++nslot;
       }
       if (nslot == kFlush || (j == 0 && hi - 64 <= 0 && nslot > 0)) {
-        // one lane per parked splat: add the four row sums, then one float64 atomic per component
+        // one lane per parked splat: add the four row sums and store the tile's sums of the splat in the row
+        // of its slot (the row reduction adds a splat's rows in slot order), marking the slot
         __syncthreads();
-        if (lane < nslot) {   // slots 0 .. nslot-1 hold row partials
-          const uint32_t id = sId[lane];
+        if (lane < nslot) {   // entries 0 .. nslot-1 hold row partials
+          const uint32_t slot = sSlot[lane];
           float val[10];
 #pragma unroll
           for (int c = 0; c < 10; ++c)
@@ -387,11 +389,16 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
           val[0] = 2.f * val[0];   // dL/du = 2 sum dq (a dx + b dy)
           val[1] = 2.f * val[1];   // dL/dv = 2 sum dq (b dx + c dy)
           val[3] = 2.f * val[3];   // dL/db = 2 sum dq dx dy
-          GlobalF64* dst = grad2d + (size_t)id * kGradStride;
-          constexpr int ncomp = FALLOFF == GES_FALLOFF_GEF ? 10 : 9;
-#pragma unroll
-          for (int c = 0; c < ncomp; ++c)
-            if (val[c] != 0.f) __hip_atomic_fetch_add(dst + c, (double)val[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (FALLOFF != GES_FALLOFF_GEF) val[9] = 0.f;
+          GlobalVec4* r = rows + (size_t)slot * (kRowFloats / 4);
+          Vec4 v0, v1, v2;
+          v0[0] = val[0]; v0[1] = val[1]; v0[2] = val[2]; v0[3] = val[3];
+          v1[0] = val[4]; v1[1] = val[5]; v1[2] = val[6]; v1[3] = val[7];
+          v2[0] = val[8]; v2[1] = val[9]; v2[2] = 0.f; v2[3] = 0.f;
+          r[0] = v0;
+          r[1] = v1;
+          r[2] = v2;
+          __hip_atomic_fetch_or(bits + (slot >> 5), 1u << (slot & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
         nslot = 0;
@@ -479,10 +486,10 @@ hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipS
   const dim3 grid((unsigned)((b.total_tiles + span - 1) / span * span));
   // every view of a batch shares the falloff (the server fixes it per instance)
   if (b.falloff != GES_FALLOFF_GEF)   // Gaussian falloff (PHI, PHI_EXACT)
-    hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_PHI>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
+    hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_PHI>, grid, dim3(64), 0, stream, dbatch, b.sorted_pairs,
                        b.total_tiles, b.key_capacity);
   else
-    hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_GEF>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
+    hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_GEF>, grid, dim3(64), 0, stream, dbatch, b.sorted_pairs,
                        b.total_tiles, b.key_capacity);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -496,10 +503,10 @@ hipError_t launch_raster_backward(const DeviceBatch* dbatch, const Batch& b, hip
   const int64_t span = 8 * kXcdGroup;   // the grid covers whole rounds of groups
   const dim3 grid((unsigned)((b.total_tiles + span - 1) / span * span));
   if (b.falloff != GES_FALLOFF_GEF)
-    hipLaunchKernelGGL(raster_backward_kernel<GES_FALLOFF_PHI>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
+    hipLaunchKernelGGL(raster_backward_kernel<GES_FALLOFF_PHI>, grid, dim3(64), 0, stream, dbatch, b.sorted_pairs,
                        b.total_tiles, ordered);
   else
-    hipLaunchKernelGGL(raster_backward_kernel<GES_FALLOFF_GEF>, grid, dim3(64), 0, stream, dbatch, b.sorted_ids,
+    hipLaunchKernelGGL(raster_backward_kernel<GES_FALLOFF_GEF>, grid, dim3(64), 0, stream, dbatch, b.sorted_pairs,
                        b.total_tiles, ordered);
   return hipGetLastError();
 }

@@ -173,7 +173,7 @@ ServeInspectLayout serve_inspect_layout(int64_t n, int32_t w, int32_t h, uint64_
   L.off_n_contrib = L.off_ranges + align256(8 * tiles);
   L.off_header = L.off_n_contrib + align256(4 * (size_t)w * (size_t)h);
   L.off_ids = L.off_header + 256;
-  L.bytes = L.off_ids + align256(4 * (size_t)batch_keys);
+  L.bytes = L.off_ids + align256(8 * (size_t)batch_keys);
   return L;
 }
 
@@ -242,7 +242,7 @@ class GpuExecutor : public Executor {
       if (e == hipSuccess) e = hipMemcpyAsync(dst + L.off_ranges, V.ranges, 8 * (size_t)tiles, hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess) e = hipMemcpyAsync(dst + L.off_header, V.header, 32, hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess && b.keys > 0 && L.bytes <= b.inspect[(size_t)v].second)
-        e = hipMemcpyAsync(dst + L.off_ids, bt.sorted_ids, 4 * (size_t)b.keys, hipMemcpyDeviceToDevice, st);
+        e = hipMemcpyAsync(dst + L.off_ids, bt.sorted_pairs, 8 * (size_t)b.keys, hipMemcpyDeviceToDevice, st);
     }
     if (e == hipSuccess && !b.done) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(b.done, st);
@@ -274,8 +274,8 @@ class GpuExecutor : public Executor {
     bt.tile_passes = tile_passes(bt.total_tiles);
     bt.dup_buffer = bt.tile_passes & 1;
     if (b.has_keys && b.keys > 0) {
-      bt.kw = attach_key_ws(plan_keys(b.keys, bt.total_tiles), pool + b.key_off);
-      bt.sorted_ids = bt.kw.val[0];
+      bt.kw = attach_key_ws(plan_keys(b.keys, false), pool + b.key_off);
+      bt.sorted_pairs = bt.kw.pv[0];
       bt.sorted_tiles = bt.kw.key[0];
       bt.key_capacity = b.keys;
     }
@@ -459,7 +459,7 @@ void worker_loop(ges_server* s) {
     // ---- 3. key buffer under the budget: wait for older batches, then give back the newest views
     bool placed = false;
     for (;;) {
-      const size_t kb = plan_keys(b.keys, batch_tiles(b)).bytes;
+      const size_t kb = plan_keys(b.keys, false).bytes;
       if (b.keys == 0 || s->alloc->alloc(kb, &b.key_off)) {
         b.key_bytes = kb;
         b.has_keys = b.keys > 0;

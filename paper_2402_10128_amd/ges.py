@@ -43,7 +43,8 @@ class ges_camera(C.Structure):
 
 
 class ges_raster_params(C.Structure):
-    _fields_ = [("falloff", C.c_int32), ("tile_cull", C.c_int32), ("rho", C.c_float), ("bg", C.c_float * 3)]
+    _fields_ = [("falloff", C.c_int32), ("tile_cull", C.c_int32), ("rho", C.c_float), ("bg", C.c_float * 3),
+                ("flags", C.c_uint32)]
 
 
 class ges_splat_grads(C.Structure):
@@ -51,10 +52,10 @@ class ges_splat_grads(C.Structure):
 
 
 class ges_frame_view(C.Structure):
-    _fields_ = [("records", C.c_void_p), ("tile_ranges", C.c_void_p), ("sorted_ids", C.c_void_p),
+    _fields_ = [("records", C.c_void_p), ("tile_ranges", C.c_void_p), ("sorted_pairs", C.c_void_p),
                 ("sorted_tiles", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
                 ("grad2d", C.c_void_p), ("stats", C.c_void_p), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
-                ("tile_work", C.c_void_p), ("group_order", C.c_void_p)]
+                ("tile_work", C.c_void_p), ("group_order", C.c_void_p), ("row_marks", C.c_void_p)]
 
 
 class ges_serve_config(C.Structure):
@@ -190,10 +191,14 @@ def camera_struct(cam) -> ges_camera:
     return c
 
 
-def params_struct(falloff=FALLOFF_PHI, tile_cull=TILES_SQUARE, rho=0.1, bg=(0.0, 0.0, 0.0)) -> ges_raster_params:
+RASTER_KEEP_GRAD2D = 1
+
+
+def params_struct(falloff=FALLOFF_PHI, tile_cull=TILES_SQUARE, rho=0.1, bg=(0.0, 0.0, 0.0), flags=0) -> ges_raster_params:
     p = ges_raster_params()
     p.falloff, p.tile_cull, p.rho = int(falloff), int(tile_cull), float(rho)
     p.bg[:] = [float(b) for b in bg]
+    p.flags = int(flags)
     return p
 
 
@@ -258,7 +263,7 @@ def ges_frame_view_get(n, width, height, splat_ws, key_ws, num_keys, pixel_ws) -
 
 
 STAGES = ["preprocess", "depth_sort", "key_scan", "duplicate", "tile_sort", "raster_forward", "raster_backward",
-          "preprocess_backward", "zero", "loss", "adam", "ssim", "mix_fit"]
+          "preprocess_backward", "zero", "loss", "adam", "ssim", "mix_fit", "row_reduce"]
 
 
 def ges_profile_enable(on: bool):
@@ -512,8 +517,12 @@ def frame_arrays(frame: Frame, n: int) -> dict:
     out["group_order"] = sl(v.group_order, 4 * ((T + 7) // 8), ws).view(torch.int32).cpu().numpy().view(np.uint32)
     if frame.key_ws is not None and frame.num_keys > 0:
         K = min(out["keys"], frame.num_keys)
-        out["sorted_ids"] = sl(v.sorted_ids, 4 * K, frame.key_ws).view(torch.int32).cpu().numpy().view(np.uint32)
+        pairs = sl(v.sorted_pairs, 8 * K, frame.key_ws).view(torch.int32).reshape(K, 2).cpu().numpy().view(np.uint32)
+        out["sorted_ids"] = pairs[:, 0].copy()
+        out["sorted_slots"] = pairs[:, 1].copy()
         out["sorted_tiles"] = sl(v.sorted_tiles, 4 * K, frame.key_ws).view(torch.int32).cpu().numpy().view(np.uint32)
+        marks = sl(v.row_marks, 4 * ((frame.num_keys + 31) // 32), frame.key_ws).cpu().numpy()
+        out["rows_stored"] = int(np.unpackbits(marks).sum())
     px = frame.width * frame.height
     out["final_T"] = sl(v.final_T, 4 * px, frame.pixel_ws).view(torch.float32).reshape(frame.height, frame.width).cpu().numpy()
     out["n_contrib"] = sl(v.n_contrib, 4 * px, frame.pixel_ws).view(torch.int32).reshape(

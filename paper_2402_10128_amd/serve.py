@@ -149,6 +149,6 @@ def inspect_arrays(buf, n: int, width: int, height: int, batch_keys: int) -> dic
                ranges=b[off_ranges:off_ranges + 8 * tiles].view(np.uint32).reshape(tiles, 2),
                n_contrib=b[off_nc:off_nc + 4 * px].view(np.uint32).reshape(height, width),
                header=b[off_hdr:off_hdr + 32].view(np.uint64))
-    if b.size >= off_ids + 4 * batch_keys:
-        out["ids"] = b[off_ids:off_ids + 4 * batch_keys].view(np.uint32)
+    if b.size >= off_ids + 8 * batch_keys:
+        out["ids"] = b[off_ids:off_ids + 8 * batch_keys].view(np.uint32).reshape(batch_keys, 2)[:, 0]
     return out

@@ -40,7 +40,7 @@ def gpu_render(arrays, sh_degree, cam, falloff=0, tile_cull=0, rho=0.1, bg=(0.0,
     sc = to_device(arrays)
     s = G.splats_struct(sc["means"], sc["log_scales"], sc["quats"], sc["opacity_logits"], sc["sh"], sc["beta"])
     c = G.camera_struct(cam)
-    p = G.params_struct(falloff, tile_cull, rho, bg)
+    p = G.params_struct(falloff, tile_cull, rho, bg, flags=G.RASTER_KEEP_GRAD2D)
     frame = G.Frame.create(s.n, c.width, c.height)
     k = G.ges_preprocess(s, c, p, frame.splat_ws, True)
     frame.ensure_keys(k)

@@ -171,6 +171,20 @@ def test_forward_is_deterministic():
     assert np.array_equal(a["sorted_ids"], b["sorted_ids"])
 
 
+@pytest.mark.parametrize("falloff", [O.FALLOFF_PHI, O.FALLOFF_GEF], ids=["phi", "gef"])
+def test_backward_is_deterministic(falloff):
+    """The backward pass stores each (tile, splat) sum at the pair's slot and every splat adds its rows in slot
+    order, so two runs give the same bits: 2-D gradients and every parameter gradient (Sec. 4.4)."""
+    sc, cam = _inputs(1, 20000, 200, 136)
+    dL = np.random.default_rng(3).standard_normal((cam.height, cam.width, 3)).astype(np.float32)
+    a = gpu_render(sc.arrays(), 3, cam, falloff, O.TILES_ELLIPSE, dL=dL)
+    b = gpu_render(sc.arrays(), 3, cam, falloff, O.TILES_ELLIPSE, dL=dL)
+    assert np.array_equal(a["grad2d"], b["grad2d"])
+    for k in a["grads"]:
+        assert np.array_equal(a["grads"][k], b["grads"][k]), k
+    assert np.abs(a["grad2d"]).sum() > 0
+
+
 @pytest.mark.parametrize("rho", [0.01, 0.05, 0.15], ids=["rho001", "rho005", "rho015"])
 def test_parity_across_shape_strength(rho):
     """The shape strength rho of the approximate modification phi_rho(beta) (Sec. 4.2, Eq. approx; the paper's

@@ -144,7 +144,7 @@ def test_inspection_submit_validates_its_buffer():
     before the request is queued."""
     n, w, h = 10_000, 256, 256
     a = lambda x: (x + 255) // 256 * 256
-    want = a(64 * n) + a(8 * 256) + a(4 * w * h) + 256 + a(4 * 1000)
+    want = a(64 * n) + a(8 * 256) + a(4 * w * h) + 256 + a(8 * 1000)
     assert G.lib().ges_serve_inspect_bytes(n, w, h, 1000) == want
     assert G.lib().ges_serve_inspect_bytes(n, 0, h, 0) == 0
 
