@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define GES_ABI_VERSION 3u
+#define GES_ABI_VERSION 4u
 #define GES_TILE 16
 #define GES_GRAD2D_STRIDE 12   /* binary64 slots per splat in the 2-D gradient rows */
 
@@ -328,6 +328,50 @@ ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* 
                                     void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
                                     const ges_splat_grads* grads, const ges_adam_splats* opt, void* stream);
 
+/* ---- several views of one scene per launch (multi-view optimisation steps) -----------------
+ * A step that fits the splats to B camera views (App. B.2 trains Gaussian-splatting style, view by view;
+ * these calls take B of the views at once) renders and back-propagates them through one launch sequence:
+ * the B x n (view, splat) items are preprocessed together, sorted by depth together (ties by view, then
+ * splat index), binned into the B x tiles batch tiles, sorted by batch tile and rasterised in shared
+ * launches, and the preprocess backward chains every splat through the B views in view order.  Every view
+ * gives exactly (bit for bit) what the single-view calls give for it, and the summed gradients are those of
+ * the single-view backward of view 0 followed by ges_render_backward_accumulate of views 1..B-1.
+ * All views have one width and height; 1 <= num_views <= 64 and num_views x n < 2^31 (INVALID_ARGUMENT
+ * otherwise).  cams: [num_views] host array.  Image arrays (out_rgb, dL_drgb) are [num_views,height,width,3]
+ * FP32.  The workspaces come from ges_views_workspace_query (splat_ws: the single-view layout of each view
+ * one after another, then the binning buffers of all items; pixel_ws: the views' pixel workspaces one after
+ * another) and ges_key_workspace_query with the slot count ges_preprocess_views returns (the sum over the
+ * views).  num_views = 1 is the single-view layout and behaviour.  Errors as for the single-view calls. */
+ges_status ges_views_workspace_query(int64_t n, int32_t num_views, int32_t width, int32_t height,
+                                     size_t* splat_ws_bytes, size_t* pixel_ws_bytes);
+ges_status ges_preprocess_views(const ges_splats* splats, const ges_camera* cams, int32_t num_views,
+                                const ges_raster_params* params, void* splat_ws, size_t splat_ws_bytes,
+                                uint64_t* num_keys_host, void* stream);
+ges_status ges_render_forward_views(const ges_splats* splats, const ges_camera* cams, int32_t num_views,
+                                    const ges_raster_params* params, void* splat_ws, void* key_ws,
+                                    size_t key_ws_bytes, uint64_t num_keys, void* pixel_ws, float* out_rgb,
+                                    void* stream);
+/* Sum over the views of the parameter gradients, written to (accumulate = 0) or added to (accumulate != 0)
+ * `grads`; grad_accum / grad_count as for ges_render_backward_accumulate (every view adds to them). */
+ges_status ges_render_backward_views(const ges_splats* splats, const ges_camera* cams, int32_t num_views,
+                                     const ges_raster_params* params, void* splat_ws, void* key_ws, void* pixel_ws,
+                                     const float* dL_drgb, const ges_splat_grads* grads, int32_t accumulate,
+                                     float* grad_accum, float* grad_count, void* stream);
+/* The fused optimiser step of ges_render_backward_adam over the views' summed gradients.  With more than
+ * one view every member of `grads` is required (it receives the summed gradients; the update reads the
+ * earlier views' sum from it) and opt->grads_in must be NULL.  Parameters and moments are bit-identical to
+ * the single-view sequence (view 0: ges_render_backward, views 1..B-2: ges_render_backward_accumulate, view
+ * B-1: ges_render_backward_adam with grads_in = that sum). */
+ges_status ges_render_backward_views_adam(const ges_splats* splats, const ges_camera* cams, int32_t num_views,
+                                          const ges_raster_params* params, void* splat_ws, void* key_ws,
+                                          void* pixel_ws, const float* dL_drgb, const ges_splat_grads* grads,
+                                          const ges_adam_splats* opt, void* stream);
+/* ges_frame_view_get of view `view` (0 <= view < num_views) of a multi-view step; sorted_pairs and
+ * sorted_tiles cover the whole batch (tile t of view v is batch tile v x tiles + t). */
+ges_status ges_frame_view_get_views(int64_t n, int32_t num_views, int32_t width, int32_t height, void* splat_ws,
+                                    void* key_ws, uint64_t num_keys, void* pixel_ws, int32_t view,
+                                    ges_frame_view* out);
+
 /* ---- shape/opacity pruning and shape reset (Sec. 4.4, Sec. 5.2, App. B.2) --------
  * The paper prunes splats on their shape every 100 iterations (threshold 0.5 in Sec. 5.2,
  * 0.005 in App. B.2), keeps the opacity pruning of Gaussian splatting (0.005) and resets
@@ -429,6 +473,14 @@ ges_status ges_opacity_reset(float* opacity_logits, float* exp_avg, float* exp_a
  * lr_final <= 0 or max_steps < 1. */
 double ges_expon_lr(int64_t step, double lr_init, double lr_final, int64_t max_steps, int64_t delay_steps,
                     double delay_mult);
+
+/* Loss schedule of an iteration (host function): the frequency-mask strength omega grows linearly with
+ * training progress, omega = iteration / total_iterations clamped to [0, 1] (Sec. 4.3), and the L1 weight
+ * is what the SSIM and masked-L1 weights leave, lam_l1 = 1 - lam_ssim - lam_omega (Sec. 4.4, Eq. final;
+ * the paper uses lam_ssim = 0.2, lam_omega = 0.5).  Both in binary64, rounded once to binary32.  Either
+ * output may be NULL.  INVALID_ARGUMENT for total_iterations < 1 or non-finite weights. */
+ges_status ges_loss_schedule(int64_t iteration, int64_t total_iterations, float lam_ssim, float lam_omega,
+                             float* omega, float* lam_l1);
 
 /* ---- serving: continuous batching of render requests -----------------------------
  * Forward renders (Sec. 4.2, Eq. transimttance, the same kernels as ges_render_forward)

@@ -79,57 +79,61 @@ hipError_t timed(int stage, hipStream_t stream, F&& launch) {
   return hipSuccess;
 }
 
-// Build the single-view batch of a frame and copy it into the splat workspace.
-hipError_t upload_single_view(const ges_splats* s, const ges_camera* c, const ges_raster_params* p,
-                              const ges::FramePlan& fp, void* splat_ws, void* pixel_ws, float* out_rgb,
-                              const float* dL_drgb, hipStream_t stream, void* key_ws = nullptr,
-                              uint64_t key_slots = 0) {
+// Build the batch of a step's views (one scene, one resolution) and copy it into the splat workspace.
+hipError_t upload_views(const ges_splats* s, const ges_camera* cams, int32_t nv, const ges_raster_params* p,
+                        const ges::ViewsPlan& vp, void* splat_ws, void* pixel_ws, float* out_rgb,
+                        const float* dL_drgb, hipStream_t stream, void* key_ws = nullptr, uint64_t key_slots = 0) {
   ges::DeviceBatch& hb = g_host_batch;
-  hb.nviews = 1;
-  hb.pre_prefix[0] = 0;
-  hb.pre_prefix[1] = (s->n + 255) / 256;
-  hb.item_prefix[0] = 0;
-  hb.item_prefix[1] = s->n;
-  hb.tile_prefix[0] = 0;
-  hb.tile_prefix[1] = fp.tiles;
-  ges::ViewDesc& V = hb.views[0];
-  ges::fill_view(V, s, c, p);
-  ges::attach_splat_ws(V, fp, splat_ws);
-  const ges::SortWs sw = ges::attach_sort_ws(ges::plan_sort(s->n), reinterpret_cast<char*>(splat_ws) + fp.off_sort);
-  V.item_key = sw.item_key;
-  V.item_cand = sw.item_cand;
-  if (pixel_ws) {
-    char* pw = reinterpret_cast<char*>(pixel_ws);
-    V.final_T = reinterpret_cast<float*>(pw + fp.off_final_T);
-    V.n_contrib = reinterpret_cast<uint32_t*>(pw + fp.off_n_contrib);
+  const ges::FramePlan& fp = vp.fp;
+  const int64_t pre = (s->n + 255) / 256;
+  const size_t px3 = (size_t)3 * cams[0].width * cams[0].height;
+  hb.nviews = nv;
+  for (int32_t v = 0; v <= nv; ++v) {
+    hb.pre_prefix[v] = v * pre;
+    hb.item_prefix[v] = v * s->n;
+    hb.tile_prefix[v] = v * fp.tiles;
   }
-  V.out_rgb = out_rgb;
-  V.dL_drgb = dL_drgb;
-  if (key_ws && key_slots) {   // the backward's rows of per-(tile, splat) sums
-    const ges::KeyPlan kp = ges::plan_keys(key_slots, true);
-    char* kw = reinterpret_cast<char*>(key_ws);
-    V.sorted_pairs = reinterpret_cast<const uint2*>(kw + kp.off_pv0);
-    V.grad_rows = reinterpret_cast<float*>(kw + kp.off_rows);
-    V.grad_bits = reinterpret_cast<uint32_t*>(kw + kp.off_bits);
-    V.grad_slots = key_slots;
+  char* sw_base = reinterpret_cast<char*>(splat_ws);
+  const ges::SortWs sw = ges::attach_sort_ws(ges::plan_sort((int64_t)nv * s->n), sw_base + vp.off_sort);
+  for (int32_t v = 0; v < nv; ++v) {
+    ges::ViewDesc& V = hb.views[v];
+    ges::fill_view(V, s, &cams[v], p);
+    ges::attach_splat_ws(V, fp, sw_base + (size_t)v * vp.view_stride);
+    V.item_key = sw.item_key + (size_t)v * s->n;
+    V.item_cand = sw.item_cand + (size_t)v * s->n;
+    if (pixel_ws) {
+      char* pw = reinterpret_cast<char*>(pixel_ws) + (size_t)v * fp.pixel_bytes;
+      V.final_T = reinterpret_cast<float*>(pw + fp.off_final_T);
+      V.n_contrib = reinterpret_cast<uint32_t*>(pw + fp.off_n_contrib);
+    }
+    V.out_rgb = out_rgb ? out_rgb + v * px3 : nullptr;
+    V.dL_drgb = dL_drgb ? dL_drgb + v * px3 : nullptr;
+    if (key_ws && key_slots) {   // the backward's rows of per-(tile, splat) sums (one slot space per batch)
+      const ges::KeyPlan kp = ges::plan_keys(key_slots, true);
+      char* kw = reinterpret_cast<char*>(key_ws);
+      V.sorted_pairs = reinterpret_cast<const uint2*>(kw + kp.off_pv0);
+      V.grad_rows = reinterpret_cast<float*>(kw + kp.off_rows);
+      V.grad_bits = reinterpret_cast<uint32_t*>(kw + kp.off_bits);
+      V.grad_slots = key_slots;
+    }
+    V.keep_grad2d = (p->flags & GES_RASTER_KEEP_GRAD2D) ? 1 : 0;
   }
-  V.keep_grad2d = (p->flags & GES_RASTER_KEEP_GRAD2D) ? 1 : 0;
-  void* dst = reinterpret_cast<char*>(splat_ws) + fp.off_db;
-  return hipMemcpyAsync(dst, &hb, ges::device_batch_bytes(1), hipMemcpyHostToDevice, stream);
+  return hipMemcpyAsync(sw_base + fp.off_db, &hb, ges::device_batch_bytes(nv), hipMemcpyHostToDevice, stream);
 }
 
-ges::Batch single_batch(const ges_splats* s, const ges_raster_params* p, const ges::FramePlan& fp, void* splat_ws) {
+ges::Batch views_batch(const ges_splats* s, const ges_raster_params* p, const ges::ViewsPlan& vp, void* splat_ws) {
   ges::Batch b{};
-  b.nviews = 1;
+  b.nviews = vp.views;
   b.falloff = p->falloff;
-  b.total_tiles = fp.tiles;
+  b.total_tiles = vp.views * vp.fp.tiles;
   b.tile_cull = p->tile_cull;
-  b.pre_blocks = (s->n + 255) / 256;
-  b.items = s->n;
-  b.sw = ges::attach_sort_ws(ges::plan_sort(s->n), reinterpret_cast<char*>(splat_ws) + fp.off_sort);
+  b.pre_blocks = vp.views * ((s->n + 255) / 256);
+  b.items = vp.views * s->n;
+  b.sw = ges::attach_sort_ws(ges::plan_sort(b.items), reinterpret_cast<char*>(splat_ws) + vp.off_sort);
   b.keys_total = &b.sw.cells[1];
-  b.tile_passes = ges::tile_passes(fp.tiles);
+  b.tile_passes = ges::tile_passes(b.total_tiles);
   b.dup_buffer = b.tile_passes & 1;
+  b.shared_scene = 1;
   return b;
 }
 
@@ -144,47 +148,34 @@ std::string check_all(const ges_splats* s, const ges_camera* c, const ges_raster
   return e;
 }
 
-}  // namespace
-
-extern "C" {
-
-uint32_t ges_abi_version(void) { return GES_ABI_VERSION; }
-
-const char* ges_last_error(void) { return g_last_error.c_str(); }
-
-ges_status ges_workspace_query(int64_t n, int32_t width, int32_t height, size_t* splat_ws_bytes,
-                               size_t* pixel_ws_bytes) {
-  if (n < 0 || n >= (int64_t(1) << 31)) return fail(GES_ERR_INVALID_ARGUMENT, "n outside [0, 2^31)");
-  if (width < 1 || height < 1 || width > 16384 || height > 16384)
-    return fail(GES_ERR_INVALID_ARGUMENT, "width/height outside [1,16384]");
-  const ges::FramePlan fp = ges::plan_frame(n, width, height);
-  if (splat_ws_bytes) *splat_ws_bytes = fp.splat_bytes;
-  if (pixel_ws_bytes) *pixel_ws_bytes = fp.pixel_bytes;
-  return GES_OK;
+// The views of one step: 1..kMaxViews cameras of one resolution over one scene.
+std::string check_views(const ges_splats* s, const ges_camera* cams, int32_t nv, const ges_raster_params* p) {
+  if (nv < 1 || nv > ges::kMaxViews) return "num_views outside [1, 64]";
+  if (!cams) return "cams is NULL";
+  std::string e = ges::check_splats(s);
+  if (e.empty()) e = ges::check_params(p);
+  for (int32_t v = 0; v < nv && e.empty(); ++v) {
+    e = ges::check_camera(&cams[v]);
+    if (e.empty() && (cams[v].width != cams[0].width || cams[v].height != cams[0].height))
+      e = "every view of a step must have the same width and height";
+  }
+  if (e.empty() && (int64_t)nv * s->n >= (int64_t(1) << 31)) e = "num_views x n outside [0, 2^31)";
+  return e;
 }
 
-ges_status ges_key_workspace_query(uint64_t num_keys, int64_t n, int32_t width, int32_t height, size_t* key_ws_bytes) {
-  (void)n;
-  if (!key_ws_bytes) return fail(GES_ERR_INVALID_ARGUMENT, "key_ws_bytes is NULL");
-  if (width < 1 || height < 1 || width > 16384 || height > 16384)
-    return fail(GES_ERR_INVALID_ARGUMENT, "width/height outside [1,16384]");
-  if (num_keys >= 0xffffffffull) return fail(GES_ERR_CAPACITY, "more than 2^32-2 keys");
-  *key_ws_bytes = ges::plan_keys(num_keys, true).bytes;
-  return GES_OK;
-}
-
-ges_status ges_preprocess(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
-                          void* splat_ws, size_t splat_ws_bytes, uint64_t* num_keys_host, void* stream_) {
-  const std::string e = check_all(splats, cam, params);
+ges_status preprocess_views(const ges_splats* splats, const ges_camera* cams, int32_t nv,
+                            const ges_raster_params* params, void* splat_ws, size_t splat_ws_bytes,
+                            uint64_t* num_keys_host, void* stream_) {
+  const std::string e = check_views(splats, cams, nv, params);
   if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
   if (!splat_ws) return fail(GES_ERR_INVALID_ARGUMENT, "splat_ws is NULL");
   if (reinterpret_cast<uintptr_t>(splat_ws) & 255u) return fail(GES_ERR_INVALID_ARGUMENT, "splat_ws must be 256-byte aligned");
-  const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
-  if (splat_ws_bytes < fp.splat_bytes) return fail(GES_ERR_CAPACITY, "splat workspace too small");
+  const ges::ViewsPlan vp = ges::plan_views(splats->n, nv, cams[0].width, cams[0].height);
+  if (splat_ws_bytes < vp.splat_bytes) return fail(GES_ERR_CAPACITY, "splat workspace too small");
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-  GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, nullptr, nullptr, nullptr, stream), "upload");
-  ges::Batch b = single_batch(splats, params, fp, splat_ws);
-  const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
+  GES_CHECK_HIP(upload_views(splats, cams, nv, params, vp, splat_ws, nullptr, nullptr, nullptr, stream), "upload");
+  ges::Batch b = views_batch(splats, params, vp, splat_ws);
+  const ges::DeviceBatch* db = dev_batch(splat_ws, vp.fp);
   GES_CHECK_HIP(timed(GES_STAGE_PREPROCESS, stream, [&] { return ges::launch_preprocess(db, b, stream); }), "preprocess");
   GES_CHECK_HIP(timed(GES_STAGE_DEPTH_SORT, stream, [&] { return ges::launch_depth_sort(db, b, stream); }), "depth_sort");
   GES_CHECK_HIP(timed(GES_STAGE_KEY_SCAN, stream, [&] { return ges::launch_key_scan(db, b, stream); }), "key_scan");
@@ -192,22 +183,22 @@ ges_status ges_preprocess(const ges_splats* splats, const ges_camera* cam, const
     uint32_t k = 0;
     GES_CHECK_HIP(hipMemcpyAsync(&k, b.keys_total, 4, hipMemcpyDeviceToHost, stream), "read num_keys");
     GES_CHECK_HIP(hipStreamSynchronize(stream), "sync");
-    if (k == 0xffffffffu) return fail(GES_ERR_CAPACITY, "more than 2^32-2 candidate (tile, splat) pairs in one frame");
+    if (k == 0xffffffffu) return fail(GES_ERR_CAPACITY, "more than 2^32-2 candidate (tile, splat) pairs in one step");
     *num_keys_host = k;
   }
   return GES_OK;
 }
 
-ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
-                              void* splat_ws, void* key_ws, size_t key_ws_bytes, uint64_t num_keys, void* pixel_ws,
-                              float* out_rgb, void* stream_) {
-  const std::string e = check_all(splats, cam, params);
+ges_status render_forward_views(const ges_splats* splats, const ges_camera* cams, int32_t nv,
+                                const ges_raster_params* params, void* splat_ws, void* key_ws, size_t key_ws_bytes,
+                                uint64_t num_keys, void* pixel_ws, float* out_rgb, void* stream_) {
+  const std::string e = check_views(splats, cams, nv, params);
   if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
   if (!splat_ws || !pixel_ws || !out_rgb) return fail(GES_ERR_INVALID_ARGUMENT, "NULL workspace or output");
   if ((reinterpret_cast<uintptr_t>(splat_ws) | reinterpret_cast<uintptr_t>(pixel_ws)) & 255u)
     return fail(GES_ERR_INVALID_ARGUMENT, "workspaces must be 256-byte aligned");
   if (num_keys >= 0xffffffffull) return fail(GES_ERR_CAPACITY, "more than 2^32-2 keys");
-  const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
+  const ges::ViewsPlan vp = ges::plan_views(splats->n, nv, cams[0].width, cams[0].height);
   const ges::KeyPlan kp = ges::plan_keys(num_keys, true);
   if (num_keys > 0 && (!key_ws || key_ws_bytes < kp.bytes)) return fail(GES_ERR_CAPACITY, "key workspace too small");
   if (num_keys > 0 && (reinterpret_cast<uintptr_t>(key_ws) & 255u))
@@ -217,26 +208,26 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
     g_keys_of_frame[splat_ws] = {num_keys > 0 ? key_ws : nullptr, num_keys};
   }
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-  GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, out_rgb, nullptr, stream), "upload");
-  ges::Batch b = single_batch(splats, params, fp, splat_ws);
+  GES_CHECK_HIP(upload_views(splats, cams, nv, params, vp, splat_ws, pixel_ws, out_rgb, nullptr, stream), "upload");
+  ges::Batch b = views_batch(splats, params, vp, splat_ws);
   b.key_capacity = num_keys;
   if (num_keys > 0) {
     b.kw = ges::attach_key_ws(kp, key_ws);
     b.sorted_pairs = b.kw.pv[0];
     b.sorted_tiles = b.kw.key[0];
   }
-  const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
+  const ges::DeviceBatch* db = dev_batch(splat_ws, vp.fp);
   GES_CHECK_HIP(timed(GES_STAGE_DUPLICATE, stream, [&] { return ges::launch_duplicate(db, b, stream); }), "duplicate");
   GES_CHECK_HIP(timed(GES_STAGE_TILE_SORT, stream, [&] { return ges::launch_tile_sort(db, b, stream); }), "tile_sort");
   GES_CHECK_HIP(timed(GES_STAGE_RASTER_FORWARD, stream, [&] { return ges::launch_raster_forward(db, b, stream); }), "raster_forward");
   return GES_OK;
 }
 
-static ges_status render_backward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
-                                  void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
-                                  const ges_splat_grads* grads, const ges::AdamSplats* adam, bool fused,
-                                  void* stream_) {
-  const std::string e = check_all(splats, cam, params);
+ges_status render_backward(const ges_splats* splats, const ges_camera* cams, int32_t nv,
+                           const ges_raster_params* params, void* splat_ws, void* key_ws, void* pixel_ws,
+                           const float* dL_drgb, const ges_splat_grads* grads, const ges::AdamSplats* adam,
+                           bool fused, void* stream_) {
+  const std::string e = check_views(splats, cams, nv, params);
   if (!e.empty()) return fail(GES_ERR_INVALID_ARGUMENT, e);
   if (!splat_ws || !pixel_ws || !dL_drgb || (!grads && !fused)) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
   if ((reinterpret_cast<uintptr_t>(splat_ws) | reinterpret_cast<uintptr_t>(pixel_ws)) & 255u)
@@ -247,7 +238,7 @@ static ges_status render_backward(const ges_splats* splats, const ges_camera* ca
     return fail(GES_ERR_INVALID_ARGUMENT, "grads->quats must be 16-byte aligned");
   if (grads->sh && (splats->sh_degree == 1 || splats->sh_degree == 3) && (reinterpret_cast<uintptr_t>(grads->sh) & 15u))
     return fail(GES_ERR_INVALID_ARGUMENT, "grads->sh must be 16-byte aligned");
-  const ges::FramePlan fp = ges::plan_frame(splats->n, cam->width, cam->height);
+  const ges::ViewsPlan vp = ges::plan_views(splats->n, nv, cams[0].width, cams[0].height);
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
   uint64_t slots = 0;
   {
@@ -258,12 +249,12 @@ static ges_status render_backward(const ges_splats* splats, const ges_camera* ca
       return fail(GES_ERR_INVALID_ARGUMENT, "key_ws differs from the forward pass of this splat workspace");
     slots = it->second.second;
   }
-  GES_CHECK_HIP(upload_single_view(splats, cam, params, fp, splat_ws, pixel_ws, nullptr, dL_drgb, stream, key_ws,
-                                   slots), "upload");
-  ges::Batch b = single_batch(splats, params, fp, splat_ws);
+  GES_CHECK_HIP(upload_views(splats, cams, nv, params, vp, splat_ws, pixel_ws, nullptr, dL_drgb, stream, key_ws,
+                             slots), "upload");
+  ges::Batch b = views_batch(splats, params, vp, splat_ws);
   const ges::KeyPlan kp = ges::plan_keys(slots, true);
   if (slots) b.sorted_pairs = reinterpret_cast<const uint2*>(reinterpret_cast<char*>(key_ws) + kp.off_pv0);
-  const ges::DeviceBatch* db = dev_batch(splat_ws, fp);
+  const ges::DeviceBatch* db = dev_batch(splat_ws, vp.fp);
   if (slots)
     GES_CHECK_HIP(timed(GES_STAGE_ZERO, stream, [&] {
                     return ges::launch_zero(reinterpret_cast<char*>(key_ws) + kp.off_bits, (slots + 31) / 32 * 4,
@@ -283,38 +274,14 @@ static ges_status render_backward(const ges_splats* splats, const ges_camera* ca
   return GES_OK;
 }
 
-ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
-                               void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
-                               const ges_splat_grads* grads, void* stream) {
-  if (!grads) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
-  return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, nullptr, false, stream);
-}
-
-ges_status ges_render_backward_accumulate(const ges_splats* splats, const ges_camera* cam,
-                                          const ges_raster_params* params, void* splat_ws, void* key_ws,
-                                          void* pixel_ws, const float* dL_drgb, const ges_splat_grads* grads,
-                                          float* grad_accum, float* grad_count, void* stream) {
-  if (!grads || !cam) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
-  if ((grad_accum == nullptr) != (grad_count == nullptr))
-    return fail(GES_ERR_INVALID_ARGUMENT, "grad_accum and grad_count go together");
-  ges::AdamSplats a{};
-  a.accumulate = 1;
-  a.stat_accum = grad_accum;
-  a.stat_count = grad_count;
-  a.half_w = 0.5 * (double)cam->width;
-  a.half_h = 0.5 * (double)cam->height;
-  return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, &a, false, stream);
-}
-
-ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
-                                    void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
-                                    const ges_splat_grads* grads, const ges_adam_splats* opt, void* stream) {
+// The optimiser arguments of a fused backward (the Adam update of ges_adam_step).
+ges_status adam_args(const ges_splats* splats, const ges_camera* cam, const ges_adam_splats* opt, ges::AdamSplats& a) {
   if (!opt || !splats) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
   if (opt->step < 1) return fail(GES_ERR_INVALID_ARGUMENT, "step < 1");
   if (!(opt->beta1 >= 0.f && opt->beta1 < 1.f) || !(opt->beta2 >= 0.f && opt->beta2 < 1.f))
     return fail(GES_ERR_INVALID_ARGUMENT, "beta outside [0,1)");
   if (!(opt->eps >= 0.f) || !std::isfinite(opt->eps)) return fail(GES_ERR_INVALID_ARGUMENT, "bad eps");
-  ges::AdamSplats a{};
+  a = ges::AdamSplats{};
   const float* params_in[ges::kNumPar] = {splats->means, splats->log_scales, splats->quats, splats->opacity_logits,
                                           splats->sh, splats->beta};
   const double bc1 = 1.0 - std::pow((double)opt->beta1, (double)opt->step);
@@ -345,20 +312,38 @@ ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* 
   a.half_w = cam ? 0.5 * (double)cam->width : 0.0;
   a.half_h = cam ? 0.5 * (double)cam->height : 0.0;
   for (int k = 0; k < ges::kNumPar; ++k) a.gin[k] = opt->grads_in[k];
-  const bool sh_vec_in = splats->sh_degree == 1 || splats->sh_degree == 3;
   if ((reinterpret_cast<uintptr_t>(a.gin[ges::kParQuats]) & 15u) ||
-      (sh_vec_in && (reinterpret_cast<uintptr_t>(a.gin[ges::kParSh]) & 15u)))
+      (sh_vec && (reinterpret_cast<uintptr_t>(a.gin[ges::kParSh]) & 15u)))
     return fail(GES_ERR_INVALID_ARGUMENT, "grads_in quats/sh must be 16-byte aligned");
-  return render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, &a, true, stream);
+  return GES_OK;
 }
 
-ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* splat_ws, void* key_ws, uint64_t num_keys,
-                              void* pixel_ws, ges_frame_view* out) {
+ges_status backward_views_plain(const ges_splats* splats, const ges_camera* cams, int32_t nv,
+                                const ges_raster_params* params, void* splat_ws, void* key_ws, void* pixel_ws,
+                                const float* dL_drgb, const ges_splat_grads* grads, int32_t accumulate,
+                                float* grad_accum, float* grad_count, void* stream) {
+  if (!grads || !cams) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  if ((grad_accum == nullptr) != (grad_count == nullptr))
+    return fail(GES_ERR_INVALID_ARGUMENT, "grad_accum and grad_count go together");
+  ges::AdamSplats a{};
+  a.accumulate = accumulate ? 1 : 0;
+  a.stat_accum = grad_accum;
+  a.stat_count = grad_count;
+  a.half_w = 0.5 * (double)cams[0].width;
+  a.half_h = 0.5 * (double)cams[0].height;
+  return render_backward(splats, cams, nv, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, &a, false, stream);
+}
+
+ges_status frame_view(int64_t n, int32_t nv, int32_t width, int32_t height, void* splat_ws, void* key_ws,
+                      uint64_t num_keys, void* pixel_ws, int32_t view, ges_frame_view* out) {
   if (!out || !splat_ws) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
   if (n < 0 || width < 1 || height < 1 || width > 16384 || height > 16384)
     return fail(GES_ERR_INVALID_ARGUMENT, "bad sizes");
-  const ges::FramePlan fp = ges::plan_frame(n, width, height);
-  char* sw = reinterpret_cast<char*>(splat_ws);
+  if (nv < 1 || nv > ges::kMaxViews || view < 0 || view >= nv)
+    return fail(GES_ERR_INVALID_ARGUMENT, "view outside [0, num_views)");
+  const ges::ViewsPlan vp = ges::plan_views(n, nv, width, height);
+  const ges::FramePlan& fp = vp.fp;
+  char* sw = reinterpret_cast<char*>(splat_ws) + (size_t)view * vp.view_stride;
   std::memset(out, 0, sizeof(*out));
   out->records = reinterpret_cast<const float*>(sw + fp.off_rec);
   out->tile_ranges = reinterpret_cast<const uint32_t*>(sw + fp.off_ranges);
@@ -372,7 +357,7 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
     out->row_marks = reinterpret_cast<const uint32_t*>(kw + kp.off_bits);
   }
   if (pixel_ws) {
-    char* pw = reinterpret_cast<char*>(pixel_ws);
+    char* pw = reinterpret_cast<char*>(pixel_ws) + (size_t)view * fp.pixel_bytes;
     out->final_T = reinterpret_cast<const float*>(pw + fp.off_final_T);
     out->n_contrib = reinterpret_cast<const uint32_t*>(pw + fp.off_n_contrib);
   }
@@ -381,6 +366,137 @@ ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* sp
   out->tile_work = reinterpret_cast<const uint32_t*>(sw + fp.off_twork);
   out->group_order = reinterpret_cast<const uint32_t*>(sw + fp.off_gorder);
   return GES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t ges_abi_version(void) { return GES_ABI_VERSION; }
+
+const char* ges_last_error(void) { return g_last_error.c_str(); }
+
+ges_status ges_workspace_query(int64_t n, int32_t width, int32_t height, size_t* splat_ws_bytes,
+                               size_t* pixel_ws_bytes) {
+  return ges_views_workspace_query(n, 1, width, height, splat_ws_bytes, pixel_ws_bytes);
+}
+
+ges_status ges_views_workspace_query(int64_t n, int32_t num_views, int32_t width, int32_t height,
+                                     size_t* splat_ws_bytes, size_t* pixel_ws_bytes) {
+  if (n < 0 || n >= (int64_t(1) << 31)) return fail(GES_ERR_INVALID_ARGUMENT, "n outside [0, 2^31)");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(GES_ERR_INVALID_ARGUMENT, "width/height outside [1,16384]");
+  if (num_views < 1 || num_views > ges::kMaxViews) return fail(GES_ERR_INVALID_ARGUMENT, "num_views outside [1, 64]");
+  if ((int64_t)num_views * n >= (int64_t(1) << 31))
+    return fail(GES_ERR_INVALID_ARGUMENT, "num_views x n outside [0, 2^31)");
+  const ges::ViewsPlan vp = ges::plan_views(n, num_views, width, height);
+  if (splat_ws_bytes) *splat_ws_bytes = vp.splat_bytes;
+  if (pixel_ws_bytes) *pixel_ws_bytes = vp.pixel_bytes;
+  return GES_OK;
+}
+
+ges_status ges_key_workspace_query(uint64_t num_keys, int64_t n, int32_t width, int32_t height, size_t* key_ws_bytes) {
+  (void)n;
+  if (!key_ws_bytes) return fail(GES_ERR_INVALID_ARGUMENT, "key_ws_bytes is NULL");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(GES_ERR_INVALID_ARGUMENT, "width/height outside [1,16384]");
+  if (num_keys >= 0xffffffffull) return fail(GES_ERR_CAPACITY, "more than 2^32-2 keys");
+  *key_ws_bytes = ges::plan_keys(num_keys, true).bytes;
+  return GES_OK;
+}
+
+ges_status ges_preprocess(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                          void* splat_ws, size_t splat_ws_bytes, uint64_t* num_keys_host, void* stream) {
+  if (!cam) return fail(GES_ERR_INVALID_ARGUMENT, "camera is NULL");
+  return preprocess_views(splats, cam, 1, params, splat_ws, splat_ws_bytes, num_keys_host, stream);
+}
+
+ges_status ges_preprocess_views(const ges_splats* splats, const ges_camera* cams, int32_t num_views,
+                                const ges_raster_params* params, void* splat_ws, size_t splat_ws_bytes,
+                                uint64_t* num_keys_host, void* stream) {
+  return preprocess_views(splats, cams, num_views, params, splat_ws, splat_ws_bytes, num_keys_host, stream);
+}
+
+ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                              void* splat_ws, void* key_ws, size_t key_ws_bytes, uint64_t num_keys, void* pixel_ws,
+                              float* out_rgb, void* stream) {
+  if (!cam) return fail(GES_ERR_INVALID_ARGUMENT, "camera is NULL");
+  return render_forward_views(splats, cam, 1, params, splat_ws, key_ws, key_ws_bytes, num_keys, pixel_ws, out_rgb,
+                              stream);
+}
+
+ges_status ges_render_forward_views(const ges_splats* splats, const ges_camera* cams, int32_t num_views,
+                                    const ges_raster_params* params, void* splat_ws, void* key_ws,
+                                    size_t key_ws_bytes, uint64_t num_keys, void* pixel_ws, float* out_rgb,
+                                    void* stream) {
+  return render_forward_views(splats, cams, num_views, params, splat_ws, key_ws, key_ws_bytes, num_keys, pixel_ws,
+                              out_rgb, stream);
+}
+
+ges_status ges_render_backward(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                               void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
+                               const ges_splat_grads* grads, void* stream) {
+  if (!grads || !cam) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  return render_backward(splats, cam, 1, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, nullptr, false, stream);
+}
+
+ges_status ges_render_backward_accumulate(const ges_splats* splats, const ges_camera* cam,
+                                          const ges_raster_params* params, void* splat_ws, void* key_ws,
+                                          void* pixel_ws, const float* dL_drgb, const ges_splat_grads* grads,
+                                          float* grad_accum, float* grad_count, void* stream) {
+  return backward_views_plain(splats, cam, 1, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, 1, grad_accum,
+                              grad_count, stream);
+}
+
+ges_status ges_render_backward_views(const ges_splats* splats, const ges_camera* cams, int32_t num_views,
+                                     const ges_raster_params* params, void* splat_ws, void* key_ws, void* pixel_ws,
+                                     const float* dL_drgb, const ges_splat_grads* grads, int32_t accumulate,
+                                     float* grad_accum, float* grad_count, void* stream) {
+  return backward_views_plain(splats, cams, num_views, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, accumulate,
+                              grad_accum, grad_count, stream);
+}
+
+ges_status ges_render_backward_adam(const ges_splats* splats, const ges_camera* cam, const ges_raster_params* params,
+                                    void* splat_ws, void* key_ws, void* pixel_ws, const float* dL_drgb,
+                                    const ges_splat_grads* grads, const ges_adam_splats* opt, void* stream) {
+  if (!cam) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  ges::AdamSplats a;
+  const ges_status st = adam_args(splats, cam, opt, a);
+  if (st != GES_OK) return st;
+  return render_backward(splats, cam, 1, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, &a, true, stream);
+}
+
+ges_status ges_render_backward_views_adam(const ges_splats* splats, const ges_camera* cams, int32_t num_views,
+                                          const ges_raster_params* params, void* splat_ws, void* key_ws,
+                                          void* pixel_ws, const float* dL_drgb, const ges_splat_grads* grads,
+                                          const ges_adam_splats* opt, void* stream) {
+  if (!cams) return fail(GES_ERR_INVALID_ARGUMENT, "NULL argument");
+  ges::AdamSplats a;
+  const ges_status st = adam_args(splats, &cams[0], opt, a);
+  if (st != GES_OK) return st;
+  if (num_views > 1) {   // the earlier views' sum goes through `grads`, which the last view's update reads
+    for (int k = 0; k < ges::kNumPar; ++k)
+      if (opt->grads_in[k]) return fail(GES_ERR_INVALID_ARGUMENT, "grads_in must be NULL with more than one view");
+    if (!grads || !grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh ||
+        !grads->beta)
+      return fail(GES_ERR_INVALID_ARGUMENT, "every grads buffer is needed with more than one view");
+    const float* g[ges::kNumPar] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->sh,
+                                    grads->beta};
+    for (int k = 0; k < ges::kNumPar; ++k) a.gin[k] = g[k];
+  }
+  return render_backward(splats, cams, num_views, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads, &a, true,
+                         stream);
+}
+
+ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* splat_ws, void* key_ws, uint64_t num_keys,
+                              void* pixel_ws, ges_frame_view* out) {
+  return frame_view(n, 1, width, height, splat_ws, key_ws, num_keys, pixel_ws, 0, out);
+}
+
+ges_status ges_frame_view_get_views(int64_t n, int32_t num_views, int32_t width, int32_t height, void* splat_ws,
+                                    void* key_ws, uint64_t num_keys, void* pixel_ws, int32_t view,
+                                    ges_frame_view* out) {
+  return frame_view(n, num_views, width, height, splat_ws, key_ws, num_keys, pixel_ws, view, out);
 }
 
 ges_status ges_profile_enable(int32_t on) {
@@ -651,6 +767,15 @@ double ges_expon_lr(int64_t step, double lr_init, double lr_final, int64_t max_s
     lr *= delay_mult + (1.0 - delay_mult) * std::sin(0.5 * M_PI * r);
   }
   return lr;
+}
+
+ges_status ges_loss_schedule(int64_t iteration, int64_t total_iterations, float lam_ssim, float lam_omega,
+                             float* omega, float* lam_l1) {
+  if (total_iterations < 1) return fail(GES_ERR_INVALID_ARGUMENT, "total_iterations < 1");
+  if (!std::isfinite(lam_ssim) || !std::isfinite(lam_omega)) return fail(GES_ERR_INVALID_ARGUMENT, "non-finite weight");
+  if (omega) *omega = (float)std::min(std::max((double)iteration / (double)total_iterations, 0.0), 1.0);
+  if (lam_l1) *lam_l1 = (float)(1.0 - (double)lam_ssim - (double)lam_omega);
+  return GES_OK;
 }
 
 }  // extern "C"

@@ -91,6 +91,28 @@ inline FramePlan plan_frame(int64_t n, int w, int h) {
   return p;
 }
 
+// Workspaces of a step over `views` views of one scene at one resolution: the view table, the per-view
+// regions of the single-view layout one after another (view 0 at the single-view offsets), then the
+// binning buffers of the views x n items; the views' pixel workspaces one after another.  One view gives
+// exactly the single-view layout.
+struct ViewsPlan {
+  FramePlan fp;                  // the layout of one view
+  int32_t views = 1;
+  size_t view_stride = 0;        // bytes between the per-view regions
+  size_t off_sort = 0, splat_bytes = 0, pixel_bytes = 0;
+};
+
+inline ViewsPlan plan_views(int64_t n, int32_t views, int w, int h) {
+  ViewsPlan p;
+  p.fp = plan_frame(n, w, h);
+  p.views = views;
+  p.view_stride = p.fp.view_bytes - p.fp.off_hdr;
+  p.off_sort = p.fp.view_bytes + (size_t)(views - 1) * p.view_stride;
+  p.splat_bytes = p.off_sort + plan_sort((int64_t)views * n).bytes;
+  p.pixel_bytes = (size_t)views * p.fp.pixel_bytes;
+  return p;
+}
+
 // Tile passes of a batch: 8-bit digits covering the largest batch tile id.
 inline int tile_passes(int64_t total_tiles) {
   int bits = 1;

@@ -119,6 +119,8 @@ struct Batch {
   uint32_t* sorted_tiles;        // [key capacity] batch tile per sorted pair (kw.key[0])
   int dup_buffer;                // buffer the duplication writes (so that the last tile pass ends in 0)
   uint64_t key_capacity;
+  int32_t shared_scene;          // every view renders the same splats (the views of a training step): the
+                                 // preprocess backward sums the views' gradients per splat, in view order
 };
 
 // Device view table and per-batch constants, copied to the device by the host before launches.

@@ -378,17 +378,54 @@ __device__ __forceinline__ void backward_wave(const ViewDesc& V, const ges_splat
   }
 }
 
-template <bool kAdam>
+template <int D, bool kAdam>
+__device__ __forceinline__ void backward_views(const DeviceBatch* db, const ges_splat_grads& G, const AdamSplats& A,
+                                               int64_t w0, float4* rows) {
+  // the views of one scene, in order: every view before the last adds its gradients to the stored ones (the
+  // first overwrites unless the caller accumulates); the last applies the update (kAdam) with the stored
+  // sum as the other views' gradients, or adds its gradients like the others
+  const int nv = db->nviews;
+  for (int v = 0; v < nv; ++v) {
+    AdamSplats a = A;
+    if (v > 0) a.accumulate = 1;
+    if (kAdam && v == nv - 1) {
+      a.accumulate = 0;
+      backward_wave<D, true>(db->views[v], G, a, w0, rows);
+    } else {
+      backward_wave<D, false>(db->views[v], G, a, w0, rows);
+    }
+    // the next view's rows reuse the LDS rows this view's SH stores read
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// One block per 256 splats of a view.  SHARED: the batch's views render the same splats and the grid
+// covers them once; each thread chains its splat through every view (backward_views).
+template <bool kAdam, bool SHARED>
 __global__ void __launch_bounds__(256) preprocess_backward_kernel(const DeviceBatch* __restrict__ db,
                                                                    ges_splat_grads G, AdamSplats A) {
   __shared__ float4 sRows[4 * 64 * kRowPad];
   const int64_t blk = blockIdx.x;
+  const int wave = threadIdx.x >> 6;
+  float4* rows = sRows + wave * 64 * kRowPad;
+  if constexpr (SHARED) {
+    const ViewDesc& V0 = db->views[0];
+    const int64_t w0 = blk * 256 + wave * 64;
+    if (w0 >= V0.n) return;
+    switch (V0.sh_degree) {
+      case 0: backward_views<0, kAdam>(db, G, A, w0, rows); break;
+      case 1: backward_views<1, kAdam>(db, G, A, w0, rows); break;
+      case 2: backward_views<2, kAdam>(db, G, A, w0, rows); break;
+      default: backward_views<3, kAdam>(db, G, A, w0, rows); break;
+    }
+    return;
+  }
   const int v = view_of_block(db->pre_prefix, db->nviews, blk);
   const ViewDesc& V = db->views[v];
-  const int wave = threadIdx.x >> 6;
   const int64_t w0 = (blk - db->pre_prefix[v]) * 256 + wave * 64;
   if (w0 >= V.n) return;
-  float4* rows = sRows + wave * 64 * kRowPad;
   switch (V.sh_degree) {   // uniform per block: one view per block
     case 0: backward_wave<0, kAdam>(V, G, A, w0, rows); break;
     case 1: backward_wave<1, kAdam>(V, G, A, w0, rows); break;
@@ -403,12 +440,16 @@ hipError_t launch_preprocess_backward(const DeviceBatch* dbatch, const Batch& b,
   const ges_splat_grads none{};
   const ges_splat_grads& g = grads ? *grads : none;
   const AdamSplats a = args ? *args : AdamSplats{};
-  if (fused)
-    hipLaunchKernelGGL(preprocess_backward_kernel<true>, dim3((unsigned)b.pre_blocks), dim3(256), 0, stream, dbatch, g,
-                       a);
+  const bool shared = b.shared_scene && b.nviews > 1;
+  const dim3 grid((unsigned)(shared ? b.pre_blocks / b.nviews : b.pre_blocks));
+  if (shared && fused)
+    hipLaunchKernelGGL((preprocess_backward_kernel<true, true>), grid, dim3(256), 0, stream, dbatch, g, a);
+  else if (shared)
+    hipLaunchKernelGGL((preprocess_backward_kernel<false, true>), grid, dim3(256), 0, stream, dbatch, g, a);
+  else if (fused)
+    hipLaunchKernelGGL((preprocess_backward_kernel<true, false>), grid, dim3(256), 0, stream, dbatch, g, a);
   else
-    hipLaunchKernelGGL(preprocess_backward_kernel<false>, dim3((unsigned)b.pre_blocks), dim3(256), 0, stream, dbatch,
-                       g, a);
+    hipLaunchKernelGGL((preprocess_backward_kernel<false, false>), grid, dim3(256), 0, stream, dbatch, g, a);
   return hipGetLastError();
 }
 

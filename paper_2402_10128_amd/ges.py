@@ -104,6 +104,24 @@ _SIGS = {
                                       C.c_void_p]),
     "ges_frame_view_get": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64,
                                      C.c_void_p, C.POINTER(ges_frame_view)]),
+    "ges_views_workspace_query": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t),
+                                            C.POINTER(C.c_size_t)]),
+    "ges_preprocess_views": (C.c_int, [C.POINTER(ges_splats), C.POINTER(ges_camera), C.c_int32,
+                                       C.POINTER(ges_raster_params), C.c_void_p, C.c_size_t, C.POINTER(C.c_uint64),
+                                       C.c_void_p]),
+    "ges_render_forward_views": (C.c_int, [C.POINTER(ges_splats), C.POINTER(ges_camera), C.c_int32,
+                                           C.POINTER(ges_raster_params), C.c_void_p, C.c_void_p, C.c_size_t,
+                                           C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ges_render_backward_views": (C.c_int, [C.POINTER(ges_splats), C.POINTER(ges_camera), C.c_int32,
+                                            C.POINTER(ges_raster_params), C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.POINTER(ges_splat_grads), C.c_int32, C.c_void_p,
+                                            C.c_void_p, C.c_void_p]),
+    "ges_render_backward_views_adam": (C.c_int, [C.POINTER(ges_splats), C.POINTER(ges_camera), C.c_int32,
+                                                 C.POINTER(ges_raster_params), C.c_void_p, C.c_void_p, C.c_void_p,
+                                                 C.c_void_p, C.POINTER(ges_splat_grads), C.POINTER(ges_adam_splats),
+                                                 C.c_void_p]),
+    "ges_frame_view_get_views": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                           C.c_uint64, C.c_void_p, C.c_int32, C.POINTER(ges_frame_view)]),
     "ges_profile_enable": (C.c_int, [C.c_int32]),
     "ges_profile_select": (C.c_int, [C.c_uint32]),
     "ges_profile_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
@@ -136,6 +154,8 @@ _SIGS = {
     "ges_opacity_reset": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p]),
     "ges_adam_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "ges_expon_lr": (C.c_double, [C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_double]),
+    "ges_loss_schedule": (C.c_int, [C.c_int64, C.c_int64, C.c_float, C.c_float, C.POINTER(C.c_float),
+                                    C.POINTER(C.c_float)]),
     "ges_serve_create": (C.c_int, [C.POINTER(ges_serve_config), C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
     "ges_serve_create_simulated": (C.c_int, [C.POINTER(ges_serve_config), C.c_size_t, C.c_uint64, C.c_uint64,
                                              C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
@@ -255,11 +275,65 @@ def ges_render_backward(splats, cam, params, splat_ws, key_ws, pixel_ws, dL_drgb
                                      _ptr(pixel_ws), _ptr(dL_drgb), C.byref(g), _stream(stream)))
 
 
-def ges_frame_view_get(n, width, height, splat_ws, key_ws, num_keys, pixel_ws) -> ges_frame_view:
+def ges_frame_view_get(n, width, height, splat_ws, key_ws, num_keys, pixel_ws, views=1, view=0) -> ges_frame_view:
     v = ges_frame_view()
-    _check(lib().ges_frame_view_get(int(n), int(width), int(height), _ptr(splat_ws), _ptr(key_ws), int(num_keys),
-                                    _ptr(pixel_ws), C.byref(v)))
+    _check(lib().ges_frame_view_get_views(int(n), int(views), int(width), int(height), _ptr(splat_ws), _ptr(key_ws),
+                                          int(num_keys), _ptr(pixel_ws), int(view), C.byref(v)))
     return v
+
+
+# ---- several views of one scene per launch sequence -----------------------------------------------------
+def _cams(cams):
+    return (ges_camera * len(cams))(*cams)
+
+
+def ges_views_workspace_query(n, views, width, height):
+    a, b = C.c_size_t(0), C.c_size_t(0)
+    _check(lib().ges_views_workspace_query(int(n), int(views), int(width), int(height), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def ges_preprocess_views(splats, cams, params, splat_ws, read_num_keys=True, stream=None):
+    """cams: list of ges_camera (one resolution).  Returns the batch's slot count when read_num_keys."""
+    k = C.c_uint64(0)
+    _check(lib().ges_preprocess_views(C.byref(splats), _cams(cams), len(cams), C.byref(params), _ptr(splat_ws),
+                                      splat_ws.numel(), C.byref(k) if read_num_keys else None, _stream(stream)))
+    return k.value if read_num_keys else None
+
+
+def ges_render_forward_views(splats, cams, params, splat_ws, key_ws, num_keys, pixel_ws, out_rgb, stream=None):
+    """out_rgb: [len(cams), H, W, 3] float32."""
+    _check(lib().ges_render_forward_views(C.byref(splats), _cams(cams), len(cams), C.byref(params), _ptr(splat_ws),
+                                          _ptr(key_ws), 0 if key_ws is None else key_ws.numel(), int(num_keys),
+                                          _ptr(pixel_ws), _ptr(out_rgb), _stream(stream)))
+
+
+def _grads_struct(grads):
+    g = ges_splat_grads()
+    if grads is not None:
+        for name in SPLAT_PARAMS:
+            t = grads.get(name)
+            setattr(g, name, None if t is None else t.data_ptr())
+    return g
+
+
+def ges_render_backward_views(splats, cams, params, splat_ws, key_ws, pixel_ws, dL_drgb, grads: dict,
+                              accumulate=False, grad_accum=None, grad_count=None, stream=None):
+    """Summed parameter gradients of the views (dL_drgb: [len(cams), H, W, 3]) written to (or added to) grads."""
+    _check(lib().ges_render_backward_views(C.byref(splats), _cams(cams), len(cams), C.byref(params), _ptr(splat_ws),
+                                           _ptr(key_ws), _ptr(pixel_ws), _ptr(dL_drgb), C.byref(_grads_struct(grads)),
+                                           1 if accumulate else 0, _ptr(grad_accum), _ptr(grad_count),
+                                           _stream(stream)))
+
+
+def ges_render_backward_views_adam(splats, cams, params, splat_ws, key_ws, pixel_ws, dL_drgb, exp_avg: dict,
+                                   exp_avg_sq: dict, lrs: dict, step, beta1=0.9, beta2=0.999, eps=1e-15, grads=None,
+                                   grad_accum=None, grad_count=None, stream=None):
+    """Fused Adam over the views' summed gradients (grads: required with more than one view; receives the sum)."""
+    opt = _adam_struct(exp_avg, exp_avg_sq, lrs, step, beta1, beta2, eps, grad_accum, grad_count, None)
+    _check(lib().ges_render_backward_views_adam(C.byref(splats), _cams(cams), len(cams), C.byref(params),
+                                                _ptr(splat_ws), _ptr(key_ws), _ptr(pixel_ws), _ptr(dL_drgb),
+                                                C.byref(_grads_struct(grads)), C.byref(opt), _stream(stream)))
 
 
 STAGES = ["preprocess", "depth_sort", "key_scan", "duplicate", "tile_sort", "raster_forward", "raster_backward",
@@ -349,6 +423,13 @@ def ges_render_backward_adam(splats, cam, params, splat_ws, key_ws, pixel_ws, dL
     """Backward pass with Adam fused in: updates the tensors behind ``splats`` and the moments in place; with
     grad_accum/grad_count also accumulates the densification statistic; grads_in (dict) holds other views'
     gradients added to this view's before the update."""
+    opt = _adam_struct(exp_avg, exp_avg_sq, lrs, step, beta1, beta2, eps, grad_accum, grad_count, grads_in)
+    _check(lib().ges_render_backward_adam(C.byref(splats), C.byref(cam), C.byref(params), _ptr(splat_ws),
+                                          _ptr(key_ws), _ptr(pixel_ws), _ptr(dL_drgb), C.byref(_grads_struct(grads)),
+                                          C.byref(opt), _stream(stream)))
+
+
+def _adam_struct(exp_avg, exp_avg_sq, lrs, step, beta1, beta2, eps, grad_accum, grad_count, grads_in):
     opt = ges_adam_splats()
     for k, name in enumerate(SPLAT_PARAMS):
         opt.grads_in[k] = None if grads_in is None else grads_in[name].data_ptr()
@@ -359,14 +440,7 @@ def ges_render_backward_adam(splats, cam, params, splat_ws, key_ws, pixel_ws, dL
         opt.exp_avg_sq[k] = exp_avg_sq[name].data_ptr()
         opt.lr[k] = float(lrs[name])
     opt.step, opt.beta1, opt.beta2, opt.eps = int(step), float(beta1), float(beta2), float(eps)
-    g = ges_splat_grads()
-    if grads is not None:
-        for name in SPLAT_PARAMS:
-            t = grads.get(name)
-            setattr(g, name, None if t is None else t.data_ptr())
-    _check(lib().ges_render_backward_adam(C.byref(splats), C.byref(cam), C.byref(params), _ptr(splat_ws),
-                                          _ptr(key_ws), _ptr(pixel_ws), _ptr(dL_drgb), C.byref(g), C.byref(opt),
-                                          _stream(stream)))
+    return opt
 
 
 def _splat_set(d: dict | None) -> ges_splat_set:
@@ -464,6 +538,14 @@ def ges_expon_lr(step, lr_init, lr_final, max_steps, delay_steps=0, delay_mult=1
                               float(delay_mult))
 
 
+def ges_loss_schedule(iteration, total_iterations, lam_ssim, lam_omega):
+    """(omega, lam_l1) of an iteration: the mask strength and the L1 weight (binary32)."""
+    w, l1 = C.c_float(0.0), C.c_float(0.0)
+    _check(lib().ges_loss_schedule(int(iteration), int(total_iterations), float(lam_ssim), float(lam_omega),
+                                   C.byref(w), C.byref(l1)))
+    return w.value, l1.value
+
+
 # ---- a frame: owns the workspaces of one (scene, camera) render --------------------------------------
 @dataclass
 class Frame:
@@ -476,12 +558,13 @@ class Frame:
     key_ws: torch.Tensor | None = None
     num_keys: int = 0        # the slot count (or capacity) the frame was rendered with
     key_capacity: int = 0    # slots the current key workspace holds
+    views: int = 1           # views of one scene rendered together (the ..._views calls)
 
     @staticmethod
-    def create(n, width, height, device="cuda"):
-        sb, pb = ges_workspace_query(n, width, height)
+    def create(n, width, height, device="cuda", views=1):
+        sb, pb = ges_views_workspace_query(n, views, width, height)
         return Frame(n, width, height, torch.empty(sb, dtype=torch.uint8, device=device),
-                     torch.empty(pb, dtype=torch.uint8, device=device))
+                     torch.empty(pb, dtype=torch.uint8, device=device), views=views)
 
     def ensure_keys(self, num_keys):
         if self.key_ws is None or self.key_capacity < num_keys:
@@ -492,14 +575,14 @@ class Frame:
             self.key_capacity = cap
         self.num_keys = num_keys
 
-    def view(self) -> ges_frame_view:
+    def view(self, v=0) -> ges_frame_view:
         return ges_frame_view_get(self.n, self.width, self.height, self.splat_ws, self.key_ws, self.num_keys,
-                                  self.pixel_ws)
+                                  self.pixel_ws, self.views, v)
 
 
-def frame_arrays(frame: Frame, n: int) -> dict:
-    """Copies of a frame's inspection arrays as numpy (tests)."""
-    v = frame.view()
+def frame_arrays(frame: Frame, n: int, view=0) -> dict:
+    """Copies of a frame's inspection arrays (of view `view` of a multi-view frame) as numpy (tests)."""
+    v = frame.view(view)
     out = {}
     ws = frame.splat_ws
 
@@ -516,7 +599,10 @@ def frame_arrays(frame: Frame, n: int) -> dict:
     out["tile_work"] = sl(v.tile_work, 4 * T, ws).view(torch.int32).cpu().numpy().view(np.uint32)
     out["group_order"] = sl(v.group_order, 4 * ((T + 7) // 8), ws).view(torch.int32).cpu().numpy().view(np.uint32)
     if frame.key_ws is not None and frame.num_keys > 0:
-        K = min(out["keys"], frame.num_keys)
+        K = out["keys"]
+        if frame.views > 1:   # the sorted pairs cover every view of the batch
+            K = sum(int(sl(frame.view(u).stats, 8, ws).view(torch.int64).cpu()[0]) for u in range(frame.views))
+        K = min(K, frame.num_keys)
         pairs = sl(v.sorted_pairs, 8 * K, frame.key_ws).view(torch.int32).reshape(K, 2).cpu().numpy().view(np.uint32)
         out["sorted_ids"] = pairs[:, 0].copy()
         out["sorted_slots"] = pairs[:, 1].copy()

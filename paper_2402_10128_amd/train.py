@@ -9,7 +9,9 @@ The step follows the paper's training recipe:
     over 30,000 steps (App. B.2).
 Every stage runs in the library's kernels; this module only owns buffers and orders the calls on one stream.
 By default the Adam update runs inside the backward pass (ges_render_backward_adam), so the parameter
-gradients never go through memory.
+gradients never go through memory.  Several views of one step are rendered and back-propagated through one
+launch sequence (the ..._views calls; batch_views=False renders them one after another, with the same bits).
+The loss schedule (omega and lambda_L1) comes from the library (ges_loss_schedule).
 After the update, every shape_prune_interval iterations the splats whose opacity is below min_opacity or
 whose beta is below min_beta are removed with their moments, and every shape_reset_interval iterations every
 beta goes back to 2 (Sec. 4.4; Sec. 5.2; App. B.2: intervals 100 and 1,000).  When both fall on one
@@ -65,6 +67,7 @@ class TrainConfig:
     tile_cull: int = G.TILES_ELLIPSE
     rho: float = 0.1
     bg: tuple = (0.0, 0.0, 0.0)
+    batch_views: bool = True               # the views of a step share one launch sequence
 
 
 class TrainStep:
@@ -90,12 +93,16 @@ class TrainStep:
         self.c = self.cstructs[0]
         self.p = G.params_struct(self.cfg.falloff, self.cfg.tile_cull, self.cfg.rho, self.cfg.bg)
         H, W = self.cam.height, self.cam.width
+        B = len(self.cams)
+        self.batched = self.cfg.batch_views and B > 1
         self._bind_scene()
-        self.image = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
-        self.dL = torch.empty_like(self.image)
-        self.view_loss = torch.empty(len(self.cams), dtype=torch.float32, device=dev)
+        # per view: rendered image, dL/dimage and frequency mask ([B, ...]; image / dL / mask are view 0's)
+        self.images = torch.empty((B, H, W, 3), dtype=torch.float32, device=dev)
+        self.dLs = torch.empty_like(self.images)
+        self.masks = torch.empty((B, H, W), dtype=torch.uint8, device=dev)
+        self.image, self.dL, self.mask = self.images[0], self.dLs[0], self.masks[0]
+        self.view_loss = torch.empty(B, dtype=torch.float32, device=dev)
         self.loss = self.view_loss[0]
-        self.mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
         self.mask_scratch = torch.empty(G.lib().ges_mask_scratch_bytes(W, H), dtype=torch.uint8, device=dev)
         self.loss_scratch = torch.empty(G.lib().ges_loss_scratch_bytes(), dtype=torch.uint8, device=dev)
         self.ssim_scratch = torch.empty(G.lib().ges_ssim_scratch_bytes(W, H), dtype=torch.uint8, device=dev)
@@ -108,18 +115,31 @@ class TrainStep:
     def _bind_scene(self):
         """Point the splat descriptor and the frame at the current scene tensors (after creation or pruning)."""
         self.s = G.splats_struct(*(self.scene[k] for k in G.SPLAT_PARAMS))
-        self.frame = G.Frame.create(self.s.n, self.cam.width, self.cam.height, self.target.device)
+        self.frame = G.Frame.create(self.s.n, self.cam.width, self.cam.height, self.target.device,
+                                    views=len(self.cams) if self.batched else 1)
         self.grads = None
+        self.keys_known = False  # a new frame has no key workspace: its first step reads the key count back
 
     def _reset_stats(self):
         self.grad_accum = torch.zeros(self.n, dtype=torch.float32, device=self.target.device)
         self.grad_count = torch.zeros(self.n, dtype=torch.float32, device=self.target.device)
+
+    def check_keys(self):
+        """Raise if a step rendered with a key capacity below its slot count (the overflowing pairs were
+        dropped, so that step's image and gradients are incomplete).  Waits for the stream."""
+        ws = self.frame.splat_ws
+        for v in range(self.frame.views):
+            off = self.frame.view(v).stats - ws.data_ptr()
+            if int(ws[off:off + 32].view(torch.int64)[1].cpu()) & 1:
+                raise RuntimeError("key capacity too small for a step rendered without reading the key count back "
+                                   "(its image and gradients miss the dropped pairs)")
 
     def densify(self) -> int:
         """Clone or split the splats whose mean statistic reaches the threshold; returns the new count.  The
         scene, moments, statistics and frame are replaced (read ``self.scene`` afterwards)."""
         c = self.cfg
         n = self.n
+        self.check_keys()
         normals = torch.randn((n, 2, 3), generator=self.gen, device=self.target.device)
         src = [self.scene, self.exp_avg, self.exp_avg_sq]
         dst = [{k: torch.empty((2 * n,) + tuple(v.shape[1:]), dtype=v.dtype, device=v.device) for k, v in d.items()}
@@ -146,6 +166,7 @@ class TrainStep:
         src = [self.scene, self.exp_avg, self.exp_avg_sq]
         dst = [{k: torch.empty_like(v) for k, v in d.items()} for d in src]
         sh_degree = int(self.s.sh_degree)
+        self.check_keys()
         kept = G.ges_prune_splats(src, dst, sh_degree, c.min_opacity, c.min_beta)
         if kept == self.n:
             return kept
@@ -164,7 +185,7 @@ class TrainStep:
         G.ges_shape_reset(self.scene["beta"], self.exp_avg["beta"], self.exp_avg_sq["beta"], self.cfg.beta_init)
 
     def omega(self, it: int) -> float:
-        return min(max(it / self.cfg.total_iterations, 0.0), 1.0)
+        return G.ges_loss_schedule(it, self.cfg.total_iterations, self.cfg.lam_ssim, self.cfg.lam_omega)[0]
 
     def learning_rates(self, it: int) -> dict:
         c = self.cfg
@@ -174,9 +195,11 @@ class TrainStep:
 
     def step(self, it: int, read_num_keys: bool = True, fused: bool = True):
         """Iteration ``it`` (counting from 1).  With read_num_keys=False the render takes the key count from
-        the device and the frame's key capacity must already hold it (an overflow is flagged in the frame).
-        fused=True applies Adam inside the backward pass (the gradients are not stored); fused=False stores
-        the gradients in ``self.grads`` and runs the stand-alone Adam step (the same bits)."""
+        the device and the frame's key capacity must already hold it (an overflow is flagged in the frame and
+        raised by check_keys, which densify and prune call); the first step on a new frame (after creation,
+        densification or pruning) reads the count back regardless.  fused=True applies Adam inside the
+        backward pass (the gradients are not stored); fused=False stores the gradients in ``self.grads`` and
+        runs the stand-alone Adam step (the same bits)."""
         c = self.cfg
         _check = G._check
         L = G.lib()
@@ -189,9 +212,17 @@ class TrainStep:
         cnt = self.grad_count if stats else None
         if (B > 1 or not fused) and self.grads is None:
             self.grads = {k: torch.empty_like(v) for k, v in self.scene.items()}
-        for v in range(B):
+        omega, lam_l1 = G.ges_loss_schedule(it, c.total_iterations, c.lam_ssim, c.lam_omega)
+        read_num_keys = read_num_keys or not self.keys_known
+        self.keys_known = True
+        # the step's loss is the mean over the views: each view's terms carry 1/B
+        lam_l1, lam_w, lam_s = lam_l1 / B, c.lam_omega / B, c.lam_ssim / B
+        if self.batched:
+            self._views_step(it, read_num_keys, fused, omega, lam_l1, lam_w, lam_s, lrs, acc, cnt, stream)
+        for v in range(0 if self.batched else B):
             cs, target = self.cstructs[v], self.targets[v]
-            _check(L.ges_freq_mask(G._ptr(target), W, H, float(self.omega(it)), G._ptr(self.mask_scratch),
+            self.mask, self.image, self.dL = self.masks[v], self.images[v], self.dLs[v]
+            _check(L.ges_freq_mask(G._ptr(target), W, H, float(omega), G._ptr(self.mask_scratch),
                                    G._ptr(self.mask), stream))
             if read_num_keys:
                 k = G.ges_preprocess(self.s, cs, self.p, self.frame.splat_ws, True)
@@ -202,11 +233,9 @@ class TrainStep:
             self.frame.num_keys = k
             G.ges_render_forward(self.s, cs, self.p, self.frame.splat_ws, self.frame.key_ws, k, self.frame.pixel_ws,
                                  self.image)
-            # the step's loss is the mean over the views: each view's terms carry 1/B
-            lam_l1 = (1.0 - c.lam_ssim - c.lam_omega) / B
             loss_v = self.view_loss[v]
-            G.ges_loss(self.image, target, self.mask, lam_l1, c.lam_omega / B, self.dL, loss_v, self.loss_scratch)
-            G.ges_ssim_loss(self.image, target, c.lam_ssim / B, loss_v, self.dL, self.ssim_scratch)
+            G.ges_loss(self.image, target, self.mask, lam_l1, lam_w, self.dL, loss_v, self.loss_scratch)
+            G.ges_ssim_loss(self.image, target, lam_s, loss_v, self.dL, self.ssim_scratch)
             ws = (self.s, cs, self.p, self.frame.splat_ws, self.frame.key_ws, self.frame.pixel_ws, self.dL)
             last = v == B - 1
             if fused and last:   # the last view's backward updates from the sum of every view's gradients
@@ -223,6 +252,7 @@ class TrainStep:
             groups = [(self.scene[k], self.grads[k], self.exp_avg[k], self.exp_avg_sq[k], lrs[k])
                       for k in GROUP_ORDER]
             G.ges_adam_step(groups, it, c.beta1, c.beta2, c.eps)
+        self.mask, self.image, self.dL = self.masks[0], self.images[0], self.dLs[0]
         self.loss = self.view_loss.sum() if B > 1 else self.view_loss[0]
         if stats and it > c.densify_from and it % c.densify_interval == 0:
             self.densify()
@@ -233,3 +263,31 @@ class TrainStep:
         if c.opacity_reset_interval and it % c.opacity_reset_interval == 0:
             self.opacity_reset()
         return self.loss
+
+    def _views_step(self, it, read_num_keys, fused, omega, lam_l1, lam_w, lam_s, lrs, acc, cnt, stream):
+        """The step's views through one launch sequence: masks and losses per view, everything else batched."""
+        c = self.cfg
+        L = G.lib()
+        H, W = self.cam.height, self.cam.width
+        f = self.frame
+        for v, target in enumerate(self.targets):
+            G._check(L.ges_freq_mask(G._ptr(target), W, H, float(omega), G._ptr(self.mask_scratch),
+                                     G._ptr(self.masks[v]), stream))
+        if read_num_keys:
+            k = G.ges_preprocess_views(self.s, self.cstructs, self.p, f.splat_ws, True)
+            f.ensure_keys(k)
+        else:
+            G.ges_preprocess_views(self.s, self.cstructs, self.p, f.splat_ws, False)
+            k = f.key_capacity
+        f.num_keys = k
+        G.ges_render_forward_views(self.s, self.cstructs, self.p, f.splat_ws, f.key_ws, k, f.pixel_ws, self.images)
+        for v, target in enumerate(self.targets):
+            loss_v = self.view_loss[v]
+            G.ges_loss(self.images[v], target, self.masks[v], lam_l1, lam_w, self.dLs[v], loss_v, self.loss_scratch)
+            G.ges_ssim_loss(self.images[v], target, lam_s, loss_v, self.dLs[v], self.ssim_scratch)
+        ws = (self.s, self.cstructs, self.p, f.splat_ws, f.key_ws, f.pixel_ws, self.dLs)
+        if fused:
+            G.ges_render_backward_views_adam(*ws, self.exp_avg, self.exp_avg_sq, lrs, it, c.beta1, c.beta2, c.eps,
+                                             grads=self.grads, grad_accum=acc, grad_count=cnt)
+        else:
+            G.ges_render_backward_views(*ws, self.grads, False, acc, cnt)

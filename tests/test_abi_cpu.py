@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_queries():
-    assert G.ges_abi_version() == 3
+    assert G.ges_abi_version() == 4
     sb, pb = G.ges_workspace_query(1000, 64, 64)
     assert sb > 1000 * 64 and pb >= 64 * 64 * 8
     assert G.ges_key_workspace_query(100, 1000, 64, 64) >= 100 * 20
@@ -219,3 +219,59 @@ def test_static_scratch_mask_validates_before_any_device_work():
     assert lib.ges_freq_mask_static(None, 64, 64, C.c_float(0.75), fake, None) == 1
     assert lib.ges_freq_mask_static(fake, 64, 64, C.c_float(1.5), fake, None) == 1
     assert lib.ges_freq_mask_static(fake, 0, 64, C.c_float(0.5), fake, None) == 1
+
+
+def test_views_workspace_query():
+    """One view is the single-view layout; B views hold B per-view regions, B pixel workspaces and the
+    binning buffers of B x n items."""
+    one = G.ges_workspace_query(1000, 64, 48)
+    assert G.ges_views_workspace_query(1000, 1, 64, 48) == one
+    s3, p3 = G.ges_views_workspace_query(1000, 3, 64, 48)
+    assert p3 == 3 * one[1] and s3 > 2 * one[0]
+    for bad in ((1000, 0, 64, 48), (1000, 65, 64, 48), (1 << 30, 4, 64, 48)):
+        with pytest.raises(G.GESError) as e:
+            G.ges_views_workspace_query(*bad)
+        assert e.value.status == 1
+
+
+def test_views_calls_validate_before_any_device_work():
+    lib = G.lib()
+    p = G.params_struct()
+    s = G.ges_splats()
+    s.n, s.sh_degree = 0, 0
+    cams = (G.ges_camera * 2)(G.camera_struct(synth.pinhole(64, 64, (0, 0, -4.0))),
+                              G.camera_struct(synth.pinhole(64, 48, (0, 1, -4.0))))
+    ws = C.c_void_p(1 << 20)
+    assert lib.ges_preprocess_views(C.byref(s), cams, 2, C.byref(p), ws, 1 << 30, None, None) == 1
+    assert b"same width and height" in lib.ges_last_error()
+    assert lib.ges_preprocess_views(C.byref(s), cams, 0, C.byref(p), ws, 1 << 30, None, None) == 1
+    assert lib.ges_preprocess_views(C.byref(s), None, 1, C.byref(p), ws, 1 << 30, None, None) == 1
+    assert lib.ges_render_forward_views(C.byref(s), cams, 65, C.byref(p), ws, None, 0, 0, ws, ws, None) == 1
+    g = G.ges_splat_grads()
+    assert lib.ges_render_backward_views(C.byref(s), cams, 2, C.byref(p), ws, None, ws, ws, C.byref(g), 0, None,
+                                         None, None) == 1
+    # fused with two views: grads_in must be NULL and every grads buffer set
+    opt = G.ges_adam_splats()
+    for k in range(6):
+        opt.exp_avg[k] = opt.exp_avg_sq[k] = 1 << 20
+        opt.lr[k] = 1e-3
+    opt.step, opt.beta1, opt.beta2, opt.eps = 1, 0.9, 0.999, 1e-15
+    same = (G.ges_camera * 2)(cams[0], cams[0])
+    assert lib.ges_render_backward_views_adam(C.byref(s), same, 2, C.byref(p), ws, None, ws, ws, C.byref(g),
+                                              C.byref(opt), None) == 1
+    assert b"every grads buffer" in lib.ges_last_error()
+    v = G.ges_frame_view()
+    assert lib.ges_frame_view_get_views(10, 2, 64, 64, ws, None, 0, None, 2, C.byref(v)) == 1
+
+
+def test_loss_schedule():
+    """omega grows linearly with progress and is clamped (Sec. 4.3); lambda_L1 = 1 - lambda_ssim - lambda_omega
+    (Sec. 4.4, Eq. final), i.e. 0.3 for the paper's weights."""
+    assert G.ges_loss_schedule(0, 40000, 0.2, 0.5) == (0.0, pytest.approx(0.3, abs=1e-7))
+    assert G.ges_loss_schedule(10000, 40000, 0.2, 0.5)[0] == 0.25
+    assert G.ges_loss_schedule(40000, 40000, 0.2, 0.5)[0] == 1.0
+    assert G.ges_loss_schedule(60000, 40000, 0.2, 0.5)[0] == 1.0
+    assert G.ges_loss_schedule(-5, 40000, 0.2, 0.5)[0] == 0.0
+    assert G.ges_loss_schedule(1, 3, 0.0, 0.0) == (pytest.approx(1 / 3, rel=1e-7), 1.0)
+    with pytest.raises(G.GESError):
+        G.ges_loss_schedule(1, 0, 0.2, 0.5)
