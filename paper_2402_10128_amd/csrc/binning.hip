@@ -165,7 +165,7 @@ struct WaveSplats {
   uint32_t filled[64];   // candidates enumerated so far (checked against slots)
   int32_t tx0[64], tx1[64], ty0[64];
   uint32_t spans[64];
-  float u[64], v[64], a[64], b[64], c[64], qm[64], inv_a[64], inv_c[64], q2[64], det[64], X[64], Y[64];
+  float u[64], v[64], a[64], b[64], c[64], qm[64], inv_a[64], inv_c[64], q2[64], det[64], Xe[64], Y[64], ra[64];
   uint32_t id[64];       // splat index in its view
   uint32_t tbase[64];    // the view's first batch tile
   int32_t tx[64];        // the view's tiles per row
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(256) duplicate_kernel(const DeviceBatch* __res
       W.spans[lane] = s.spans ? 1u : 0u;
       W.u[lane] = s.u; W.v[lane] = s.v; W.a[lane] = s.a; W.b[lane] = s.b; W.c[lane] = s.c;
       W.qm[lane] = s.qm; W.inv_a[lane] = s.inv_a; W.inv_c[lane] = s.inv_c;
-      W.q2[lane] = s.q2; W.det[lane] = s.det; W.X[lane] = s.X; W.Y[lane] = s.Y;
+      W.q2[lane] = s.q2; W.det[lane] = s.det; W.Xe[lane] = s.Xe; W.Y[lane] = s.Y; W.ra[lane] = s.ra;
       W.id[lane] = (uint32_t)i;
       W.tbase[lane] = (uint32_t)db->tile_prefix[v];
       W.tx[lane] = V.tiles_x;
@@ -286,7 +286,8 @@ __global__ void __launch_bounds__(256) duplicate_kernel(const DeviceBatch* __res
         s.tx0 = W.tx0[j]; s.tx1 = W.tx1[j]; s.ty0 = W.ty0[j];
         s.spans = W.spans[j] != 0u;
         s.u = W.u[j]; s.v = W.v[j]; s.a = W.a[j]; s.b = W.b[j]; s.c = W.c[j]; s.qm = W.qm[j];
-        s.inv_a = W.inv_a[j]; s.inv_c = W.inv_c[j]; s.q2 = W.q2[j]; s.det = W.det[j]; s.X = W.X[j]; s.Y = W.Y[j];
+        s.inv_a = W.inv_a[j]; s.inv_c = W.inv_c[j]; s.q2 = W.q2[j]; s.det = W.det[j]; s.Xe = W.Xe[j]; s.Y = W.Y[j];
+        s.ra = W.ra[j];
         int chi;
         row_span(s, ty, W.wh[j] >> 16, clo, chi);
         width = chi >= clo ? (uint32_t)(chi - clo + 1) : 0u;

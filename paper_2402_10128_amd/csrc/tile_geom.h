@@ -54,14 +54,20 @@ __device__ __forceinline__ bool ellipse_hits_tile(float u, float v, float a, flo
 // pixel centres (its chord extremes, again enlarged by 1% of their offsets and half a pixel).  Near-degenerate conics
 // (rho within 1e-4 of 1) keep the whole rectangle.  A superset only: the exact test decides.  The
 // preprocess counts a splat's candidates with this code and the duplication enumerates them with it, from
-// the same binary32 values, so both see the same tiles in the same order.
+// the same binary32 values, so both see the same tiles in the same order.  Being a superset with margins of
+// 1e-3 and more, it uses the hardware's approximate square root and reciprocal (relative errors near 1e-7,
+// the same instructions on both sides) rather than the correctly rounded sequences of the exact path.
 struct SplatTiles {
   int tx0, ty0, tx1, ty1;        // box of rows and columns to enumerate
   uint32_t rows;                 // ty1 - ty0 + 1, or 0: no candidate
   bool spans;                    // per-row spans of the ellipse (else whole rows of the box)
   float u, v, a, b, c, qm, inv_a, inv_c;
-  float q2, det, X, Y;           // the enlarged ellipse
+  float q2, det, Xe, Y, ra;      // the enlarged ellipse: q', det, its half-width sqrt(q' c / det), the
+                                 // band half-height Y (1% and half a pixel added) and 1/a (approximate)
 };
+
+__device__ __forceinline__ float geom_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float geom_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ void candidate_tiles(float u, float v, float a, float b, float c, float qm, int tx0, int ty0,
                                                 int tx1, int ty1, bool ellipse, SplatTiles& s) {
@@ -71,16 +77,18 @@ __device__ __forceinline__ void candidate_tiles(float u, float v, float a, float
   s.u = u; s.v = v; s.a = a; s.b = b; s.c = c; s.qm = qm;
   s.inv_a = 1.0f / a;
   s.inv_c = 1.0f / c;
-  s.q2 = 0.f; s.det = 0.f; s.X = 0.f; s.Y = 0.f;
+  s.q2 = 0.f; s.det = 0.f; s.Xe = 0.f; s.Y = 0.f; s.ra = 0.f;
   if (!ellipse) return;
   const float ac = a * c;
   const float det = ac - b * b;
-  const float gap = 1.f - __builtin_fabsf(b) / __builtin_sqrtf(ac);
+  const float gap = 1.f - __builtin_fabsf(b) * geom_rcp(geom_sqrt(ac));
   if (!(det > 0.f) || !(gap > 1e-4f)) return;
-  const float grow = 2.5e-5f / gap;
-  const float q2 = qm / (1.f - grow);
-  const float X = __builtin_sqrtf(q2 * c / det) * 1.01f + 0.5f;
-  const float Y = __builtin_sqrtf(q2 * a / det) * 1.01f + 0.5f;
+  const float grow = 2.5e-5f * geom_rcp(gap);
+  const float q2 = qm * geom_rcp(1.f - grow);
+  const float rdet = geom_rcp(det);
+  const float Xe = geom_sqrt(q2 * c * rdet);
+  const float X = Xe * 1.01f + 0.5f;
+  const float Y = geom_sqrt(q2 * a * rdet) * 1.01f + 0.5f;
   if (!(X < 1e7f) || !(Y < 1e7f)) return;
   // tile tx can meet [u - X, u + X] when 16 tx + 15 >= u - X and 16 tx <= u + X
   s.tx0 = max(s.tx0, (int)__builtin_ceilf((u - X - 15.f) * 0.0625f));
@@ -90,7 +98,7 @@ __device__ __forceinline__ void candidate_tiles(float u, float v, float a, float
   if (s.tx0 > s.tx1 || s.ty0 > s.ty1) { s.rows = 0u; return; }
   s.rows = (uint32_t)(s.ty1 - s.ty0 + 1);
   s.spans = true;
-  s.q2 = q2; s.det = det; s.X = X; s.Y = Y;
+  s.q2 = q2; s.det = det; s.Xe = Xe; s.Y = Y; s.ra = geom_rcp(a);
 }
 
 // Chord of the enlarged ellipse at height f (relative to v): x offsets e with a e^2 + 2 b e f + c f^2 = q'.
@@ -100,8 +108,8 @@ __device__ __forceinline__ float chord_lo(const SplatTiles& s, float f) {
   r = r - t;
   r = geom_max(r, 0.f);
   float e = s.b * f; e = -e;
-  e = e - __builtin_sqrtf(r);
-  return e * s.inv_a;
+  e = e - geom_sqrt(r);
+  return e * s.ra;
 }
 __device__ __forceinline__ float chord_hi(const SplatTiles& s, float f) {
   float r = s.a * s.q2;
@@ -109,8 +117,8 @@ __device__ __forceinline__ float chord_hi(const SplatTiles& s, float f) {
   r = r - t;
   r = geom_max(r, 0.f);
   float e = s.b * f; e = -e;
-  e = e + __builtin_sqrtf(r);
-  return e * s.inv_a;
+  e = e + geom_sqrt(r);
+  return e * s.ra;
 }
 
 // Candidate columns [lo, hi] of tile row ty (ty0 <= ty <= ty1); lo > hi: none.
@@ -126,7 +134,7 @@ __device__ __forceinline__ void row_span(const SplatTiles& s, int ty, int H, int
   if (!(f0 <= f1)) { lo = 1; hi = 0; return; }
   // the extremes over the band: at its ends, or at the ellipse's leftmost / rightmost points
   // f = +- b X' / c (X' = sqrt(q' c / det)) when those lie inside the band
-  const float Xe = __builtin_sqrtf(s.q2 * s.c / s.det);
+  const float Xe = s.Xe;
   float fl = s.b * Xe; fl = fl * s.inv_c;   // leftmost point at f = b X' / c
   const float fr = -fl;                     // rightmost point at f = -b X' / c
   float emin = geom_min(chord_lo(s, f0), chord_lo(s, f1));
