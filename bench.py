@@ -90,9 +90,9 @@ def algorithmic_bytes(stage, n, sh_coeffs, K, C, L, px, R=0):
         "duplicate": L * (4 + 64 + 4 + 8) + 8 * C,
         # the slots in, the sorted (tile, splat) pairs out
         "tile_sort": 8 * C + 8 * K,
-        # per listed splat its order entry, count and first slot in and its 2-D gradient out (80 B); the slot
-        # marks (1 bit per slot); the 10 sums of every stored row
-        "row_reduce": L * (4 + 4 + 4 + 80) + C // 8 + 40 * R,
+        # the slot marks (1 bit per slot) and every stored row's 10 sums and splat (44 B); the 2-D gradients
+        # written (80 B per splat with a row, at most R) are left out, so this is a lower bound
+        "row_reduce": C // 8 + 44 * R,
         "preprocess_backward": n * (16 + 12 + 16 + 4 + 12 * sh_coeffs + 48 + 80 + 4 * (3 + 3 + 4 + 1 + 1 + 3 * sh_coeffs)),
         # the row marks cleared before the backward raster
         "zero": C // 8,

@@ -357,16 +357,42 @@ hipError_t launch_duplicate(const DeviceBatch* dbatch, const Batch& b, hipStream
   return hipGetLastError();
 }
 
-// After the backward raster: each listed splat's 2-D gradient, the sum of the rows the raster stored at its
-// slots (one per tile whose pixels it reached), added in binary64 in an order fixed by the slot layout alone,
-// so the backward is deterministic.  One lane per splat, in depth order (a wave's rows lie in one stretch of
-// the row buffer).  A splat with at most kSmallSlots slots is summed by its own lane in slot order, the
-// marked rows of a 32-slot word fetched kRowBatch at a time (their loads issued together).  Larger splats
-// (a lane would walk them alone, and their rows would be fetched one lane at a time) are summed after that
-// by groups of 16 lanes, four splats of the wave at a time: lane q of a group adds the slots q, q + 16, ...
-// in order, and the group's sums are added by a fixed butterfly.
-constexpr int kRowBatch = 4;
-constexpr uint32_t kSmallSlots = 32;
+// After the backward raster: each splat's 2-D gradient, the sum of the rows the raster stored at its
+// candidate slots (one per tile in which some pixel composited it; about a tenth of the slots, as the tiles'
+// walks end where their pixels saturate), added in binary64 in slot order -- the same order on every run,
+// so the backward is deterministic.  A wave takes 8 words of the row marks (256 slots): it lists their marked
+// slots in LDS, loads 64 rows at a time (one per lane; a row carries its splat's batch item and first
+// candidate slot) and the first lane of each run of one splat's rows adds the run from LDS, carrying an
+// unfinished run into the next 64 and, past the wave's words, through the rest of the splat's slot range.
+// The run at the start of the range belongs to the wave holding the splat's first row if that lies before
+// the range.  The splat's 2-D gradient is written and kRowBit set in its visibility word (the preprocess
+// backward takes zero without it).
+constexpr int kReduceWords = 8;
+constexpr uint32_t kNoItem = 0xffffffffu;
+
+struct ReduceLds {
+  uint32_t slot[kReduceWords * 32];   // marked slots, in order
+  Vec4 row[64][3];                    // the current 64 rows
+  uint32_t owner[64];
+  double carry[10];                   // sums of the run left open by the last 64 rows
+  uint32_t carry_owner;
+};
+
+__device__ __forceinline__ void reduce_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void write_grad2d(const DeviceBatch* db, uint32_t item, const double* g) {
+  const int v = view_of_item(db, item);
+  const ViewDesc& V = db->views[v];
+  const int64_t i = (int64_t)item - db->item_prefix[v];
+  double2* gs = reinterpret_cast<double2*>(V.grad2d + (int64_t)kGradStride * i);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) gs[c] = make_double2(g[2 * c], g[2 * c + 1]);
+  __hip_atomic_fetch_or(V.vis + i, kRowBit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ void add_row(double* g, const Vec4* r) {
   g[0] += r[0][0]; g[1] += r[0][1]; g[2] += r[0][2]; g[3] += r[0][3];
@@ -374,129 +400,159 @@ __device__ __forceinline__ void add_row(double* g, const Vec4* r) {
   g[8] += r[2][0]; g[9] += r[2][1];
 }
 
-__device__ __forceinline__ void store_grad2d(double* dst, const double* g) {
-  double2* gs = reinterpret_cast<double2*>(dst);
+// The marked slots of words [w0, w0 + kReduceWords) below `end` into L.slot, in order; returns their count.
+__device__ __forceinline__ uint32_t list_marks(const GlobalU32* bits, uint64_t w0, uint64_t nwords, uint64_t end,
+                                               ReduceLds& L, int lane) {
+  const uint64_t q = w0 + (uint64_t)lane;
+  uint32_t m = 0u;
+  if (lane < kReduceWords && q < nwords && q * 32 < end) {
+    m = bits[q];
+    if (end - q * 32 < 32) m &= (1u << (uint32_t)(end - q * 32)) - 1u;
+  }
+  const uint32_t cnt = (uint32_t)__builtin_popcount(m);
+  uint32_t incl = cnt;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) gs[c] = make_double2(g[2 * c], g[2 * c + 1]);
+  for (int d = 1; d < kReduceWords; d <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  const uint32_t total = (uint32_t)__shfl((int)incl, kReduceWords - 1, 64);
+  uint32_t p = incl - cnt;
+  while (m) {
+    L.slot[p++] = (uint32_t)(q * 32) + (uint32_t)__builtin_ctz(m);
+    m &= m - 1u;
+  }
+  reduce_fence();
+  return total;
 }
 
-// ONE: the batch holds a single view (its descriptor then reads through scalar loads).
-template <bool ONE>
+// Lane-per-row load of rows [c0, c0 + n) of the list into LDS; returns the lane's row's item and first slot.
+__device__ __forceinline__ void load_rows(const GlobalVec4* rows, ReduceLds& L, uint32_t c0, uint32_t n, int lane,
+                                          uint32_t& item, uint32_t& first) {
+  item = kNoItem;
+  first = 0u;
+  if ((uint32_t)lane < n) {
+    const GlobalVec4* r = rows + (uint64_t)L.slot[c0 + lane] * (kRowFloats / 4);
+    const Vec4 a0 = r[0], a1 = r[1], a2 = r[2];
+    item = __float_as_uint(a2[2]);
+    first = __float_as_uint(a2[3]);
+    L.row[lane][0] = a0;
+    L.row[lane][1] = a1;
+    L.row[lane][2] = a2;
+  }
+  L.owner[lane] = item;
+}
+
 __global__ void __launch_bounds__(256) row_reduce_kernel(const DeviceBatch* __restrict__ db,
-                                                         const uint32_t* __restrict__ order,
-                                                         const uint32_t* __restrict__ item_cand,
-                                                         const uint32_t* __restrict__ cells,
                                                          const float* __restrict__ rows_,
                                                          const uint32_t* __restrict__ bits_, uint64_t nslots) {
-  const int lane = threadIdx.x & 63;
-  const int64_t listed = (int64_t)cells[0];
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k - lane >= listed) return;   // the whole wave lies past the listed splats
-  const bool valid = k < listed;
-  uint32_t j = 0, cand = 0;
-  if (valid) {
-    j = order[k];
-    cand = item_cand[j];
-  }
-  int v = 0;
-  int64_t i = j;
-  if (!ONE && valid) {
-    v = view_of_item(db, j);
-    i = (int64_t)j - db->item_prefix[v];
-  }
-  const ViewDesc& V = db->views[ONE ? 0 : v];
-  uint64_t off = 0, end = 0;
-  if (valid) {
-    off = min<uint64_t>(V.slot_off[i], nslots);
-    end = min<uint64_t>(off + cand, nslots);
-  }
-  const bool big = cand > kSmallSlots;   // cand is 0 on lanes past the listed splats
+  __shared__ ReduceLds lds[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  ReduceLds& L = lds[wave];
+  const uint64_t nwords = (nslots + 31) / 32;
+  const uint64_t w0 = ((uint64_t)blockIdx.x * 4 + wave) * kReduceWords;
+  if (w0 >= nwords) return;
+  const uint64_t wend = min<uint64_t>((w0 + kReduceWords) * 32, nslots);   // first slot after the range
   const GlobalU32* bits = (const GlobalU32*)bits_;
   const GlobalVec4* rows = (const GlobalVec4*)rows_;
-  if (valid && !big) {
-    double g[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (uint64_t lo = off & ~(uint64_t)31; lo < end; lo += 32) {
-      uint32_t m = bits[lo >> 5];
-      if (lo < off) m &= ~0u << (uint32_t)(off - lo);
-      if (end - lo < 32) m &= (1u << (uint32_t)(end - lo)) - 1u;
-      while (m) {
-        Vec4 r[kRowBatch][3];
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) {
-          if (m) {
-            const GlobalVec4* q = rows + (lo + (uint32_t)__builtin_ctz(m)) * (kRowFloats / 4);
-            r[u][0] = q[0];
-            r[u][1] = q[1];
-            r[u][2] = q[2];
-          } else {
-            r[u][0] = Vec4{0.f, 0.f, 0.f, 0.f};
-            r[u][1] = r[u][0];
-            r[u][2] = r[u][0];
-          }
-          m &= m - 1u;
+  const uint32_t total = list_marks(bits, w0, nwords, wend, L, lane);
+  if (total == 0) return;
+  if (lane == 0) L.carry_owner = kNoItem;
+  uint32_t skip = kNoItem;
+  for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+    const uint32_t n = min<uint32_t>(64u, total - c0);
+    uint32_t o, lo;
+    load_rows(rows, L, c0, n, lane, o, lo);
+    if (c0 == 0) {
+      // the first run's splat is summed by the wave of its first row: is that before this range?
+      const uint32_t o0 = (uint32_t)__shfl((int)o, 0, 64);
+      const uint64_t lo0 = (uint32_t)__shfl((int)lo, 0, 64);
+      bool earlier = false;
+      for (uint64_t q0 = lo0 >> 5; q0 < w0 && !earlier; q0 += 64) {
+        const uint64_t q = q0 + (uint64_t)lane;
+        uint32_t m = 0u;
+        if (q < w0) {
+          m = bits[q];
+          if (q == lo0 >> 5) m &= ~0u << (uint32_t)(lo0 & 31u);
         }
+        earlier = __ballot(m != 0u) != 0ull;
+      }
+      if (earlier) skip = o0;
+    }
+    const uint32_t co = L.carry_owner;
+    double g[10];
 #pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) add_row(g, r[u]);   // in slot order; a missing row adds zeros
+    for (int k = 0; k < 10; ++k) g[k] = (lane == 0 && co != kNoItem) ? L.carry[k] : 0.0;
+    reduce_fence();
+    // a run left open by the previous 64 rows that does not go on here ended with them
+    if (lane == 0 && co != kNoItem && co != L.owner[0]) {
+      write_grad2d(db, co, g);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) g[k] = 0.0;
+    }
+    const bool head = (uint32_t)lane < n && (lane == 0 || L.owner[lane - 1] != o);
+    bool open = false;
+    if (head) {
+      if (!(lane == 0 && co == o)) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) g[k] = 0.0;
+      }
+      uint32_t k = (uint32_t)lane;
+      if (o != skip)
+        for (; k < n && L.owner[k] == o; ++k) add_row(g, L.row[k]);
+      else
+        while (k < n && L.owner[k] == o) ++k;
+      open = k == n;
+    }
+    reduce_fence();
+    if (head) {
+      if (open) {
+#pragma unroll
+        for (int c = 0; c < 10; ++c) L.carry[c] = g[c];
+        L.carry_owner = o == skip ? kNoItem : o;
+      } else if (o != skip) {
+        write_grad2d(db, o, g);
       }
     }
-    store_grad2d(V.grad2d + (int64_t)kGradStride * i, g);
+    reduce_fence();
   }
-  // the wave's large splats, four at a time (group grp of 16 lanes takes the grp-th one left)
-  uint64_t pending = __ballot(big);
-  const int grp = lane >> 4, q = lane & 15;
-  while (pending) {
-    uint64_t m = pending;
-    for (int r = 0; r < grp; ++r) m &= m - 1;
-    const bool has = m != 0;
-    const int src = has ? (int)__builtin_ctzll(m) : lane;
+  // the last run: finished here, or continued through the rest of its splat's slots
+  const uint32_t co = L.carry_owner;
+  if (co == kNoItem) return;
+  double g[10];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) pending &= pending - 1;
-    const unsigned long long so = __shfl((unsigned long long)off, src, 64);
-    unsigned long long se = __shfl((unsigned long long)end, src, 64);
-    const long long si = __shfl((long long)i, src, 64);
-    const int sv = ONE ? 0 : __shfl(v, src, 64);
-    if (!has) se = so;
-    double h[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (uint64_t base = so; base < se; base += 16 * kRowBatch) {
-      Vec4 r[kRowBatch][3];
-#pragma unroll
-      for (int u = 0; u < kRowBatch; ++u) {
-        const uint64_t s = base + (uint64_t)(q + 16 * u);
-        if (s < se && ((bits[s >> 5] >> (uint32_t)(s & 31u)) & 1u)) {
-          const GlobalVec4* p = rows + s * (kRowFloats / 4);
-          r[u][0] = p[0];
-          r[u][1] = p[1];
-          r[u][2] = p[2];
-        } else {
-          r[u][0] = Vec4{0.f, 0.f, 0.f, 0.f};
-          r[u][1] = r[u][0];
-          r[u][2] = r[u][0];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kRowBatch; ++u) add_row(h, r[u]);
-    }
-    // every lane of the group ends with the same sums (each step adds the same two values on both sides)
-#pragma unroll
-    for (int d = 8; d >= 1; d >>= 1) {
-#pragma unroll
-      for (int c = 0; c < 10; ++c) h[c] += __shfl_xor(h[c], d, 16);
-    }
-    if (has && q == 0) store_grad2d(db->views[sv].grad2d + (int64_t)kGradStride * si, h);
+  for (int k = 0; k < 10; ++k) g[k] = L.carry[k];
+  uint64_t hi;
+  {
+    const int v = view_of_item(db, co);
+    const ViewDesc& V = db->views[v];
+    const int64_t i = (int64_t)co - db->item_prefix[v];
+    hi = min<uint64_t>((uint64_t)V.slot_off[i] + V.item_cand[i], nslots);
   }
+  for (uint64_t q0 = w0 + kReduceWords; q0 * 32 < hi; q0 += kReduceWords) {
+    reduce_fence();
+    const uint32_t cnt = list_marks(bits, q0, nwords, hi, L, lane);
+    for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
+      const uint32_t n = min<uint32_t>(64u, cnt - c0);
+      uint32_t o, lo;
+      load_rows(rows, L, c0, n, lane, o, lo);
+      reduce_fence();
+      if (lane == 0)
+        for (uint32_t k = 0; k < n; ++k) add_row(g, L.row[k]);
+      reduce_fence();
+    }
+  }
+  if (lane == 0) write_grad2d(db, co, g);
 }
 
 hipError_t launch_row_reduce(const DeviceBatch* dbatch, const Batch& b, const float* rows, const uint32_t* bits,
                              uint64_t nslots, hipStream_t stream) {
-  if (b.items == 0) return hipSuccess;
-  const SortWs& w = b.sw;
-  const dim3 grid((unsigned)((b.items + 255) / 256));
-  if (b.nviews == 1)
-    hipLaunchKernelGGL(row_reduce_kernel<true>, grid, dim3(256), 0, stream, dbatch, w.dv[w.depth_final], w.item_cand,
-                       w.cells, rows, bits, nslots);
-  else
-    hipLaunchKernelGGL(row_reduce_kernel<false>, grid, dim3(256), 0, stream, dbatch, w.dv[w.depth_final],
-                       w.item_cand, w.cells, rows, bits, nslots);
+  (void)b;
+  if (nslots == 0) return hipSuccess;
+  const uint64_t nwords = (nslots + 31) / 32;
+  const uint64_t waves = (nwords + kReduceWords - 1) / kReduceWords;
+  hipLaunchKernelGGL(row_reduce_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream, dbatch, rows, bits,
+                     nslots);
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ constexpr int kRecWords = 16;            // 64-byte per-splat record
 constexpr int kGradStride = GES_GRAD2D_STRIDE;   // doubles per splat in the 2-D gradient accumulator
 constexpr int kMaxViews = 64;
 constexpr int kRadixThreads = 256;       // radix passes: blocks of 256 threads ...
-constexpr int kRadixItemsDepth = 16;     // ... holding 16 items each (the depth sort of the splats) ...
+constexpr int kRadixItemsDepth = 8;      // ... holding 8 items each (the depth sort of the splats) ...
 constexpr int kRadixItemsPair = 8;       // ... or 8 (the pair sort: its 12-byte items need twice the LDS)
 constexpr uint32_t kNoKey = 0xffffffffu; // radix key of an item that a filtering pass drops
 constexpr float kAlphaMax = 0.99f;
@@ -26,6 +26,8 @@ constexpr float kTMin = 1e-4f;
 
 // Record words (see ges.h)
 constexpr uint32_t kVisBit = 0x80000000u;
+constexpr uint32_t kRowBit = 0x40000000u;   // visibility word: the backward stored rows of the splat (its 2-D
+                                            // gradient is the row reduction's sum; without it, zero)
 
 enum : int {
   R_U = 0, R_V, R_A, R_B, R_C, R_QMAX, R_OPA, R_BETA, R_CR, R_CG, R_CB, R_DEPTH, R_RADFLAGS, R_RECT0, R_RECT1, R_TOUCHED
@@ -176,8 +178,8 @@ hipError_t launch_depth_sort(const DeviceBatch* dbatch, Batch& b, hipStream_t st
 hipError_t launch_key_scan(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_duplicate(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
-// after the backward raster: every listed splat's 2-D gradient from its rows (nslots of kRowFloats floats,
-// marked in bits), in slot order (binary64); zero for a splat whose slots lie beyond nslots
+// after the backward raster: the 2-D gradient of every splat with a row (nslots rows of kRowFloats floats,
+// marked in bits), its rows added in slot order (binary64); splats without a row are left alone
 hipError_t launch_row_reduce(const DeviceBatch* dbatch, const Batch& b, const float* rows, const uint32_t* bits,
                              uint64_t nslots, hipStream_t stream);
 // one stable LSD radix pass over (u32 key, u32 value) items with 8-bit digits (radix.hip)

@@ -109,6 +109,8 @@ __device__ __forceinline__ double digamma(double x) {
 
 constexpr int kRowPad = 13;   // float4 slots per staged SH-gradient row (12 used at degree 3; 13 spreads LDS banks)
 
+
+
 // Chain rule of splat i.  SH-gradient rows of degrees 1 and 3 (whole float4s) go to `row` in LDS; other
 // degrees are written straight to memory.
 template <int D, bool kAdam>
@@ -140,9 +142,16 @@ __device__ __forceinline__ void backward_splat(const ViewDesc& V, const ges_spla
     return;
   }
   const uint32_t flags = vis & 0xffu;
-  // the splat's 2-D gradient, summed from its rows by the reduction that follows the backward raster
-  const double2* gp = reinterpret_cast<const double2*>(V.grad2d + (int64_t)kGradStride * i);
-  const double2 g01 = gp[0], g23 = gp[1], g45 = gp[2], g67 = gp[3], g89 = gp[4];
+  // the splat's 2-D gradient, summed from its rows by the reduction that follows the backward raster (zero
+  // when no pixel composited it)
+  double2 g01 = make_double2(0.0, 0.0), g23 = g01, g45 = g01, g67 = g01, g89 = g01;
+  double2* gp = reinterpret_cast<double2*>(V.grad2d + (int64_t)kGradStride * i);
+  if (vis & kRowBit) {
+    g01 = gp[0]; g23 = gp[1]; g45 = gp[2]; g67 = gp[3]; g89 = gp[4];
+  } else if (V.keep_grad2d) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) gp[k] = make_double2(0.0, 0.0);
+  }
   if (A.stat_accum) {   // densification statistic: the mean-2D gradient in NDC units
     const double su = g01.x * A.half_w, sv = g01.y * A.half_h;
     A.stat_accum[i] += (float)sqrt(su * su + sv * sv);

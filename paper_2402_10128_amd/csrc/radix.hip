@@ -10,9 +10,9 @@
 //              digit) against wave-private digit counters -- places them in LDS in digit order, and writes
 //              each digit's run to its global position (exclusive digit total prefix + the block's offset),
 //              so that consecutive threads write consecutive addresses.
-// A block holds 256 x ITEMS items: 16 per thread for the depth sort of the splats, 8 for the pair sort
-// (whose 12-byte items would otherwise leave room for two blocks per compute unit in LDS).  A filtering pass drops items whose key
-// is kNoKey (compaction) and stores the kept count.  With PAIR, a value is a (u32, slot) pair whose slot is
+// A block holds 256 x ITEMS items, 8 per thread for both sorts (measured against 4, 12 and 16: more items
+// leave room for fewer blocks per compute unit in LDS, fewer make the digit table longer).  A filtering pass
+// drops items whose key is kNoKey (compaction) and stores the kept count.  With PAIR, a value is a (u32, slot) pair whose slot is
 // the item's index in the pass that makes the pairs: the pair sort carries each pair's slot in the
 // candidate layout to the backward pass.
 #include "ges_internal.h"

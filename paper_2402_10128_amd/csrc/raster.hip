@@ -234,6 +234,10 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   __shared__ float4 sA[64], sB[64], sC[64];
   __shared__ float sRed[kFlush][4][10];   // [parked splat][lane row][component]
   __shared__ uint32_t sSlot[kFlush];      // the parked splat's slot: its row of this tile's sums
+  __shared__ uint32_t sItem[kFlush];      // the parked splat's batch item and first candidate slot (written
+  __shared__ uint32_t sFirst[kFlush];     // into its row)
+  __shared__ uint32_t sIdx[64];           // batch item and first candidate slot of each staged splat
+  __shared__ uint32_t sLo[64];
   const int64_t gt = ordered ? ordered_tile(blockIdx.x, db->views[0].group_order, total_tiles) : xcd_tile(blockIdx.x);
   if (gt < 0 || gt >= total_tiles) return;
   const int v = view_of_block(db->tile_prefix, db->nviews, gt);
@@ -289,6 +293,8 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
       sA[lane] = make_float4(a.x, a.y, a.z, a.w);
       sB[lane] = b;
       sC[lane] = make_float4(c.x, c.y, c.z, __uint_as_float(pr.y));
+      sIdx[lane] = (uint32_t)db->item_prefix[v] + pr.x;
+      sLo[lane] = V.slot_off[pr.x];
     }
     __syncthreads();
     for (int j = cnt - 1; j >= 0; --j) {
@@ -373,12 +379,17 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
           d[8] = r8;
           d[9] = FALLOFF == GES_FALLOFF_GEF ? (-0.25f * 0.69314718055994531f * B.z) * r9 : 0.f;
         }
-        if (lane == 0) sSlot[nslot] = __float_as_uint(Cc.w);
+        if (lane == 0) {
+          sSlot[nslot] = __float_as_uint(Cc.w);
+          sItem[nslot] = sIdx[j];
+          sFirst[nslot] = sLo[j];
+        }
         ++nslot;
       }
       if (nslot == kFlush || (j == 0 && hi - 64 <= 0 && nslot > 0)) {
-        // one lane per parked splat: add the four row sums and store the tile's sums of the splat in the row
-        // of its slot (the row reduction adds a splat's rows in slot order), marking the slot
+        // one lane per parked splat: add the four row sums and store the tile's sums of the splat, the splat's
+        // batch item and its first candidate slot in the row of its slot (the row reduction adds a splat's rows
+        // in slot order), marking the slot
         __syncthreads();
         if (lane < nslot) {   // entries 0 .. nslot-1 hold row partials
           const uint32_t slot = sSlot[lane];
@@ -394,7 +405,7 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
           Vec4 v0, v1, v2;
           v0[0] = val[0]; v0[1] = val[1]; v0[2] = val[2]; v0[3] = val[3];
           v1[0] = val[4]; v1[1] = val[5]; v1[2] = val[6]; v1[3] = val[7];
-          v2[0] = val[8]; v2[1] = val[9]; v2[2] = 0.f; v2[3] = 0.f;
+          v2[0] = val[8]; v2[1] = val[9]; v2[2] = __uint_as_float(sItem[lane]); v2[3] = __uint_as_float(sFirst[lane]);
           r[0] = v0;
           r[1] = v1;
           r[2] = v2;
