@@ -3,9 +3,9 @@
 // The 3DGS lineage the paper builds on (Sec. 5.2 keeps its design choices) duplicates every splat once
 // per tile it covers and sorts the pairs by (tile, depth).  Here the depth part of that order is settled
 // once per splat instead of once per pair, and only the tile part is sorted over the pairs:
-//   1. depth sort (in ges_preprocess): the listed splats of every view, as (depth bits, item) keys written
-//      by the preprocess, in four stable 8-bit LSD radix passes; the first pass drops unlisted splats.
-//      Stability keeps equal depths in index order.
+//   1. depth sort (in ges_preprocess): the listed splats of every view, keyed by the depth bits the
+//      preprocess writes, in four stable 8-bit LSD radix passes carrying (candidate count, item); the first
+//      pass drops unlisted splats.  Stability keeps equal depths in index order.
 //   2. key scan: every listed splat owns one slot per candidate tile (tile_geom.h), laid out along the
 //      depth order; the offset of each 256-splat chunk and the batch's slot count (the key capacity a frame
 //      needs, read back by the host).
@@ -16,7 +16,7 @@
 //      drops the empty slots.  Pairs of one tile keep the depth order of step 3, hence (depth, index).
 //   5. ranges: each tile's [start, end) from the boundaries of the sorted tile ids (empty tiles (0, 0)).
 // HBM: per listed splat its record (64 B, gathered in depth order) and a few words; per slot 8 B written
-// by the duplication and 16 B moved per radix pass.
+// by the duplication and 12 B read and written per radix pass.
 #include <algorithm>
 
 #include "ges_internal.h"
@@ -38,17 +38,21 @@ hipError_t launch_depth_sort(const DeviceBatch* /*dbatch*/, Batch& b, hipStream_
     w.depth_final = 1;
     return hipGetLastError();
   }
+  // the values are (candidate count, item) pairs, made by the first pass from the counts and the item
+  // indices, so that the key scan and the duplication read the counts in depth order
   const uint32_t* kin = w.item_key;
-  const uint32_t* vin = nullptr;
+  const uint2* vin = nullptr;
   int cur = 0;
   for (int pass = 0; pass < kDepthPasses; ++pass) {
     RadixPass p{};
     p.items = kRadixItemsDepth;
     p.bits = 8;
+    p.pair = 1;
     p.keys_in = kin;
-    p.vals_in = vin;
+    if (pass == 0) p.vals_in = w.item_cand;
+    else p.pvals_in = vin;
     p.keys_out = w.dk[cur];
-    p.vals_out = w.dv[cur];
+    p.pvals_out = w.dv[cur];
     p.count_dev = pass == 0 ? nullptr : &w.cells[0];
     p.count_host = (uint32_t)b.items;
     p.nblocks = nb;
@@ -73,8 +77,7 @@ __device__ __forceinline__ int view_of_item(const DeviceBatch* db, int64_t j) {
 }
 
 // Candidate slots of each 256-splat chunk of the depth order (before its exclusive scan).
-__global__ void __launch_bounds__(256) chunk_sum_kernel(const uint32_t* __restrict__ order,
-                                                        const uint32_t* __restrict__ item_cand,
+__global__ void __launch_bounds__(256) chunk_sum_kernel(const uint2* __restrict__ order,
                                                         const uint32_t* __restrict__ cells, uint32_t* chunk_off) {
   __shared__ uint32_t wsum[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -82,7 +85,7 @@ __global__ void __launch_bounds__(256) chunk_sum_kernel(const uint32_t* __restri
   const int64_t base = (int64_t)blockIdx.x * 256;
   if (base >= (int64_t)listed) return;   // whole block
   const int64_t k = base + threadIdx.x;
-  uint32_t c = k < (int64_t)listed ? item_cand[order[k]] : 0u;
+  uint32_t c = k < (int64_t)listed ? order[k].x : 0u;
   for (int off = 32; off > 0; off >>= 1) c += (uint32_t)__shfl_xor((int)c, off, 64);
   if (lane == 0) wsum[w] = c;
   __syncthreads();
@@ -149,8 +152,8 @@ hipError_t launch_key_scan(const DeviceBatch* dbatch, const Batch& b, hipStream_
   const SortWs& w = b.sw;
   const int64_t chunks = (b.items + 255) / 256;
   if (chunks > 0) {
-    hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)chunks), dim3(256), 0, stream, w.dv[w.depth_final],
-                       w.item_cand, w.cells, w.chunk_off);
+    hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)chunks), dim3(256), 0, stream, w.dv[w.depth_final], w.cells,
+                       w.chunk_off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -197,8 +200,7 @@ __device__ __forceinline__ int owner_of(const uint32_t* ex, uint32_t x) {
 // admits the tile (always for SQUARE), else a dropped key.  Also per splat its tile count and visibility
 // bit, and per view its number of keys.
 __global__ void __launch_bounds__(256) duplicate_kernel(const DeviceBatch* __restrict__ db,
-                                                        const uint32_t* __restrict__ order,
-                                                        const uint32_t* __restrict__ item_cand,
+                                                        const uint2* __restrict__ order,
                                                         const uint32_t* __restrict__ chunk_off, uint32_t* cells,
                                                         uint32_t* keys, uint32_t* vals, uint64_t capacity,
                                                         int ellipse) {
@@ -225,7 +227,8 @@ __global__ void __launch_bounds__(256) duplicate_kernel(const DeviceBatch* __res
   if (busy) {
     const int64_t k = chunk * 64 + lane;
     if (k < (int64_t)listed) {
-      const uint32_t j = order[k];
+      const uint2 cj = order[k];   // (candidate count, item)
+      const uint32_t j = cj.y;
       v = view_of_item(db, j);
       const ViewDesc& V = db->views[v];
       i = (int64_t)j - db->item_prefix[v];
@@ -240,7 +243,7 @@ __global__ void __launch_bounds__(256) duplicate_kernel(const DeviceBatch* __res
       live = true;
       // the splat's slots are the ones the key scan counted (the preprocess ran candidate_count on the same
       // values); its rows are enumerated until they are filled
-      nslots = item_cand[j];
+      nslots = cj.x;
       nrows = nslots ? s.rows : 0u;
       W.slots[lane] = nslots;
       W.filled[lane] = 0u;
@@ -351,7 +354,7 @@ hipError_t launch_duplicate(const DeviceBatch* dbatch, const Batch& b, hipStream
   if (chunks == 0 || b.key_capacity == 0) return hipSuccess;
   const int X = b.dup_buffer;
   hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)chunks), dim3(256), 0, stream, dbatch,
-                     w.dv[w.depth_final], w.item_cand, w.chunk_off, w.cells, b.kw.key[X],
+                     w.dv[w.depth_final], w.chunk_off, w.cells, b.kw.key[X],
                      reinterpret_cast<uint32_t*>(b.kw.pv[X]),
                      b.key_capacity, b.tile_cull == GES_TILES_ELLIPSE ? 1 : 0);
   return hipGetLastError();

@@ -24,9 +24,9 @@ inline SortPlan plan_sort(int64_t items) {
   p.off_key = o;    o += align256(n * 4);
   p.off_cand = o;   o += align256(n * 4);
   p.off_dk0 = o;    o += align256(n * 4);
-  p.off_dv0 = o;    o += align256(n * 4);
+  p.off_dv0 = o;    o += align256(n * 8);
   p.off_dk1 = o;    o += align256(n * 4);
-  p.off_dv1 = o;    o += align256(n * 4);
+  p.off_dv1 = o;    o += align256(n * 8);
   p.off_table = o;  o += align256((size_t)256 * radix_blocks((uint64_t)n, kRadixItemsDepth) * 4);
   p.off_totals = o; o += 1024;
   p.off_chunks = o; o += align256(((n + 255) / 256 + 1) * 4);
@@ -41,9 +41,9 @@ inline SortWs attach_sort_ws(const SortPlan& p, void* base) {
   w.item_key = reinterpret_cast<uint32_t*>(b + p.off_key);
   w.item_cand = reinterpret_cast<uint32_t*>(b + p.off_cand);
   w.dk[0] = reinterpret_cast<uint32_t*>(b + p.off_dk0);
-  w.dv[0] = reinterpret_cast<uint32_t*>(b + p.off_dv0);
+  w.dv[0] = reinterpret_cast<uint2*>(b + p.off_dv0);
   w.dk[1] = reinterpret_cast<uint32_t*>(b + p.off_dk1);
-  w.dv[1] = reinterpret_cast<uint32_t*>(b + p.off_dv1);
+  w.dv[1] = reinterpret_cast<uint2*>(b + p.off_dv1);
   w.table = reinterpret_cast<uint32_t*>(b + p.off_table);
   w.totals = reinterpret_cast<uint32_t*>(b + p.off_totals);
   w.chunk_off = reinterpret_cast<uint32_t*>(b + p.off_chunks);

@@ -87,7 +87,7 @@ struct SortWs {
   uint32_t* item_key;            // [items]
   uint32_t* item_cand;           // [items]
   uint32_t* dk[2];               // [items] depth-sort keys, ping-pong
-  uint32_t* dv[2];               // [items] depth-sort values (item index), ping-pong
+  uint2* dv[2];                  // [items] depth-sort values (candidate count, item index), ping-pong
   uint32_t* table;               // [256][items_blocks] per-block digit counts of a pass, then their prefix
   uint32_t* totals;              // [256] per-digit totals of a pass
   uint32_t* chunk_off;           // [items / 256 + 1] candidate slots before each 256-item chunk of the depth order
