@@ -32,7 +32,8 @@ __global__ void clear_cells_kernel(uint32_t* cells) {
 
 hipError_t launch_depth_sort(const DeviceBatch* /*dbatch*/, Batch& b, hipStream_t stream) {
   SortWs& w = b.sw;
-  const uint32_t nb = radix_blocks((uint64_t)b.items, kRadixItemsDepth);
+  const int sub = radix_sub((uint64_t)b.items, kRadixItemsDepth);
+  const uint32_t nb = radix_blocks((uint64_t)b.items, kRadixItemsDepth, sub);
   if (nb == 0) {   // no splat: no pass runs, so nothing else would write the listed count
     hipLaunchKernelGGL(clear_cells_kernel, dim3(1), dim3(64), 0, stream, w.cells);
     w.depth_final = 1;
@@ -46,6 +47,7 @@ hipError_t launch_depth_sort(const DeviceBatch* /*dbatch*/, Batch& b, hipStream_
   for (int pass = 0; pass < kDepthPasses; ++pass) {
     RadixPass p{};
     p.items = kRadixItemsDepth;
+    p.sub = sub;
     p.bits = 8;
     p.pair = 1;
     p.keys_in = kin;
@@ -580,7 +582,8 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const DeviceBatch* __r
 hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream) {
   if (b.key_capacity == 0) return hipSuccess;
   const SortWs& w = b.sw;
-  const uint32_t nb = radix_blocks(b.key_capacity, kRadixItemsPair);
+  const int sub = radix_sub(b.key_capacity, kRadixItemsPair);
+  const uint32_t nb = radix_blocks(b.key_capacity, kRadixItemsPair, sub);
   // the tile bits split evenly over the passes (13 bits: 7 + 6), so that no pass scatters to more digit
   // runs than it must
   int bits = 1;
@@ -591,6 +594,7 @@ hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream
     const int pb = (bits - shift + left - 1) / left;
     RadixPass p{};
     p.items = kRadixItemsPair;
+    p.sub = sub;
     p.bits = pb;
     p.pair = 1;   // the first pass pairs each splat index with its slot
     p.keys_in = b.kw.key[cur];

@@ -5,6 +5,8 @@
 // is a batch of one.  All per-view buffers live in caller-provided workspaces.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -196,7 +198,8 @@ struct RadixPass {
   uint2* pvals_out;
   const uint32_t* count_dev;     // number of items (device), or NULL: count_host
   uint32_t count_host;
-  uint32_t nblocks;              // table width: blocks of 256 x items items covering the largest count
+  int32_t sub;                   // tiles of 256 x items items per block
+  uint32_t nblocks;              // table width: blocks of sub x 256 x items items covering the largest count
   int32_t shift;                 // digit = (key >> shift) & ((1 << bits) - 1)
   int32_t filter;                // drop items whose key is kNoKey; the kept count goes to count_out
   uint32_t* table;               // [256][nblocks]
@@ -204,9 +207,15 @@ struct RadixPass {
   uint32_t* count_out;
 };
 hipError_t launch_radix_pass(const RadixPass& p, hipStream_t stream);
-inline uint32_t radix_blocks(uint64_t n, int items) {
-  const uint64_t tile = (uint64_t)kRadixThreads * items;
-  return (uint32_t)((n + tile - 1) / tile);
+// Tiles of kRadixThreads x items items that one radix block takes in turn: 1 up to 8,192 tiles (enough
+// blocks to fill the device), then up to 8 (fewer, longer blocks: a shorter digit table).
+inline int radix_sub(uint64_t n, int items) {
+  const uint64_t tiles = (n + (uint64_t)kRadixThreads * items - 1) / ((uint64_t)kRadixThreads * items);
+  return (int)std::min<uint64_t>(8, std::max<uint64_t>(1, tiles / 8192));
+}
+inline uint32_t radix_blocks(uint64_t n, int items, int sub = 1) {
+  const uint64_t span = (uint64_t)kRadixThreads * items * sub;
+  return (uint32_t)((n + span - 1) / span);
 }
 hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
 hipError_t launch_raster_backward(const DeviceBatch* dbatch, const Batch& b, hipStream_t stream);
