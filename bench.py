@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--mixture-epochs", type=int, default=1000)
     ap.add_argument("--no-train-step", action="store_true",
                     help="skip the full optimisation-step measurement (adds SSIM, per-step mask and Adam)")
+    ap.add_argument("--no-views-step", action="store_true",
+                    help="skip the multi-view optimisation step (views batched vs one after another)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof FETCH/WRITE counters)")
@@ -434,6 +436,48 @@ def train_step_bench(dev, cfg, falloff, tile_cull, nsteps, warmup):
     return out
 
 
+def views_step_bench(dev, cfg, falloff, tile_cull, nsteps, warmup, views=4):
+    """The optimisation step over several views of the scene (the workload's camera and views-1 more orbit
+    cameras, one resolution): the views batched into one launch sequence against the same views rendered and
+    back-propagated one after another (the same bits; checked on the parameters after the timed steps)."""
+    import torch
+    from paper_2402_10128_amd import synth
+    from paper_2402_10128_amd.train import TrainConfig, TrainStep
+    sc, cam = cfg["scene"], cfg["camera"]
+    rng = np.random.default_rng(77)
+    cams = [cam] + [synth.orbit_camera(rng, cam.width, cam.height) for _ in range(views - 1)]
+    target = torch.as_tensor(cfg["target"]).to(dev)
+    targets = [target] + [torch.flip(target, dims=[1 + (v % 2)]).contiguous() for v in range(views - 1)]
+    out, params = {}, {}
+    for batched in (True, False):
+        scene = {k: torch.as_tensor(np.ascontiguousarray(v, np.float32)).to(dev) for k, v in sc.arrays().items()}
+        ts = TrainStep(scene, cams, targets, TrainConfig(falloff=falloff, tile_cull=tile_cull, batch_views=batched))
+        it = 1
+        for _ in range(max(1, warmup)):
+            ts.step(it, read_num_keys=True)
+            it += 1
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(nsteps):
+            ts.step(it, read_num_keys=False)
+            it += 1
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / nsteps
+        ts.check_keys()
+        out["batched" if batched else "view_by_view"] = {
+            "ms_per_step": round(ms, 4), "mpix_per_s": round(views * cam.width * cam.height / (ms / 1e3) / 1e6, 3)}
+        params[batched] = scene
+        del ts
+    out["identical_parameters"] = all(torch.equal(params[True][k], params[False][k]) for k in params[True])
+    out["views"] = views
+    out["workload"] = f"{sc.n} splats, {views} views of {cam.width}x{cam.height}"
+    del params
+    torch.cuda.empty_cache()
+    return out
+
+
 def mixture_bench(dev, epochs, log_fn):
     """The paper's 1-D mixture sweep (4 models x 6 signals x 8 N x 20 runs x 2 weight modes on 1,000
     points) in one launch; reports problem-epochs/s, NaN runs and mean final losses per model, and the oracle's
@@ -695,6 +739,11 @@ def main():
         log("optimisation step (mask + render + L1/SSIM/frequency loss + adjoint + Adam)")
         train = train_step_bench(dev, cfg, falloff, tile_cull, args.steps, args.warmup)
         log(f"optimisation step {train['ms_per_step']:.3f} ms: " + json.dumps(train["stage_ms_per_launch"]))
+    views_step = None
+    if not args.no_train_step and not args.no_views_step:
+        log("multi-view optimisation step (4 views batched vs one after another)")
+        views_step = views_step_bench(dev, cfg, falloff, tile_cull, min(args.steps, 10), args.warmup)
+        log(f"views step: {json.dumps(views_step)}")
     variants = None
     if not args.no_variants:
         log("shape-strength sweep and falloff comparison")
@@ -745,6 +794,7 @@ def main():
         "cpu_baseline": cpu,
         "other_workloads": others,
         "train_step": train,
+        "views_step": views_step,
         "variants": variants,
         "mixture_sweep": mixture,
         "serving": serving,
