@@ -561,19 +561,39 @@ hipError_t launch_row_reduce(const DeviceBatch* dbatch, const Batch& b, const fl
   return hipGetLastError();
 }
 
-// Tile ranges from the boundaries of the sorted tile ids (ranges were cleared by the key scan).
+// Tile ranges from the boundaries of the sorted tile ids (ranges were cleared by the key scan).  Each thread
+// reads 4 consecutive ids as one 16-byte load; the ids either side come from the neighbouring lanes.
 __global__ void __launch_bounds__(256) tile_ranges_kernel(const DeviceBatch* __restrict__ db,
                                                           const uint32_t* __restrict__ tiles,
                                                           const uint32_t* __restrict__ cells, int64_t total_tiles) {
-  const uint32_t K = cells[2];
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < (int64_t)K; k += (int64_t)gridDim.x * 256) {
-    const uint32_t t = tiles[k];
-    if ((int64_t)t >= total_tiles) continue;   // not a tile of the batch (never written by the duplication)
-    const bool first = k == 0 || tiles[k - 1] != t;
-    const bool last = k + 1 == (int64_t)K || tiles[k + 1] != t;
+  const uint64_t K = cells[2];
+  const int lane = threadIdx.x & 63;
+  const uint64_t k0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (k0 - 4 * (uint64_t)lane >= K) return;   // the whole wave lies past the keys
+  uint32_t t[4] = {~0u, ~0u, ~0u, ~0u};
+  if (k0 + 4 <= K) {
+    const uint4 q = reinterpret_cast<const uint4*>(tiles)[k0 >> 2];
+    t[0] = q.x; t[1] = q.y; t[2] = q.z; t[3] = q.w;
+  } else {
+    for (int e = 0; e < 4; ++e)
+      if (k0 + e < K) t[e] = tiles[k0 + e];
+  }
+  uint32_t prev = (uint32_t)__shfl_up((int)t[3], 1, 64), next = (uint32_t)__shfl_down((int)t[0], 1, 64);
+  if (lane == 0) prev = k0 > 0 && k0 <= K ? tiles[k0 - 1] : ~0u;
+  if (lane == 63) next = k0 + 4 < K ? tiles[k0 + 4] : ~0u;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint64_t k = k0 + e;
+    if (k >= K) break;
+    const uint32_t tt = t[e];
+    if ((int64_t)tt >= total_tiles) continue;   // not a tile of the batch (never written by the duplication)
+    const uint32_t before = e == 0 ? prev : t[e - 1];
+    const uint32_t after = e == 3 ? next : t[e + 1];
+    const bool first = k == 0 || before != tt;
+    const bool last = k + 1 == K || after != tt;
     if (!first && !last) continue;
-    const int v = view_of_block(db->tile_prefix, db->nviews, (int64_t)t);
-    uint2* r = db->views[v].ranges + ((int64_t)t - db->tile_prefix[v]);
+    const int v = view_of_block(db->tile_prefix, db->nviews, (int64_t)tt);
+    uint2* r = db->views[v].ranges + ((int64_t)tt - db->tile_prefix[v]);
     if (first) r->x = (uint32_t)k;
     if (last) r->y = (uint32_t)(k + 1);
   }
@@ -615,7 +635,7 @@ hipError_t launch_tile_sort(const DeviceBatch* dbatch, const Batch& b, hipStream
     cur ^= 1;
   }
   if (cur != 0) return hipErrorInvalidValue;   // the plan puts the final order in buffer 0
-  const uint64_t rblocks = std::min<uint64_t>((b.key_capacity + 255) / 256, 4096);
+  const uint64_t rblocks = (b.key_capacity + 1023) / 1024;
   hipLaunchKernelGGL(tile_ranges_kernel, dim3((unsigned)rblocks), dim3(256), 0, stream, dbatch,
                      b.kw.key[0], w.cells, b.total_tiles);
   return hipGetLastError();
