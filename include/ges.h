@@ -112,8 +112,8 @@ const char* ges_last_error(void);
 
 /* Sizes of the per-frame workspaces for n splats at width x height.
  * splat_ws holds the per-splat projected records, the depth order of the splats and
- * the candidate offsets along it, the tile ranges and the per-splat 2-D gradient
- * accumulators; pixel_ws holds the
+ * the candidate offsets along it, the tile ranges and the per-splat 2-D gradients;
+ * pixel_ws holds the
  * per-pixel final transmittance and contributor count that the backward pass
  * re-uses (so no per-pixel lists are stored).  Either output pointer may be NULL.
  * Both workspaces are caller-owned device memory and must be 256-byte aligned (device allocations
@@ -164,10 +164,12 @@ ges_status ges_render_forward(const ges_splats* splats, const ges_camera* cam, c
  * shape are optimised through the rasterizer's gradients; the derivative of the
  * compositing of Sec. 4.2, Eq. transimttance): given dL/d(out_rgb) [height,width,3],
  * walks every pixel's contributors back to front recovering the transmittance by
- * division, accumulates
- * the gradient of each splat's 2-D quantities (mean2D, conic, opacity, colour and,
- * with the GEF falloff, beta), then maps them to the parameters through the
- * preprocess chain rule (evaluated in binary64).  Every gradient buffer of `grads`
+ * division, sums the gradient of each splat's 2-D quantities (mean2D, conic, opacity,
+ * colour and, with the GEF falloff, beta) per tile in binary32 and over its tiles in
+ * binary64 in a fixed order (no atomics: two calls give identical bits), then maps them
+ * to the parameters through the preprocess chain rule (evaluated in binary64).  Uses
+ * the key workspace of the forward pass for its per-(tile, splat) rows (key_ws must be
+ * the one ges_render_forward was given).  Every gradient buffer of `grads`
  * is overwritten; NULL members are skipped.  grads->quats, and grads->sh at SH degree
  * 1 or 3, must be 16-byte aligned (INVALID_ARGUMENT otherwise), like the inputs.
  * Must follow the ges_render_forward of the same frame. */

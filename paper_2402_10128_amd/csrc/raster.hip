@@ -16,8 +16,10 @@
 // before splat j as T_j = T_(j+1) / (1 - alpha_j) from the stored final T, so no per-pixel lists are
 // kept.  Per splat, the 4 pixels of a lane are summed in registers and each row of 16 lanes by a DPP
 // reduce-scatter; the row's lanes park the row sums in LDS, and every 32 splats each lane finishes one
-// parked splat (4 row sums) and adds its components to binary64 accumulators with float64 atomics
-// (the cross-tile sums of a splat often cancel; binary32 accumulation would lose accuracy there).
+// parked splat (4 row sums) and stores the tile's ten sums of the splat as a row at the pair's candidate
+// slot, marking the slot; a row reduction then adds each splat's rows in binary64 in slot order (the
+// cross-tile sums of a splat often cancel; binary32 accumulation would lose accuracy there), with no
+// atomics, so the backward is deterministic.
 // Factors of 2 common to a splat's terms (the mean2D and b gradients) are applied once per (tile, splat).
 #include "ges_internal.h"
 
@@ -225,7 +227,7 @@ __device__ __forceinline__ float row_scatter8(float a0, float a1, float a2, floa
   return dpp_add<0xB1, 0xf>(d0);                                               // quad_perm [1,0,3,2]
 }
 
-constexpr int kFlush = 32;   // splats whose row partials are parked in LDS before one atomic flush
+constexpr int kFlush = 32;   // splats whose row partials are parked in LDS before one flush of rows
 
 template <int FALLOFF>
 __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* __restrict__ db,

@@ -189,7 +189,7 @@ def test_mix_fit_validates_before_any_device_work():
 
 
 def test_workspaces_must_be_256_byte_aligned():
-    # the kernels move records and tile words as 16-byte vectors and accumulate binary64 atomics in place
+    # the kernels move records, tile words and backward rows as 16-byte vectors
     lib = G.lib()
     cam = G.camera_struct(synth.pinhole(64, 64, (0, 0, -4.0)))
     p = G.params_struct()
