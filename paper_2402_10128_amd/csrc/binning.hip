@@ -96,7 +96,8 @@ __global__ void __launch_bounds__(256) chunk_sum_kernel(const uint2* __restrict_
 
 // One block: exclusive scan of the chunk sums (saturating at 2^32 - 1, which the host reports as
 // capacity exceeded); the batch's slot count into cells[1]; the per-view header words and ranges cleared
-// for the coming render.
+// for the coming render.  Each thread scans kPer consecutive sums of a round in registers, so a round takes
+// one block-wide scan of the thread totals.
 __global__ void __launch_bounds__(1024) chunk_scan_kernel(const DeviceBatch* __restrict__ db, uint32_t* chunk_off,
                                                           uint32_t* cells) {
   constexpr int kPer = 8;
@@ -108,34 +109,32 @@ __global__ void __launch_bounds__(1024) chunk_scan_kernel(const DeviceBatch* __r
   if (threadIdx.x == 0) carry = 0ull;
   __syncthreads();
   for (int64_t base = 0; base < nchunks; base += 1024 * kPer) {
+    const int64_t c0 = base + (int64_t)threadIdx.x * kPer;   // this thread's kPer consecutive entries
     uint32_t x[kPer];
     unsigned long long local = 0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {   // thread t takes entries t, t + 1024, ...: coalesced loads
-      const int64_t c = base + (int64_t)k * 1024 + threadIdx.x;
-      x[k] = c < nchunks ? chunk_off[c] : 0u;
+    for (int k = 0; k < kPer; ++k) {
+      x[k] = c0 + k < nchunks ? chunk_off[c0 + k] : 0u;
+      local += x[k];
     }
-    // the scan runs over the entries in order: thread t's k-th entry is entry base + k * 1024 + t, so scan
-    // round by round (each round a block-wide scan of 1024 entries)
+    unsigned long long s = local;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const unsigned long long y = __shfl_up(s, d, 64);
+      if (lane >= d) s += y;
+    }
+    if (lane == 63) wsum[wid] = s;
+    __syncthreads();
+    unsigned long long run = carry + s - local;
+    for (int q = 0; q < wid; ++q) run += wsum[q];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int64_t c = base + (int64_t)k * 1024 + threadIdx.x;
-      unsigned long long s = x[k];
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const unsigned long long y = __shfl_up(s, d, 64);
-        if (lane >= d) s += y;
-      }
-      if (lane == 63) wsum[wid] = s;
-      __syncthreads();
-      unsigned long long run = carry + s - x[k];
-      for (int q = 0; q < wid; ++q) run += wsum[q];
-      if (c < nchunks) chunk_off[c] = run > 0xffffffffull ? 0xffffffffu : (uint32_t)run;
-      __syncthreads();
-      if (threadIdx.x == 1023) carry = run + x[k];
-      __syncthreads();
+      if (c0 + k < nchunks) chunk_off[c0 + k] = run > 0xffffffffull ? 0xffffffffu : (uint32_t)run;
+      run += x[k];
     }
-    (void)local;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = run;
+    __syncthreads();
   }
   if (threadIdx.x == 0) {
     cells[1] = carry >= 0xffffffffull ? 0xffffffffu : (uint32_t)carry;
