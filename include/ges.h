@@ -201,7 +201,8 @@ typedef struct {
 /* Record layout, 16 x 32-bit words per splat:
  *   0 u, 1 v, 2 conic a, 3 conic b, 4 conic c, 5 q_max, 6 opacity, 7 beta,
  *   8 r, 9 g, 10 b, 11 depth, 12 radius | flags << 24 (int32), 13 tx0 | ty0 << 16,
- *   14 tx1 | ty1 << 16 (inclusive), 15 tiles_touched (uint32; 0 = culled).
+ *   14 tx1 | ty1 << 16 (inclusive), 15 tiles_touched (uint32; 0 = culled; between ges_preprocess
+ *   and ges_render_forward, GES_TILES_ELLIPSE: the splat's candidate count, an upper bound).
  *   flags: bit0..2 colour channel clamped at 0, bit3/4 x/y guard clamp. */
 ges_status ges_frame_view_get(int64_t n, int32_t width, int32_t height, void* splat_ws, void* key_ws,
                               uint64_t num_keys, void* pixel_ws, ges_frame_view* out);

@@ -335,10 +335,12 @@ __global__ void __launch_bounds__(256) duplicate_kernel(const DeviceBatch* __res
     }
     if (live && W.filled[lane] != nslots) atomicOr(&db->views[0].header[1], 2ull);   // never expected
     if (live) {
+      // the preprocess left the candidate count in tiles_touched and the visibility bit set when it is
+      // non-zero: rewrite them only where the exact count differs (scattered 4-byte stores)
       const ViewDesc& V = db->views[v];
       const uint32_t h = W.hits[lane];
-      reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = h;
-      V.vis[i] = (h ? kVisBit : 0u) | flags;
+      if (h != nslots) reinterpret_cast<uint32_t*>(V.rec)[16 * i + R_TOUCHED] = h;
+      if (h == 0u && nslots != 0u) V.vis[i] = flags;
       const uint64_t first = slot0 + (sincl - nslots);   // the splat's first slot (its rows in the backward)
       V.slot_off[i] = first > 0xffffffffull ? 0xffffffffu : (uint32_t)first;
       if (h) atomicAdd(&view_keys[v], h);

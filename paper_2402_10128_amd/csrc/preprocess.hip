@@ -219,9 +219,6 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
   if (!(xl <= xh) || !(yl <= yh)) { write_culled(V, i); return; }
   const int tx0 = (int)xl / kTile, tx1 = (int)xh / kTile;
   const int ty0 = (int)yl / kTile, ty1 = (int)yh / kTile;
-  // SQUARE: every tile of the rectangle.  ELLIPSE: the rectangle's area here; the duplication
-  // replaces it by the exact number of tiles the ellipse meets (possibly 0).
-  const uint32_t touched = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
 
   float shv[3 * K];
   if constexpr ((3 * K) % 4 == 0) {
@@ -259,21 +256,25 @@ __device__ __forceinline__ void preprocess_splat(const ViewDesc& V, int64_t i) {
     rgb[ch] = acc;
   }
 
-  // visibility and clamp flags for the backward pass (ELLIPSE: the duplication clears the bit of a
-  // splat whose ellipse meets no tile); the splat's depth-sort key and its number of candidate tiles
-  V.vis[i] = (touched ? kVisBit : 0u) | bits;
+  // the splat's depth-sort key and its number of candidate tiles (SQUARE: the rectangle); the candidate
+  // count stands in for tiles_touched and the visibility bit until the duplication has counted the tiles
+  // the exact test accepts (it rewrites the two words only where that count differs), with the clamp flags
+  // for the backward pass
+  uint32_t cand;
   {
     SplatTiles st;
     candidate_tiles(u, vv, ca, cb, cc, qm, tx0, ty0, tx1, ty1, V.tile_cull == GES_TILES_ELLIPSE, st);
-    V.item_key[i] = __float_as_uint(z);
-    V.item_cand[i] = candidate_count(st, V.height);
+    cand = candidate_count(st, V.height);
   }
+  V.item_key[i] = __float_as_uint(z);
+  V.item_cand[i] = cand;
+  V.vis[i] = (cand ? kVisBit : 0u) | bits;
   rec[4 * i + 0] = make_float4(u, vv, ca, cb);
   rec[4 * i + 1] = make_float4(cc, qm, op, beta);
   rec[4 * i + 2] = make_float4(rgb[0], rgb[1], rgb[2], z);
   rec[4 * i + 3] = make_float4(__int_as_float((int)((uint32_t)radius | (bits << 24))),
                                __uint_as_float((uint32_t)tx0 | ((uint32_t)ty0 << 16)),
-                               __uint_as_float((uint32_t)tx1 | ((uint32_t)ty1 << 16)), __uint_as_float(touched));
+                               __uint_as_float((uint32_t)tx1 | ((uint32_t)ty1 << 16)), __uint_as_float(cand));
 }
 
 __global__ void __launch_bounds__(256) preprocess_kernel(const DeviceBatch* __restrict__ db) {
