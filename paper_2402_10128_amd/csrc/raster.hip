@@ -7,11 +7,14 @@
 //   skip unless q <= q_max (alpha >= 1/255);   falloff G = exp(-q/2) (PHI) or exp(-q^(beta/2)/2) (GEF)
 //   alpha = min(0.99, o G);  t = T (1 - alpha);  stop before compositing when t < 1e-4
 //   C += alpha T rgb;  T = t.
-// Launch shape (gfx950): one wave64 per 16x16 tile, each lane owning 4 pixels of one column
-// (rows y, y+4, y+8, y+12), so each splat read from LDS is used four times per lane.  Splats are
-// staged 64 at a time: lane l gathers record l of the batch into LDS, then every lane reads the batch
-// back as broadcasts.  The wave stops as soon as no lane has a live pixel (ballot).  Tiles are dealt
-// to the 8 XCDs in groups of 8 neighbours (see xcd_tile).
+// Launch shape (gfx950): the forward pass gives a 16x16 tile two wave64s, each owning 8 rows with 2
+// pixels per lane (one column, rows y and y+4): the tile's serial walk is halved, which shortens the tail
+// of the heaviest tiles (3M-splat 1080p frame: 0.27 -> 0.24 ms; four waves with 1 pixel per lane: 0.30 ms).
+// The backward pass, whose issue rate is saturated, keeps one wave per tile with 4 pixels per lane (rows
+// y, y+4, y+8, y+12), so each splat read from LDS is used four times per lane.  Splats are staged 64 at a
+// time into LDS, then every lane reads the batch back as broadcasts.  A wave stops as soon as no lane has a
+// live pixel (ballot); the forward block once neither wave has.  Tiles are dealt to the 8 XCDs in groups of
+// 8 neighbours (see xcd_tile).
 // The backward pass walks each pixel's contributors back to front, recovering the transmittance
 // before splat j as T_j = T_(j+1) / (1 - alpha_j) from the stored final T, so no per-pixel lists are
 // kept.  Per splat, the 4 pixels of a lane are summed in registers and each row of 16 lanes by a DPP
@@ -68,32 +71,44 @@ __device__ __forceinline__ int64_t ordered_tile(int64_t blk, const uint32_t* gro
   return t < tiles ? t : -1;
 }
 
+constexpr int kFwdWaves = 2;                // waves per tile in the forward pass
+constexpr int kFwdPix = 4 / kFwdWaves;      // pixels per lane (one column, rows 4 apart)
+static_assert(kFwdWaves == 2 || kFwdWaves == 4, "waves 0 and 1 stage the records; 16 rows split evenly");
+
 template <int FALLOFF>
-__global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* __restrict__ db,
-                                                            const uint2* __restrict__ sorted_pairs,
-                                                            int64_t total_tiles,
-                                                            uint64_t capacity) {
+__global__ void __launch_bounds__(64 * kFwdWaves) raster_forward_kernel(const DeviceBatch* __restrict__ db,
+                                                             const uint2* __restrict__ sorted_pairs,
+                                                             int64_t total_tiles,
+                                                             uint64_t capacity) {
   __shared__ float4 sA[64], sB[64], sC[64];
+  __shared__ uint32_t live[kFwdWaves];
+  __shared__ unsigned long long red[kFwdWaves][2];
+  __shared__ uint32_t red_m[kFwdWaves];
   const int64_t gt = xcd_tile(blockIdx.x);
-  if (gt >= total_tiles) return;
+  if (gt >= total_tiles) return;   // the whole block
   const int v = view_of_block(db->tile_prefix, db->nviews, gt);
   const ViewDesc& V = db->views[v];
   const int lt = (int)(gt - db->tile_prefix[v]);
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int px = tx * kTile + (lane & 15);
-  const int py0 = ty * kTile + (lane >> 4);
+  const int py0 = ty * kTile + (kTile / kFwdWaves) * w + (lane >> 4);   // the wave's rows: py0 + 4 k
   const float pxf = (float)px;
-  float pyf[4];
+  float pyf[kFwdPix];
   uint32_t alive = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kFwdPix; ++k) {
     pyf[k] = (float)(py0 + 4 * k);
     if (px < V.width && py0 + 4 * k < V.height) alive |= 1u << k;
   }
-  float T[4] = {1.f, 1.f, 1.f, 1.f};
-  float C[4][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-  uint32_t last[4] = {0u, 0u, 0u, 0u};
+  float T[kFwdPix], C[kFwdPix][3];
+  uint32_t last[kFwdPix];
+#pragma unroll
+  for (int k = 0; k < kFwdPix; ++k) {
+    T[k] = 1.f;
+    C[k][0] = C[k][1] = C[k][2] = 0.f;
+    last[k] = 0u;
+  }
   uint32_t n_exam = 0;    // pairs examined: each terminated pixel adds 1 + its terminating position
   uint32_t n_blend = 0;   // pairs composited, for the statistics
   const uint2 rg = V.ranges[lt];
@@ -101,51 +116,62 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
   const int n = (uint64_t)rg.y <= capacity ? (int)(rg.y - rg.x) : 0;
   const GlobalRec* rec = (const GlobalRec*)(V.rec);
   for (int base = 0; base < n; base += 64) {
-    if (!__any(alive != 0)) break;
     const int cnt = min(64, n - base);
-    if (lane < cnt) {
+    if (lane < cnt) {   // wave 0 stages words 0-7 of the batch's records, wave 1 words 8-11
       const uint32_t id = sorted_pairs[rg.x + base + lane].x;
-      const float4 a = rec_load(rec, 4 * (size_t)id);
-      const float4 b = rec_load(rec, 4 * (size_t)id + 1);
-      const float4 c = rec_load(rec, 4 * (size_t)id + 2);
-      sA[lane] = make_float4(a.x, a.y, a.z, a.w + a.w);
-      sB[lane] = b;
-      sC[lane] = c;
-    }
-    __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const float4 A = sA[j];
-      const float4 B = sB[j];
-      const float4 Cc = sC[j];
-      const uint32_t pos1 = (uint32_t)(base + j + 1);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (!(alive & (1u << k))) continue;
-        float dx, dy;
-        float q = pair_q(A.x, A.y, A.z, A.w, B.x, pxf, pyf[k], dx, dy);
-        if (!(q <= B.y)) continue;
-        q = fmaxf(q, 0.f);
-        float G;
-        if (FALLOFF == GES_FALLOFF_PHI) {
-          G = fast_exp2(kNegHalfLog2e * q);
-        } else {
-          const float qb = fast_exp2(0.5f * B.w * fast_log2(q));
-          G = fast_exp2(kNegHalfLog2e * qb);
-        }
-        const float alpha = fminf(kAlphaMax, B.z * G);
-        const float t = T[k] * (1.f - alpha);
-        if (t < kTMin) { alive &= ~(1u << k); n_exam += pos1; continue; }
-        const float w = alpha * T[k];
-        C[k][0] = __builtin_fmaf(w, Cc.x, C[k][0]);
-        C[k][1] = __builtin_fmaf(w, Cc.y, C[k][1]);
-        C[k][2] = __builtin_fmaf(w, Cc.z, C[k][2]);
-        T[k] = t;
-        last[k] = pos1;
-        ++n_blend;
+      if (w == 0) {
+        const float4 a = rec_load(rec, 4 * (size_t)id);
+        const float4 b = rec_load(rec, 4 * (size_t)id + 1);
+        sA[lane] = make_float4(a.x, a.y, a.z, a.w + a.w);
+        sB[lane] = b;
+      } else if (w == 1) {
+        sC[lane] = rec_load(rec, 4 * (size_t)id + 2);
       }
-      if (!__any(alive != 0)) break;
     }
     __syncthreads();
+    if (__any(alive != 0)) {   // wave-uniform: a wave whose pixels have all stopped only stages
+      for (int j = 0; j < cnt; ++j) {
+        const float4 A = sA[j];
+        const float4 B = sB[j];
+        const float4 Cc = sC[j];
+        const uint32_t pos1 = (uint32_t)(base + j + 1);
+#pragma unroll
+        for (int k = 0; k < kFwdPix; ++k) {
+          if (!(alive & (1u << k))) continue;
+          float dx, dy;
+          float q = pair_q(A.x, A.y, A.z, A.w, B.x, pxf, pyf[k], dx, dy);
+          if (!(q <= B.y)) continue;
+          q = fmaxf(q, 0.f);
+          float G;
+          if (FALLOFF == GES_FALLOFF_PHI) {
+            G = fast_exp2(kNegHalfLog2e * q);
+          } else {
+            const float qb = fast_exp2(0.5f * B.w * fast_log2(q));
+            G = fast_exp2(kNegHalfLog2e * qb);
+          }
+          const float alpha = fminf(kAlphaMax, B.z * G);
+          const float t = T[k] * (1.f - alpha);
+          if (t < kTMin) { alive &= ~(1u << k); n_exam += pos1; continue; }
+          const float wgt = alpha * T[k];
+          C[k][0] = __builtin_fmaf(wgt, Cc.x, C[k][0]);
+          C[k][1] = __builtin_fmaf(wgt, Cc.y, C[k][1]);
+          C[k][2] = __builtin_fmaf(wgt, Cc.z, C[k][2]);
+          T[k] = t;
+          last[k] = pos1;
+          ++n_blend;
+        }
+        if (!__any(alive != 0)) break;
+      }
+    }
+    // the block stops once every pixel of the tile has (the same decision in both waves, taken after the
+    // barrier that also ends the reads of this batch)
+    const bool wl = __any(alive != 0);
+    if (lane == 0) live[w] = wl ? 1u : 0u;
+    __syncthreads();
+    uint32_t any_live = 0;
+#pragma unroll
+    for (int q = 0; q < kFwdWaves; ++q) any_live |= live[q];
+    if (!any_live) break;
   }
   {
     // pair statistics of the tile: pairs examined (each pixel up to and including its terminating splat)
@@ -154,20 +180,32 @@ __global__ void __launch_bounds__(64) raster_forward_kernel(const DeviceBatch* _
     // pixels still alive examined the whole list (out-of-image pixels were never alive)
     unsigned long long e = (unsigned long long)n_exam + (unsigned long long)__popc(alive) * (uint32_t)n, b = n_blend;
     // and the length of the backward walk over the tile: its last composited position
-    uint32_t m = max(max(last[0], last[1]), max(last[2], last[3]));
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < kFwdPix; ++k) m = max(m, last[k]);
     for (int off = 32; off > 0; off >>= 1) {
       e += __shfl_xor(e, off, 64);
       b += __shfl_xor(b, off, 64);
       m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
     }
-    if (lane == 0) {
-      V.tile_stats[2 * lt] = e;
-      V.tile_stats[2 * lt + 1] = b;
-      V.tile_work[lt] = m;
+    if (lane == 0) { red[w][0] = e; red[w][1] = b; red_m[w] = m; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long se = 0, sb = 0;
+      uint32_t sm = 0;
+#pragma unroll
+      for (int q = 0; q < kFwdWaves; ++q) {
+        se += red[q][0];
+        sb += red[q][1];
+        sm = max(sm, red_m[q]);
+      }
+      V.tile_stats[2 * lt] = se;
+      V.tile_stats[2 * lt + 1] = sb;
+      V.tile_work[lt] = sm;
     }
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kFwdPix; ++k) {
     const int py = py0 + 4 * k;
     if (px >= V.width || py >= V.height) continue;
     const size_t pix = (size_t)py * V.width + px;
@@ -499,10 +537,10 @@ hipError_t launch_raster_forward(const DeviceBatch* dbatch, const Batch& b, hipS
   const dim3 grid((unsigned)((b.total_tiles + span - 1) / span * span));
   // every view of a batch shares the falloff (the server fixes it per instance)
   if (b.falloff != GES_FALLOFF_GEF)   // Gaussian falloff (PHI, PHI_EXACT)
-    hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_PHI>, grid, dim3(64), 0, stream, dbatch, b.sorted_pairs,
+    hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_PHI>, grid, dim3(64 * kFwdWaves), 0, stream, dbatch, b.sorted_pairs,
                        b.total_tiles, b.key_capacity);
   else
-    hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_GEF>, grid, dim3(64), 0, stream, dbatch, b.sorted_pairs,
+    hipLaunchKernelGGL(raster_forward_kernel<GES_FALLOFF_GEF>, grid, dim3(64 * kFwdWaves), 0, stream, dbatch, b.sorted_pairs,
                        b.total_tiles, b.key_capacity);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
