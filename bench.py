@@ -79,7 +79,7 @@ def log(msg):
 
 def algorithmic_bytes(stage, n, sh_coeffs, K, C, L, px, R=0):
     """Minimum HBM bytes of one launch of an HBM-bound stage: n splats, K keys, C candidate slots, L listed
-    splats, px pixels, R rows stored by the backward raster (the per-unit figures are listed in the design doc)."""
+    splats, px pixels, R rows stored by the backward raster (the per-unit figures are the comments below)."""
     splat_in = 12 + 12 + 16 + 4 + 4 + 12 * sh_coeffs
     return {
         # parameters in; record, visibility word, depth key and candidate count out
@@ -674,8 +674,8 @@ def fwd_bwd(dev, cfg, falloff, tile_cull, steps, warmup, log_fn):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
+                                   "(sharding across GPUs is not implemented)"}))
         sys.exit(2)
     import torch
     from paper_2402_10128_amd import ges as G
