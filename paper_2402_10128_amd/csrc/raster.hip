@@ -112,8 +112,9 @@ __global__ void __launch_bounds__(64 * kFwdWaves) raster_forward_kernel(const De
   uint32_t n_exam = 0;    // pairs examined: each terminated pixel adds 1 + its terminating position
   uint32_t n_blend = 0;   // pairs composited, for the statistics
   const uint2 rg = V.ranges[lt];
-  // a range beyond the key buffer (inconsistent key count) renders as background
-  const int n = (uint64_t)rg.y <= capacity ? (int)(rg.y - rg.x) : 0;
+  // a range beyond the key buffer (inconsistent key count) renders as background; the list length is made
+  // a scalar, so that the batch and splat loop control runs on the scalar unit
+  const int n = __builtin_amdgcn_readfirstlane((uint64_t)rg.y <= capacity ? (int)(rg.y - rg.x) : 0);
   const GlobalRec* rec = (const GlobalRec*)(V.rec);
   for (int base = 0; base < n; base += 64) {
     const int cnt = min(64, n - base);
@@ -313,8 +314,10 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
     TfB[k] = T[k] * (V.bg[0] * g[k][0] + V.bg[1] * g[k][1] + V.bg[2] * g[k][2]);
     maxlast = max(maxlast, last[k]);
   }
-  // wave max of the last contributor position
+  // wave max of the last contributor position, made a scalar: the walk's loop control (positions, the
+  // parked-splat count, the flush test) then runs on the scalar unit instead of taking VALU issue slots
   for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, off, 64));
+  maxlast = (uint32_t)__builtin_amdgcn_readfirstlane((int)maxlast);
   const uint2 rg = V.ranges[lt];
   const GlobalRec* rec = (const GlobalRec*)(V.rec);
   // global address space: the row stores then count only against vmcnt, and the LDS waits of the following
@@ -347,13 +350,14 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
       // (dq = dL/dq; halves of the mean2D and b gradients), of G dL/dalpha (opacity), of alpha T g
       // (colour) and, for GEF, of dL/dbeta
       float su = 0.f, sv = 0.f, pa = 0.f, pb = 0.f, pc = 0.f, po = 0.f, pr = 0.f, pg = 0.f, pbl = 0.f, pbeta = 0.f;
-      bool any = false;
+      bool entered = false;   // wave-uniform: some row band had a pixel that took the splat
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         float dx, dy;
         const float q0 = pair_q(A.x, A.y, A.z, bb, B.x, pxf, pyf[k], dx, dy);
         const bool valid = (pos < last[k]) && (q0 <= B.y);
         if (!__any(valid)) continue;   // wave-uniform: no pixel of this row band took the splat
+        entered = true;
         // straight-line for every lane; a pixel that did not take the splat gets alpha = 0 (T, S and every
         // accumulated term are then unchanged: 1/(1 - 0) = 1 exactly)
         const float q = fmaxf(q0, 0.f);
@@ -380,7 +384,6 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         S[k][0] = __builtin_fmaf(alpha, d0, S[k][0]);
         S[k][1] = __builtin_fmaf(alpha, d1, S[k][1]);
         S[k][2] = __builtin_fmaf(alpha, d2, S[k][2]);
-        any = any || valid;
         // below the clamp: dL/do = G dL/dalpha and G dL/dG = alpha dL/dalpha = o (G dL/dalpha); above it
         // both are 0.  Per pixel only gd = G dL/dalpha is formed: the opacity o and the constant of dG/dq
         // are common to the splat's terms and multiply its row sums once (dq below is dL/dq / (o k)).
@@ -404,7 +407,7 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         pb = __builtin_fmaf(dqdx, dy, pb);
         pc = __builtin_fmaf(dqdy, dy, pc);
       }
-      if (__any(any)) {
+      if (entered) {
         // rows of 16 lanes reduce in registers: the first 8 sums by a reduce-scatter (after it, lanes 2i and
         // 2i+1 of a row hold row sum i), the blue and beta sums by a full row sum; the row's lanes then park
         // the 10 sums in LDS, each scaled by the splat's common factor (o k for the dq sums, o for dL/dbeta)
