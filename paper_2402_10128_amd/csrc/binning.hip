@@ -267,8 +267,9 @@ __global__ void __launch_bounds__(256) duplicate_kernel(const DeviceBatch* __res
     const uint32_t z = (uint32_t)__shfl_up((int)rincl, d, 64);
     if (lane >= d) { sincl += y; rincl += z; }
   }
-  const uint32_t total = (uint32_t)__shfl((int)sincl, 63, 64);
-  const uint32_t rtotal = (uint32_t)__shfl((int)rincl, 63, 64);
+  // wave totals as scalars: the loops below then keep their control on the scalar unit
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)sincl, 63, 64));
+  const uint32_t rtotal = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)rincl, 63, 64));
   if (lane == 0) wave_total[wave] = total;
   __syncthreads();
   if (busy) {
@@ -302,7 +303,7 @@ __global__ void __launch_bounds__(256) duplicate_kernel(const DeviceBatch* __res
         const uint32_t y = (uint32_t)__shfl_up((int)wincl, d, 64);
         if (lane >= d) wincl += y;
       }
-      const uint32_t ctotal = (uint32_t)__shfl((int)wincl, 63, 64);
+      const uint32_t ctotal = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)wincl, 63, 64));
       W.rown[lane] = (uint32_t)j;
       W.rty[lane] = ty;
       W.rlo[lane] = clo;

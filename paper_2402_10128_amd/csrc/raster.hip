@@ -34,6 +34,10 @@ __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_ex
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// max(q, 0) for q that is not NaN, as one integer max of the bits (a negative q, -0 included, has a negative
+// bit pattern); fmaxf costs a canonicalisation besides under IEEE mode.
+__device__ __forceinline__ float clamp_q(float q) { return __int_as_float(max(__float_as_int(q), 0)); }
+
 __device__ __forceinline__ float pair_q(float u, float v, float a, float bb, float c, float px, float py,
                                         float& dx, float& dy) {
   dx = u - px;
@@ -142,7 +146,7 @@ __global__ void __launch_bounds__(64 * kFwdWaves) raster_forward_kernel(const De
           float dx, dy;
           float q = pair_q(A.x, A.y, A.z, A.w, B.x, pxf, pyf[k], dx, dy);
           if (!(q <= B.y)) continue;
-          q = fmaxf(q, 0.f);
+          q = clamp_q(q);
           float G;
           if (FALLOFF == GES_FALLOFF_PHI) {
             G = fast_exp2(kNegHalfLog2e * q);
@@ -360,7 +364,7 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         entered = true;
         // straight-line for every lane; a pixel that did not take the splat gets alpha = 0 (T, S and every
         // accumulated term are then unchanged: 1/(1 - 0) = 1 exactly)
-        const float q = fmaxf(q0, 0.f);
+        const float q = clamp_q(q0);
         float G, qb = 0.f, lq = 0.f;
         if (FALLOFF == GES_FALLOFF_PHI) {
           G = fast_exp2(kNegHalfLog2e * q);
@@ -395,7 +399,7 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
         } else {
           // dG/dq = -(beta/4) q^(beta/2 - 1) G  (q floored at 1e-12): k = -beta/4;
           // dG/dbeta = -(1/4) q^(beta/2) ln q G: the row sum of q^(beta/2) log2 q gd takes -(ln 2)/4 o
-          const float qf = fmaxf(q, 1e-12f);
+          const float qf = __int_as_float(max(__float_as_int(q), __float_as_int(1e-12f)));   // q >= +0
           const float qpow = fast_exp2((0.5f * B.w - 1.f) * fast_log2(qf));
           dq = q0 >= 0.f ? qpow * gd : 0.f;
           pbeta = __builtin_fmaf(q > 0.f ? qb * lq : 0.f, gd, pbeta);
