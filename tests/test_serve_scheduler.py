@@ -129,7 +129,9 @@ def test_continuous_batching_admits_arrivals_while_busy():
     with Server(1 << 30, max_slots=16, simulated=dict(batch_ns=5_000_000, per_view_ns=50_000)) as s:
         sid = s.add_scene(dict(n=1000))
         first = s.submit(sid, CAM, 1)
-        time.sleep(0.001)
+        t0 = time.monotonic()   # the first batch has taken the first request (it runs for 5 ms)
+        while s.poll(first)["state"] == "QUEUED" and time.monotonic() - t0 < 5.0:
+            time.sleep(0.0001)
         rest = [s.submit(sid, CAM, 1) for _ in range(8)]
         s.drain()
         b0 = s.poll(first)["batch_size"]
