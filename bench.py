@@ -160,8 +160,13 @@ def kernel_source_hash(stage):
            "preprocess_backward": "preprocess_bwd.hip", "tile_sort": "radix.hip", "depth_sort": "radix.hip",
            "duplicate": "binning.hip", "key_scan": "binning.hip", "row_reduce": "binning.hip", "loss": "loss.hip",
            "zero": "loss.hip"}[stage]
-    with open(os.path.join(HERE, "paper_2402_10128_amd", "csrc", src), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    # the kernel's source file and the shared headers it is built with (layouts and constants live there)
+    csrc = os.path.join(HERE, "paper_2402_10128_amd", "csrc")
+    h = hashlib.sha256()
+    for name in [src] + sorted(f for f in os.listdir(csrc) if f.endswith(".h")):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_counter(stage, workload, field):
