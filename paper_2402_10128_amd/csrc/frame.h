@@ -122,7 +122,7 @@ inline int tile_passes(int64_t total_tiles) {
 
 // Key workspace of `slots` candidate slots: two buffers of (tile; splat index, slot) pairs, the values of
 // buffer 0 first (the sorted pairs the raster reads); the table of the tile passes; and, for frames that
-// run the backward pass, one 64-byte row per slot for the backward's per-(tile, splat) sums with a bit per
+// run the backward pass, one 48-byte row per slot for the backward's per-(tile, splat) sums with a bit per
 // slot marking the written rows.
 struct KeyPlan {
   size_t off_pv0 = 0, off_key0 = 0, off_pv1 = 0, off_key1 = 0, off_table = 0, off_totals = 0, off_rows = 0,

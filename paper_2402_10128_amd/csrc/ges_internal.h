@@ -106,8 +106,7 @@ struct KeyWs {
   uint32_t* table;               // [256][key_blocks]
   uint32_t* totals;              // [256]
 };
-constexpr int kRowFloats = 16;   // floats per backward row (12 written: 10 sums, item, first slot); 64-byte rows each
-                                 // fill one aligned 64-byte memory segment (48-byte rows straddled two)
+constexpr int kRowFloats = 12;   // floats per backward row (10 used; 48 bytes keep rows 16-byte aligned)
 
 struct Batch {
   int32_t nviews;
