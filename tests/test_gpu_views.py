@@ -22,6 +22,7 @@ CASES = [
     # (name, splats, width, height, views, falloff, tile_cull)
     ("20k_256x192_3views_phi_ellipse", 20_000, 256, 192, 3, G.FALLOFF_PHI, G.TILES_ELLIPSE),
     ("20k_200x136_4views_gef_square", 20_000, 200, 136, 4, G.FALLOFF_GEF, G.TILES_SQUARE),
+    ("5k_75x61_3views_gef_ellipse", 5_000, 75, 61, 3, G.FALLOFF_GEF, G.TILES_ELLIPSE),   # ragged tiles
 ]
 
 
