@@ -83,16 +83,23 @@ __global__ void __launch_bounds__(kRadixThreads) radix_upsweep_kernel(RadixPass 
   p.table[(size_t)threadIdx.x * p.nblocks + blockIdx.x] = c;
 }
 
-// Block d: exclusive scan of row d (8 consecutive entries per thread per round), the row total to totals[d].
-__global__ void __launch_bounds__(kRadixThreads) radix_scan_kernel(RadixPass p) {
+// Block d: exclusive scan of row d (8 consecutive entries per thread per round, 1024 threads: one round for
+// up to 8,192 blocks), the row total to totals[d].  Digits beyond the pass's width have empty rows: their
+// blocks only clear the total.
+constexpr int kScanThreads = 1024;
+__global__ void __launch_bounds__(kScanThreads) radix_scan_kernel(RadixPass p) {
   constexpr int kPer = 8;
-  __shared__ uint32_t wsum[kRadixThreads / 64];
+  __shared__ uint32_t wsum[kScanThreads / 64];
   __shared__ uint32_t carry;
+  if (blockIdx.x >= (1u << p.bits)) {
+    if (threadIdx.x == 0) p.totals[blockIdx.x] = 0u;
+    return;
+  }
   uint32_t* row = p.table + (size_t)blockIdx.x * p.nblocks;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x == 0) carry = 0u;
   __syncthreads();
-  for (uint32_t base = 0; base < p.nblocks; base += kRadixThreads * kPer) {
+  for (uint32_t base = 0; base < p.nblocks; base += kScanThreads * kPer) {
     const uint32_t j0 = base + threadIdx.x * kPer;
     uint32_t x[kPer];
     uint32_t local = 0;
@@ -117,7 +124,7 @@ __global__ void __launch_bounds__(kRadixThreads) radix_scan_kernel(RadixPass p) 
       run += x[k];
     }
     __syncthreads();
-    if (threadIdx.x == kRadixThreads - 1) carry = run;
+    if (threadIdx.x == kScanThreads - 1) carry = run;
     __syncthreads();
   }
   if (threadIdx.x == 0) p.totals[blockIdx.x] = carry;
@@ -359,7 +366,7 @@ hipError_t launch_radix_pass_t(const RadixPass& p, hipStream_t stream) {
   hipLaunchKernelGGL(radix_upsweep_kernel<ITEMS>, dim3(p.nblocks), dim3(kRadixThreads), 0, stream, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(kRadixThreads), 0, stream, p);
+  hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(kScanThreads), 0, stream, p);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (p.sub == 1)
