@@ -90,7 +90,7 @@ struct SortWs {
   uint32_t* item_cand;           // [items]
   uint32_t* dk[2];               // [items] depth-sort keys, ping-pong
   uint2* dv[2];                  // [items] depth-sort values (candidate count, item index), ping-pong
-  uint32_t* table;               // [256][items_blocks] per-block digit counts of a pass, then their prefix
+  uint32_t* table;               // [16][items_blocks][16] per-block digit counts of a pass, then their prefix
   uint32_t* totals;              // [256] per-digit totals of a pass
   uint32_t* chunk_off;           // [items / 256 + 1] candidate slots before each 256-item chunk of the depth order
   uint32_t* cells;               // [0] listed items, [1] candidate slots (saturating), [2] keys, [3] spare
@@ -103,7 +103,7 @@ struct KeyWs {
   uint2* pv[2];                  // (splat index, slot) values of the tile passes; the duplication writes the
                                  // splat indices as u32 into the first half of pv[dup_buffer]
   uint32_t* key[2];
-  uint32_t* table;               // [256][key_blocks]
+  uint32_t* table;               // [16][key_blocks][16]
   uint32_t* totals;              // [256]
 };
 constexpr int kRowFloats = 12;   // floats per backward row (10 used; 48 bytes keep rows 16-byte aligned)
@@ -202,7 +202,7 @@ struct RadixPass {
   uint32_t nblocks;              // table width: blocks of sub x 256 x items items covering the largest count
   int32_t shift;                 // digit = (key >> shift) & ((1 << bits) - 1)
   int32_t filter;                // drop items whose key is kNoKey; the kept count goes to count_out
-  uint32_t* table;               // [256][nblocks]
+  uint32_t* table;               // [16][nblocks][16] (digit group, block, digit in the group)
   uint32_t* totals;              // [256]
   uint32_t* count_out;
 };

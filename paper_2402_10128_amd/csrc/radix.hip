@@ -1,10 +1,10 @@
 // radix.hip -- one stable LSD radix pass over (u32 key, u32 value) items with digits of up to 8 bits.
 //
 // Reduce-then-scan, three launches per pass:
-//   upsweep:   each block counts the digits of its items in per-wave LDS histograms and writes its row of
-//              counts into the digit-major table [256][nblocks];
-//   scan:      one block per digit turns its row into exclusive per-block offsets and writes the digit's
-//              total;
+//   upsweep:   each block counts the digits of its items in per-wave LDS histograms and writes its 256
+//              counts into the digit table ([16 digit groups][nblocks][16], see radix_tidx);
+//   scan:      one block per digit turns its counts into exclusive per-block offsets and writes the
+//              digit's total;
 //   downsweep: each block ranks its items stably -- every wave owns a contiguous quarter of the block's
 //              items and ranks them 64 at a time with one ballot per digit bit (lanes holding the same
 //              digit) against wave-private digit counters -- places them in LDS in digit order, and writes
@@ -52,6 +52,16 @@ __device__ __forceinline__ uint32_t radix_digit(const RadixPass& p, uint32_t k) 
   return (k >> p.shift) & ((1u << p.bits) - 1u);
 }
 
+// The digit table holds, per block b and digit d, the block's count of d and then its exclusive prefix over
+// the blocks.  Layout [d / 16][b][d % 16]: a block's 256 entries are 16 runs of 64 contiguous bytes (its
+// writes in the upsweep and reads in the downsweep are whole segments; digit-major rows of 4-byte entries
+// left a partial segment per entry), and a group of 16 digits is a contiguous [blocks][16] array for the
+// scan.
+constexpr int kDigitGroup = 16;
+__device__ __forceinline__ size_t radix_tidx(uint32_t d, uint32_t b, uint32_t nblocks) {
+  return ((size_t)(d / kDigitGroup) * nblocks + b) * kDigitGroup + (d % kDigitGroup);
+}
+
 template <int ITEMS>
 __global__ void __launch_bounds__(kRadixThreads) radix_upsweep_kernel(RadixPass p) {
   constexpr int kWaves = kRadixThreads / 64;
@@ -80,39 +90,42 @@ __global__ void __launch_bounds__(kRadixThreads) radix_upsweep_kernel(RadixPass 
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < kWaves; ++k) c += hist[k][threadIdx.x];
-  p.table[(size_t)threadIdx.x * p.nblocks + blockIdx.x] = c;
+  p.table[radix_tidx(threadIdx.x, blockIdx.x, p.nblocks)] = c;
 }
 
-// Block d: exclusive scan of row d (8 consecutive entries per thread per round, 1024 threads: one round for
-// up to 8,192 blocks), the row total to totals[d].  Digits beyond the pass's width have empty rows: their
-// blocks only clear the total.
+// One block per digit: the exclusive scan of the digit's counts over the blocks (8 entries per thread per
+// round, 1,024 threads: one round for up to 8,192 blocks), its total to totals[].  The 16 digits of a group
+// share the table's 64-byte segments, so they are dealt to one XCD (blocks go to the XCDs round-robin) and
+// each segment is fetched once into that XCD's L2.  Digits beyond the pass's width only clear their total.
 constexpr int kScanThreads = 1024;
 __global__ void __launch_bounds__(kScanThreads) radix_scan_kernel(RadixPass p) {
   constexpr int kPer = 8;
   __shared__ uint32_t wsum[kScanThreads / 64];
   __shared__ uint32_t carry;
-  if (blockIdx.x >= (1u << p.bits)) {
-    if (threadIdx.x == 0) p.totals[blockIdx.x] = 0u;
+  const uint32_t x = blockIdx.x & 7u, i = blockIdx.x >> 3;   // XCD, and the block's index on it
+  const uint32_t d = (((i / kDigitGroup) << 3) + x) * kDigitGroup + (i % kDigitGroup);
+  if (d >= (1u << p.bits)) {
+    if (threadIdx.x == 0) p.totals[d] = 0u;
     return;
   }
-  uint32_t* row = p.table + (size_t)blockIdx.x * p.nblocks;
+  uint32_t* col = p.table + radix_tidx(d, 0, p.nblocks);   // entry of block b at col[16 b]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x == 0) carry = 0u;
   __syncthreads();
   for (uint32_t base = 0; base < p.nblocks; base += kScanThreads * kPer) {
     const uint32_t j0 = base + threadIdx.x * kPer;
-    uint32_t x[kPer];
+    uint32_t v[kPer];
     uint32_t local = 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      x[k] = j0 + k < p.nblocks ? row[j0 + k] : 0u;
-      local += x[k];
+      v[k] = j0 + k < p.nblocks ? col[(size_t)(j0 + k) * kDigitGroup] : 0u;
+      local += v[k];
     }
     uint32_t s = local;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t y = (uint32_t)__shfl_up((int)s, d, 64);
-      if (lane >= d) s += y;
+    for (int dd = 1; dd < 64; dd <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)s, dd, 64);
+      if (lane >= dd) s += y;
     }
     if (lane == 63) wsum[w] = s;
     __syncthreads();
@@ -120,14 +133,14 @@ __global__ void __launch_bounds__(kScanThreads) radix_scan_kernel(RadixPass p) {
     for (int k = 0; k < w; ++k) run += wsum[k];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      if (j0 + k < p.nblocks) row[j0 + k] = run;
-      run += x[k];
+      if (j0 + k < p.nblocks) col[(size_t)(j0 + k) * kDigitGroup] = run;
+      run += v[k];
     }
     __syncthreads();
     if (threadIdx.x == kScanThreads - 1) carry = run;
     __syncthreads();
   }
-  if (threadIdx.x == 0) p.totals[blockIdx.x] = carry;
+  if (threadIdx.x == 0) p.totals[d] = carry;
 }
 
 template <bool PAIR>
@@ -214,7 +227,7 @@ __global__ void __launch_bounds__(kRadixThreads) radix_downsweep_kernel(RadixPas
     uint32_t ls = s - tot, gs = g - gtot;
     for (int k = 0; k < w; ++k) { ls += wsum[0][k]; gs += wsum[1][k]; }
     dstart[t] = ls;
-    gstart[t] = gs + p.table[(size_t)t * p.nblocks + blockIdx.x];
+    gstart[t] = gs + p.table[radix_tidx(t, blockIdx.x, p.nblocks)];
     if (t == 255) kept = ls + tot;
   }
   __syncthreads();
@@ -274,7 +287,7 @@ __global__ void __launch_bounds__(kRadixThreads) radix_downsweep_multi_kernel(Ra
     __syncthreads();
     uint32_t gs = g - gtot;
     for (int k = 0; k < w; ++k) gs += wsum[1][k];
-    gstart[t] = gs + p.table[(size_t)t * p.nblocks + blockIdx.x];
+    gstart[t] = gs + p.table[radix_tidx(t, blockIdx.x, p.nblocks)];
   }
   // the block's tiles in turn; gstart advances by each tile's digit counts
   for (int sub = 0; sub < p.sub; ++sub) {
