@@ -25,6 +25,9 @@ CASES = [
     # ragged in both directions with the last tile row 13 rows high: the forward's second wave (rows 8-15 of
     # a tile) has pixels in its first band only
     ("w0_gef_ellipse_ragged", 0, 800, 75, 61, O.FALLOFF_GEF, O.TILES_ELLIPSE),
+    # tile sorts with digits of 1 and 3 bits (one tile; 3 x 2 tiles)
+    ("w0_phi_ellipse_1tile", 0, 300, 16, 16, O.FALLOFF_PHI, O.TILES_ELLIPSE),
+    ("w0_gef_square_6tiles", 0, 300, 40, 20, O.FALLOFF_GEF, O.TILES_SQUARE),
     ("w1_small_sh3", 1, 20000, 200, 136, O.FALLOFF_PHI, O.TILES_SQUARE),
     ("w1_small_sh3_gef", 1, 20000, 200, 136, O.FALLOFF_GEF, O.TILES_ELLIPSE),
     ("w0_phi_exact_ellipse", 0, 1000, None, None, O.FALLOFF_PHI_EXACT, O.TILES_ELLIPSE),
