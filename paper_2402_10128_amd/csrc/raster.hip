@@ -296,7 +296,6 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
   const float pxf = (float)px;
   float pyf[4], T[4], TfB[4], g[4][3], S[4][3];
   uint32_t last[4];
-  uint32_t maxlast = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int py = py0 + 4 * k;
@@ -316,12 +315,18 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
     }
     // T_final (bg . g): the background's share of dL/dalpha, divided by (1 - alpha) per splat
     TfB[k] = T[k] * (V.bg[0] * g[k][0] + V.bg[1] * g[k][1] + V.bg[2] * g[k][2]);
-    maxlast = max(maxlast, last[k]);
   }
-  // wave max of the last contributor position, made a scalar: the walk's loop control (positions, the
-  // parked-splat count, the flush test) then runs on the scalar unit instead of taking VALU issue slots
-  for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, off, 64));
-  maxlast = (uint32_t)__builtin_amdgcn_readfirstlane((int)maxlast);
+  // wave max of the last contributor position per band of 4 rows and over the tile, made scalars: the walk's
+  // loop control (positions, the parked-splat count, the flush test) then runs on the scalar unit instead of
+  // taking VALU issue slots, and a band skips its test of the splats behind all of its pixels' last ones
+  uint32_t band_last[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t m = last[k];
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
+    band_last[k] = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
+  }
+  const uint32_t maxlast = max(max(band_last[0], band_last[1]), max(band_last[2], band_last[3]));
   const uint2 rg = V.ranges[lt];
   const GlobalRec* rec = (const GlobalRec*)(V.rec);
   // global address space: the row stores then count only against vmcnt, and the LDS waits of the following
@@ -357,6 +362,7 @@ __global__ void __launch_bounds__(64) raster_backward_kernel(const DeviceBatch* 
       bool entered = false;   // wave-uniform: some row band had a pixel that took the splat
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
+        if (pos >= band_last[k]) continue;   // scalar: every pixel of the band composited its last splat before
         float dx, dy;
         const float q0 = pair_q(A.x, A.y, A.z, bb, B.x, pxf, pyf[k], dx, dy);
         const bool valid = (pos < last[k]) && (q0 <= B.y);
